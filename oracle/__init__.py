@@ -1,0 +1,175 @@
+"""CPU FP64 reference for the geodesic ray tracer (test infrastructure only).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package.  It shares no code with the HIP
+implementation in ``paper_2310_15183_amd``; see ``oracle.c`` for the
+arithmetic and the passages of the paper each step follows.
+
+Flags: 0 timeout (step limit reached), 1 escape (r > escape_factor * r0),
+2 horizon (|dt/dtau| > horizon_norm), 3 invalid (non-finite state).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# Flags chosen so that no product is fused behind the source's back and libm is
+# used exactly as written.
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-pthread",
+          "-std=c11", "-Wall", "-Wextra"]
+
+FLAG_TIMEOUT, FLAG_ESCAPE, FLAG_HORIZON, FLAG_INVALID = 0, 1, 2, 3
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so next to it (gcc, plain C11)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        d, i, i64 = ctypes.c_double, ctypes.c_int, ctypes.c_int64
+        vp = ctypes.c_void_p
+        lib.oracle_trace_frame.restype = i64
+        lib.oracle_trace_frame.argtypes = [d, d, d, d, d, d, d, i, i, d, d, d, d, i,
+                                           vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, i]
+        lib.oracle_trace_rays.restype = i64
+        lib.oracle_trace_rays.argtypes = [d, d, d, d, d, d, d, i, vp, i64,
+                                          vp, vp, vp, vp, vp, vp, vp, vp, i]
+        lib.oracle_camera.restype = None
+        lib.oracle_camera.argtypes = [d, d, d, d, d, d, d, i, i, vp, i64, vp]
+        lib.oracle_inverse_metric.restype = None
+        lib.oracle_inverse_metric.argtypes = [d, d, d, d, d, vp]
+        lib.oracle_set_trig_mode.restype = None
+        lib.oracle_set_trig_mode.argtypes = [i]
+        lib.oracle_sincos.restype = None
+        lib.oracle_sincos.argtypes = [vp, i64, vp]
+        lib.oracle_rhs.restype = None
+        lib.oracle_rhs.argtypes = [d, d, d, d, d, d, d, d, d, d, vp, vp]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_threads() -> int:
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+@dataclass
+class Result:
+    t: np.ndarray
+    r: np.ndarray
+    theta: np.ndarray
+    phi: np.ndarray
+    pr: np.ndarray
+    ptheta: np.ndarray
+    flag: np.ndarray
+    steps: np.ndarray
+    p0: np.ndarray | None = None   # (n, 4) initial covector, frame mode only
+
+
+def _alloc(n):
+    return [np.empty(n, np.float64) for _ in range(6)] + [np.empty(n, np.int8),
+                                                          np.empty(n, np.int32)]
+
+
+def trace_frame(M, a, Q, r0, theta0, phi0, fov, width, height, dt=0.01, eps=1e-8,
+                horizon_norm=1e4, escape_factor=1.5, max_steps=20000, pixels=None,
+                threads=None, want_p0=False) -> Result:
+    """Trace the camera rays of a width x height frame (or the listed pixels)."""
+    lib = _load()
+    if pixels is not None:
+        pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+        n = int(pixels.size)
+    else:
+        n = int(width) * int(height)
+    t, r, th, ph, pr, pth, flag, steps = _alloc(n)
+    p0 = np.empty((n, 4), np.float64) if want_p0 else None
+    lib.oracle_trace_frame(M, a, Q, r0, theta0, phi0, fov, int(width), int(height), dt, eps,
+                           horizon_norm, escape_factor, int(max_steps), _ptr(pixels), n,
+                           _ptr(t), _ptr(r), _ptr(th), _ptr(ph), _ptr(pr), _ptr(pth), _ptr(p0),
+                           _ptr(flag), _ptr(steps), int(threads or default_threads()))
+    return Result(t, r, th, ph, pr, pth, flag, steps, p0)
+
+
+def trace_rays(M, a, Q, init, dt=0.01, eps=1e-8, horizon_norm=1e4, escape_factor=1.5,
+               max_steps=20000, threads=None) -> Result:
+    """Trace rays from explicit initial states, init[k] = (t, r, th, ph, p_t, p_r, p_th, p_ph)."""
+    lib = _load()
+    init = np.ascontiguousarray(init, dtype=np.float64).reshape(-1, 8)
+    n = init.shape[0]
+    t, r, th, ph, pr, pth, flag, steps = _alloc(n)
+    lib.oracle_trace_rays(M, a, Q, dt, eps, horizon_norm, escape_factor, int(max_steps),
+                          _ptr(init), n, _ptr(t), _ptr(r), _ptr(th), _ptr(ph), _ptr(pr),
+                          _ptr(pth), _ptr(flag), _ptr(steps), int(threads or default_threads()))
+    return Result(t, r, th, ph, pr, pth, flag, steps)
+
+
+def camera(M, a, Q, r0, theta0, phi0, fov, width, height, pixels=None) -> np.ndarray:
+    """Initial states (n, 8) = (q^mu, p_mu) of the camera rays."""
+    lib = _load()
+    if pixels is not None:
+        pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+        n = int(pixels.size)
+    else:
+        n = int(width) * int(height)
+    out = np.empty((n, 8), np.float64)
+    lib.oracle_camera(M, a, Q, r0, theta0, phi0, fov, int(width), int(height), _ptr(pixels),
+                      n, _ptr(out))
+    return out
+
+
+def inverse_metric(M, a, Q, r, theta) -> np.ndarray:
+    """(g^tt, g^tphi, g^rr, g^thth, g^phph) at (r, theta)."""
+    lib = _load()
+    g = np.empty(5, np.float64)
+    lib.oracle_inverse_metric(M, a, Q, float(r), float(theta), _ptr(g))
+    return g
+
+
+def rhs(M, a, Q, r, theta, p, eps=1e-8):
+    """Hamilton right-hand side at (r, theta, p): (qdot[4], (pdot_r, pdot_theta))."""
+    lib = _load()
+    qd = np.empty(4, np.float64)
+    pd = np.empty(2, np.float64)
+    lib.oracle_rhs(M, a, Q, eps, float(r), float(theta), float(p[0]), float(p[1]),
+                   float(p[2]), float(p[3]), _ptr(qd), _ptr(pd))
+    return qd, pd
+
+
+def set_trig_mode(mode: int) -> None:
+    """0: sin/cos from their series definition (default); 1: the C library."""
+    _load().oracle_set_trig_mode(int(mode))
+
+
+def sincos(x) -> tuple[np.ndarray, np.ndarray]:
+    """The oracle's sin/cos definition applied elementwise."""
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    sc = np.empty((x.size, 2), np.float64)
+    _load().oracle_sincos(_ptr(x), x.size, _ptr(sc))
+    return sc[:, 0], sc[:, 1]

@@ -1,0 +1,491 @@
+/*
+ * CPU reference ("oracle") for backward null-geodesic ray tracing around a
+ * Kerr-Newman black hole in Boyer-Lindquist coordinates.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call this file;
+ * only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * load it.  It shares no code with the HIP implementation.
+ *
+ * What it computes (paper: Sec. 2.1 "The Equation of Motion", eq. hamGeodesic,
+ * Appendix A "The Legendre Transform for Pseudo-Riemannian geodesics";
+ * Sec. 3.1.2 "Runge Kutta Integrators"; Sec. 3.3 "Raytracing"; the appendix
+ * listing "Code for propagation of rays"):
+ *
+ *   H(q,p) = 1/2 g^{mu nu}(r,theta) p_mu p_nu,
+ *   dq^mu/dtau = g^{mu nu} p_nu,
+ *   dp_mu/dtau = -1/2 d_mu g^{nu sigma} p_nu p_sigma,
+ *
+ * integrated with classical RK4 whose step h = dt / |dq^t/dtau| is fixed for
+ * the whole step from the first stage, so that coordinate time advances by
+ * about dt per step.  d_r g and d_theta g are one-sided forward differences
+ * with step eps; the t and phi derivatives vanish (stationary, axisymmetric),
+ * so p_t and p_phi never change.  A ray stops when r exceeds escape_factor
+ * times its starting radius (escape), else when |dq^t/dtau| exceeds
+ * horizon_norm (step collapse at the horizon), else when its state is no
+ * longer finite, else after max_steps updates.
+ *
+ * Everything is IEEE binary64.  Build with -O2 -ffp-contract=off
+ * -fno-fast-math: every fused multiply-add below is an explicit fma() and no
+ * other product is fused.  sin and cos are evaluated from their definition
+ * (reduction by multiples of pi/2, then the Taylor series with coefficients
+ * 1/n!, see trig_sincos) rather than taken from the C library: the forward
+ * difference divides rounding noise by eps, so a one-ulp change anywhere in a
+ * ray's state moves its end angles by ~1e-9 rad, and a reproducible result
+ * needs every operation to be defined.  The C library's sin/cos can be
+ * selected instead (trig_mode 1) to show that the physics does not depend
+ * on that choice.
+ *
+ * Parity status: pinned (flat space, Schwarzschild critical impact parameter
+ * and deflection integral, Kerr/Kerr-Newman capture by the radial potential,
+ * conserved p_t, p_phi, H and Carter constant, mirror symmetries).
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { FLAG_TIMEOUT = 0, FLAG_ESCAPE = 1, FLAG_HORIZON = 2, FLAG_INVALID = 3 };
+
+typedef struct {
+    double M, a, Q;              /* mass, spin length a = J/M, charge (G=c=1) */
+    double dt, eps;              /* coordinate-time step, finite-difference step */
+    double horizon_norm;         /* stop when |dq^t/dtau| exceeds this */
+    double escape_factor;        /* stop when r > escape_factor * r_start */
+    int max_steps;
+    int trig_mode;               /* 0: trig_sincos below; 1: C library sin/cos */
+} oracle_params;
+
+/* ------------------------------------------------------------------------ */
+/* sin and cos from their definitions.
+ *   x = k pi/2 + r with k the integer nearest to x (2/pi) and |r| <= pi/4;
+ *   pi/2 is split as PIO2_HI + PIO2_LO (PIO2_HI = fl(pi/2)) so that
+ *   x - k PIO2_HI is exact in one fma for moderate |x|.
+ *   sin r = r + r z (S1 + z (S2 + ... + z S8)),  S_n = (-1)^n / (2n+1)!
+ *   cos r = 1 + z (C1 + z (C2 + ... + z C8)),    C_n = (-1)^n / (2n)!
+ *   with z = r^2 (truncation error below 1e-18 on |r| <= pi/4).
+ *   Quadrant k mod 4 = 0, 1, 2, 3 maps (sin x, cos x) to (s, c), (c, -s),
+ *   (-s, -c), (-c, s) of the reduced pair (s, c).
+ * Each coefficient is 1/m! rounded once (m! is exact in binary64 for m <= 18). */
+static const double TWO_OVER_PI = 0x1.45f306dc9c883p-1;   /* fl(2/pi) */
+static const double PIO2_HI = 0x1.921fb54442d18p+0;       /* fl(pi/2) */
+static const double PIO2_LO = 0x1.1a62633145c07p-54;      /* fl(pi/2 - PIO2_HI) */
+
+static double SIN_C[9], COS_C[9];                          /* index n = 1..8 */
+static pthread_once_t trig_once = PTHREAD_ONCE_INIT;
+
+static void trig_init(void)
+{
+    double fact = 1.0;                                     /* m! */
+    for (int m = 1; m <= 17; ++m) {
+        fact *= (double)m;
+        const double sign = ((m / 2) % 2) ? -1.0 : 1.0;    /* (-1)^n, n = floor(m/2) */
+        if (m % 2) SIN_C[m / 2] = sign * (1.0 / fact);     /* m = 2n+1 */
+        else       COS_C[m / 2] = sign * (1.0 / fact);     /* m = 2n   */
+    }
+}
+
+static void trig_sincos(double x, double *s_out, double *c_out)
+{
+    const double k = rint(x * TWO_OVER_PI);
+    double r = fma(-k, PIO2_HI, x);
+    r = fma(-k, PIO2_LO, r);
+    const double z = r * r;
+    double ps = SIN_C[8], pc = COS_C[8];
+    for (int n = 7; n >= 1; --n) {
+        ps = fma(ps, z, SIN_C[n]);
+        pc = fma(pc, z, COS_C[n]);
+    }
+    const double sr = fma(r * z, ps, r);
+    const double cr = fma(z, pc, 1.0);
+    const double quad = k - 4.0 * floor(0.25 * k);         /* k mod 4 */
+    const int swap = (quad == 1.0) || (quad == 3.0);
+    double s = swap ? cr : sr, c = swap ? sr : cr;
+    if (quad >= 2.0) s = -s;
+    if (quad == 1.0 || quad == 2.0) c = -c;
+    *s_out = s;
+    *c_out = c;
+}
+
+static void sincos_mode(int mode, double x, double *s, double *c)
+{
+    if (mode == 1) {
+        *s = sin(x);
+        *c = cos(x);
+    } else {
+        trig_sincos(x, s, c);               /* tables set by make_params */
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Inverse Kerr-Newman metric at (r, theta).  Paper Sec. 2.2.2 "The Kerr
+ * Metric" (Boyer-Lindquist coordinates in Carroll's convention; the printed
+ * covariant metric has typos, the textbook form is used) extended by the
+ * charge term Q^2 in Delta.  Five independent components:
+ *   g[0] = g^{tt}, g[1] = g^{t phi}, g[2] = g^{rr}, g[3] = g^{theta theta},
+ *   g[4] = g^{phi phi}.
+ *
+ *   Delta  = r^2 - 2 M r + a^2 + Q^2
+ *   rho^2  = r^2 + a^2 cos^2 theta
+ *   Sigma2 = (r^2 + a^2)^2 - a^2 Delta sin^2 theta
+ *   g^{tt}   = -Sigma2 / (rho^2 Delta)
+ *   g^{tphi} = -a (2 M r - Q^2) / (rho^2 Delta)
+ *   g^{rr}   = Delta / rho^2
+ *   g^{thth} = 1 / rho^2
+ *   g^{phph} = (Delta - a^2 sin^2 theta) / (rho^2 Delta sin^2 theta)
+ *
+ * The sequence of roundings is fixed (it matters: the forward difference
+ * divides rounding noise by eps).  sin^2 and cos^2 are passed in so that the
+ * same rounded values serve every evaluation at one theta. */
+static void inverse_metric(const oracle_params *P, double r, double s2, double c2,
+                           double g[5])
+{
+    const double a2 = P->a * P->a;
+    const double r2 = r * r;
+    const double ra = r2 + a2;                                 /* r^2 + a^2 */
+    const double rho2 = fma(a2, c2, r2);                       /* r^2 + a^2 cos^2 */
+    const double Delta = fma(r, r - 2.0 * P->M, a2 + P->Q * P->Q);
+    const double w = a2 * s2;                                  /* a^2 sin^2 */
+    const double Sigma2 = fma(-w, Delta, ra * ra);
+    const double inv = 1.0 / (rho2 * Delta);                   /* 1/(rho^2 Delta) */
+    const double is2 = 1.0 / s2;
+    g[0] = -(Sigma2 * inv);
+    g[1] = -((P->a * fma(2.0 * P->M, r, -(P->Q * P->Q))) * inv);
+    g[2] = (Delta * Delta) * inv;
+    g[3] = Delta * inv;
+    g[4] = ((Delta - w) * inv) * is2;
+}
+
+/* g^{mu nu} at (r, theta) from the angle itself (the listing's metricAtPoint). */
+static void metric_at_point(const oracle_params *P, double r, double theta, double g[5])
+{
+    double s, c;
+    sincos_mode(P->trig_mode, theta, &s, &c);
+    inverse_metric(P, r, s * s, c * c, g);
+}
+
+/* Right-hand side of Hamilton's equations at one RK4 stage point.
+ * Paper eq. hamGeodesic with the factor 1/2 of Appendix A; derivatives by
+ * forward differences of step eps as in the listing (metric evaluated at
+ * (r,theta), (r+eps,theta) and (r,theta+eps)).  The difference quotient is
+ * formed by multiplying with 1/eps (for eps = 1e-8 that reciprocal is exactly
+ * 1e8 in binary64).  The contraction sums the five nonzero terms in the order
+ * tt, t-phi (counted twice via the weight 2 p_t p_phi), rr, theta-theta,
+ * phi-phi. */
+static void hamilton_rhs(const oracle_params *P, double inv_eps,
+                         double r, double theta, double pt, double pr,
+                         double pth, double pph, double qdot[4], double pdot[2])
+{
+    double g[5], gr[5], gth[5], dR[5], dT[5];
+    metric_at_point(P, r, theta, g);
+    metric_at_point(P, r + P->eps, theta, gr);
+    metric_at_point(P, r, theta + P->eps, gth);
+    for (int k = 0; k < 5; ++k) {
+        dR[k] = (gr[k] - g[k]) * inv_eps;
+        dT[k] = (gth[k] - g[k]) * inv_eps;
+    }
+    /* weights p_nu p_sigma of the five independent components */
+    const double wtt = pt * pt, wtp = (2.0 * pt) * pph, wpp = pph * pph;
+    const double wrr = pr * pr, wth = pth * pth;
+
+    double acc = dR[0] * wtt;
+    acc = fma(dR[1], wtp, acc);
+    acc = fma(dR[2], wrr, acc);
+    acc = fma(dR[3], wth, acc);
+    acc = fma(dR[4], wpp, acc);
+    pdot[0] = -0.5 * acc;                                      /* dp_r/dtau */
+
+    acc = dT[0] * wtt;
+    acc = fma(dT[1], wtp, acc);
+    acc = fma(dT[2], wrr, acc);
+    acc = fma(dT[3], wth, acc);
+    acc = fma(dT[4], wpp, acc);
+    pdot[1] = -0.5 * acc;                                      /* dp_theta/dtau */
+
+    qdot[0] = fma(g[0], pt, g[1] * pph);                       /* dt/dtau */
+    qdot[1] = g[2] * pr;                                       /* dr/dtau */
+    qdot[2] = g[3] * pth;                                      /* dtheta/dtau */
+    qdot[3] = fma(g[1], pt, g[4] * pph);                       /* dphi/dtau */
+}
+
+static int all_finite(const double q[4], double pr, double pth)
+{
+    return isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && isfinite(q[3]) &&
+           isfinite(pr) && isfinite(pth);
+}
+
+/* Integrate one ray.  q = (t, r, theta, phi), p = (p_t, p_r, p_theta, p_phi)
+ * are updated in place; returns the flag, *nsteps = updates taken.
+ * Paper: listing loop body (stages K1..K4, update, exit tests), Sec. 3.1.2
+ * (RK4 weights 1/6, 2/6, 2/6, 1/6), Sec. 3.3.2 "Propagation". */
+int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nsteps)
+{
+    const double inv_eps = 1.0 / P->eps;
+    const double r_esc = P->escape_factor * q[1];
+    const double pt = p[0], pph = p[3];
+    double pr = p[1], pth = p[2];
+    int flag = FLAG_TIMEOUT, s = 0;
+    *nsteps = 0;
+    if (!(all_finite(q, pr, pth) && isfinite(pt) && isfinite(pph)))
+        return FLAG_INVALID;
+
+    for (s = 1; s <= P->max_steps; ++s) {
+        double k1q[4], k1p[2], k2q[4], k2p[2], k3q[4], k3p[2], k4q[4], k4p[2];
+        /* K1 at the current point; its dt/dtau fixes the step. */
+        hamilton_rhs(P, inv_eps, q[1], q[2], pt, pr, pth, pph, k1q, k1p);
+        const double nu = fabs(k1q[0]);
+        const double h = P->dt / nu;
+        const double hh = 0.5 * h;
+        /* K2, K3 at half steps, K4 at the full step. */
+        hamilton_rhs(P, inv_eps, fma(hh, k1q[1], q[1]), fma(hh, k1q[2], q[2]), pt,
+                     fma(hh, k1p[0], pr), fma(hh, k1p[1], pth), pph, k2q, k2p);
+        hamilton_rhs(P, inv_eps, fma(hh, k2q[1], q[1]), fma(hh, k2q[2], q[2]), pt,
+                     fma(hh, k2p[0], pr), fma(hh, k2p[1], pth), pph, k3q, k3p);
+        hamilton_rhs(P, inv_eps, fma(h, k3q[1], q[1]), fma(h, k3q[2], q[2]), pt,
+                     fma(h, k3p[0], pr), fma(h, k3p[1], pth), pph, k4q, k4p);
+        /* x += h/6 (k1 + 2 k2 + 2 k3 + k4) */
+        const double h6 = h * (1.0 / 6.0);
+        for (int m = 0; m < 4; ++m)
+            q[m] = fma(h6, ((k1q[m] + 2.0 * k2q[m]) + 2.0 * k3q[m]) + k4q[m], q[m]);
+        pr = fma(h6, ((k1p[0] + 2.0 * k2p[0]) + 2.0 * k3p[0]) + k4p[0], pr);
+        pth = fma(h6, ((k1p[1] + 2.0 * k2p[1]) + 2.0 * k3p[1]) + k4p[1], pth);
+
+        if (q[1] > r_esc) { flag = FLAG_ESCAPE; break; }
+        if (nu > P->horizon_norm) { flag = FLAG_HORIZON; break; }
+        if (!all_finite(q, pr, pth)) { flag = FLAG_INVALID; break; }
+    }
+    if (s > P->max_steps) s = P->max_steps;
+    p[1] = pr;
+    p[2] = pth;
+    *nsteps = s;
+    return flag;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pinhole camera (paper Sec. 3.3.1 "Initial positions"; listing lightlikeT).
+ * A static camera at (r0, theta0, phi0) looks toward the hole.  Pixel (i, j),
+ * column i from the left and row j from the top, has image-plane coordinates
+ *   x = ((2i+1-W)/W) tan(fov/2),  y = ((H-2j-1)/H) tan(fov/2) H/W
+ * (fov is the full horizontal angle, square pixels).  Its line-of-sight unit
+ * vector in the orthonormal frame (e_r, e_theta, e_phi) of the locally
+ * non-rotating observer is n = (-1, -y, x)/sqrt(1 + x^2 + y^2): image right is
+ * +phi, image up is -theta.  The spatial covector is p_j = n_j sqrt(g_jj);
+ * p_t is the root of H = 0 that makes dt/dtau negative (past-directed, the
+ * ray is traced backward), and the whole covector is then scaled so that
+ * dt/dtau = -1 at the camera (the normalisation the paper uses for redshift). */
+typedef struct {
+    double tan_half, tan_half_v;       /* horizontal and vertical half-extent */
+    double er, eth, eph;               /* sqrt(g_rr), sqrt(g_thth), sqrt(g_phph) */
+    double g[5];                       /* inverse metric at the camera */
+} camera_consts;
+
+static void camera_setup(const oracle_params *P, double r0, double th0, double fov,
+                         int W, int H, camera_consts *C)
+{
+    double sf, cf, s, c;
+    sincos_mode(P->trig_mode, 0.5 * fov, &sf, &cf);
+    C->tan_half = sf / cf;
+    C->tan_half_v = (C->tan_half * (double)H) / (double)W;
+    sincos_mode(P->trig_mode, th0, &s, &c);
+    const double s2 = s * s, c2 = c * c;
+    const double a2 = P->a * P->a;
+    const double r2 = r0 * r0;
+    const double ra = r2 + a2;
+    const double rho2 = fma(a2, c2, r2);
+    const double Delta = fma(r0, r0 - 2.0 * P->M, a2 + P->Q * P->Q);
+    const double Sigma2 = fma(-(a2 * s2), Delta, ra * ra);
+    /* covariant g_rr = rho^2/Delta, g_thth = rho^2, g_phph = Sigma2 sin^2/rho^2 */
+    C->er = sqrt(rho2 / Delta);
+    C->eth = sqrt(rho2);
+    C->eph = sqrt((Sigma2 * s2) / rho2);
+    inverse_metric(P, r0, s2, c2, C->g);
+}
+
+static void camera_ray(const camera_consts *C, int W, int H, int64_t pix,
+                       double r0, double th0, double ph0, double q[4], double p[4])
+{
+    const int64_t i = pix % W, j = pix / W;
+    /* (2i+1-W)/W is exactly antisymmetric under i -> W-1-i (integer numerator) */
+    const double x = ((double)(2 * i + 1 - W) / (double)W) * C->tan_half;
+    const double y = ((double)(H - 2 * j - 1) / (double)H) * C->tan_half_v;
+    const double inv_n = 1.0 / sqrt(1.0 + x * x + y * y);
+    const double pr = (-inv_n) * C->er;
+    const double pth = (-y * inv_n) * C->eth;
+    const double pph = (x * inv_n) * C->eph;
+    /* null condition g^tt p_t^2 + 2 g^tph p_t p_ph + S = 0 */
+    const double S = C->g[2] * (pr * pr) + C->g[3] * (pth * pth) + C->g[4] * (pph * pph);
+    const double b = C->g[1] * pph;
+    const double D = b * b - C->g[0] * S;
+    const double sD = sqrt(D);
+    const double pt = (-b - sD) / C->g[0];     /* gives dt/dtau = -sqrt(D) */
+    const double k = 1.0 / sD;                 /* rescale to dt/dtau = -1 */
+    q[0] = 0.0; q[1] = r0; q[2] = th0; q[3] = ph0;
+    p[0] = pt * k; p[1] = pr * k; p[2] = pth * k; p[3] = pph * k;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Multithreaded drivers: one ray per work item, dynamic chunks of rays. */
+
+typedef struct {
+    const oracle_params *P;
+    /* frame mode */
+    const camera_consts *C;
+    double r0, th0, ph0;
+    int W, H;
+    const int64_t *pixels;            /* NULL: ray k is pixel k */
+    /* ray-list mode (C == NULL): initial states, 8 doubles per ray */
+    const double *init;
+    int64_t n;
+    /* outputs, any may be NULL except flag */
+    double *t, *r, *th, *ph, *pr, *pth, *p0;
+    int8_t *flag;
+    int32_t *steps;
+    int64_t next;                     /* shared work counter */
+} job;
+
+static void run_one(job *J, int64_t k)
+{
+    double q[4], p[4];
+    if (J->C) {
+        const int64_t pix = J->pixels ? J->pixels[k] : k;
+        camera_ray(J->C, J->W, J->H, pix, J->r0, J->th0, J->ph0, q, p);
+    } else {
+        memcpy(q, J->init + 8 * k, 4 * sizeof(double));
+        memcpy(p, J->init + 8 * k + 4, 4 * sizeof(double));
+    }
+    if (J->p0) memcpy(J->p0 + 4 * k, p, 4 * sizeof(double));
+    int ns = 0;
+    const int f = oracle_integrate(J->P, q, p, &ns);
+    if (J->t) J->t[k] = q[0];
+    if (J->r) J->r[k] = q[1];
+    if (J->th) J->th[k] = q[2];
+    if (J->ph) J->ph[k] = q[3];
+    if (J->pr) J->pr[k] = p[1];
+    if (J->pth) J->pth[k] = p[2];
+    J->flag[k] = (int8_t)f;
+    if (J->steps) J->steps[k] = ns;
+}
+
+static void *worker(void *arg)
+{
+    job *J = (job *)arg;
+    const int64_t chunk = 8;
+    for (;;) {
+        const int64_t b = __atomic_fetch_add(&J->next, chunk, __ATOMIC_RELAXED);
+        if (b >= J->n) break;
+        const int64_t e = b + chunk < J->n ? b + chunk : J->n;
+        for (int64_t k = b; k < e; ++k) run_one(J, k);
+    }
+    return NULL;
+}
+
+static void run_job(job *J, int nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t tid[256];
+    int started = 0;
+    J->next = 0;
+    for (int i = 1; i < nthreads; ++i)
+        if (pthread_create(&tid[started], NULL, worker, J) == 0) ++started;
+    worker(J);
+    for (int i = 0; i < started; ++i) pthread_join(tid[i], NULL);
+}
+
+static int g_trig_mode = 0;
+
+/* Select the sin/cos used by later calls: 0 (default) the definition above,
+ * 1 the C library. */
+void oracle_set_trig_mode(int mode) { g_trig_mode = mode; }
+
+/* Accuracy checks of the sin/cos definition: n values in, 2n out (s, c). */
+void oracle_sincos(const double *x, int64_t n, double *sc)
+{
+    pthread_once(&trig_once, trig_init);
+    for (int64_t k = 0; k < n; ++k) trig_sincos(x[k], sc + 2 * k, sc + 2 * k + 1);
+}
+
+static oracle_params make_params(double M, double a, double Q, double dt, double eps,
+                                 double horizon_norm, double escape_factor, int max_steps)
+{
+    oracle_params P;
+    P.M = M; P.a = a; P.Q = Q; P.dt = dt; P.eps = eps;
+    P.horizon_norm = horizon_norm; P.escape_factor = escape_factor;
+    P.max_steps = max_steps; P.trig_mode = g_trig_mode;
+    pthread_once(&trig_once, trig_init);
+    return P;
+}
+
+/* Trace pixels of a W x H frame.  pixels == NULL traces all W*H pixels in
+ * raster order, else n pixel indices (row-major, j*W + i).  Outputs have n
+ * entries (p0: 4 per ray, the initial covector).  Returns the ray count. */
+int64_t oracle_trace_frame(double M, double a, double Q,
+                           double r0, double th0, double ph0, double fov, int W, int H,
+                           double dt, double eps, double horizon_norm,
+                           double escape_factor, int max_steps,
+                           const int64_t *pixels, int64_t n,
+                           double *t, double *r, double *th, double *ph,
+                           double *pr, double *pth, double *p0,
+                           int8_t *flag, int32_t *steps, int nthreads)
+{
+    oracle_params P = make_params(M, a, Q, dt, eps, horizon_norm, escape_factor, max_steps);
+    camera_consts C;
+    camera_setup(&P, r0, th0, fov, W, H, &C);
+    job J;
+    memset(&J, 0, sizeof J);
+    J.P = &P; J.C = &C; J.r0 = r0; J.th0 = th0; J.ph0 = ph0; J.W = W; J.H = H;
+    J.pixels = pixels;
+    J.n = pixels ? n : (int64_t)W * H;
+    J.t = t; J.r = r; J.th = th; J.ph = ph; J.pr = pr; J.pth = pth; J.p0 = p0;
+    J.flag = flag; J.steps = steps;
+    run_job(&J, nthreads);
+    return J.n;
+}
+
+/* Trace n rays from given initial states init[8k..8k+7] = (q^0..q^3, p_0..p_3). */
+int64_t oracle_trace_rays(double M, double a, double Q, double dt, double eps,
+                          double horizon_norm, double escape_factor, int max_steps,
+                          const double *init, int64_t n,
+                          double *t, double *r, double *th, double *ph,
+                          double *pr, double *pth, int8_t *flag, int32_t *steps,
+                          int nthreads)
+{
+    oracle_params P = make_params(M, a, Q, dt, eps, horizon_norm, escape_factor, max_steps);
+    job J;
+    memset(&J, 0, sizeof J);
+    J.P = &P; J.init = init; J.n = n;
+    J.t = t; J.r = r; J.th = th; J.ph = ph; J.pr = pr; J.pth = pth;
+    J.flag = flag; J.steps = steps;
+    run_job(&J, nthreads);
+    return n;
+}
+
+/* Initial states (q, p), 8 doubles per ray, of the given pixels. */
+void oracle_camera(double M, double a, double Q, double r0, double th0, double ph0,
+                   double fov, int W, int H, const int64_t *pixels, int64_t n,
+                   double *init)
+{
+    oracle_params P = make_params(M, a, Q, 0.01, 1e-8, 1e4, 1.5, 1);
+    camera_consts C;
+    camera_setup(&P, r0, th0, fov, W, H, &C);
+    const int64_t cnt = pixels ? n : (int64_t)W * H;
+    for (int64_t k = 0; k < cnt; ++k)
+        camera_ray(&C, W, H, pixels ? pixels[k] : k, r0, th0, ph0, init + 8 * k,
+                   init + 8 * k + 4);
+}
+
+/* Inverse metric components at (r, theta) (tests). */
+void oracle_inverse_metric(double M, double a, double Q, double r, double theta,
+                           double *g5)
+{
+    oracle_params P = make_params(M, a, Q, 0.01, 1e-8, 1e4, 1.5, 1);
+    metric_at_point(&P, r, theta, g5);
+}
+
+/* Right-hand side at a state (tests): qdot[4], pdot[2] (p_r, p_theta). */
+void oracle_rhs(double M, double a, double Q, double eps, double r, double theta,
+                double pt, double pr, double pth, double pph, double *qdot, double *pdot)
+{
+    oracle_params P = make_params(M, a, Q, 0.01, eps, 1e4, 1.5, 1);
+    hamilton_rhs(&P, 1.0 / eps, r, theta, pt, pr, pth, pph, qdot, pdot);
+}
