@@ -1,0 +1,188 @@
+/*
+ * grtrace: backward ray tracing of null geodesics around a Kerr-Newman black
+ * hole on AMD Instinct MI355X (gfx950), C ABI.
+ *
+ * Method (arXiv 2310.15183, "Graphical Processing of Geodesic Propagation in
+ * Python"): every pixel of a pinhole camera launches one ray; the ray follows
+ * Hamilton's equations for H = 1/2 g^{mu nu}(r,theta) p_mu p_nu (Sec. 2.1,
+ * eq. hamGeodesic, with the factor 1/2 of Appendix A) in Boyer-Lindquist
+ * coordinates (Sec. 2.2.2; the charge Q enters through
+ * Delta = r^2 - 2Mr + a^2 + Q^2), integrated by classical RK4 (Sec. 3.1.2)
+ * whose step h = dt / |dt/dtau| is fixed from the first stage so that
+ * coordinate time advances by about dt per step (appendix listing).  The
+ * metric derivatives d_r g and d_theta g are forward differences of step
+ * fd_eps (listing; Sec. 3.3.3 explains the choice: any metric works).  A ray
+ * stops on escape (r > escape_factor * r0, Sec. 3.3.2 "Propagation"), at the
+ * horizon (|dt/dtau| > horizon_norm: the coordinate-time step collapses), on
+ * a non-finite state, or after max_steps updates.  The camera is the one of
+ * Sec. 3.3.1 "Initial positions": directions in the camera's local frame,
+ * dt/dtau from the null condition, then scaled so that dt/dtau = -1.
+ *
+ * Conventions shared by every call:
+ *   - All pointers to per-ray data are DEVICE pointers, caller-owned, with
+ *     room for one entry per traced ray (W*H for a whole frame, or n_pixels
+ *     for a pixel list).  Entry k belongs to pixel k (whole frame, row-major
+ *     j*W + i, row 0 at the top) or to pixels[k] (pixel list).
+ *   - Calls are asynchronous on the HIP stream passed in (NULL = the null
+ *     stream); outputs are valid once that stream has completed.  A context
+ *     holds a small device work counter and must not be used by two calls
+ *     that may run concurrently (two host threads, or two streams).
+ *   - Return values: GR_OK (0) or a negative error code.  Arguments are
+ *     validated on the host before anything is launched; on error nothing is
+ *     launched and no output is touched.  Device errors reported by the HIP
+ *     runtime come back as GR_EDEVICE (see gr_trace_last_device_error).
+ *   - Flags written per ray: GR_FLAG_TIMEOUT (0, step limit), GR_FLAG_ESCAPE
+ *     (1), GR_FLAG_HORIZON (2), GR_FLAG_INVALID (3, non-finite state).
+ *     Escape is tested before horizon, both after the update.
+ *   - GR_FP64 results are a deterministic function of the inputs: they do not
+ *     depend on the launch configuration, the stream, or which other pixels
+ *     are traced in the same call.
+ */
+#ifndef GRTRACE_H
+#define GRTRACE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GR_OK = 0,
+    GR_EINVAL = -1,        /* an argument is out of range or a required pointer is NULL */
+    GR_ENOMEM = -2,        /* device allocation for the context failed */
+    GR_EDEVICE = -3,       /* the HIP runtime reported an error */
+    GR_EUNSUPPORTED = -4   /* valid request this build does not support */
+};
+
+enum { GR_FLAG_TIMEOUT = 0, GR_FLAG_ESCAPE = 1, GR_FLAG_HORIZON = 2, GR_FLAG_INVALID = 3 };
+
+/* Integrator precision. */
+enum { GR_FP64 = 0,        /* binary64 state, stages and metric */
+       GR_MIXED = 1 };     /* reserved: binary32 state and stages, binary64 differences */
+
+/* Element type of the floating-point outputs. */
+enum { GR_F64 = 0, GR_F32 = 1 };
+
+/* Kerr-Newman black hole, geometric units G = c = 1: mass M >= 0, spin
+ * length a = J/M (|a| < M for a black hole; a > 0 rotates toward +phi) and
+ * charge Q.  Requires a^2 + Q^2 <= M^2, except M = Q = 0 with any a, which
+ * is flat space in oblate spheroidal coordinates (no horizon).  Q = 0 is Kerr,
+ * a = Q = 0 Schwarzschild. */
+typedef struct {
+    double M, a, Q;
+} gr_metric;
+
+/* Static pinhole camera at Boyer-Lindquist (r0, theta0, phi0) looking toward
+ * the hole.  fov is the full horizontal field of view in radians, pixels are
+ * square, image right is +phi and image up is -theta.  Requires
+ * r0 > r_+ = M + sqrt(M^2 - a^2 - Q^2), 0 < theta0 < pi, 0 < fov < pi,
+ * width >= 1, height >= 1. */
+typedef struct {
+    double r0, theta0, phi0, fov;
+    int32_t width, height;
+} gr_camera;
+
+/* Integrator settings.  dt > 0 is the coordinate-time step, fd_eps > 0 the
+ * forward-difference step, horizon_norm > 0 the |dt/dtau| at which a ray is
+ * declared captured, escape_factor > 1 the escape radius in units of r0,
+ * max_steps >= 0 the step limit (0 returns the initial state), precision
+ * GR_FP64.  Suggested: 0.01, 1e-8, 1e4, 1.5, 20000, GR_FP64. */
+typedef struct {
+    double dt, fd_eps, horizon_norm, escape_factor;
+    int32_t max_steps;
+    int32_t precision;
+} gr_integrator;
+
+/* Per-ray outputs (device pointers).  The eight floating-point arrays hold
+ * the state after the last update, elements of type dtype (GR_F64 or
+ * GR_F32, rounded to nearest); any of them may be NULL (not written).  p_t
+ * and p_phi are constant along a ray (t and phi derivatives of the metric
+ * vanish).  flag (int8) is required; steps (int32, number of updates taken)
+ * may be NULL. */
+typedef struct {
+    void *t, *r, *theta, *phi;
+    void *p_t, *p_r, *p_theta, *p_phi;
+    int8_t *flag;
+    int32_t *steps;
+    int32_t dtype;
+} gr_output;
+
+/* One image of a batch: its black hole, camera and outputs.  n_pixels = -1
+ * traces all width*height pixels (pixels is ignored); n_pixels >= 0 traces
+ * the n_pixels entries of the device list pixels (indices j*width + i, any
+ * order, repeats allowed, each in [0, width*height)).  An instance with no
+ * rays (n_pixels = 0) may leave pixels and every output pointer NULL. */
+typedef struct {
+    gr_metric metric;
+    gr_camera camera;
+    gr_output out;
+    const int32_t *pixels;
+    int64_t n_pixels;
+} gr_instance;
+
+typedef struct gr_ctx gr_ctx;
+
+/* Launch shape of the tracing kernels (results never depend on it).
+ * block: threads per workgroup (64, 128, 256 or 512); waves_per_simd: target
+ * residency used to size the persistent grid (1..8, 0 = as many as fit);
+ * refill: 1 = lanes that finish take the next ray from the work queue,
+ * 0 = each lane traces one ray and the grid covers every ray. */
+typedef struct {
+    int32_t block;
+    int32_t waves_per_simd;
+    int32_t refill;
+} gr_launch;
+
+/* Create a context on HIP device `device` with the given integrator.
+ * Allocates a few bytes of device memory (work counter).  *ctx is set to
+ * NULL on error.  Errors: GR_EINVAL (ctx NULL, integrator out of range),
+ * GR_ENOMEM, GR_EDEVICE. */
+int gr_trace_init(gr_ctx **ctx, int device, const gr_integrator *integ);
+
+/* Trace every pixel of one frame.  Errors: GR_EINVAL (validation above, NULL
+ * ctx/m/c/out or out->flag), GR_EUNSUPPORTED (precision not built),
+ * GR_EDEVICE (launch failed). */
+int gr_trace_frame(gr_ctx *ctx, const gr_metric *m, const gr_camera *c,
+                   const gr_output *out, void *hip_stream);
+
+/* Trace n >= 1 instances (possibly different black holes, cameras and image
+ * sizes) in one persistent launch fed by one work queue.  Same errors as
+ * gr_trace_frame; an error in any instance rejects the whole call. */
+int gr_trace_batch(gr_ctx *ctx, const gr_instance *inst, int32_t n, void *hip_stream);
+
+/* Replace the integrator settings of a context (same validation as init). */
+int gr_trace_set_integrator(gr_ctx *ctx, const gr_integrator *integ);
+
+/* Override (or with launch == NULL restore) the launch shape. */
+int gr_trace_set_launch(gr_ctx *ctx, const gr_launch *launch);
+
+/* Launch shape the next call will use. */
+int gr_trace_get_launch(const gr_ctx *ctx, gr_launch *launch);
+
+/* Free the context (waits for nothing: the caller synchronises its streams
+ * first).  NULL is accepted. */
+int gr_trace_destroy(gr_ctx *ctx);
+
+/* Static description of an error code. */
+const char *gr_trace_strerror(int code);
+
+/* Text of the last HIP error seen by this library in the calling thread
+ * ("" if none). */
+const char *gr_trace_last_device_error(void);
+
+/* Run the host-side validation of gr_trace_frame on its arguments without a
+ * device or context (integ may be NULL to skip it).  Returns GR_OK or
+ * GR_EINVAL. */
+int gr_trace_validate(const gr_metric *m, const gr_camera *c, const gr_integrator *integ,
+                      const gr_output *out);
+
+/* Outer event horizon r_+ = M + sqrt(M^2 - a^2 - Q^2) (host helper; 0 for
+ * flat space). */
+double gr_horizon_radius(const gr_metric *m);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRTRACE_H */

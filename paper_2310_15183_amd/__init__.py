@@ -1,0 +1,209 @@
+"""Python binding of libgrtrace (MI355X geodesic ray tracer).
+
+Argument marshalling only: every step of the tracing runs in the HIP kernels
+of ``libgrtrace.so``; PyTorch supplies device memory and streams.  The
+functions carry the names of the C entry points declared in
+``include/grtrace.h``; see that header for the meaning of every field.
+
+Importing this package loads the built library and raises ImportError if it
+is missing (build it with ``python paper_2310_15183_amd/build.py``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgrtrace.so")
+
+GR_OK, GR_EINVAL, GR_ENOMEM, GR_EDEVICE, GR_EUNSUPPORTED = 0, -1, -2, -3, -4
+GR_FLAG_TIMEOUT, GR_FLAG_ESCAPE, GR_FLAG_HORIZON, GR_FLAG_INVALID = 0, 1, 2, 3
+GR_FP64, GR_MIXED = 0, 1
+GR_F64, GR_F32 = 0, 1
+
+
+class gr_metric(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_double), ("a", ctypes.c_double), ("Q", ctypes.c_double)]
+
+
+class gr_camera(ctypes.Structure):
+    _fields_ = [("r0", ctypes.c_double), ("theta0", ctypes.c_double),
+                ("phi0", ctypes.c_double), ("fov", ctypes.c_double),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
+class gr_integrator(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("fd_eps", ctypes.c_double),
+                ("horizon_norm", ctypes.c_double), ("escape_factor", ctypes.c_double),
+                ("max_steps", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class gr_output(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_void_p), ("r", ctypes.c_void_p), ("theta", ctypes.c_void_p),
+                ("phi", ctypes.c_void_p), ("p_t", ctypes.c_void_p), ("p_r", ctypes.c_void_p),
+                ("p_theta", ctypes.c_void_p), ("p_phi", ctypes.c_void_p),
+                ("flag", ctypes.c_void_p), ("steps", ctypes.c_void_p),
+                ("dtype", ctypes.c_int32)]
+
+
+class gr_instance(ctypes.Structure):
+    _fields_ = [("metric", gr_metric), ("camera", gr_camera), ("out", gr_output),
+                ("pixels", ctypes.c_void_p), ("n_pixels", ctypes.c_int64)]
+
+
+class gr_launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
+                ("refill", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python paper_2310_15183_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    sig = {
+        "gr_trace_init": (ctypes.c_int, [P(vp), ctypes.c_int, P(gr_integrator)]),
+        "gr_trace_frame": (ctypes.c_int, [vp, P(gr_metric), P(gr_camera), P(gr_output), vp]),
+        "gr_trace_batch": (ctypes.c_int, [vp, P(gr_instance), ctypes.c_int32, vp]),
+        "gr_trace_set_integrator": (ctypes.c_int, [vp, P(gr_integrator)]),
+        "gr_trace_set_launch": (ctypes.c_int, [vp, P(gr_launch)]),
+        "gr_trace_get_launch": (ctypes.c_int, [vp, P(gr_launch)]),
+        "gr_trace_destroy": (ctypes.c_int, [vp]),
+        "gr_trace_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "gr_trace_last_device_error": (ctypes.c_char_p, []),
+        "gr_horizon_radius": (ctypes.c_double, [P(gr_metric)]),
+        "gr_trace_validate": (ctypes.c_int, [P(gr_metric), P(gr_camera), P(gr_integrator),
+                                             P(gr_output)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ["gr_trace_init", "gr_trace_frame", "gr_trace_batch", "gr_trace_set_integrator",
+            "gr_trace_set_launch", "gr_trace_get_launch", "gr_trace_destroy",
+            "gr_trace_strerror", "gr_trace_last_device_error", "gr_horizon_radius",
+            "gr_trace_validate"]
+
+
+class GrError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.gr_trace_strerror(code).decode()
+        if code == GR_EDEVICE:
+            msg += ": " + _lib.gr_trace_last_device_error().decode()
+        super().__init__(f"{where}: {msg} ({code})")
+        self.code = code
+
+
+def _check(code: int, where: str) -> None:
+    if code != GR_OK:
+        raise GrError(code, where)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------- C entry points
+def gr_trace_init(device: int = 0, integrator: gr_integrator | None = None) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    integ = integrator if integrator is not None else make_integrator()
+    _check(_lib.gr_trace_init(ctypes.byref(ctx), int(device), ctypes.byref(integ)),
+           "gr_trace_init")
+    return ctx
+
+
+def gr_trace_frame(ctx, metric: gr_metric, camera: gr_camera, out: gr_output, stream=None):
+    _check(_lib.gr_trace_frame(ctx, ctypes.byref(metric), ctypes.byref(camera),
+                               ctypes.byref(out), _stream_handle(stream)), "gr_trace_frame")
+
+
+def gr_trace_batch(ctx, instances, stream=None):
+    arr = (gr_instance * len(instances))(*instances)
+    _check(_lib.gr_trace_batch(ctx, arr, len(instances), _stream_handle(stream)),
+           "gr_trace_batch")
+
+
+def gr_trace_set_integrator(ctx, integrator: gr_integrator):
+    _check(_lib.gr_trace_set_integrator(ctx, ctypes.byref(integrator)),
+           "gr_trace_set_integrator")
+
+
+def gr_trace_set_launch(ctx, launch: gr_launch | None):
+    _check(_lib.gr_trace_set_launch(ctx, ctypes.byref(launch) if launch is not None else None),
+           "gr_trace_set_launch")
+
+
+def gr_trace_get_launch(ctx) -> gr_launch:
+    out = gr_launch()
+    _check(_lib.gr_trace_get_launch(ctx, ctypes.byref(out)), "gr_trace_get_launch")
+    return out
+
+
+def gr_trace_destroy(ctx):
+    _check(_lib.gr_trace_destroy(ctx), "gr_trace_destroy")
+
+
+def gr_trace_strerror(code: int) -> str:
+    return _lib.gr_trace_strerror(int(code)).decode()
+
+
+def gr_trace_last_device_error() -> str:
+    return _lib.gr_trace_last_device_error().decode()
+
+
+def gr_trace_validate(metric: gr_metric, camera: gr_camera, integrator: gr_integrator | None,
+                      out: gr_output) -> int:
+    """Host-side argument validation only (no device needed); returns the code."""
+    return _lib.gr_trace_validate(ctypes.byref(metric), ctypes.byref(camera),
+                                  ctypes.byref(integrator) if integrator is not None else None,
+                                  ctypes.byref(out))
+
+
+def gr_horizon_radius(metric: gr_metric) -> float:
+    return _lib.gr_horizon_radius(ctypes.byref(metric))
+
+
+# ---------------------------------------------------------------- marshalling helpers
+def make_integrator(dt=0.01, fd_eps=1e-8, horizon_norm=1e4, escape_factor=1.5,
+                    max_steps=20000, precision=GR_FP64) -> gr_integrator:
+    return gr_integrator(dt, fd_eps, horizon_norm, escape_factor, int(max_steps),
+                         int(precision))
+
+
+FIELDS = ("t", "r", "theta", "phi", "p_t", "p_r", "p_theta", "p_phi")
+
+
+@dataclass
+class Outputs:
+    """Torch device tensors backing a gr_output (kept alive with it)."""
+    tensors: dict = field(default_factory=dict)
+    struct: gr_output = None
+
+    def __getitem__(self, k):
+        return self.tensors[k]
+
+
+def alloc_outputs(n: int, dtype=GR_F64, fields=("t", "r", "theta", "phi"), steps=True,
+                  device="cuda") -> Outputs:
+    """Allocate per-ray output tensors on the device and the gr_output that
+    points at them.  flag is int8 (pre-filled with -1), steps int32 (-1)."""
+    import torch
+    fdt = torch.float64 if dtype == GR_F64 else torch.float32
+    ten = {f: torch.empty(n, dtype=fdt, device=device) for f in fields}
+    ten["flag"] = torch.full((n,), -1, dtype=torch.int8, device=device)
+    if steps:
+        ten["steps"] = torch.full((n,), -1, dtype=torch.int32, device=device)
+    ptr = lambda k: ten[k].data_ptr() if k in ten else None  # noqa: E731
+    st = gr_output(*(ptr(f) for f in FIELDS), ptr("flag"), ptr("steps"), int(dtype))
+    return Outputs(ten, st)

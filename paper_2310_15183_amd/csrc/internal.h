@@ -1,0 +1,61 @@
+// Internal interface between the C-ABI host code and the kernel translation
+// units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "grmath.h"
+#include "grtrace.h"
+
+namespace gr {
+
+// Per-ray outputs; any float pointer may be null.
+struct OutPtrs {
+    void* t;
+    void* r;
+    void* th;
+    void* ph;
+    void* pt;
+    void* pr;
+    void* pth;
+    void* pph;
+    int8_t* flag;
+    int32_t* steps;
+};
+
+struct Integrator {
+    double dt, eps, inv_eps, hnorm, esc_factor;
+    int32_t max_steps;
+};
+
+// Everything one frame launch needs, passed by value as the kernel argument
+// (uniform values live in scalar registers).
+struct FrameArgs {
+    Hole hole;
+    Camera cam;
+    Integrator in;
+    double r_esc;           // esc_factor * r0
+    int64_t nray;           // rays to trace
+    const int32_t* pixels;  // null: ray k is pixel k
+    OutPtrs out;
+};
+
+struct LaunchShape {
+    int block;           // threads per workgroup
+    int grid;            // workgroups
+    int refill;          // persistent lanes pull rays from the queue
+};
+
+// Fill the queue counter with zero (a kernel, so that it can sit in a
+// captured graph).
+hipError_t launch_reset_counter(unsigned long long* counter, hipStream_t s);
+
+// FP64 frame tracer.  f32_out selects binary32 outputs.
+hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, const LaunchShape& L,
+                             unsigned long long* counter, hipStream_t s);
+
+// Workgroups of `block` threads that fit on one CU for the FP64 tracer.
+int occupancy_trace_fp64(int block, bool f32_out);
+
+}  // namespace gr

@@ -1,0 +1,163 @@
+"""Parity of the HIP FP64 tracer with the CPU oracle, through the C ABI.
+
+Gate: flags and step counts bit-exact; end theta/phi within 1e-9 rad.  The
+kernel and the oracle follow the same IEEE operation sequence, so the rays
+are expected to be bit-identical in every field, and that is asserted too.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import DEG, compare, fp32_round, gpu_trace, oracle_trace
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2310_15183_amd as g
+    return g
+
+
+@pytest.fixture()
+def ctx(g):
+    c = g.gr_trace_init(0, g.make_integrator(dt=0.01, max_steps=20000))
+    yield c
+    g.gr_trace_destroy(c)
+
+
+KERR64 = (0.5, 0.24, 0.0, 20.0, math.pi / 2, 0.0, 75 * DEG, 64, 64)
+
+
+def _both(g, ctx, case, integ=None, **kw):
+    integ = integ or g.make_integrator(dt=0.01, max_steps=20000)
+    g.gr_trace_set_integrator(ctx, integ)
+    gpu = gpu_trace(ctx, *case, **kw)
+    ref = oracle_trace(*case, integ, pixels=kw.get("pixels"))
+    return gpu, ref
+
+
+def test_small_kerr_frame_is_bit_exact(g, ctx):
+    """64x64 Kerr frame (M=0.5, a=0.24, r0=20 on the equator, fov 75 deg,
+    dt=0.01, 20000 steps)."""
+    gpu, ref = _both(g, ctx, KERR64)
+    st = compare(gpu, ref)
+    print(st)
+    assert st["bit_identical"] == st["n"]
+    assert (ref["flag"] == g.GR_FLAG_HORIZON).sum() > 0
+
+
+def test_camera_initial_state_is_bit_exact(g, ctx):
+    integ = g.make_integrator(max_steps=0)
+    case = (0.5, 0.24, 0.3, 20.0, 80 * DEG, 0.25, 75 * DEG, 17, 9)
+    gpu, ref = _both(g, ctx, case, integ=integ)
+    st = compare(gpu, ref)
+    assert st["bit_identical"] == st["n"]
+    assert np.all(gpu["flag"] == g.GR_FLAG_TIMEOUT) and np.all(gpu["steps"] == 0)
+    assert np.all(gpu["t"] == 0.0) and np.all(gpu["r"] == 20.0)
+
+
+@pytest.mark.parametrize("case", [
+    (0.5, 0.24, 0.3, 20.0, 80 * DEG, 0.0, 75 * DEG, 37, 23),     # Kerr-Newman, ragged
+    (0.5, 0.49, 0.0, 20.0, 60 * DEG, 0.0, 75 * DEG, 30, 30),     # near-extremal
+    (0.5, 0.1, 0.2, 35.0, 20 * DEG, 1.0, 40 * DEG, 19, 41),      # tall image, high latitude
+    (0.5, 0.24, 0.0, 20.0, math.pi / 2, 0.0, 75 * DEG, 1, 1),    # single pixel
+    (0.0, 0.3, 0.0, 20.0, 70 * DEG, 0.3, 75 * DEG, 13, 7),       # flat space
+])
+def test_frames_are_bit_exact(g, ctx, case):
+    gpu, ref = _both(g, ctx, case)
+    st = compare(gpu, ref)
+    assert st["bit_identical"] == st["n"]
+
+
+def test_f32_outputs_are_rounded_fp64(g, ctx):
+    case = (0.5, 0.24, 0.3, 20.0, 80 * DEG, 0.0, 75 * DEG, 24, 16)
+    gpu, ref = _both(g, ctx, case, dtype=g.GR_F32)
+    st = compare(gpu, ref, angle_tol=0.0, f32=True)
+    assert st["bit_identical"] == st["n"]
+
+
+def test_step_limit_is_bit_exact(g, ctx):
+    integ = g.make_integrator(max_steps=137)
+    gpu, ref = _both(g, ctx, KERR64, integ=integ)
+    st = compare(gpu, ref)
+    assert st["bit_identical"] == st["n"]
+    assert np.all(gpu["flag"] == g.GR_FLAG_TIMEOUT) and np.all(gpu["steps"] == 137)
+
+
+def test_launch_shape_does_not_change_results(g, ctx):
+    g.gr_trace_set_integrator(ctx, g.make_integrator(dt=0.01, max_steps=20000))
+    case = (0.5, 0.24, 0.3, 20.0, 80 * DEG, 0.0, 75 * DEG, 48, 40)
+    base = gpu_trace(ctx, *case)
+    for block, wps, refill in [(64, 1, 1), (128, 2, 1), (256, 4, 1), (256, 0, 0), (64, 0, 0)]:
+        g.gr_trace_set_launch(ctx, g.gr_launch(block, wps, refill))
+        other = gpu_trace(ctx, *case)
+        for k in base:
+            np.testing.assert_array_equal(other[k], base[k], err_msg=f"{k} {block} {wps} {refill}")
+    g.gr_trace_set_launch(ctx, None)
+
+
+def test_pixel_list_matches_frame(g, ctx):
+    g.gr_trace_set_integrator(ctx, g.make_integrator(dt=0.01, max_steps=20000))
+    case = (0.5, 0.24, 0.3, 20.0, 80 * DEG, 0.0, 75 * DEG, 32, 24)
+    frame = gpu_trace(ctx, *case)
+    rng = np.random.default_rng(3)
+    pix = np.concatenate([rng.integers(0, 32 * 24, 200), [0, 0, 32 * 24 - 1]])
+    sub = gpu_trace(ctx, *case, pixels=pix)
+    for k in frame:
+        np.testing.assert_array_equal(sub[k], frame[k][pix], err_msg=k)
+    empty = gpu_trace(ctx, *case, pixels=np.zeros(0, np.int32))
+    assert empty["flag"].size == 0
+
+
+def test_spin_reversal_mirror_on_gpu(g, ctx):
+    g.gr_trace_set_integrator(ctx, g.make_integrator(dt=0.01, max_steps=20000))
+    W, H = 24, 16
+    A = gpu_trace(ctx, 0.5, 0.24, 0.3, 20.0, 80 * DEG, 0.0, 75 * DEG, W, H)
+    B = gpu_trace(ctx, 0.5, -0.24, 0.3, 20.0, 80 * DEG, 0.0, 75 * DEG, W, H)
+    mirror = lambda x: x.reshape(H, W)[:, ::-1].ravel()  # noqa: E731
+    np.testing.assert_array_equal(A["phi"], -mirror(B["phi"]))
+    np.testing.assert_array_equal(A["p_phi"], -mirror(B["p_phi"]))
+    for k in ("t", "r", "theta", "p_t", "p_r", "p_theta", "flag", "steps"):
+        np.testing.assert_array_equal(A[k], mirror(B[k]), err_msg=k)
+
+
+def test_invalid_arguments_launch_nothing(g, ctx):
+    import torch
+    out = g.alloc_outputs(16, fields=("r",))
+    m = g.gr_metric(0.5, 0.24, 0.0)
+    bad = g.gr_camera(0.3, math.pi / 2, 0.0, 75 * DEG, 4, 4)          # inside the horizon
+    with pytest.raises(g.GrError) as e:
+        g.gr_trace_frame(ctx, m, bad, out.struct)
+    assert e.value.code == g.GR_EINVAL
+    torch.cuda.synchronize()
+    assert np.all(out["flag"].cpu().numpy() == -1)
+
+
+def test_kerr_newman_megapixel_sampled(g, ctx):
+    """Full-size Kerr-Newman frame in the benchmark's launch configuration:
+    1000x1000, M=0.5, a=0.24, Q=0.3, r0=20, theta0=80 deg, fov 75 deg,
+    dt=0.005, 50000 steps, parameters rounded to binary32, binary32 end
+    coordinates.  The oracle re-traces a stratified sample (every 32nd pixel
+    in both axes) plus pixels on the shadow edge."""
+    f = fp32_round
+    case = (f(0.5), f(0.24), f(0.3), f(20.0), f(80 * DEG), 0.0, f(75 * DEG), 1000, 1000)
+    integ = g.make_integrator(dt=0.005, max_steps=50000)
+    g.gr_trace_set_integrator(ctx, integ)
+    gpu = gpu_trace(ctx, *case, dtype=g.GR_F32, fields=("t", "r", "theta", "phi"))
+    flag = gpu["flag"].reshape(1000, 1000)
+    assert np.all((flag == g.GR_FLAG_ESCAPE) | (flag == g.GR_FLAG_HORIZON) |
+                  (flag == g.GR_FLAG_TIMEOUT))
+    edge = np.zeros_like(flag, bool)
+    edge[1:-1, 1:-1] = (flag[1:-1, 1:-1] != flag[:-2, 1:-1]) | (flag[1:-1, 1:-1] != flag[2:, 1:-1])
+    edge_pix = np.nonzero(edge.ravel())[0]
+    rng = np.random.default_rng(7)
+    edge_pix = rng.choice(edge_pix, size=min(256, edge_pix.size), replace=False)
+    grid = (np.arange(16, 1000, 32)[:, None] * 1000 + np.arange(16, 1000, 32)[None, :]).ravel()
+    pix = np.unique(np.concatenate([grid, edge_pix]))
+    ref = oracle_trace(*case, integ, pixels=pix)
+    sub = {k: v[pix] for k, v in gpu.items()}
+    st = compare(sub, ref, angle_tol=0.0, f32=True)
+    print(st, "escape", int((ref["flag"] == 1).sum()), "horizon", int((ref["flag"] == 2).sum()))
+    assert st["bit_identical"] == st["n"]
