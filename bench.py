@@ -1,0 +1,218 @@
+"""Benchmark: geodesic rays/s on a 1000x1000 Kerr-Newman frame (one GPU).
+
+One step = one complete trace of the frame: camera rays built in-kernel,
+metric and forward differences, Hamilton right-hand side, RK4 with the
+coordinate-time normaliser, termination, lane refill and the per-ray stores.
+Inputs are synthetic (an analytic camera grid); nothing is cached between
+steps.  Prints one JSON line.
+
+Workload (the paper-scale configuration): M=0.5, a=0.24, Q=0.3 (Boyer-
+Lindquist), camera r0=20, theta0=80 deg, phi0=0, fov 75 deg, 1000x1000;
+dt=0.005, fd_eps=1e-8, at most 50000 steps, horizon at |dt/dtau| > 1e4,
+escape at r > 30.  Parameters are rounded to binary32 first (the camera and
+black-hole inputs of this configuration are binary32); state is binary64;
+end coordinates are stored as binary32 with an int8 flag.
+
+The roofline object reports the tracing kernel against the MI355X FP64
+vector peak: achieved = algorithmic flops per launch (881 per ray-step times
+the ray-steps of the launch, read from the kernel's own step counts) divided
+by the launch's duration measured with HIP events on the launch stream.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "geodesic rays/s @1000² Kerr: FP64 vs mixed vs surrogate, ≤1e-4 rad err"
+FLOPS_PER_RAY_STEP = 881          # binary64 ops of one RK4 step (add/sub/mul/div 1, fma 2)
+FP64_PEAK_TFLOPS = 78.6           # MI355X FP64 vector (256 CU x 128 flop/clk x 2.4 GHz)
+KERNEL_SOURCES = ["paper_2310_15183_amd/csrc/trace_fp64.hip",
+                  "paper_2310_15183_amd/csrc/grmath.h"]
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "trace_fp64_kn1000_traffic.md")
+
+
+def f32(x):
+    import numpy as np
+    return float(np.float32(x))
+
+
+def workload():
+    deg = math.pi / 180.0
+    return dict(M=f32(0.5), a=f32(0.24), Q=f32(0.3), r0=f32(20.0), theta0=f32(80 * deg),
+                phi0=0.0, fov=f32(75 * deg), W=1000, H=1000, dt=0.005, fd_eps=1e-8,
+                horizon_norm=1e4, escape_factor=1.5, max_steps=50000)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(units_per_launch):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source (else None)."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    text = open(TRAFFIC_PROFILE).read()
+    m_hash = re.search(r"kernel source hash:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"HBM bytes per launch:\s*([0-9.eE+]+)", text)
+    if not (m_hash and m_bytes) or m_hash.group(1) != kernel_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def cpu_baseline(w, stride, threads):
+    """Time the CPU oracle on every stride-th pixel in both axes of the same
+    frame; returns rays/s and the sample's mean steps."""
+    import numpy as np
+
+    import oracle
+    ii = np.arange(stride // 2, w["W"], stride)
+    jj = np.arange(stride // 2, w["H"], stride)
+    pix = (jj[:, None] * w["W"] + ii[None, :]).ravel()
+    t0 = time.perf_counter()
+    res = oracle.trace_frame(w["M"], w["a"], w["Q"], w["r0"], w["theta0"], w["phi0"], w["fov"],
+                             w["W"], w["H"], dt=w["dt"], eps=w["fd_eps"],
+                             horizon_norm=w["horizon_norm"], escape_factor=w["escape_factor"],
+                             max_steps=w["max_steps"], pixels=pix, threads=threads)
+    dt = time.perf_counter() - t0
+    return pix.size / dt, pix.size, float(res.steps.mean()), dt
+
+
+def copy_calibration(mib=256, reps=3):
+    """A plain elementwise copy y = 1.0 * x over `mib` MiB of binary32: it
+    reads and writes exactly mib MiB per launch, which fixes the scale of the
+    FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    x = torch.rand(n, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-stride", type=int, default=5,
+                    help="oracle sample: every n-th pixel in both axes")
+    ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of known size (HBM counter scale)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the tracer has no multi-GPU path "
+              "(rays are independent, so a frame would shard by pixel blocks with no "
+              "exchange between GPUs).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2310_15183_amd as g
+
+    w = workload()
+    torch.cuda.set_device(0)
+    n = w["W"] * w["H"]
+    integ = g.make_integrator(dt=w["dt"], fd_eps=w["fd_eps"], horizon_norm=w["horizon_norm"],
+                              escape_factor=w["escape_factor"], max_steps=w["max_steps"])
+    ctx = g.gr_trace_init(0, integ)
+    metric = g.gr_metric(w["M"], w["a"], w["Q"])
+    cam = g.gr_camera(w["r0"], w["theta0"], w["phi0"], w["fov"], w["W"], w["H"])
+    out = g.alloc_outputs(n, dtype=g.GR_F32, fields=("t", "r", "theta", "phi"))
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        g.gr_trace_frame(ctx, metric, cam, out.struct, stream)
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        g.gr_trace_frame(ctx, metric, cam, out.struct, stream)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_s = sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / 1e3 / args.steps
+
+    steps = out["steps"].cpu().numpy().astype(np.int64)
+    flags = out["flag"].cpu().numpy()
+    ray_steps = int(steps.sum())
+    g.gr_trace_destroy(ctx)
+
+    achieved = FLOPS_PER_RAY_STEP * ray_steps / launch_s / 1e12
+    traffic = recorded_traffic(ray_steps)
+    result = {
+        "metric": METRIC,
+        "value": n * args.steps / wall,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "kerr-newman 1000x1000 fp64: M=0.5 a=0.24 Q=0.3 r0=20 theta0=80deg "
+                        "fov=75deg dt=0.005 eps=1e-8 max_steps=50000 (binary32 params, "
+                        "binary32 end coordinates + int8 flag)",
+            "rays_per_step": n,
+            "ray_steps_per_step": ray_steps,
+            "mean_steps_per_ray": ray_steps / n,
+            "flags": {"timeout": int((flags == 0).sum()), "escape": int((flags == 1).sum()),
+                      "horizon": int((flags == 2).sum()), "invalid": int((flags == 3).sum())},
+            "ray_steps_per_s": ray_steps * args.steps / wall,
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": traffic,
+            "kernel": "trace_fp64",
+            "flops_per_ray_step": FLOPS_PER_RAY_STEP,
+            "launch_ms": launch_s * 1e3,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.skip_cpu_baseline:
+        import oracle
+        threads = min(16, oracle.default_threads())
+        rays_s, nsample, mean_steps, secs = cpu_baseline(w, args.cpu_stride, threads)
+        result["cpu_baseline"] = {
+            "value": rays_s, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {args.cpu_stride}th pixel in both axes of the same frame "
+                      f"({nsample} rays, mean {mean_steps:.0f} steps/ray vs "
+                      f"{ray_steps / n:.0f} for the full frame), {secs:.1f} s",
+        }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()
