@@ -124,14 +124,18 @@ typedef struct {
 typedef struct gr_ctx gr_ctx;
 
 /* Launch shape of the tracing kernels (results never depend on it).
- * block: threads per workgroup (64, 128, 256 or 512); waves_per_simd: target
+ * block: threads per workgroup (64, 128 or 256); waves_per_simd: target
  * residency used to size the persistent grid (1..8, 0 = as many as fit);
  * refill: 1 = lanes that finish take the next ray from the work queue,
- * 0 = each lane traces one ray and the grid covers every ray. */
+ * 0 = each lane traces one ray and the grid covers every ray (frames only;
+ * batches always refill); order (batches): 0 = instances are queued in the
+ * order given, 1 = instances with the longest expected rays (largest
+ * escape radius over dt) are queued first, which shortens the tail. */
 typedef struct {
     int32_t block;
     int32_t waves_per_simd;
     int32_t refill;
+    int32_t order;
 } gr_launch;
 
 /* Create a context on HIP device `device` with the given integrator.
@@ -147,8 +151,11 @@ int gr_trace_frame(gr_ctx *ctx, const gr_metric *m, const gr_camera *c,
                    const gr_output *out, void *hip_stream);
 
 /* Trace n >= 1 instances (possibly different black holes, cameras and image
- * sizes) in one persistent launch fed by one work queue.  Same errors as
- * gr_trace_frame; an error in any instance rejects the whole call. */
+ * sizes) in one persistent launch fed by one work queue.  The instance table
+ * (about 330 bytes per instance) is copied to device memory owned by the
+ * context, which grows it with hipMalloc when a larger batch arrives.  Same
+ * errors as gr_trace_frame (GR_ENOMEM if the table cannot grow); an error in
+ * any instance rejects the whole call. */
 int gr_trace_batch(gr_ctx *ctx, const gr_instance *inst, int32_t n, void *hip_stream);
 
 /* Replace the integrator settings of a context (same validation as init). */
@@ -159,6 +166,19 @@ int gr_trace_set_launch(gr_ctx *ctx, const gr_launch *launch);
 
 /* Launch shape the next call will use. */
 int gr_trace_get_launch(const gr_ctx *ctx, gr_launch *launch);
+
+/* Pick the launch shape for a batch by measurement, store it in the context
+ * and trace the batch with it.  Candidate shapes (block 64/128/256, residency
+ * 2 or as many as fit, both queue orders) are timed on the batch with the
+ * step limit lowered to trial_steps (0 = no lowering); every candidate gives
+ * identical results, so the outputs hold the final full run, made with the
+ * winner.  If cache_path is non-NULL, a winner recorded there for the same
+ * device architecture and batch size class is reused without trials, and a
+ * new winner is appended.  *best (may be NULL) receives the shape.  Blocks
+ * the calling thread until the stream has finished the trials.  Errors: those
+ * of gr_trace_batch, GR_EINVAL for trial_steps < 0. */
+int gr_trace_autotune(gr_ctx *ctx, const gr_instance *inst, int32_t n, int32_t trial_steps,
+                      const char *cache_path, gr_launch *best, void *hip_stream);
 
 /* Free the context (waits for nothing: the caller synchronises its streams
  * first).  NULL is accepted. */

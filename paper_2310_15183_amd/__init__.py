@@ -54,10 +54,15 @@ class gr_instance(ctypes.Structure):
 
 class gr_launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
-                ("refill", ctypes.c_int32)]
+                ("refill", ctypes.c_int32), ("order", ctypes.c_int32)]
 
 
 def _load():
+    # Load torch's HIP runtime first: libgrtrace.so then binds to the same
+    # libamdhip64.so.7 (one runtime per process, so torch's device pointers and
+    # streams are valid in the library).  Loading the library first would pull
+    # in a second runtime that does not share torch's device state.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run python paper_2310_15183_amd/build.py")
     lib = ctypes.CDLL(LIB_PATH)
@@ -70,6 +75,8 @@ def _load():
         "gr_trace_set_integrator": (ctypes.c_int, [vp, P(gr_integrator)]),
         "gr_trace_set_launch": (ctypes.c_int, [vp, P(gr_launch)]),
         "gr_trace_get_launch": (ctypes.c_int, [vp, P(gr_launch)]),
+        "gr_trace_autotune": (ctypes.c_int, [vp, P(gr_instance), ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_char_p, P(gr_launch), vp]),
         "gr_trace_destroy": (ctypes.c_int, [vp]),
         "gr_trace_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "gr_trace_last_device_error": (ctypes.c_char_p, []),
@@ -86,7 +93,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ["gr_trace_init", "gr_trace_frame", "gr_trace_batch", "gr_trace_set_integrator",
-            "gr_trace_set_launch", "gr_trace_get_launch", "gr_trace_destroy",
+            "gr_trace_set_launch", "gr_trace_get_launch", "gr_trace_autotune", "gr_trace_destroy",
             "gr_trace_strerror", "gr_trace_last_device_error", "gr_horizon_radius",
             "gr_trace_validate"]
 
@@ -148,6 +155,16 @@ def gr_trace_get_launch(ctx) -> gr_launch:
     out = gr_launch()
     _check(_lib.gr_trace_get_launch(ctx, ctypes.byref(out)), "gr_trace_get_launch")
     return out
+
+
+def gr_trace_autotune(ctx, instances, trial_steps=0, cache_path=None, stream=None) -> gr_launch:
+    arr = (gr_instance * len(instances))(*instances)
+    best = gr_launch()
+    path = cache_path.encode() if cache_path else None
+    _check(_lib.gr_trace_autotune(ctx, arr, len(instances), int(trial_steps), path,
+                                  ctypes.byref(best), _stream_handle(stream)),
+           "gr_trace_autotune")
+    return best
 
 
 def gr_trace_destroy(ctx):

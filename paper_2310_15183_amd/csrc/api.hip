@@ -1,11 +1,14 @@
 // C-ABI entry points of libgrtrace: argument validation, context, launch
-// shape and dispatch to the kernels.  Host code only.
+// shape, batch tables, autotuning and dispatch to the kernels.  Host code.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
 #include <new>
+#include <numeric>
+#include <string>
+#include <vector>
 
 #include "grtrace.h"
 #include "internal.h"
@@ -13,9 +16,13 @@
 struct gr_ctx {
     int device;
     gr_integrator integ;
-    gr_launch launch;          // user override (block == 0: none)
-    unsigned long long* counter;
+    gr_launch launch;                 // user or autotuned shape (block == 0: default)
+    unsigned long long* counter;      // work counter (device)
     int num_cu;
+    char arch[64];
+    gr::BatchInstance* table;         // batch instance table (device)
+    int64_t* firsts;                  // batch prefix offsets (device)
+    int64_t table_cap;                // instances the device table holds
 };
 
 namespace {
@@ -75,32 +82,46 @@ int check_output(const gr_output* o) {
     return GR_OK;
 }
 
-// Resident-grid launch shape for `nray` rays.
-gr::LaunchShape shape_for(const gr_ctx* ctx, int64_t nray, bool f32_out) {
-    gr::LaunchShape L;
+gr_launch effective_launch(const gr_ctx* ctx) {
     gr_launch l = ctx->launch;
     if (l.block == 0) {
         l.block = 256;
         l.waves_per_simd = 0;
         l.refill = 1;
+        l.order = 1;
     }
+    return l;
+}
+
+// Grid for a persistent launch of `nray` rays with `per_cu_max` resident
+// workgroups per CU.
+gr::LaunchShape resident_shape(const gr_ctx* ctx, const gr_launch& l, int per_cu_max,
+                               int64_t nray) {
+    gr::LaunchShape L;
     L.block = l.block;
-    L.refill = l.refill;
-    const int64_t blocks_needed = (nray + L.block - 1) / L.block;
-    if (!L.refill) {
-        L.grid = (int)std::max<int64_t>(1, blocks_needed);
-        return L;
-    }
-    int per_cu = gr::occupancy_trace_fp64(L.block, f32_out);
-    if (per_cu < 1) per_cu = 1;
+    L.refill = 1;
+    int per_cu = std::max(1, per_cu_max);
     if (l.waves_per_simd > 0) {
         const int waves_per_block = L.block / 64;
         const int want = std::max(1, (l.waves_per_simd * 4) / waves_per_block);
         per_cu = std::min(per_cu, want);
     }
+    const int64_t blocks_needed = (nray + L.block - 1) / L.block;
     const int64_t resident = (int64_t)per_cu * ctx->num_cu;
     L.grid = (int)std::max<int64_t>(1, std::min<int64_t>(resident, blocks_needed));
     return L;
+}
+
+gr::LaunchShape frame_shape(const gr_ctx* ctx, int64_t nray, bool f32_out) {
+    const gr_launch l = effective_launch(ctx);
+    if (!l.refill) {
+        gr::LaunchShape L;
+        L.block = l.block;
+        L.refill = 0;
+        L.grid = (int)std::max<int64_t>(1, (nray + L.block - 1) / L.block);
+        return L;
+    }
+    return resident_shape(ctx, l, gr::occupancy_trace_fp64(l.block, f32_out), nray);
 }
 
 struct DeviceGuard {
@@ -115,43 +136,191 @@ struct DeviceGuard {
     }
 };
 
+gr::Integrator device_integrator(const gr_integrator& in) {
+    gr::Integrator I;
+    I.dt = in.dt;
+    I.eps = in.fd_eps;
+    I.inv_eps = 1.0 / in.fd_eps;
+    I.hnorm = in.horizon_norm;
+    I.esc_factor = in.escape_factor;
+    I.max_steps = in.max_steps;
+    return I;
+}
+
+gr::OutPtrs out_ptrs(const gr_output* o) {
+    gr::OutPtrs p;
+    p.t = o->t;
+    p.r = o->r;
+    p.th = o->theta;
+    p.ph = o->phi;
+    p.pt = o->p_t;
+    p.pr = o->p_r;
+    p.pth = o->p_theta;
+    p.pph = o->p_phi;
+    p.flag = o->flag;
+    p.steps = o->steps;
+    return p;
+}
+
 gr::FrameArgs frame_args(const gr_ctx* ctx, const gr_metric* m, const gr_camera* c,
                          const gr_output* o, const int32_t* pixels, int64_t nray) {
     gr::FrameArgs A;
     memset(&A, 0, sizeof A);
     A.hole = gr::make_hole(m->M, m->a, m->Q);
     A.cam = gr::make_camera(A.hole, c->r0, c->theta0, c->phi0, c->fov, c->width, c->height);
-    A.in.dt = ctx->integ.dt;
-    A.in.eps = ctx->integ.fd_eps;
-    A.in.inv_eps = 1.0 / ctx->integ.fd_eps;
-    A.in.hnorm = ctx->integ.horizon_norm;
-    A.in.esc_factor = ctx->integ.escape_factor;
-    A.in.max_steps = ctx->integ.max_steps;
+    A.in = device_integrator(ctx->integ);
     A.r_esc = ctx->integ.escape_factor * c->r0;
     A.nray = nray;
     A.pixels = pixels;
-    A.out.t = o->t;
-    A.out.r = o->r;
-    A.out.th = o->theta;
-    A.out.ph = o->phi;
-    A.out.pt = o->p_t;
-    A.out.pr = o->p_r;
-    A.out.pth = o->p_theta;
-    A.out.pph = o->p_phi;
-    A.out.flag = o->flag;
-    A.out.steps = o->steps;
+    A.out = out_ptrs(o);
     return A;
 }
 
-int launch_frame(gr_ctx* ctx, const gr_metric* m, const gr_camera* c, const gr_output* o,
-                 const int32_t* pixels, int64_t nray, hipStream_t s) {
-    if (nray == 0) return GR_OK;
-    const bool f32 = o->dtype == GR_F32;
-    const gr::FrameArgs A = frame_args(ctx, m, c, o, pixels, nray);
-    const gr::LaunchShape L = shape_for(ctx, nray, f32);
-    hipError_t e = gr::launch_trace_fp64(A, f32, L, ctx->counter, s);
-    if (e != hipSuccess) return device_error(e, "trace_fp64 launch");
+int64_t instance_rays(const gr_instance* I) {
+    return I->n_pixels < 0 ? (int64_t)I->camera.width * I->camera.height : I->n_pixels;
+}
+
+int validate_batch(const gr_ctx* ctx, const gr_instance* inst, int32_t n) {
+    if (!ctx || !inst || n < 1) return GR_EINVAL;
+    for (int32_t k = 0; k < n; ++k) {
+        const gr_instance* I = &inst[k];
+        int rc = check_metric(&I->metric);
+        if (!rc) rc = check_camera(&I->metric, &I->camera);
+        if (rc) return rc;
+        if (I->n_pixels < -1) return GR_EINVAL;
+        if (instance_rays(I) == 0) continue;
+        rc = check_output(&I->out);
+        if (rc) return rc;
+        if (I->n_pixels > 0 && !I->pixels) return GR_EINVAL;
+    }
+    if (ctx->integ.precision != GR_FP64) return GR_EUNSUPPORTED;
     return GR_OK;
+}
+
+// Build and upload the instance table; returns the total ray count in *total.
+int upload_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, int order,
+                 hipStream_t s, int32_t* ninst, int64_t* total) {
+    std::vector<int32_t> idx;
+    for (int32_t k = 0; k < n; ++k)
+        if (instance_rays(&inst[k]) > 0) idx.push_back(k);
+    if (order == 1) {
+        // longest expected rays first: path length grows with the escape radius
+        std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) {
+            return inst[x].camera.r0 > inst[y].camera.r0;
+        });
+    }
+    const int64_t m = (int64_t)idx.size();
+    std::vector<gr::BatchInstance> tab(m);
+    std::vector<int64_t> firsts(m + 1, 0);
+    for (int64_t q = 0; q < m; ++q) {
+        const gr_instance* I = &inst[idx[q]];
+        gr::BatchInstance& B = tab[q];
+        memset(&B, 0, sizeof B);
+        B.hole = gr::make_hole(I->metric.M, I->metric.a, I->metric.Q);
+        B.cam = gr::make_camera(B.hole, I->camera.r0, I->camera.theta0, I->camera.phi0,
+                                I->camera.fov, I->camera.width, I->camera.height);
+        B.r_esc = ctx->integ.escape_factor * I->camera.r0;
+        B.pixels = I->n_pixels < 0 ? nullptr : I->pixels;
+        B.out = out_ptrs(&I->out);
+        B.f32 = I->out.dtype == GR_F32;
+        firsts[q + 1] = firsts[q] + instance_rays(I);
+    }
+    *ninst = (int32_t)m;
+    *total = firsts[m];
+    if (m == 0) return GR_OK;
+    if (m > ctx->table_cap) {
+        const int64_t cap = std::max<int64_t>(m, 2 * ctx->table_cap);
+        gr::BatchInstance* t = nullptr;
+        int64_t* f = nullptr;
+        if (hipMalloc(&t, cap * sizeof(gr::BatchInstance)) != hipSuccess) return GR_ENOMEM;
+        if (hipMalloc(&f, (cap + 1) * sizeof(int64_t)) != hipSuccess) {
+            hipFree(t);
+            return GR_ENOMEM;
+        }
+        // the old table may still be read by queued work on another stream the
+        // caller synchronises; free after the device is idle for this context
+        hipDeviceSynchronize();
+        hipFree(ctx->table);
+        hipFree(ctx->firsts);
+        ctx->table = t;
+        ctx->firsts = f;
+        ctx->table_cap = cap;
+    }
+    // pageable sources: the copies are staged before hipMemcpyAsync returns
+    hipError_t e = hipMemcpyAsync(ctx->table, tab.data(), m * sizeof(gr::BatchInstance),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->firsts, firsts.data(), (m + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return device_error(e, "batch table upload");
+    return GR_OK;
+}
+
+int run_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, const gr_launch& l,
+              hipStream_t s) {
+    int32_t ninst = 0;
+    int64_t total = 0;
+    int rc = upload_batch(ctx, inst, n, l.order, s, &ninst, &total);
+    if (rc) return rc;
+    if (total == 0) return GR_OK;
+    gr::BatchArgs B;
+    memset(&B, 0, sizeof B);
+    B.in = device_integrator(ctx->integ);
+    B.inst = ctx->table;
+    B.firsts = ctx->firsts;
+    B.ninst = ninst;
+    B.total = total;
+    const gr::LaunchShape L =
+        resident_shape(ctx, l, gr::occupancy_trace_fp64_batch(l.block), total);
+    hipError_t e = gr::launch_trace_fp64_batch(B, L, ctx->counter, s);
+    if (e != hipSuccess) return device_error(e, "trace_fp64_batch launch");
+    return GR_OK;
+}
+
+// ---------------------------------------------------------------- autotune cache
+// One JSON object per line:
+// {"key": "...", "block": B, "waves_per_simd": W, "refill": 1, "order": O, "ms": T}
+std::string cache_key(const gr_ctx* ctx, int64_t total, int32_t ninst) {
+    int lg = 0;
+    while (((int64_t)1 << (lg + 1)) <= total) ++lg;
+    int ln = 0;
+    while ((1 << (ln + 1)) <= ninst) ++ln;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s/trace_fp64_batch/rays2^%d/inst2^%d", ctx->arch, lg, ln);
+    return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& key, gr_launch* out) {
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        const std::string pat = "\"key\": \"" + key + "\"";
+        if (!strstr(line, pat.c_str())) continue;
+        gr_launch l;
+        const char* p;
+        if ((p = strstr(line, "\"block\": ")) && sscanf(p, "\"block\": %d", &l.block) == 1 &&
+            (p = strstr(line, "\"waves_per_simd\": ")) &&
+            sscanf(p, "\"waves_per_simd\": %d", &l.waves_per_simd) == 1 &&
+            (p = strstr(line, "\"order\": ")) && sscanf(p, "\"order\": %d", &l.order) == 1) {
+            l.refill = 1;
+            *out = l;      // the last matching line wins
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_append(const char* path, const std::string& key, const gr_launch& l, double ms) {
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f,
+            "{\"key\": \"%s\", \"block\": %d, \"waves_per_simd\": %d, \"refill\": 1, "
+            "\"order\": %d, \"ms\": %.3f}\n",
+            key.c_str(), l.block, l.waves_per_simd, l.order, ms);
+    fclose(f);
 }
 
 }  // namespace
@@ -173,11 +342,16 @@ int gr_trace_init(gr_ctx** ctx, int device, const gr_integrator* integ) {
     memset(c, 0, sizeof *c);
     c->device = device;
     c->integ = *integ;
-    e = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
     if (e != hipSuccess) {
         delete c;
-        return device_error(e, "hipDeviceGetAttribute");
+        return device_error(e, "hipGetDeviceProperties");
     }
+    c->num_cu = prop.multiProcessorCount;
+    snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
+    for (char* p = c->arch; *p; ++p)
+        if (*p == ':') *p = '\0';      // drop feature suffixes such as ":sramecc+"
     e = hipMalloc(&c->counter, sizeof(unsigned long long));
     if (e != hipSuccess) {
         delete c;
@@ -205,19 +379,14 @@ int gr_trace_set_launch(gr_ctx* ctx, const gr_launch* l) {
     if (l->block != 64 && l->block != 128 && l->block != 256) return GR_EINVAL;
     if (l->waves_per_simd < 0 || l->waves_per_simd > 8) return GR_EINVAL;
     if (l->refill != 0 && l->refill != 1) return GR_EINVAL;
+    if (l->order != 0 && l->order != 1) return GR_EINVAL;
     ctx->launch = *l;
     return GR_OK;
 }
 
 int gr_trace_get_launch(const gr_ctx* ctx, gr_launch* l) {
     if (!ctx || !l) return GR_EINVAL;
-    if (ctx->launch.block) {
-        *l = ctx->launch;
-    } else {
-        l->block = 256;
-        l->waves_per_simd = 0;
-        l->refill = 1;
-    }
+    *l = effective_launch(ctx);
     return GR_OK;
 }
 
@@ -230,45 +399,89 @@ int gr_trace_frame(gr_ctx* ctx, const gr_metric* m, const gr_camera* c, const gr
     if (rc) return rc;
     if (ctx->integ.precision != GR_FP64) return GR_EUNSUPPORTED;
     DeviceGuard guard(ctx->device);
-    return launch_frame(ctx, m, c, out, nullptr, (int64_t)c->width * c->height,
-                        (hipStream_t)hip_stream);
-}
-
-static int64_t instance_rays(const gr_instance* I) {
-    return I->n_pixels < 0 ? (int64_t)I->camera.width * I->camera.height : I->n_pixels;
+    const int64_t nray = (int64_t)c->width * c->height;
+    const bool f32 = out->dtype == GR_F32;
+    const gr::FrameArgs A = frame_args(ctx, m, c, out, nullptr, nray);
+    const gr::LaunchShape L = frame_shape(ctx, nray, f32);
+    hipError_t e = gr::launch_trace_fp64(A, f32, L, ctx->counter, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return device_error(e, "trace_fp64 launch");
+    return GR_OK;
 }
 
 int gr_trace_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, void* hip_stream) {
-    if (!ctx || !inst || n < 1) return GR_EINVAL;
-    for (int32_t k = 0; k < n; ++k) {
-        const gr_instance* I = &inst[k];
-        int rc = check_metric(&I->metric);
-        if (!rc) rc = check_camera(&I->metric, &I->camera);
-        if (rc) return rc;
-        if (I->n_pixels < -1) return GR_EINVAL;
-        if (instance_rays(I) == 0) continue;
-        rc = check_output(&I->out);
-        if (rc) return rc;
-        if (I->n_pixels > 0 && !I->pixels) return GR_EINVAL;
-    }
-    if (ctx->integ.precision != GR_FP64) return GR_EUNSUPPORTED;
+    const int rc = validate_batch(ctx, inst, n);
+    if (rc) return rc;
     DeviceGuard guard(ctx->device);
+    return run_batch(ctx, inst, n, effective_launch(ctx), (hipStream_t)hip_stream);
+}
+
+int gr_trace_autotune(gr_ctx* ctx, const gr_instance* inst, int32_t n, int32_t trial_steps,
+                      const char* cache_path, gr_launch* best, void* hip_stream) {
+    int rc = validate_batch(ctx, inst, n);
+    if (rc) return rc;
+    if (trial_steps < 0) return GR_EINVAL;
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    int64_t total = 0;
+    int32_t ninst = 0;
     for (int32_t k = 0; k < n; ++k) {
-        const gr_instance* I = &inst[k];
-        const int64_t nray = instance_rays(I);
-        if (nray == 0) continue;
-        const int32_t* pix = I->n_pixels < 0 ? nullptr : I->pixels;
-        const int rc = launch_frame(ctx, &I->metric, &I->camera, &I->out, pix, nray,
-                                    (hipStream_t)hip_stream);
-        if (rc) return rc;
+        total += instance_rays(&inst[k]);
+        ninst += instance_rays(&inst[k]) > 0;
     }
-    return GR_OK;
+    const std::string key = cache_key(ctx, total, ninst);
+    gr_launch win;
+    bool have = cache_path && cache_lookup(cache_path, key, &win);
+    if (!have) {
+        const gr_integrator full = ctx->integ;
+        if (trial_steps > 0 && trial_steps < full.max_steps) ctx->integ.max_steps = trial_steps;
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            ctx->integ = full;
+            return device_error(hipGetLastError(), "hipEventCreate");
+        }
+        double best_ms = 1e300;
+        const int blocks[3] = {64, 128, 256};
+        const int waves[2] = {2, 0};
+        for (int order = 0; order <= 1 && !rc; ++order)
+            for (int b = 0; b < 3 && !rc; ++b)
+                for (int w = 0; w < 2 && !rc; ++w) {
+                    gr_launch l;
+                    l.block = blocks[b];
+                    l.waves_per_simd = waves[w];
+                    l.refill = 1;
+                    l.order = order;
+                    hipEventRecord(e0, s);
+                    rc = run_batch(ctx, inst, n, l, s);
+                    hipEventRecord(e1, s);
+                    if (rc) break;
+                    if (hipEventSynchronize(e1) != hipSuccess) {
+                        rc = device_error(hipGetLastError(), "autotune trial");
+                        break;
+                    }
+                    float ms = 0.f;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        win = l;
+                    }
+                }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        ctx->integ = full;
+        if (rc) return rc;
+        if (cache_path) cache_append(cache_path, key, win, best_ms);
+    }
+    ctx->launch = win;
+    if (best) *best = win;
+    return run_batch(ctx, inst, n, win, s);
 }
 
 int gr_trace_destroy(gr_ctx* ctx) {
     if (!ctx) return GR_OK;
     DeviceGuard guard(ctx->device);
     hipFree(ctx->counter);
+    hipFree(ctx->table);
+    hipFree(ctx->firsts);
     delete ctx;
     return GR_OK;
 }

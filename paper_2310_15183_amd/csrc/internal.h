@@ -41,6 +41,24 @@ struct FrameArgs {
     OutPtrs out;
 };
 
+// One instance of a batch (device table entry).
+struct BatchInstance {
+    Hole hole;
+    Camera cam;
+    double r_esc;
+    const int32_t* pixels;  // null: ray k is pixel k
+    OutPtrs out;
+    int32_t f32;
+};
+
+struct BatchArgs {
+    Integrator in;
+    const BatchInstance* inst;  // device table, ninst entries
+    const int64_t* firsts;      // device prefix offsets, ninst + 1 entries (firsts[0] = 0)
+    int32_t ninst;
+    int64_t total;              // firsts[ninst]
+};
+
 struct LaunchShape {
     int block;           // threads per workgroup
     int grid;            // workgroups
@@ -57,5 +75,10 @@ hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, const LaunchShape
 
 // Workgroups of `block` threads that fit on one CU for the FP64 tracer.
 int occupancy_trace_fp64(int block, bool f32_out);
+
+// All instances of a batch in one persistent launch.
+hipError_t launch_trace_fp64_batch(const BatchArgs& B, const LaunchShape& L,
+                                   unsigned long long* counter, hipStream_t s);
+int occupancy_trace_fp64_batch(int block);
 
 }  // namespace gr

@@ -69,14 +69,13 @@ struct Ray {
     double wtt, wtp, wpp;    // p_t^2, 2 p_t p_phi, p_phi^2 (constant along the ray)
 };
 
-__device__ __forceinline__ void start_ray(const FrameArgs& A, int64_t k, Ray& y) {
-    const int64_t pix = A.pixels ? (int64_t)A.pixels[k] : k;
-    const int64_t i = pix % A.cam.W, j = pix / A.cam.W;
-    camera_ray(A.cam, i, j, y.pt, y.pr, y.pth, y.pph);
+__device__ __forceinline__ void start_ray(const Camera& C, int64_t pix, Ray& y) {
+    const int64_t i = pix % C.W, j = pix / C.W;
+    camera_ray(C, i, j, y.pt, y.pr, y.pth, y.pph);
     y.t = 0.0;
-    y.r = A.cam.r0;
-    y.th = A.cam.th0;
-    y.ph = A.cam.ph0;
+    y.r = C.r0;
+    y.th = C.th0;
+    y.ph = C.ph0;
     y.wtt = y.pt * y.pt;
     y.wtp = (2.0 * y.pt) * y.pph;
     y.wpp = y.pph * y.pph;
@@ -88,12 +87,11 @@ __device__ __forceinline__ bool finite6(const Ray& y) {
 }
 
 // One RK4 step; returns nu = |dt/dtau| of the first stage.
-__device__ __forceinline__ double rk4_step(const FrameArgs& A, Ray& y) {
-    const Hole& H = A.hole;
-    const double eps = A.in.eps, inv_eps = A.in.inv_eps;
+__device__ __forceinline__ double rk4_step(const Hole& H, const Integrator& in, Ray& y) {
+    const double eps = in.eps, inv_eps = in.inv_eps;
     Deriv k = rhs(H, eps, inv_eps, y.r, y.th, y.pt, y.pr, y.pth, y.pph, y.wtt, y.wtp, y.wpp);
     const double nu = fabs(k.qt);
-    const double h = A.in.dt / nu;
+    const double h = in.dt / nu;
     const double hh = 0.5 * h;
     double st = k.qt, sr = k.qr, sh = k.qh, sp = k.qp, spr = k.pr, sph = k.ph;
     k = rhs(H, eps, inv_eps, fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), y.pt,
@@ -118,11 +116,12 @@ __device__ __forceinline__ double rk4_step(const FrameArgs& A, Ray& y) {
     return nu;
 }
 
-__device__ __forceinline__ int exit_flag(const FrameArgs& A, const Ray& y, double nu, int s) {
-    if (y.r > A.r_esc) return GR_FLAG_ESCAPE;
-    if (nu > A.in.hnorm) return GR_FLAG_HORIZON;
+__device__ __forceinline__ int exit_flag(const Integrator& in, double r_esc, const Ray& y,
+                                         double nu, int s) {
+    if (y.r > r_esc) return GR_FLAG_ESCAPE;
+    if (nu > in.hnorm) return GR_FLAG_HORIZON;
     if (!finite6(y)) return GR_FLAG_INVALID;
-    if (s >= A.in.max_steps) return GR_FLAG_TIMEOUT;
+    if (s >= in.max_steps) return GR_FLAG_TIMEOUT;
     return RUNNING;
 }
 
@@ -147,10 +146,24 @@ __device__ __forceinline__ void write_ray(const OutPtrs& o, int64_t k, const Ray
 }
 
 // Flag for a freshly started ray: invalid start or a zero step limit end it.
-__device__ __forceinline__ int start_flag(const FrameArgs& A, const Ray& y) {
+__device__ __forceinline__ int start_flag(const Integrator& in, const Ray& y) {
     if (!(finite6(y) && isfinite(y.pt) && isfinite(y.pph))) return GR_FLAG_INVALID;
-    if (A.in.max_steps <= 0) return GR_FLAG_TIMEOUT;
+    if (in.max_steps <= 0) return GR_FLAG_TIMEOUT;
     return RUNNING;
+}
+
+// Wave-wide work distribution: lanes with `want` set receive consecutive ids
+// from the global counter (one atomic per wave), in lane order.
+__device__ __forceinline__ int64_t take_ids(bool want, unsigned long long* counter) {
+    const int lane = (int)__lane_id();
+    const unsigned long long want_mask = __ballot(want);
+    if (!want_mask) return -1;
+    const int leader = __ffsll((unsigned long long)want_mask) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(want_mask));
+    base = __shfl(base, leader);
+    const unsigned long long below = want_mask & ((1ull << lane) - 1ull);
+    return want ? (int64_t)(base + (unsigned long long)__popcll(below)) : -1;
 }
 
 // One lane, one ray; the grid covers every ray.
@@ -159,13 +172,13 @@ __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= A.nray) return;
     Ray y;
-    start_ray(A, k, y);
+    start_ray(A.cam, A.pixels ? (int64_t)A.pixels[k] : k, y);
     int s = 0;
-    int f = start_flag(A, y);
+    int f = start_flag(A.in, y);
     while (f == RUNNING) {
-        const double nu = rk4_step(A, y);
+        const double nu = rk4_step(A.hole, A.in, y);
         ++s;
-        f = exit_flag(A, y, nu, s);
+        f = exit_flag(A.in, A.r_esc, y, nu, s);
     }
     write_ray<T>(A.out, k, y, f, s);
 }
@@ -174,45 +187,98 @@ __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
 template <typename T>
 __global__ void __launch_bounds__(256) trace_fp64_refill(const FrameArgs A,
                                                           unsigned long long* counter) {
-    const int lane = (int)__lane_id();
     Ray y;
     int64_t k = 0;
     int s = 0;
     bool live = false;   // lane holds a ray in flight
     bool want = true;    // lane asks for a new ray
     for (;;) {
-        const unsigned long long want_mask = __ballot(want);
-        if (want_mask) {
-            const int leader = __ffsll((unsigned long long)want_mask) - 1;
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(want_mask));
-            base = __shfl(base, leader);
-            if (want) {
-                const unsigned long long below = want_mask & ((1ull << lane) - 1ull);
-                const int64_t id = (int64_t)(base + (unsigned long long)__popcll(below));
-                want = false;
-                live = false;
-                if (id < A.nray) {
-                    k = id;
-                    start_ray(A, k, y);
-                    s = 0;
-                    const int f = start_flag(A, y);
-                    if (f == RUNNING) {
-                        live = true;
-                    } else {
-                        write_ray<T>(A.out, k, y, f, 0);
-                        want = true;
-                    }
+        const int64_t id = take_ids(want, counter);
+        if (want) {
+            want = false;
+            if (id < A.nray) {
+                k = id;
+                start_ray(A.cam, A.pixels ? (int64_t)A.pixels[k] : k, y);
+                s = 0;
+                const int f = start_flag(A.in, y);
+                if (f == RUNNING) {
+                    live = true;
+                } else {
+                    write_ray<T>(A.out, k, y, f, 0);
+                    want = true;
                 }
             }
         }
         if (!__any(live || want)) break;
         if (live) {
-            const double nu = rk4_step(A, y);
+            const double nu = rk4_step(A.hole, A.in, y);
             ++s;
-            const int f = exit_flag(A, y, nu, s);
+            const int f = exit_flag(A.in, A.r_esc, y, nu, s);
             if (f != RUNNING) {
                 write_ray<T>(A.out, k, y, f, s);
+                live = false;
+                want = true;
+            }
+        }
+    }
+}
+
+// Many instances in one launch.  Global ray ids run over the instances in
+// table order; a lane finds its instance by binary search of the prefix
+// offsets and keeps that instance's black-hole constants in registers.
+__device__ __forceinline__ int find_instance(const BatchArgs& B, int64_t id) {
+    int lo = 0, hi = B.ninst;                     // firsts[lo] <= id < firsts[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (B.firsts[mid] <= id) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void write_batch(const BatchInstance& I, int64_t k, const Ray& y,
+                                            int f, int s) {
+    if (I.f32) write_ray<float>(I.out, k, y, f, s);
+    else write_ray<double>(I.out, k, y, f, s);
+}
+
+__global__ void __launch_bounds__(256) trace_fp64_batch(const BatchArgs B,
+                                                         unsigned long long* counter) {
+    Ray y;
+    Hole H;
+    double r_esc = 0.0;
+    int inst = 0;
+    int64_t k = 0;
+    int s = 0;
+    bool live = false;
+    bool want = true;
+    for (;;) {
+        const int64_t id = take_ids(want, counter);
+        if (want) {
+            want = false;
+            if (id < B.total) {
+                inst = find_instance(B, id);
+                const BatchInstance& I = B.inst[inst];
+                k = id - B.firsts[inst];
+                H = I.hole;
+                r_esc = I.r_esc;
+                start_ray(I.cam, I.pixels ? (int64_t)I.pixels[k] : k, y);
+                s = 0;
+                const int f = start_flag(B.in, y);
+                if (f == RUNNING) {
+                    live = true;
+                } else {
+                    write_batch(I, k, y, f, 0);
+                    want = true;
+                }
+            }
+        }
+        if (!__any(live || want)) break;
+        if (live) {
+            const double nu = rk4_step(H, B.in, y);
+            ++s;
+            const int f = exit_flag(B.in, r_esc, y, nu, s);
+            if (f != RUNNING) {
+                write_batch(B.inst[inst], k, y, f, s);
                 live = false;
                 want = true;
             }
@@ -247,6 +313,22 @@ hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, const LaunchShape
             hipLaunchKernelGGL(trace_fp64_static<double>, dim3(L.grid), dim3(L.block), 0, s, A);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_trace_fp64_batch(const BatchArgs& B, const LaunchShape& L,
+                                   unsigned long long* counter, hipStream_t s) {
+    hipError_t e = launch_reset_counter(counter, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(trace_fp64_batch, dim3(L.grid), dim3(L.block), 0, s, B, counter);
+    return hipGetLastError();
+}
+
+int occupancy_trace_fp64_batch(int block) {
+    int n = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, trace_fp64_batch, block, 0) ==
+                   hipSuccess
+               ? n
+               : 0;
 }
 
 int occupancy_trace_fp64(int block, bool f32_out) {
