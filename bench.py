@@ -36,6 +36,7 @@ METRIC = "geodesic rays/s @1000² Kerr: FP64 vs mixed vs surrogate, ≤1e-4 rad 
 FLOPS_PER_RAY_STEP = 881          # binary64 ops of one RK4 step (add/sub/mul/div 1, fma 2)
 FP64_PEAK_TFLOPS = 78.6           # MI355X FP64 vector (256 CU x 128 flop/clk x 2.4 GHz)
 KERNEL_SOURCES = ["paper_2310_15183_amd/csrc/trace_fp64.hip",
+                  "paper_2310_15183_amd/csrc/step_fp64.h",
                   "paper_2310_15183_amd/csrc/grmath.h"]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "trace_fp64_kn1000_traffic.md")
 
@@ -89,6 +90,102 @@ def cpu_baseline(w, stride, threads):
                              max_steps=w["max_steps"], pixels=pix, threads=threads)
     dt = time.perf_counter() - t0
     return pix.size / dt, pix.size, float(res.steps.mean()), dt
+
+
+def time_frames(g, ctx, metric, cam, out, steps, warmup, stream):
+    """Run warmup untimed frames, then time `steps` frames; returns (wall
+    seconds for the timed frames, mean launch seconds from HIP events)."""
+    import torch
+    for _ in range(warmup):
+        g.gr_trace_frame(ctx, metric, cam, out.struct, stream)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record(stream)
+        g.gr_trace_frame(ctx, metric, cam, out.struct, stream)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / 1e3 / steps
+
+
+def accuracy_pair(g, w, stream):
+    """Trace the frame once in binary64 and once mixed, with every output in
+    binary64, and compare where the rays cross the escape sphere."""
+    import torch
+
+    from paper_2310_15183_amd.evaluate import mixed_errors
+    res = {}
+    for prec in (g.GR_FP64, g.GR_MIXED):
+        ctx = g.gr_trace_init(0, g.make_integrator(dt=w["dt"], fd_eps=w["fd_eps"],
+                                                   horizon_norm=w["horizon_norm"],
+                                                   escape_factor=w["escape_factor"],
+                                                   max_steps=w["max_steps"], precision=prec))
+        out = g.alloc_outputs(w["W"] * w["H"], dtype=g.GR_F64, fields=g.FIELDS)
+        g.gr_trace_frame(ctx, g.gr_metric(w["M"], w["a"], w["Q"]),
+                         g.gr_camera(w["r0"], w["theta0"], w["phi0"], w["fov"], w["W"], w["H"]),
+                         out.struct, stream)
+        torch.cuda.synchronize()
+        res[prec] = {k: v.cpu().numpy() for k, v in out.tensors.items()}
+        g.gr_trace_destroy(ctx)
+    return mixed_errors(w["M"], w["a"], w["Q"], w["escape_factor"] * w["r0"], res[g.GR_FP64],
+                        res[g.GR_MIXED])
+
+
+def mixed_variant(g, w, args, stream, fp64_rays_per_s):
+    """Mixed-precision form on the same frame: rays/s, speedup and accuracy."""
+    n = w["W"] * w["H"]
+    ctx = g.gr_trace_init(0, g.make_integrator(dt=w["dt"], fd_eps=w["fd_eps"],
+                                               horizon_norm=w["horizon_norm"],
+                                               escape_factor=w["escape_factor"],
+                                               max_steps=w["max_steps"], precision=g.GR_MIXED))
+    out = g.alloc_outputs(n, dtype=g.GR_F32, fields=("t", "r", "theta", "phi"))
+    metric = g.gr_metric(w["M"], w["a"], w["Q"])
+    cam = g.gr_camera(w["r0"], w["theta0"], w["phi0"], w["fov"], w["W"], w["H"])
+    wall, launch_s = time_frames(g, ctx, metric, cam, out, args.steps, args.warmup, stream)
+    g.gr_trace_destroy(ctx)
+    err = accuracy_pair(g, w, stream)
+    rays_s = n * args.steps / wall
+    return {"rays_per_s": rays_s, "ms_per_step": wall / args.steps * 1e3,
+            "launch_ms": launch_s * 1e3, "speedup_vs_fp64": rays_s / fp64_rays_per_s,
+            "angle_err_rad": {k: err[k] for k in ("median", "p99", "p999", "max")},
+            "flag_mismatch_frac": err["flag_mismatch"],
+            "gate": "p99.9 <= 1e-4 rad, <= 0.1% misclassified",
+            "passes_gate": err["p999"] <= 1e-4 and err["flag_mismatch"] <= 1e-3}
+
+
+def bench_mixed(args):
+    """Near-extremal Kerr (M=0.5, a=0.49, r0=20, theta0=60 deg, fov 75 deg,
+    dt=0.005, 50000 steps) at 1000x1000 and 2048x2048: binary64 vs mixed."""
+    import torch
+
+    import paper_2310_15183_amd as g
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    lines = []
+    for side in (1000, 2048):
+        w = dict(workload(), M=0.5, a=0.49, Q=0.0, r0=20.0, theta0=math.radians(60.0),
+                 fov=math.radians(75.0), W=side, H=side)
+        n = side * side
+        ctx = g.gr_trace_init(0, g.make_integrator(dt=w["dt"], fd_eps=w["fd_eps"],
+                                                   horizon_norm=w["horizon_norm"],
+                                                   escape_factor=w["escape_factor"],
+                                                   max_steps=w["max_steps"]))
+        out = g.alloc_outputs(n, dtype=g.GR_F32, fields=("t", "r", "theta", "phi"))
+        wall, launch_s = time_frames(g, ctx, g.gr_metric(w["M"], w["a"], w["Q"]),
+                                     g.gr_camera(w["r0"], w["theta0"], w["phi0"], w["fov"],
+                                                 side, side), out, args.steps, args.warmup,
+                                     stream)
+        g.gr_trace_destroy(ctx)
+        fp64 = n * args.steps / wall
+        mixed = mixed_variant(g, w, args, stream, fp64)
+        lines.append({"workload": f"near-extremal kerr {side}x{side}", "fp64_rays_per_s": fp64,
+                      "fp64_ms_per_step": wall / args.steps * 1e3, "mixed": mixed})
+    print(json.dumps({"metric": "geodesic rays/s, near-extremal Kerr: FP64 vs mixed",
+                      "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "data": "synthetic", "results": lines}), flush=True)
 
 
 def copy_calibration(mib=256, reps=3):
@@ -175,9 +272,12 @@ def main():
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter scale)")
-    ap.add_argument("--workload", choices=["frame", "batch"], default="frame",
+    ap.add_argument("--workload", choices=["frame", "batch", "mixed"], default="frame",
                     help="frame: the 1000x1000 Kerr-Newman frame (default, the headline "
-                         "line); batch: the 256-instance uneven batch in one launch")
+                         "line); batch: the 256-instance uneven batch in one launch; mixed: "
+                         "near-extremal Kerr at 1000^2 and 2048^2, binary64 vs mixed")
+    ap.add_argument("--skip-variants", action="store_true",
+                    help="frame workload: time only the binary64 path")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -190,6 +290,9 @@ def main():
 
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "mixed":
+        bench_mixed(args)
         return
 
     import numpy as np
@@ -208,21 +311,7 @@ def main():
     out = g.alloc_outputs(n, dtype=g.GR_F32, fields=("t", "r", "theta", "phi"))
     stream = torch.cuda.current_stream()
 
-    for _ in range(args.warmup):
-        g.gr_trace_frame(ctx, metric, cam, out.struct, stream)
-    torch.cuda.synchronize()
-
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        starts[k].record(stream)
-        g.gr_trace_frame(ctx, metric, cam, out.struct, stream)
-        ends[k].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    launch_s = sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / 1e3 / args.steps
+    wall, launch_s = time_frames(g, ctx, metric, cam, out, args.steps, args.warmup, stream)
 
     steps = out["steps"].cpu().numpy().astype(np.int64)
     flags = out["flag"].cpu().numpy()
@@ -267,7 +356,11 @@ def main():
             "launch_ms": launch_s * 1e3,
         },
         "cpu_baseline": None,
+        "variants": {},
     }
+    if not args.skip_variants:
+        result["variants"]["mixed"] = mixed_variant(g, w, args, stream, result["value"])
+        result["variants"]["surrogate"] = None
     if not args.skip_cpu_baseline:
         import oracle
         threads = min(16, oracle.default_threads())

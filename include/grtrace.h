@@ -57,9 +57,15 @@ enum {
 
 enum { GR_FLAG_TIMEOUT = 0, GR_FLAG_ESCAPE = 1, GR_FLAG_HORIZON = 2, GR_FLAG_INVALID = 3 };
 
-/* Integrator precision. */
-enum { GR_FP64 = 0,        /* binary64 state, stages and metric */
-       GR_MIXED = 1 };     /* reserved: binary32 state and stages, binary64 differences */
+/* Integrator precision.
+ * GR_FP64: binary64 throughout; results are reproducible bit for bit.
+ * GR_MIXED (gr_trace_frame only): binary32 state, RK4 stages and contraction;
+ *   binary64 metric evaluations and forward differences (sin/cos at
+ *   theta+eps by angle addition, reciprocals by v_rcp_f64 and two Newton
+ *   steps); whole binary64 steps while r < 1.2 r_+ or |p_r| < 1e-3, back to
+ *   binary32 once r > 1.25 r_+ and |p_r| > 2e-3.  Accuracy is stated against
+ *   GR_FP64, not bit for bit. */
+enum { GR_FP64 = 0, GR_MIXED = 1 };
 
 /* Element type of the floating-point outputs. */
 enum { GR_F64 = 0, GR_F32 = 1 };
@@ -144,14 +150,15 @@ typedef struct {
  * GR_ENOMEM, GR_EDEVICE. */
 int gr_trace_init(gr_ctx **ctx, int device, const gr_integrator *integ);
 
-/* Trace every pixel of one frame.  Errors: GR_EINVAL (validation above, NULL
- * ctx/m/c/out or out->flag), GR_EUNSUPPORTED (precision not built),
- * GR_EDEVICE (launch failed). */
+/* Trace every pixel of one frame with the context's integrator (GR_FP64 or
+ * GR_MIXED).  Errors: GR_EINVAL (validation above, NULL ctx/m/c/out or
+ * out->flag), GR_EDEVICE (launch failed). */
 int gr_trace_frame(gr_ctx *ctx, const gr_metric *m, const gr_camera *c,
                    const gr_output *out, void *hip_stream);
 
 /* Trace n >= 1 instances (possibly different black holes, cameras and image
- * sizes) in one persistent launch fed by one work queue.  The instance table
+ * sizes) in one persistent launch fed by one work queue (GR_FP64 only:
+ * GR_EUNSUPPORTED for GR_MIXED).  The instance table
  * (about 330 bytes per instance) is copied to device memory owned by the
  * context, which grows it with hipMalloc when a larger batch arrives.  Same
  * errors as gr_trace_frame (GR_ENOMEM if the table cannot grow); an error in

@@ -397,13 +397,22 @@ int gr_trace_frame(gr_ctx* ctx, const gr_metric* m, const gr_camera* c, const gr
     if (!rc) rc = check_camera(m, c);
     if (!rc) rc = check_output(out);
     if (rc) return rc;
-    if (ctx->integ.precision != GR_FP64) return GR_EUNSUPPORTED;
     DeviceGuard guard(ctx->device);
     const int64_t nray = (int64_t)c->width * c->height;
     const bool f32 = out->dtype == GR_F32;
     const gr::FrameArgs A = frame_args(ctx, m, c, out, nullptr, nray);
+    hipError_t e;
+    if (ctx->integ.precision == GR_MIXED) {
+        const gr_launch l = effective_launch(ctx);
+        const gr::LaunchShape L =
+            resident_shape(ctx, l, gr::occupancy_trace_mixed(l.block, f32), nray);
+        e = gr::launch_trace_mixed(A, horizon(m), f32, L, ctx->counter,
+                                   (hipStream_t)hip_stream);
+        if (e != hipSuccess) return device_error(e, "trace_mixed launch");
+        return GR_OK;
+    }
     const gr::LaunchShape L = frame_shape(ctx, nray, f32);
-    hipError_t e = gr::launch_trace_fp64(A, f32, L, ctx->counter, (hipStream_t)hip_stream);
+    e = gr::launch_trace_fp64(A, f32, L, ctx->counter, (hipStream_t)hip_stream);
     if (e != hipSuccess) return device_error(e, "trace_fp64 launch");
     return GR_OK;
 }

@@ -76,6 +76,13 @@ hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, const LaunchShape
 // Workgroups of `block` threads that fit on one CU for the FP64 tracer.
 int occupancy_trace_fp64(int block, bool f32_out);
 
+// Mixed-precision frame tracer (binary32 state and stages, binary64
+// differences, binary64 steps inside 1.2 r_+ or near radial turning points).
+hipError_t launch_trace_mixed(const FrameArgs& A, double r_plus, bool f32_out,
+                              const LaunchShape& L, unsigned long long* counter,
+                              hipStream_t s);
+int occupancy_trace_mixed(int block, bool f32_out);
+
 // All instances of a batch in one persistent launch.
 hipError_t launch_trace_fp64_batch(const BatchArgs& B, const LaunchShape& L,
                                    unsigned long long* counter, hipStream_t s);

@@ -17,154 +17,12 @@
 // This translation unit must be compiled with -ffp-contract=off.
 
 #include "internal.h"
+#include "step_fp64.h"
 
 namespace gr {
 namespace {
 
-enum { RUNNING = -1 };
-
-struct Deriv {
-    double qt, qr, qh, qp;   // dq^mu/dtau
-    double pr, ph;           // dp_r/dtau, dp_theta/dtau
-};
-
-// Right-hand side at one stage point: metric at (r, th), (r+eps, th),
-// (r, th+eps); difference quotients times 1/eps; p-dot = -1/2 sum of the five
-// independent terms in the order tt, tphi (weight 2 p_t p_phi), rr, thth, phph.
-__device__ __forceinline__ Deriv rhs(const Hole& H, double eps, double inv_eps, double r,
-                                     double th, double pt, double pr, double pth, double pph,
-                                     double wtt, double wtp, double wpp) {
-    const ThetaTerms T0 = theta_terms(H, th);
-    const ThetaTerms T1 = theta_terms(H, th + eps);
-    const RadialTerms R0 = radial_terms(H, r);
-    const RadialTerms R1 = radial_terms(H, r + eps);
-    const InvMetric g = inverse_metric(H, R0, T0);
-    const InvMetric gr = inverse_metric(H, R1, T0);
-    const InvMetric gh = inverse_metric(H, R0, T1);
-
-    const double wrr = pr * pr, wth = pth * pth;
-    double acc = ((gr.tt - g.tt) * inv_eps) * wtt;
-    acc = fma((gr.tp - g.tp) * inv_eps, wtp, acc);
-    acc = fma((gr.rr - g.rr) * inv_eps, wrr, acc);
-    acc = fma((gr.hh - g.hh) * inv_eps, wth, acc);
-    acc = fma((gr.pp - g.pp) * inv_eps, wpp, acc);
-    Deriv d;
-    d.pr = -0.5 * acc;
-    acc = ((gh.tt - g.tt) * inv_eps) * wtt;
-    acc = fma((gh.tp - g.tp) * inv_eps, wtp, acc);
-    acc = fma((gh.rr - g.rr) * inv_eps, wrr, acc);
-    acc = fma((gh.hh - g.hh) * inv_eps, wth, acc);
-    acc = fma((gh.pp - g.pp) * inv_eps, wpp, acc);
-    d.ph = -0.5 * acc;
-
-    d.qt = fma(g.tt, pt, g.tp * pph);
-    d.qr = g.rr * pr;
-    d.qh = g.hh * pth;
-    d.qp = fma(g.tp, pt, g.pp * pph);
-    return d;
-}
-
-struct Ray {
-    double t, r, th, ph, pt, pr, pth, pph;
-    double wtt, wtp, wpp;    // p_t^2, 2 p_t p_phi, p_phi^2 (constant along the ray)
-};
-
-__device__ __forceinline__ void start_ray(const Camera& C, int64_t pix, Ray& y) {
-    const int64_t i = pix % C.W, j = pix / C.W;
-    camera_ray(C, i, j, y.pt, y.pr, y.pth, y.pph);
-    y.t = 0.0;
-    y.r = C.r0;
-    y.th = C.th0;
-    y.ph = C.ph0;
-    y.wtt = y.pt * y.pt;
-    y.wtp = (2.0 * y.pt) * y.pph;
-    y.wpp = y.pph * y.pph;
-}
-
-__device__ __forceinline__ bool finite6(const Ray& y) {
-    return isfinite(y.t) && isfinite(y.r) && isfinite(y.th) && isfinite(y.ph) &&
-           isfinite(y.pr) && isfinite(y.pth);
-}
-
-// One RK4 step; returns nu = |dt/dtau| of the first stage.
-__device__ __forceinline__ double rk4_step(const Hole& H, const Integrator& in, Ray& y) {
-    const double eps = in.eps, inv_eps = in.inv_eps;
-    Deriv k = rhs(H, eps, inv_eps, y.r, y.th, y.pt, y.pr, y.pth, y.pph, y.wtt, y.wtp, y.wpp);
-    const double nu = fabs(k.qt);
-    const double h = in.dt / nu;
-    const double hh = 0.5 * h;
-    double st = k.qt, sr = k.qr, sh = k.qh, sp = k.qp, spr = k.pr, sph = k.ph;
-    k = rhs(H, eps, inv_eps, fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), y.pt,
-            fma(hh, k.pr, y.pr), fma(hh, k.ph, y.pth), y.pph, y.wtt, y.wtp, y.wpp);
-    st = st + 2.0 * k.qt; sr = sr + 2.0 * k.qr; sh = sh + 2.0 * k.qh; sp = sp + 2.0 * k.qp;
-    spr = spr + 2.0 * k.pr; sph = sph + 2.0 * k.ph;
-    k = rhs(H, eps, inv_eps, fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), y.pt,
-            fma(hh, k.pr, y.pr), fma(hh, k.ph, y.pth), y.pph, y.wtt, y.wtp, y.wpp);
-    st = st + 2.0 * k.qt; sr = sr + 2.0 * k.qr; sh = sh + 2.0 * k.qh; sp = sp + 2.0 * k.qp;
-    spr = spr + 2.0 * k.pr; sph = sph + 2.0 * k.ph;
-    k = rhs(H, eps, inv_eps, fma(h, k.qr, y.r), fma(h, k.qh, y.th), y.pt,
-            fma(h, k.pr, y.pr), fma(h, k.ph, y.pth), y.pph, y.wtt, y.wtp, y.wpp);
-    st = st + k.qt; sr = sr + k.qr; sh = sh + k.qh; sp = sp + k.qp;
-    spr = spr + k.pr; sph = sph + k.ph;
-    const double h6 = h * (1.0 / 6.0);
-    y.t = fma(h6, st, y.t);
-    y.r = fma(h6, sr, y.r);
-    y.th = fma(h6, sh, y.th);
-    y.ph = fma(h6, sp, y.ph);
-    y.pr = fma(h6, spr, y.pr);
-    y.pth = fma(h6, sph, y.pth);
-    return nu;
-}
-
-__device__ __forceinline__ int exit_flag(const Integrator& in, double r_esc, const Ray& y,
-                                         double nu, int s) {
-    if (y.r > r_esc) return GR_FLAG_ESCAPE;
-    if (nu > in.hnorm) return GR_FLAG_HORIZON;
-    if (!finite6(y)) return GR_FLAG_INVALID;
-    if (s >= in.max_steps) return GR_FLAG_TIMEOUT;
-    return RUNNING;
-}
-
-template <typename T>
-__device__ __forceinline__ void put(void* p, int64_t k, double v) {
-    if (p) reinterpret_cast<T*>(p)[k] = (T)v;
-}
-
-template <typename T>
-__device__ __forceinline__ void write_ray(const OutPtrs& o, int64_t k, const Ray& y, int flag,
-                                          int s) {
-    put<T>(o.t, k, y.t);
-    put<T>(o.r, k, y.r);
-    put<T>(o.th, k, y.th);
-    put<T>(o.ph, k, y.ph);
-    put<T>(o.pt, k, y.pt);
-    put<T>(o.pr, k, y.pr);
-    put<T>(o.pth, k, y.pth);
-    put<T>(o.pph, k, y.pph);
-    o.flag[k] = (int8_t)flag;
-    if (o.steps) o.steps[k] = s;
-}
-
-// Flag for a freshly started ray: invalid start or a zero step limit end it.
-__device__ __forceinline__ int start_flag(const Integrator& in, const Ray& y) {
-    if (!(finite6(y) && isfinite(y.pt) && isfinite(y.pph))) return GR_FLAG_INVALID;
-    if (in.max_steps <= 0) return GR_FLAG_TIMEOUT;
-    return RUNNING;
-}
-
-// Wave-wide work distribution: lanes with `want` set receive consecutive ids
-// from the global counter (one atomic per wave), in lane order.
-__device__ __forceinline__ int64_t take_ids(bool want, unsigned long long* counter) {
-    const int lane = (int)__lane_id();
-    const unsigned long long want_mask = __ballot(want);
-    if (!want_mask) return -1;
-    const int leader = __ffsll((unsigned long long)want_mask) - 1;
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(want_mask));
-    base = __shfl(base, leader);
-    const unsigned long long below = want_mask & ((1ull << lane) - 1ull);
-    return want ? (int64_t)(base + (unsigned long long)__popcll(below)) : -1;
-}
+using namespace detail;
 
 // One lane, one ray; the grid covers every ray.
 template <typename T>

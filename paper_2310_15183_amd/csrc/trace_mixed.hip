@@ -1,0 +1,262 @@
+// Mixed-precision tracer for gfx950: binary32 RK4 stages and contraction;
+// binary64 metric evaluations and forward differences (a difference of step
+// 1e-8 needs binary64: the binary32 spacing near r = 20 is 1.9e-6); whole
+// binary64 steps near the horizon and near radial turning points.
+//
+// Same method as the binary64 tracer (arXiv 2310.15183, Sec. 2.1 eq.
+// hamGeodesic, Sec. 3.1.2 RK4 in coordinate-time steps, forward differences
+// of the appendix listing, exits of Sec. 3.3.2, camera of Sec. 3.3.1).
+// Evaluation choices, none of which changes the method:
+//  - a stage runs on the binary32-rounded state: its point, right-hand side,
+//    contraction and the RK4 combination are binary32; the step's increment
+//    is added to the state in binary64 (one add per component), because
+//    binary32 rounding of theta and phi alone random-walks ~5e-6 rad over
+//    1e4 steps;
+//  - sin and cos of the binary32 stage angle are evaluated in binary32 and
+//    widened; sin and cos at theta+eps follow from them by the angle-addition
+//    identity in binary64 (cos eps rounds to 1, sin eps to eps), so both
+//    evaluations of the theta difference see one consistent angle and the
+//    step is exactly eps;
+//  - reciprocals use v_rcp_f64 refined by two Newton steps (about 1 ulp);
+//    the binary32 step divides by |dt/dtau| with v_rcp_f32;
+//  - 1/eps is folded into the binary32 contraction weights.
+// A ray switches to whole binary64 steps (the binary64 tracer's own step)
+// when r < 1.2 r_+ or |p_r| < 1e-3, and back when r > 1.25 r_+ and
+// |p_r| > 2e-3.
+
+#include "internal.h"
+#include "step_fp64.h"
+
+namespace gr {
+namespace {
+
+using namespace detail;
+
+constexpr double R64_ENTER = 1.2, R64_LEAVE = 1.25;   // in units of r_+
+constexpr double PR_ENTER = 1e-3, PR_LEAVE = 2e-3;
+
+__device__ __forceinline__ double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+__device__ __forceinline__ ThetaTerms theta_from(const Hole& H, double s, double c) {
+    ThetaTerms T;
+    T.s2 = s * s;
+    T.c2 = c * c;
+    T.is2 = rcp_nr(T.s2);
+    T.w = H.a2 * T.s2;
+    return T;
+}
+
+__device__ __forceinline__ InvMetric metric_fast(const Hole& H, const RadialTerms& R,
+                                                 const ThetaTerms& T) {
+    const double rho2 = fma(H.a2, T.c2, R.r2);
+    const double Sigma2 = fma(-T.w, R.Delta, R.rara);
+    const double inv = rcp_nr(rho2 * R.Delta);
+    InvMetric g;
+    g.tt = -(Sigma2 * inv);
+    g.tp = -(R.aF * inv);
+    g.rr = R.DD * inv;
+    g.hh = R.Delta * inv;
+    g.pp = ((R.Delta - T.w) * inv) * T.is2;
+    return g;
+}
+
+struct DerivF {
+    float qt, qr, qh, qp, pr, ph;
+};
+
+struct ConstF {
+    float pt, pph;              // binary32 copies of the ray constants
+    float wtt, wtp, wpp;        // p_t^2/eps, 2 p_t p_phi/eps, p_phi^2/eps
+    float ie;                   // 1/eps
+};
+
+// sin and cos in binary32: x = k pi/2 + r, |r| <= pi/4 (two-part pi/2), then
+// Taylor polynomials through r^9 and r^10 (truncation below 2e-9).
+__device__ __forceinline__ void sincos_f32(float x, float& s_out, float& c_out) {
+    const float k = rintf(x * 0.636619772f);
+    float r = fmaf(-k, 1.57079637f, x);
+    r = fmaf(-k, -4.37113883e-8f, r);
+    const float z = r * r;
+    float ps = 2.75573192e-6f;                   //  1/9!
+    ps = fmaf(ps, z, -1.98412698e-4f);           // -1/7!
+    ps = fmaf(ps, z, 8.33333333e-3f);            //  1/5!
+    ps = fmaf(ps, z, -1.66666667e-1f);           // -1/3!
+    float pc = -2.75573192e-7f;                  // -1/10!
+    pc = fmaf(pc, z, 2.48015873e-5f);            //  1/8!
+    pc = fmaf(pc, z, -1.38888889e-3f);           // -1/6!
+    pc = fmaf(pc, z, 4.16666667e-2f);            //  1/4!
+    pc = fmaf(pc, z, -0.5f);                     // -1/2!
+    const float sr = fmaf(r * z, ps, r);
+    const float cr = fmaf(z, pc, 1.0f);
+    const int q = (int)k & 3;
+    const float s = (q & 1) ? cr : sr;
+    const float c = (q & 1) ? sr : cr;
+    s_out = (q & 2) ? -s : s;
+    c_out = (q == 1 || q == 2) ? -c : c;
+}
+
+__device__ __forceinline__ float dq(double hi, double lo) { return (float)(hi - lo); }
+
+__device__ __forceinline__ DerivF rhs_mixed(const Hole& H, double eps, float r, float th,
+                                            float pr, float pth, const ConstF& K) {
+    float sf, cf;
+    sincos_f32(th, sf, cf);
+    const double s = (double)sf, c = (double)cf;
+    const ThetaTerms T0 = theta_from(H, s, c);
+    const ThetaTerms T1 = theta_from(H, fma(eps, c, s), fma(-eps, s, c));
+    const RadialTerms R0 = radial_terms(H, (double)r);
+    const RadialTerms R1 = radial_terms(H, (double)r + eps);
+    const InvMetric g = metric_fast(H, R0, T0);
+    const InvMetric gr = metric_fast(H, R1, T0);
+    const InvMetric gh = metric_fast(H, R0, T1);
+
+    const float wrr = (pr * pr) * K.ie, wth = (pth * pth) * K.ie;
+    float acc = dq(gr.tt, g.tt) * K.wtt;
+    acc = fmaf(dq(gr.tp, g.tp), K.wtp, acc);
+    acc = fmaf(dq(gr.rr, g.rr), wrr, acc);
+    acc = fmaf(dq(gr.hh, g.hh), wth, acc);
+    acc = fmaf(dq(gr.pp, g.pp), K.wpp, acc);
+    DerivF d;
+    d.pr = -0.5f * acc;
+    acc = dq(gh.tt, g.tt) * K.wtt;
+    acc = fmaf(dq(gh.tp, g.tp), K.wtp, acc);
+    acc = fmaf(dq(gh.rr, g.rr), wrr, acc);
+    acc = fmaf(dq(gh.hh, g.hh), wth, acc);
+    acc = fmaf(dq(gh.pp, g.pp), K.wpp, acc);
+    d.ph = -0.5f * acc;
+
+    const float gtt = (float)g.tt, gtp = (float)g.tp, grr = (float)g.rr, ghh = (float)g.hh,
+                gpp = (float)g.pp;
+    d.qt = fmaf(gtt, K.pt, gtp * K.pph);
+    d.qr = grr * pr;
+    d.qh = ghh * pth;
+    d.qp = fmaf(gtp, K.pt, gpp * K.pph);
+    return d;
+}
+
+// One RK4 step with binary32 stages; the increment is added in binary64.
+__device__ __forceinline__ double rk4_step_mixed(const Hole& H, const Integrator& in,
+                                                 const ConstF& K, float dt, Ray& y) {
+    const float r = (float)y.r, th = (float)y.th;
+    const float pr = (float)y.pr, pth = (float)y.pth;
+    const double eps = in.eps;
+    DerivF k = rhs_mixed(H, eps, r, th, pr, pth, K);
+    const float nu = fabsf(k.qt);
+    const float h = dt * __builtin_amdgcn_rcpf(nu);
+    const float hh = 0.5f * h;
+    float st = k.qt, sr = k.qr, sh = k.qh, sp = k.qp, spr = k.pr, sph = k.ph;
+    k = rhs_mixed(H, eps, fmaf(hh, k.qr, r), fmaf(hh, k.qh, th), fmaf(hh, k.pr, pr),
+                  fmaf(hh, k.ph, pth), K);
+    st = fmaf(2.0f, k.qt, st); sr = fmaf(2.0f, k.qr, sr); sh = fmaf(2.0f, k.qh, sh);
+    sp = fmaf(2.0f, k.qp, sp); spr = fmaf(2.0f, k.pr, spr); sph = fmaf(2.0f, k.ph, sph);
+    k = rhs_mixed(H, eps, fmaf(hh, k.qr, r), fmaf(hh, k.qh, th), fmaf(hh, k.pr, pr),
+                  fmaf(hh, k.ph, pth), K);
+    st = fmaf(2.0f, k.qt, st); sr = fmaf(2.0f, k.qr, sr); sh = fmaf(2.0f, k.qh, sh);
+    sp = fmaf(2.0f, k.qp, sp); spr = fmaf(2.0f, k.pr, spr); sph = fmaf(2.0f, k.ph, sph);
+    k = rhs_mixed(H, eps, fmaf(h, k.qr, r), fmaf(h, k.qh, th), fmaf(h, k.pr, pr),
+                  fmaf(h, k.ph, pth), K);
+    st += k.qt; sr += k.qr; sh += k.qh; sp += k.qp; spr += k.pr; sph += k.ph;
+    const float h6 = h * (1.0f / 6.0f);
+    y.t += (double)(h6 * st);
+    y.r += (double)(h6 * sr);
+    y.th += (double)(h6 * sh);
+    y.ph += (double)(h6 * sp);
+    y.pr += (double)(h6 * spr);
+    y.pth += (double)(h6 * sph);
+    return (double)nu;
+}
+
+struct MixedArgs {
+    FrameArgs f;
+    double r_enter, r_leave;   // binary64 mode boundaries (R64_* times r_+)
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+trace_mixed_refill(const MixedArgs X,
+                                                           unsigned long long* counter) {
+    const FrameArgs& A = X.f;
+    const float dtf = (float)A.in.dt;
+    Ray y;
+    ConstF K;
+    int64_t k = 0;
+    int s = 0;
+    bool live = false, want = true, in64 = false;
+    for (;;) {
+        const int64_t id = take_ids(want, counter);
+        if (want) {
+            want = false;
+            if (id < A.nray) {
+                k = id;
+                start_ray(A.cam, A.pixels ? (int64_t)A.pixels[k] : k, y);
+                s = 0;
+                in64 = false;
+                K.pt = (float)y.pt;
+                K.pph = (float)y.pph;
+                K.ie = (float)A.in.inv_eps;
+                K.wtt = (K.pt * K.pt) * K.ie;
+                K.wtp = ((2.0f * K.pt) * K.pph) * K.ie;
+                K.wpp = (K.pph * K.pph) * K.ie;
+                const int f = start_flag(A.in, y);
+                if (f == RUNNING) {
+                    live = true;
+                } else {
+                    write_ray<T>(A.out, k, y, f, 0);
+                    want = true;
+                }
+            }
+        }
+        if (!__any(live || want)) break;
+        if (live) {
+            const double apr = fabs(y.pr);
+            if (!in64 && (y.r < X.r_enter || apr < PR_ENTER)) in64 = true;
+            else if (in64 && y.r > X.r_leave && apr > PR_LEAVE) in64 = false;
+            const double nu = in64 ? rk4_step(A.hole, A.in, y)
+                                   : rk4_step_mixed(A.hole, A.in, K, dtf, y);
+            ++s;
+            const int f = exit_flag(A.in, A.r_esc, y, nu, s);
+            if (f != RUNNING) {
+                write_ray<T>(A.out, k, y, f, s);
+                live = false;
+                want = true;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_trace_mixed(const FrameArgs& A, double r_plus, bool f32_out,
+                              const LaunchShape& L, unsigned long long* counter,
+                              hipStream_t s) {
+    MixedArgs X;
+    X.f = A;
+    X.r_enter = R64_ENTER * r_plus;
+    X.r_leave = R64_LEAVE * r_plus;
+    hipError_t e = launch_reset_counter(counter, s);
+    if (e != hipSuccess) return e;
+    if (f32_out)
+        hipLaunchKernelGGL(trace_mixed_refill<float>, dim3(L.grid), dim3(L.block), 0, s, X,
+                           counter);
+    else
+        hipLaunchKernelGGL(trace_mixed_refill<double>, dim3(L.grid), dim3(L.block), 0, s, X,
+                           counter);
+    return hipGetLastError();
+}
+
+int occupancy_trace_mixed(int block, bool f32_out) {
+    int n = 0;
+    hipError_t e = f32_out ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                 &n, trace_mixed_refill<float>, block, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                 &n, trace_mixed_refill<double>, block, 0);
+    return e == hipSuccess ? n : 0;
+}
+
+}  // namespace gr

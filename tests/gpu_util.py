@@ -71,3 +71,6 @@ def fp32_round(x):
 
 
 DEG = math.pi / 180.0
+
+
+from paper_2310_15183_amd.evaluate import mixed_errors, sky_at_escape  # noqa: E402,F401
