@@ -14,7 +14,7 @@ black-hole inputs of this configuration are binary32); state is binary64;
 end coordinates are stored as binary32 with an int8 flag.
 
 The roofline object reports the tracing kernel against the MI355X FP64
-vector peak: achieved = algorithmic flops per launch (881 per ray-step times
+vector peak: achieved = algorithmic flops per launch (693 per ray-step times
 the ray-steps of the launch, read from the kernel's own step counts) divided
 by the launch's duration measured with HIP events on the launch stream.
 """
@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "geodesic rays/s @1000² Kerr: FP64 vs mixed vs surrogate, ≤1e-4 rad err"
-FLOPS_PER_RAY_STEP = 881          # binary64 ops of one RK4 step (add/sub/mul/div 1, fma 2)
+FLOPS_PER_RAY_STEP = 693          # binary64 ops of one RK4 step (add/sub/mul/div 1, fma 2)
 FP64_PEAK_TFLOPS = 78.6           # MI355X FP64 vector (256 CU x 128 flop/clk x 2.4 GHz)
 KERNEL_SOURCES = ["paper_2310_15183_amd/csrc/trace_fp64.hip",
                   "paper_2310_15183_amd/csrc/step_fp64.h",

@@ -166,41 +166,43 @@ static void metric_at_point(const oracle_params *P, double r, double theta, doub
 
 /* Right-hand side of Hamilton's equations at one RK4 stage point.
  * Paper eq. hamGeodesic with the factor 1/2 of Appendix A; derivatives by
- * forward differences of step eps as in the listing (metric evaluated at
- * (r,theta), (r+eps,theta) and (r,theta+eps)).  The difference quotient is
- * formed by multiplying with 1/eps (for eps = 1e-8 that reciprocal is exactly
- * 1e8 in binary64).  The contraction sums the five nonzero terms in the order
- * tt, t-phi (counted twice via the weight 2 p_t p_phi), rr, theta-theta,
- * phi-phi. */
-static void hamilton_rhs(const oracle_params *P, double inv_eps,
-                         double r, double theta, double pt, double pr,
-                         double pth, double pph, double qdot[4], double pdot[2])
+ * forward differences of step eps as in the listing: the metric at (r,theta),
+ * (r+eps,theta) and (r,theta+eps).  sin and cos at theta+eps are the
+ * angle-addition identity applied to those at theta and at eps (for eps =
+ * 1e-8, cos eps rounds to 1 and sin eps to eps), so the theta step is eps
+ * itself.  The contraction sums the differences of the five independent
+ * components times p_nu p_sigma in the order tt, t-phi (weight 2 p_t p_phi),
+ * rr, theta-theta, phi-phi, then scales once by -1/(2 eps). */
+static void hamilton_rhs(const oracle_params *P, const double eps_sc[2], double r,
+                         double theta, double pt, double pr, double pth, double pph,
+                         double qdot[4], double pdot[2])
 {
-    double g[5], gr[5], gth[5], dR[5], dT[5];
-    metric_at_point(P, r, theta, g);
-    metric_at_point(P, r + P->eps, theta, gr);
-    metric_at_point(P, r, theta + P->eps, gth);
-    for (int k = 0; k < 5; ++k) {
-        dR[k] = (gr[k] - g[k]) * inv_eps;
-        dT[k] = (gth[k] - g[k]) * inv_eps;
-    }
+    double s, c, g[5], gr[5], gth[5];
+    sincos_mode(P->trig_mode, theta, &s, &c);
+    inverse_metric(P, r, s * s, c * c, g);
+    inverse_metric(P, r + P->eps, s * s, c * c, gr);
+    const double se = fma(c, eps_sc[0], s * eps_sc[1]);      /* sin(theta + eps) */
+    const double ce = fma(-s, eps_sc[0], c * eps_sc[1]);     /* cos(theta + eps) */
+    inverse_metric(P, r, se * se, ce * ce, gth);
+
     /* weights p_nu p_sigma of the five independent components */
     const double wtt = pt * pt, wtp = (2.0 * pt) * pph, wpp = pph * pph;
     const double wrr = pr * pr, wth = pth * pth;
+    const double scale = -0.5 * (1.0 / P->eps);                /* -1/(2 eps) */
 
-    double acc = dR[0] * wtt;
-    acc = fma(dR[1], wtp, acc);
-    acc = fma(dR[2], wrr, acc);
-    acc = fma(dR[3], wth, acc);
-    acc = fma(dR[4], wpp, acc);
-    pdot[0] = -0.5 * acc;                                      /* dp_r/dtau */
+    double acc = (gr[0] - g[0]) * wtt;
+    acc = fma(gr[1] - g[1], wtp, acc);
+    acc = fma(gr[2] - g[2], wrr, acc);
+    acc = fma(gr[3] - g[3], wth, acc);
+    acc = fma(gr[4] - g[4], wpp, acc);
+    pdot[0] = acc * scale;                                     /* dp_r/dtau */
 
-    acc = dT[0] * wtt;
-    acc = fma(dT[1], wtp, acc);
-    acc = fma(dT[2], wrr, acc);
-    acc = fma(dT[3], wth, acc);
-    acc = fma(dT[4], wpp, acc);
-    pdot[1] = -0.5 * acc;                                      /* dp_theta/dtau */
+    acc = (gth[0] - g[0]) * wtt;
+    acc = fma(gth[1] - g[1], wtp, acc);
+    acc = fma(gth[2] - g[2], wrr, acc);
+    acc = fma(gth[3] - g[3], wth, acc);
+    acc = fma(gth[4] - g[4], wpp, acc);
+    pdot[1] = acc * scale;                                     /* dp_theta/dtau */
 
     qdot[0] = fma(g[0], pt, g[1] * pph);                       /* dt/dtau */
     qdot[1] = g[2] * pr;                                       /* dr/dtau */
@@ -220,7 +222,8 @@ static int all_finite(const double q[4], double pr, double pth)
  * (RK4 weights 1/6, 2/6, 2/6, 1/6), Sec. 3.3.2 "Propagation". */
 int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nsteps)
 {
-    const double inv_eps = 1.0 / P->eps;
+    double eps_sc[2];                                          /* sin eps, cos eps */
+    sincos_mode(P->trig_mode, P->eps, &eps_sc[0], &eps_sc[1]);
     const double r_esc = P->escape_factor * q[1];
     const double pt = p[0], pph = p[3];
     double pr = p[1], pth = p[2];
@@ -232,16 +235,16 @@ int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nste
     for (s = 1; s <= P->max_steps; ++s) {
         double k1q[4], k1p[2], k2q[4], k2p[2], k3q[4], k3p[2], k4q[4], k4p[2];
         /* K1 at the current point; its dt/dtau fixes the step. */
-        hamilton_rhs(P, inv_eps, q[1], q[2], pt, pr, pth, pph, k1q, k1p);
+        hamilton_rhs(P, eps_sc, q[1], q[2], pt, pr, pth, pph, k1q, k1p);
         const double nu = fabs(k1q[0]);
         const double h = P->dt / nu;
         const double hh = 0.5 * h;
         /* K2, K3 at half steps, K4 at the full step. */
-        hamilton_rhs(P, inv_eps, fma(hh, k1q[1], q[1]), fma(hh, k1q[2], q[2]), pt,
+        hamilton_rhs(P, eps_sc, fma(hh, k1q[1], q[1]), fma(hh, k1q[2], q[2]), pt,
                      fma(hh, k1p[0], pr), fma(hh, k1p[1], pth), pph, k2q, k2p);
-        hamilton_rhs(P, inv_eps, fma(hh, k2q[1], q[1]), fma(hh, k2q[2], q[2]), pt,
+        hamilton_rhs(P, eps_sc, fma(hh, k2q[1], q[1]), fma(hh, k2q[2], q[2]), pt,
                      fma(hh, k2p[0], pr), fma(hh, k2p[1], pth), pph, k3q, k3p);
-        hamilton_rhs(P, inv_eps, fma(h, k3q[1], q[1]), fma(h, k3q[2], q[2]), pt,
+        hamilton_rhs(P, eps_sc, fma(h, k3q[1], q[1]), fma(h, k3q[2], q[2]), pt,
                      fma(h, k3p[0], pr), fma(h, k3p[1], pth), pph, k4q, k4p);
         /* x += h/6 (k1 + 2 k2 + 2 k3 + k4) */
         const double h6 = h * (1.0 / 6.0);
@@ -487,5 +490,7 @@ void oracle_rhs(double M, double a, double Q, double eps, double r, double theta
                 double pt, double pr, double pth, double pph, double *qdot, double *pdot)
 {
     oracle_params P = make_params(M, a, Q, 0.01, eps, 1e4, 1.5, 1);
-    hamilton_rhs(&P, 1.0 / eps, r, theta, pt, pr, pth, pph, qdot, pdot);
+    double eps_sc[2];
+    sincos_mode(P.trig_mode, eps, &eps_sc[0], &eps_sc[1]);
+    hamilton_rhs(&P, eps_sc, r, theta, pt, pr, pth, pph, qdot, pdot);
 }

@@ -141,6 +141,8 @@ gr::Integrator device_integrator(const gr_integrator& in) {
     I.dt = in.dt;
     I.eps = in.fd_eps;
     I.inv_eps = 1.0 / in.fd_eps;
+    gr::sincos_def(in.fd_eps, I.sin_eps, I.cos_eps);
+    I.scale = -0.5 * (1.0 / in.fd_eps);
     I.hnorm = in.horizon_norm;
     I.esc_factor = in.escape_factor;
     I.max_steps = in.max_steps;

@@ -92,15 +92,19 @@ struct ThetaTerms {
     double s2, c2, is2, w;     // sin^2, cos^2, 1/sin^2, a^2 sin^2
 };
 
-GR_HD ThetaTerms theta_terms(const Hole& H, double theta) {
-    double s, c;
-    sincos_def(theta, s, c);
+GR_HD ThetaTerms theta_terms_sc(const Hole& H, double s, double c) {
     ThetaTerms T;
     T.s2 = s * s;
     T.c2 = c * c;
     T.is2 = 1.0 / T.s2;
     T.w = H.a2 * T.s2;
     return T;
+}
+
+GR_HD ThetaTerms theta_terms(const Hole& H, double theta) {
+    double s, c;
+    sincos_def(theta, s, c);
+    return theta_terms_sc(H, s, c);
 }
 
 // Terms that depend on r only.

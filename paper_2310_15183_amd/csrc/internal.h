@@ -26,6 +26,8 @@ struct OutPtrs {
 
 struct Integrator {
     double dt, eps, inv_eps, hnorm, esc_factor;
+    double sin_eps, cos_eps;   // sincos_def(eps): angle addition for theta + eps
+    double scale;              // -0.5 * (1/eps): p-dot = scale * sum of differences
     int32_t max_steps;
 };
 

@@ -15,34 +15,38 @@ struct Deriv {
     double pr, ph;           // dp_r/dtau, dp_theta/dtau
 };
 
-// Right-hand side at one stage point: metric at (r, th), (r+eps, th),
-// (r, th+eps); difference quotients times 1/eps; p-dot = -1/2 sum of the five
-// independent terms in the order tt, tphi (weight 2 p_t p_phi), rr, thth, phph.
-static __device__ __forceinline__ Deriv rhs(const Hole& H, double eps, double inv_eps, double r,
-                                     double th, double pt, double pr, double pth, double pph,
-                                     double wtt, double wtp, double wpp) {
-    const ThetaTerms T0 = theta_terms(H, th);
-    const ThetaTerms T1 = theta_terms(H, th + eps);
+// Right-hand side at one stage point: metric at (r, th), (r+eps, th) and
+// (r, th+eps), sin/cos at th+eps by angle addition from those at th and eps;
+// p-dot = -1/(2 eps) times the sum of the five component differences times
+// p_nu p_sigma, in the order tt, tphi (weight 2 p_t p_phi), rr, thth, phph.
+static __device__ __forceinline__ Deriv rhs(const Hole& H, const Integrator& in, double r,
+                                            double th, double pt, double pr, double pth,
+                                            double pph, double wtt, double wtp, double wpp) {
+    double s, c;
+    sincos_def(th, s, c);
+    const ThetaTerms T0 = theta_terms_sc(H, s, c);
+    const ThetaTerms T1 = theta_terms_sc(H, fma(c, in.sin_eps, s * in.cos_eps),
+                                         fma(-s, in.sin_eps, c * in.cos_eps));
     const RadialTerms R0 = radial_terms(H, r);
-    const RadialTerms R1 = radial_terms(H, r + eps);
+    const RadialTerms R1 = radial_terms(H, r + in.eps);
     const InvMetric g = inverse_metric(H, R0, T0);
     const InvMetric gr = inverse_metric(H, R1, T0);
     const InvMetric gh = inverse_metric(H, R0, T1);
 
     const double wrr = pr * pr, wth = pth * pth;
-    double acc = ((gr.tt - g.tt) * inv_eps) * wtt;
-    acc = fma((gr.tp - g.tp) * inv_eps, wtp, acc);
-    acc = fma((gr.rr - g.rr) * inv_eps, wrr, acc);
-    acc = fma((gr.hh - g.hh) * inv_eps, wth, acc);
-    acc = fma((gr.pp - g.pp) * inv_eps, wpp, acc);
+    double acc = (gr.tt - g.tt) * wtt;
+    acc = fma(gr.tp - g.tp, wtp, acc);
+    acc = fma(gr.rr - g.rr, wrr, acc);
+    acc = fma(gr.hh - g.hh, wth, acc);
+    acc = fma(gr.pp - g.pp, wpp, acc);
     Deriv d;
-    d.pr = -0.5 * acc;
-    acc = ((gh.tt - g.tt) * inv_eps) * wtt;
-    acc = fma((gh.tp - g.tp) * inv_eps, wtp, acc);
-    acc = fma((gh.rr - g.rr) * inv_eps, wrr, acc);
-    acc = fma((gh.hh - g.hh) * inv_eps, wth, acc);
-    acc = fma((gh.pp - g.pp) * inv_eps, wpp, acc);
-    d.ph = -0.5 * acc;
+    d.pr = acc * in.scale;
+    acc = (gh.tt - g.tt) * wtt;
+    acc = fma(gh.tp - g.tp, wtp, acc);
+    acc = fma(gh.rr - g.rr, wrr, acc);
+    acc = fma(gh.hh - g.hh, wth, acc);
+    acc = fma(gh.pp - g.pp, wpp, acc);
+    d.ph = acc * in.scale;
 
     d.qt = fma(g.tt, pt, g.tp * pph);
     d.qr = g.rr * pr;
@@ -75,21 +79,20 @@ static __device__ __forceinline__ bool finite6(const Ray& y) {
 
 // One RK4 step; returns nu = |dt/dtau| of the first stage.
 static __device__ __forceinline__ double rk4_step(const Hole& H, const Integrator& in, Ray& y) {
-    const double eps = in.eps, inv_eps = in.inv_eps;
-    Deriv k = rhs(H, eps, inv_eps, y.r, y.th, y.pt, y.pr, y.pth, y.pph, y.wtt, y.wtp, y.wpp);
+    Deriv k = rhs(H, in, y.r, y.th, y.pt, y.pr, y.pth, y.pph, y.wtt, y.wtp, y.wpp);
     const double nu = fabs(k.qt);
     const double h = in.dt / nu;
     const double hh = 0.5 * h;
     double st = k.qt, sr = k.qr, sh = k.qh, sp = k.qp, spr = k.pr, sph = k.ph;
-    k = rhs(H, eps, inv_eps, fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), y.pt,
+    k = rhs(H, in, fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), y.pt,
             fma(hh, k.pr, y.pr), fma(hh, k.ph, y.pth), y.pph, y.wtt, y.wtp, y.wpp);
     st = st + 2.0 * k.qt; sr = sr + 2.0 * k.qr; sh = sh + 2.0 * k.qh; sp = sp + 2.0 * k.qp;
     spr = spr + 2.0 * k.pr; sph = sph + 2.0 * k.ph;
-    k = rhs(H, eps, inv_eps, fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), y.pt,
+    k = rhs(H, in, fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), y.pt,
             fma(hh, k.pr, y.pr), fma(hh, k.ph, y.pth), y.pph, y.wtt, y.wtp, y.wpp);
     st = st + 2.0 * k.qt; sr = sr + 2.0 * k.qr; sh = sh + 2.0 * k.qh; sp = sp + 2.0 * k.qp;
     spr = spr + 2.0 * k.pr; sph = sph + 2.0 * k.ph;
-    k = rhs(H, eps, inv_eps, fma(h, k.qr, y.r), fma(h, k.qh, y.th), y.pt,
+    k = rhs(H, in, fma(h, k.qr, y.r), fma(h, k.qh, y.th), y.pt,
             fma(h, k.pr, y.pr), fma(h, k.ph, y.pth), y.pph, y.wtt, y.wtp, y.wpp);
     st = st + k.qt; sr = sr + k.qr; sh = sh + k.qh; sp = sp + k.qp;
     spr = spr + k.pr; sph = sph + k.ph;
