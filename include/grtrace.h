@@ -187,6 +187,90 @@ int gr_trace_get_launch(const gr_ctx *ctx, gr_launch *launch);
 int gr_trace_autotune(gr_ctx *ctx, const gr_instance *inst, int32_t n, int32_t trial_steps,
                       const char *cache_path, gr_launch *best, void *hip_stream);
 
+/* ------------------------------------------------------------------------ */
+/* Learned surrogate (a network trained on rays the tracer itself produced).
+ *
+ * Network: 7 inputs -> 4 hidden layers of 256 with SiLU -> 4 outputs, with
+ * bfloat16 weights and activations on the matrix cores and binary32
+ * accumulation.  Inputs of a ray: pixel angles atan(x), atan(y) of its
+ * image-plane coordinates, a/M, |Q|/M, theta0, r0/(50 M), fov (M taken as 1
+ * for flat space).  Outputs: an escape logit and a correction d of the end
+ * sky direction: the ray is predicted to escape when the logit is positive,
+ * towards normalise(u_flat + d), where u_flat is the unit vector of the point
+ * where the camera ray's straight line (flat space) leaves the escape sphere
+ * r = escape_factor * r0.  Parameters are one packed binary32 vector: for each
+ * layer, W (in x out, row-major) then b (out).  Loss of a batch of n rays with
+ * targets (escaped, d): mean of softplus(y0) - escaped*y0 +
+ * lam*escaped*|y[1:4] - d|^2.  All array arguments are device pointers unless
+ * named host_*; calls are asynchronous on the stream unless stated. */
+typedef struct gr_mlp gr_mlp;
+
+/* Number of binary32 values in the packed parameter vector (200,452). */
+int64_t gr_mlp_num_params(void);
+
+/* Create a network on `device` with workspace for max_batch rows per pass
+ * (32 <= max_batch <= 2^28; about 7.4 KB per row).  Parameters start unset:
+ * call gr_mlp_init or gr_mlp_set_params.  Errors: GR_EINVAL, GR_ENOMEM. */
+int gr_mlp_create(gr_mlp **mlp, int device, int64_t max_batch);
+int gr_mlp_destroy(gr_mlp *mlp);
+
+/* He-uniform weights (bound sqrt(6/fan_in), SplitMix64 stream from seed),
+ * zero biases; resets the optimiser.  Synchronous. */
+int gr_mlp_init(gr_mlp *mlp, uint64_t seed);
+
+/* Copy the packed parameters from / to host memory (gr_mlp_num_params
+ * floats); set resets the optimiser.  Synchronous. */
+int gr_mlp_set_params(gr_mlp *mlp, const float *host_params);
+int gr_mlp_get_params(const gr_mlp *mlp, float *host_params);
+
+/* y (n x 4) = network(x (n x 7)), in chunks of max_batch rows. */
+int gr_mlp_forward(gr_mlp *mlp, const float *x, int64_t n, float *y, void *hip_stream);
+
+/* Loss (written to *loss, a device float; may be NULL) and its gradient
+ * (grad, gr_mlp_num_params floats, overwritten) over n rows, n a multiple of
+ * 32 and <= max_batch.  rows (may be NULL) gathers row rows[i] of x (n_src x
+ * 7) and target (n_src x 4); rows outside [0, n_src) read as zeros.  lam >= 0
+ * weights the direction term. */
+int gr_mlp_loss_grad(gr_mlp *mlp, const float *x, const float *target, const int32_t *rows,
+                     int64_t n, int64_t n_src, float lam, float *loss, float *grad,
+                     void *hip_stream);
+
+/* One Adam step (Kingma and Ba, bias-corrected) on the binary32 master
+ * parameters with the given gradient; refreshes the bfloat16 copies. */
+int gr_mlp_adam_step(gr_mlp *mlp, const float *grad, float lr, float beta1, float beta2,
+                     float eps, void *hip_stream);
+
+/* Adam steps taken since the last init/set. */
+int64_t gr_mlp_steps(const gr_mlp *mlp);
+
+/* Network inputs x (total x 7) and straight-line directions u_flat (total x
+ * 3) of the rays of a batch, enumerated like gr_trace_batch with instances in
+ * the order given (frame order or pixel-list order).  Outputs of the
+ * instances are not used. */
+int gr_surrogate_inputs(gr_ctx *ctx, const gr_instance *inst, int32_t n, float *x,
+                        float *u_flat, void *hip_stream);
+
+/* Training targets (total x 4: escaped 0/1, d = u - u_flat) from the traced
+ * outputs of the same instances (theta, phi, r and all four momenta required,
+ * binary64 or binary32); u is where the traced ray crossed the escape sphere,
+ * its end state moved back along its own velocity. */
+int gr_surrogate_targets(gr_ctx *ctx, const gr_instance *inst, int32_t n, const float *u_flat,
+                         float *target, void *hip_stream);
+
+/* Surrogate frame with RK4 fallback.  Every pixel gets the network's class
+ * (flag: GR_FLAG_ESCAPE or GR_FLAG_HORIZON) and end direction (dir, 3 floats,
+ * zero unless escaped).  A pixel falls back (fallback[p] = 1) when |logit| <
+ * logit_min or a pixel within Chebyshev distance edge_px has the other class;
+ * fallback pixels are re-traced by the context's binary64 tracer and their
+ * traced flag and escape-sphere direction replace the network's.  *n_fallback
+ * (host, may be NULL) receives their number.  Workspace (about 120 B per
+ * pixel) is kept in the context.  Blocks the calling thread once, to read the
+ * fallback count.  Errors: GR_EINVAL (also for networks on another device),
+ * GR_EUNSUPPORTED (context not GR_FP64), GR_ENOMEM. */
+int gr_surrogate_frame(gr_ctx *ctx, gr_mlp *mlp, const gr_metric *m, const gr_camera *c,
+                       float logit_min, int32_t edge_px, int8_t *flag, float *dir,
+                       int8_t *fallback, int64_t *n_fallback, void *hip_stream);
+
 /* Free the context (waits for nothing: the caller synchronises its streams
  * first).  NULL is accepted. */
 int gr_trace_destroy(gr_ctx *ctx);

@@ -83,6 +83,23 @@ def _load():
         "gr_horizon_radius": (ctypes.c_double, [P(gr_metric)]),
         "gr_trace_validate": (ctypes.c_int, [P(gr_metric), P(gr_camera), P(gr_integrator),
                                              P(gr_output)]),
+        "gr_mlp_num_params": (ctypes.c_int64, []),
+        "gr_mlp_create": (ctypes.c_int, [P(vp), ctypes.c_int, ctypes.c_int64]),
+        "gr_mlp_destroy": (ctypes.c_int, [vp]),
+        "gr_mlp_init": (ctypes.c_int, [vp, ctypes.c_uint64]),
+        "gr_mlp_set_params": (ctypes.c_int, [vp, vp]),
+        "gr_mlp_get_params": (ctypes.c_int, [vp, vp]),
+        "gr_mlp_forward": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp, vp]),
+        "gr_mlp_loss_grad": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_int64,
+                                            ctypes.c_float, vp, vp, vp]),
+        "gr_mlp_adam_step": (ctypes.c_int, [vp, vp, ctypes.c_float, ctypes.c_float,
+                                            ctypes.c_float, ctypes.c_float, vp]),
+        "gr_mlp_steps": (ctypes.c_int64, [vp]),
+        "gr_surrogate_inputs": (ctypes.c_int, [vp, P(gr_instance), ctypes.c_int32, vp, vp, vp]),
+        "gr_surrogate_targets": (ctypes.c_int, [vp, P(gr_instance), ctypes.c_int32, vp, vp, vp]),
+        "gr_surrogate_frame": (ctypes.c_int, [vp, vp, P(gr_metric), P(gr_camera), ctypes.c_float,
+                                              ctypes.c_int32, vp, vp, vp,
+                                              P(ctypes.c_int64), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -95,7 +112,10 @@ _lib = _load()
 EXPORTED = ["gr_trace_init", "gr_trace_frame", "gr_trace_batch", "gr_trace_set_integrator",
             "gr_trace_set_launch", "gr_trace_get_launch", "gr_trace_autotune", "gr_trace_destroy",
             "gr_trace_strerror", "gr_trace_last_device_error", "gr_horizon_radius",
-            "gr_trace_validate"]
+            "gr_trace_validate", "gr_mlp_num_params", "gr_mlp_create", "gr_mlp_destroy",
+            "gr_mlp_init", "gr_mlp_set_params", "gr_mlp_get_params", "gr_mlp_forward",
+            "gr_mlp_loss_grad", "gr_mlp_adam_step", "gr_mlp_steps", "gr_surrogate_inputs",
+            "gr_surrogate_targets", "gr_surrogate_frame"]
 
 
 class GrError(RuntimeError):
@@ -224,3 +244,84 @@ def alloc_outputs(n: int, dtype=GR_F64, fields=("t", "r", "theta", "phi"), steps
     ptr = lambda k: ten[k].data_ptr() if k in ten else None  # noqa: E731
     st = gr_output(*(ptr(f) for f in FIELDS), ptr("flag"), ptr("steps"), int(dtype))
     return Outputs(ten, st)
+
+
+# ---------------------------------------------------------------- surrogate network
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def gr_mlp_num_params() -> int:
+    return int(_lib.gr_mlp_num_params())
+
+
+def gr_mlp_create(device: int = 0, max_batch: int = 65536):
+    m = ctypes.c_void_p()
+    _check(_lib.gr_mlp_create(ctypes.byref(m), int(device), int(max_batch)), "gr_mlp_create")
+    return m
+
+
+def gr_mlp_destroy(m):
+    _check(_lib.gr_mlp_destroy(m), "gr_mlp_destroy")
+
+
+def gr_mlp_init(m, seed: int):
+    _check(_lib.gr_mlp_init(m, int(seed)), "gr_mlp_init")
+
+
+def gr_mlp_set_params(m, host_params):
+    import numpy as np
+    arr = np.ascontiguousarray(host_params, dtype=np.float32)
+    assert arr.size == gr_mlp_num_params()
+    _check(_lib.gr_mlp_set_params(m, arr.ctypes.data_as(ctypes.c_void_p)), "gr_mlp_set_params")
+
+
+def gr_mlp_get_params(m):
+    import numpy as np
+    arr = np.empty(gr_mlp_num_params(), np.float32)
+    _check(_lib.gr_mlp_get_params(m, arr.ctypes.data_as(ctypes.c_void_p)), "gr_mlp_get_params")
+    return arr
+
+
+def gr_mlp_forward(m, x, y, stream=None):
+    """x: (n, 7) float32 cuda tensor, y: (n, 4) float32 cuda tensor."""
+    _check(_lib.gr_mlp_forward(m, _p(x), x.shape[0], _p(y), _stream_handle(stream)),
+           "gr_mlp_forward")
+
+
+def gr_mlp_loss_grad(m, x, target, grad, loss=None, rows=None, n=None, lam=100.0, stream=None):
+    n = int(rows.shape[0] if rows is not None else x.shape[0]) if n is None else int(n)
+    _check(_lib.gr_mlp_loss_grad(m, _p(x), _p(target), _p(rows), n, int(x.shape[0]),
+                                 float(lam), _p(loss), _p(grad), _stream_handle(stream)),
+           "gr_mlp_loss_grad")
+
+
+def gr_mlp_adam_step(m, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(_lib.gr_mlp_adam_step(m, _p(grad), float(lr), float(beta1), float(beta2),
+                                 float(eps), _stream_handle(stream)), "gr_mlp_adam_step")
+
+
+def gr_mlp_steps(m) -> int:
+    return int(_lib.gr_mlp_steps(m))
+
+
+def gr_surrogate_inputs(ctx, instances, x, u_flat, stream=None):
+    arr = (gr_instance * len(instances))(*instances)
+    _check(_lib.gr_surrogate_inputs(ctx, arr, len(instances), _p(x), _p(u_flat),
+                                    _stream_handle(stream)), "gr_surrogate_inputs")
+
+
+def gr_surrogate_targets(ctx, instances, u_flat, target, stream=None):
+    arr = (gr_instance * len(instances))(*instances)
+    _check(_lib.gr_surrogate_targets(ctx, arr, len(instances), _p(u_flat), _p(target),
+                                     _stream_handle(stream)), "gr_surrogate_targets")
+
+
+def gr_surrogate_frame(ctx, mlp, metric, camera, logit_min, edge_px, flag, direction, fallback,
+                       stream=None) -> int:
+    nfb = ctypes.c_int64(-1)
+    _check(_lib.gr_surrogate_frame(ctx, mlp, ctypes.byref(metric), ctypes.byref(camera),
+                                   float(logit_min), int(edge_px), _p(flag), _p(direction),
+                                   _p(fallback), ctypes.byref(nfb), _stream_handle(stream)),
+           "gr_surrogate_frame")
+    return int(nfb.value)

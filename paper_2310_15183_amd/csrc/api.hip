@@ -12,6 +12,10 @@
 
 #include "grtrace.h"
 #include "internal.h"
+#include "surrogate_internal.h"
+
+extern "C" int gr_mlp_forward(gr_mlp* m, const float* x, int64_t n, float* y, void* stream);
+int gr_mlp_device_of(const gr_mlp* m);
 
 struct gr_ctx {
     int device;
@@ -23,6 +27,15 @@ struct gr_ctx {
     gr::BatchInstance* table;         // batch instance table (device)
     int64_t* firsts;                  // batch prefix offsets (device)
     int64_t table_cap;                // instances the device table holds
+    // surrogate-frame workspace (grown on demand)
+    int64_t sw_cap;                   // pixels it holds
+    float* sw_x;                      // cap x 7 network inputs
+    float* sw_u;                      // cap x 3 straight-line directions
+    float* sw_y;                      // cap x 4 network outputs
+    int32_t* sw_list;                 // fallback pixel list
+    unsigned long long* sw_count;
+    double* sw_out[7];                // re-traced theta, phi, r, p_t, p_r, p_theta, p_phi
+    int8_t* sw_flag;                  // re-traced flags
 };
 
 namespace {
@@ -325,6 +338,54 @@ void cache_append(const char* path, const std::string& key, const gr_launch& l, 
     fclose(f);
 }
 
+int check_instance_geometry(const gr_instance* inst, int32_t n) {
+    if (!inst || n < 1) return GR_EINVAL;
+    for (int32_t k = 0; k < n; ++k) {
+        const gr_instance* I = &inst[k];
+        int rc = check_metric(&I->metric);
+        if (!rc) rc = check_camera(&I->metric, &I->camera);
+        if (rc) return rc;
+        if (I->n_pixels < -1) return GR_EINVAL;
+        if (I->n_pixels > 0 && !I->pixels) return GR_EINVAL;
+    }
+    return GR_OK;
+}
+
+void free_surrogate_ws(gr_ctx* c) {
+    hipFree(c->sw_x);
+    hipFree(c->sw_u);
+    hipFree(c->sw_y);
+    hipFree(c->sw_list);
+    hipFree(c->sw_count);
+    for (int k = 0; k < 7; ++k) hipFree(c->sw_out[k]);
+    hipFree(c->sw_flag);
+    c->sw_x = c->sw_u = c->sw_y = nullptr;
+    c->sw_list = nullptr;
+    c->sw_count = nullptr;
+    for (int k = 0; k < 7; ++k) c->sw_out[k] = nullptr;
+    c->sw_flag = nullptr;
+    c->sw_cap = 0;
+}
+
+int grow_surrogate_ws(gr_ctx* c, int64_t n) {
+    if (n <= c->sw_cap) return GR_OK;
+    hipDeviceSynchronize();
+    free_surrogate_ws(c);
+    bool ok = hipMalloc(&c->sw_x, n * 7 * sizeof(float)) == hipSuccess &&
+              hipMalloc(&c->sw_u, n * 3 * sizeof(float)) == hipSuccess &&
+              hipMalloc(&c->sw_y, n * 4 * sizeof(float)) == hipSuccess &&
+              hipMalloc(&c->sw_list, n * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&c->sw_count, sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc(&c->sw_flag, n) == hipSuccess;
+    for (int k = 0; k < 7 && ok; ++k) ok = hipMalloc(&c->sw_out[k], n * sizeof(double)) == hipSuccess;
+    if (!ok) {
+        free_surrogate_ws(c);
+        return GR_ENOMEM;
+    }
+    c->sw_cap = n;
+    return GR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -487,9 +548,112 @@ int gr_trace_autotune(gr_ctx* ctx, const gr_instance* inst, int32_t n, int32_t t
     return run_batch(ctx, inst, n, win, s);
 }
 
+int gr_surrogate_inputs(gr_ctx* ctx, const gr_instance* inst, int32_t n, float* x,
+                        float* u_flat, void* hip_stream) {
+    if (!ctx) return GR_EINVAL;
+    int rc = check_instance_geometry(inst, n);
+    if (rc) return rc;
+    int64_t total = 0;
+    for (int32_t k = 0; k < n; ++k) total += instance_rays(&inst[k]);
+    if (total > 0 && (!x || !u_flat)) return GR_EINVAL;
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    int32_t ninst = 0;
+    rc = upload_batch(ctx, inst, n, 0, s, &ninst, &total);
+    if (rc || total == 0) return rc;
+    hipError_t e = gr::sur::inputs(ctx->table, ctx->firsts, ninst, total, x, u_flat, s);
+    return e == hipSuccess ? GR_OK : device_error(e, "surrogate inputs");
+}
+
+int gr_surrogate_targets(gr_ctx* ctx, const gr_instance* inst, int32_t n, const float* u_flat,
+                         float* target, void* hip_stream) {
+    if (!ctx) return GR_EINVAL;
+    int rc = check_instance_geometry(inst, n);
+    if (rc) return rc;
+    int64_t total = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const gr_instance* I = &inst[k];
+        total += instance_rays(I);
+        if (instance_rays(I) == 0) continue;
+        const gr_output& o = I->out;
+        if (check_output(&o) || !o.theta || !o.phi || !o.r || !o.p_t || !o.p_r || !o.p_theta ||
+            !o.p_phi)
+            return GR_EINVAL;
+    }
+    if (total > 0 && (!u_flat || !target)) return GR_EINVAL;
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    int32_t ninst = 0;
+    rc = upload_batch(ctx, inst, n, 0, s, &ninst, &total);
+    if (rc || total == 0) return rc;
+    hipError_t e = gr::sur::targets(ctx->table, ctx->firsts, ninst, total, u_flat, target, s);
+    return e == hipSuccess ? GR_OK : device_error(e, "surrogate targets");
+}
+
+int gr_surrogate_frame(gr_ctx* ctx, gr_mlp* mlp, const gr_metric* m, const gr_camera* c,
+                       float logit_min, int32_t edge_px, int8_t* flag, float* dir,
+                       int8_t* fallback, int64_t* n_fallback, void* hip_stream) {
+    if (!ctx || !mlp || !flag || !dir || !fallback) return GR_EINVAL;
+    int rc = check_metric(m);
+    if (!rc) rc = check_camera(m, c);
+    if (rc) return rc;
+    if (!(logit_min >= 0.0f) || edge_px < 0 || edge_px > 16) return GR_EINVAL;
+    if (ctx->integ.precision != GR_FP64) return GR_EUNSUPPORTED;
+    if (gr_mlp_device_of(mlp) != ctx->device) return GR_EINVAL;
+    const int64_t npix = (int64_t)c->width * c->height;
+    if (npix > ((int64_t)1 << 31) - 1) return GR_EINVAL;
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    rc = grow_surrogate_ws(ctx, npix);
+    if (rc) return rc;
+    // 1. network inputs of every pixel, 2. network, 3. class and direction
+    gr_instance frame;
+    memset(&frame, 0, sizeof frame);
+    frame.metric = *m;
+    frame.camera = *c;
+    frame.n_pixels = -1;
+    int32_t ninst = 0;
+    int64_t total = 0;
+    rc = upload_batch(ctx, &frame, 1, 0, s, &ninst, &total);
+    if (rc) return rc;
+    hipError_t e = gr::sur::inputs(ctx->table, ctx->firsts, ninst, total, ctx->sw_x, ctx->sw_u, s);
+    if (e != hipSuccess) return device_error(e, "surrogate inputs");
+    rc = gr_mlp_forward(mlp, ctx->sw_x, npix, ctx->sw_y, hip_stream);
+    if (rc) return rc;
+    e = gr::sur::classify(ctx->sw_y, ctx->sw_u, npix, flag, dir, s);
+    if (e == hipSuccess)
+        e = gr::sur::fallback(ctx->sw_y, flag, c->width, c->height, logit_min, edge_px, fallback,
+                              ctx->sw_list, ctx->sw_count, s);
+    if (e != hipSuccess) return device_error(e, "surrogate fallback selection");
+    // 4. re-trace the fallback pixels with the binary64 tracer and merge
+    unsigned long long count = 0;
+    e = hipMemcpyAsync(&count, ctx->sw_count, sizeof count, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_error(e, "fallback count");
+    if (n_fallback) *n_fallback = (int64_t)count;
+    if (count == 0) return GR_OK;
+    gr_instance fb = frame;
+    fb.pixels = ctx->sw_list;
+    fb.n_pixels = (int64_t)count;
+    fb.out.theta = ctx->sw_out[0];
+    fb.out.phi = ctx->sw_out[1];
+    fb.out.r = ctx->sw_out[2];
+    fb.out.p_t = ctx->sw_out[3];
+    fb.out.p_r = ctx->sw_out[4];
+    fb.out.p_theta = ctx->sw_out[5];
+    fb.out.p_phi = ctx->sw_out[6];
+    fb.out.flag = ctx->sw_flag;
+    fb.out.dtype = GR_F64;
+    rc = run_batch(ctx, &fb, 1, effective_launch(ctx), s);
+    if (rc) return rc;
+    e = gr::sur::merge(ctx->table, ctx->sw_list, (int64_t)count, flag, dir, s);
+    return e == hipSuccess ? GR_OK : device_error(e, "fallback merge");
+}
+
 int gr_trace_destroy(gr_ctx* ctx) {
     if (!ctx) return GR_OK;
     DeviceGuard guard(ctx->device);
+    free_surrogate_ws(ctx);
     hipFree(ctx->counter);
     hipFree(ctx->table);
     hipFree(ctx->firsts);

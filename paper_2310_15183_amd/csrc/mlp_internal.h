@@ -1,0 +1,56 @@
+// Internal interface of the surrogate-network kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gr {
+namespace mlp {
+
+constexpr int IN = 7, IN_PAD = 32, HID = 256, OUT = 4, OUT_PAD = 32, NLAYER = 5;
+
+enum { EPI_F32 = 0, EPI_BIAS_F32 = 1, EPI_BIAS_SILU = 2, EPI_SILU_GRAD = 3 };
+
+// C = A B with strided bfloat16 operands and a fused epilogue (see mlp.hip).
+struct GemmArgs {
+    const __bf16* A;
+    int64_t sam, sak;
+    const __bf16* B;
+    int64_t sbk, sbn;
+    int64_t M, N, K;          // K a multiple of 32
+    int epi;
+    const float* bias;        // EPI_BIAS_*: bias[n]
+    float* outf;              // EPI_F32 / EPI_BIAS_F32 output
+    int64_t sof;
+    __bf16* outh;             // EPI_BIAS_SILU / EPI_SILU_GRAD output
+    int64_t soh;
+    float* zout;              // EPI_BIAS_SILU: pre-activation (may be null)
+    int64_t szo;
+    const float* zin;         // EPI_SILU_GRAD: pre-activation of the layer below
+    int64_t szi;
+};
+
+// One layer's parameters: offsets into the packed binary32 vector (W in x out
+// row-major, then b) and its padded device copies.
+struct Layer {
+    int in, out, in_pad, out_pad;
+    int64_t w_off, b_off;
+    __bf16* wf;     // out_pad x in_pad: forward operand B(k=in, n=out) at wf[n*in_pad + k]
+    __bf16* wb;     // in_pad x out_pad: backward operand B(k=out, n=in) at wb[n*out_pad + k]
+    float* bias;    // out_pad
+};
+
+hipError_t gemm(const GemmArgs& g, hipStream_t s);
+hipError_t pack(const float* params, const Layer& L, hipStream_t s);
+hipError_t inputs(const float* x, const int32_t* rows, int64_t n, int64_t n_src, __bf16* out,
+                  hipStream_t s);
+hipError_t loss(const float* y, const float* target, const int32_t* rows, int64_t n,
+                int64_t n_src, float lam, __bf16* dy, double* partial, float* loss_out,
+                hipStream_t s);
+hipError_t colsum(const __bf16* dz, int64_t nrows, int ld, int ncols, float* out, hipStream_t s);
+hipError_t adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t outputs(const float* y, int64_t n, float* out, hipStream_t s);
+
+}  // namespace mlp
+}  // namespace gr

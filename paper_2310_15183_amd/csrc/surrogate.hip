@@ -1,0 +1,229 @@
+// Per-ray kernels of the learned surrogate: network inputs, training targets,
+// and the frame pipeline (class and direction from the network, fallback
+// marking, merge of the rays re-traced with RK4).
+//
+// Inputs of a ray (7): pixel angles alpha = atan(x), beta = atan(y) of its
+// image-plane coordinates, a/M, |Q|/M, theta0, r0/(50 M), fov (M = 1 for flat
+// space).  The network's direction output is a correction d to u_flat, the
+// point where the straight line of the camera ray (flat space, spherical
+// coordinates) leaves the escape sphere r = escape_factor * r0, as a unit
+// vector; the end direction is normalise(u_flat + d).  Targets use the traced
+// ray's crossing of the same sphere (its end state moved back along its own
+// velocity to r_esc).
+#include "internal.h"
+#include "surrogate_internal.h"
+
+namespace gr {
+namespace sur {
+namespace {
+
+__device__ __forceinline__ int find_inst(const int64_t* firsts, int ninst, int64_t id) {
+    int lo = 0, hi = ninst;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (firsts[mid] <= id) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ void ray_inputs(const BatchInstance& I, int64_t pix, float* x, float* u) {
+    const Camera& C = I.cam;
+    const int64_t i = pix % C.W, j = pix / C.W;
+    const double xs = ((double)(2 * i + 1 - C.W) / (double)C.W) * C.tan_h;
+    const double ys = ((double)(C.H - 2 * j - 1) / (double)C.H) * C.tan_v;
+    const double M = 0.5 * I.hole.M2;
+    const double Mn = M > 0.0 ? M : 1.0;
+    x[0] = (float)atan(xs);
+    x[1] = (float)atan(ys);
+    x[2] = (float)(I.hole.a / Mn);
+    x[3] = (float)(sqrt(I.hole.Q2) / Mn);
+    x[4] = (float)C.th0;
+    x[5] = (float)(C.r0 / (50.0 * Mn));
+    x[6] = (float)(2.0 * atan(C.tan_h));
+    // straight line from the camera along its line of sight n = (-1, -y, x)
+    const double inv = 1.0 / sqrt(1.0 + xs * xs + ys * ys);
+    const double nr = -inv, nt = -ys * inv, np = xs * inv;
+    const double st = sin(C.th0), ct = cos(C.th0), sp = sin(C.ph0), cp = cos(C.ph0);
+    const double d0 = nr * st * cp + nt * ct * cp - np * sp;
+    const double d1 = nr * st * sp + nt * ct * sp + np * cp;
+    const double d2 = nr * ct - nt * st;
+    const double R = I.r_esc;
+    const double b = C.r0 * nr;                       // x0 . d
+    const double s = -b + sqrt(b * b - (C.r0 * C.r0 - R * R));
+    u[0] = (float)((C.r0 * st * cp + s * d0) / R);
+    u[1] = (float)((C.r0 * st * sp + s * d1) / R);
+    u[2] = (float)((C.r0 * ct + s * d2) / R);
+}
+
+template <typename T>
+__device__ __forceinline__ double rd(const void* p, int64_t k) {
+    return (double)reinterpret_cast<const T*>(p)[k];
+}
+
+// Unit vector where an escaped ray crossed r = r_esc.
+__device__ void escape_direction(const BatchInstance& I, int64_t k, float* u) {
+    const OutPtrs& o = I.out;
+    double th, ph, r, pt, pr, pth, pph;
+    if (I.f32) {
+        th = rd<float>(o.th, k); ph = rd<float>(o.ph, k); r = rd<float>(o.r, k);
+        pt = rd<float>(o.pt, k); pr = rd<float>(o.pr, k); pth = rd<float>(o.pth, k);
+        pph = rd<float>(o.pph, k);
+    } else {
+        th = rd<double>(o.th, k); ph = rd<double>(o.ph, k); r = rd<double>(o.r, k);
+        pt = rd<double>(o.pt, k); pr = rd<double>(o.pr, k); pth = rd<double>(o.pth, k);
+        pph = rd<double>(o.pph, k);
+    }
+    const Hole& H = I.hole;
+    const double s = sin(th), c = cos(th);
+    const double s2 = s * s, c2 = c * c;
+    const double rho2 = r * r + H.a2 * c2;
+    const double Delta = r * r - H.M2 * r + H.aq;
+    const double grr = Delta / rho2, ghh = 1.0 / rho2;
+    const double gtp = -H.a * (H.M2 * r - H.Q2) / (rho2 * Delta);
+    const double gpp = (Delta - H.a2 * s2) / (rho2 * Delta * s2);
+    const double lam = (I.r_esc - r) / (grr * pr);
+    const double thx = th + ghh * pth * lam;
+    const double phx = ph + (gtp * pt + gpp * pph) * lam;
+    u[0] = (float)(sin(thx) * cos(phx));
+    u[1] = (float)(sin(thx) * sin(phx));
+    u[2] = (float)cos(thx);
+}
+
+__global__ void inputs_kernel(const BatchInstance* __restrict__ inst,
+                              const int64_t* __restrict__ firsts, int ninst, int64_t total,
+                              float* __restrict__ x, float* __restrict__ uflat) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= total) return;
+    const int q = find_inst(firsts, ninst, id);
+    const BatchInstance& I = inst[q];
+    const int64_t k = id - firsts[q];
+    const int64_t pix = I.pixels ? (int64_t)I.pixels[k] : k;
+    ray_inputs(I, pix, x + id * 7, uflat + id * 3);
+}
+
+__global__ void targets_kernel(const BatchInstance* __restrict__ inst,
+                               const int64_t* __restrict__ firsts, int ninst, int64_t total,
+                               const float* __restrict__ uflat, float* __restrict__ target) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= total) return;
+    const int q = find_inst(firsts, ninst, id);
+    const BatchInstance& I = inst[q];
+    const int64_t k = id - firsts[q];
+    float* t = target + id * 4;
+    if (I.out.flag[k] == GR_FLAG_ESCAPE) {
+        float u[3];
+        escape_direction(I, k, u);
+        t[0] = 1.0f;
+        for (int c = 0; c < 3; ++c) t[1 + c] = u[c] - uflat[id * 3 + c];
+    } else {
+        t[0] = t[1] = t[2] = t[3] = 0.0f;
+    }
+}
+
+// Class and end direction of every pixel from the network output.
+__global__ void classify_kernel(const float* __restrict__ y, const float* __restrict__ uflat,
+                                int64_t n, int8_t* __restrict__ flag, float* __restrict__ dir) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const float* yi = y + p * 4;
+    const bool esc = yi[0] > 0.0f;
+    flag[p] = esc ? GR_FLAG_ESCAPE : GR_FLAG_HORIZON;
+    float u[3];
+    float nn = 0.0f;
+    for (int c = 0; c < 3; ++c) {
+        u[c] = uflat[p * 3 + c] + yi[1 + c];
+        nn += u[c] * u[c];
+    }
+    const float inv = esc && nn > 0.0f ? 1.0f / sqrtf(nn) : 0.0f;
+    for (int c = 0; c < 3; ++c) dir[p * 3 + c] = u[c] * inv;
+}
+
+// A pixel falls back to RK4 when its logit is small or a pixel within
+// Chebyshev distance `edge` has the other class; fallback pixels are appended
+// to list (order unspecified).
+__global__ void fallback_kernel(const float* __restrict__ y, const int8_t* __restrict__ flag,
+                                int32_t W, int32_t H, float logit_min, int32_t edge,
+                                int8_t* __restrict__ fb, int32_t* __restrict__ list,
+                                unsigned long long* __restrict__ count) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int64_t)W * H) return;
+    const int i = (int)(p % W), j = (int)(p / W);
+    bool f = fabsf(y[p * 4]) < logit_min;
+    const int8_t mine = flag[p];
+    for (int dj = -edge; dj <= edge && !f; ++dj) {
+        const int jj = j + dj;
+        if (jj < 0 || jj >= H) continue;
+        for (int di = -edge; di <= edge; ++di) {
+            const int ii = i + di;
+            if (ii < 0 || ii >= W) continue;
+            if (flag[(int64_t)jj * W + ii] != mine) {
+                f = true;
+                break;
+            }
+        }
+    }
+    fb[p] = f ? 1 : 0;
+    if (f) list[atomicAdd(count, 1ull)] = (int32_t)p;
+}
+
+// Results of the re-traced pixels replace the network's.
+__global__ void merge_kernel(const BatchInstance* __restrict__ inst, const int32_t* __restrict__ list,
+                             int64_t n, int8_t* __restrict__ flag, float* __restrict__ dir) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const BatchInstance& I = inst[0];
+    const int64_t p = list[k];
+    const int8_t f = I.out.flag[k];
+    flag[p] = f;
+    float u[3] = {0.f, 0.f, 0.f};
+    if (f == GR_FLAG_ESCAPE) escape_direction(I, k, u);
+    for (int c = 0; c < 3; ++c) dir[p * 3 + c] = u[c];
+}
+
+__global__ void zero_u64(unsigned long long* c) { *c = 0ull; }
+
+unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t inputs(const BatchInstance* inst, const int64_t* firsts, int ninst, int64_t total,
+                  float* x, float* uflat, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(inputs_kernel, dim3(blocks(total)), dim3(256), 0, s, inst, firsts, ninst,
+                       total, x, uflat);
+    return hipGetLastError();
+}
+
+hipError_t targets(const BatchInstance* inst, const int64_t* firsts, int ninst, int64_t total,
+                   const float* uflat, float* target, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(targets_kernel, dim3(blocks(total)), dim3(256), 0, s, inst, firsts, ninst,
+                       total, uflat, target);
+    return hipGetLastError();
+}
+
+hipError_t classify(const float* y, const float* uflat, int64_t n, int8_t* flag, float* dir,
+                    hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(classify_kernel, dim3(blocks(n)), dim3(256), 0, s, y, uflat, n, flag, dir);
+    return hipGetLastError();
+}
+
+hipError_t fallback(const float* y, const int8_t* flag, int32_t W, int32_t H, float logit_min,
+                    int32_t edge, int8_t* fb, int32_t* list, unsigned long long* count,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, count);
+    hipLaunchKernelGGL(fallback_kernel, dim3(blocks((int64_t)W * H)), dim3(256), 0, s, y, flag, W,
+                       H, logit_min, edge, fb, list, count);
+    return hipGetLastError();
+}
+
+hipError_t merge(const BatchInstance* inst, const int32_t* list, int64_t n, int8_t* flag,
+                 float* dir, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(merge_kernel, dim3(blocks(n)), dim3(256), 0, s, inst, list, n, flag, dir);
+    return hipGetLastError();
+}
+
+}  // namespace sur
+}  // namespace gr

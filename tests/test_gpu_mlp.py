@@ -1,0 +1,198 @@
+"""Surrogate network on the GPU against the CPU reference (oracle/mlp.py with
+the bfloat16 rounding points mirrored), and the surrogate data path."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp as ref
+from tests.gpu_util import DEG
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2310_15183_amd as g
+    return g
+
+
+@pytest.fixture()
+def net(g):
+    m = g.gr_mlp_create(0, 4096)
+    g.gr_mlp_init(m, 1234)
+    yield m
+    g.gr_mlp_destroy(m)
+
+
+def _t(a, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float32, device="cuda")
+
+
+def _batch(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(n, 7)).astype(np.float32)
+    t = np.zeros((n, 4), np.float32)
+    t[:, 0] = rng.integers(0, 2, n)
+    t[:, 1:] = rng.normal(scale=0.1, size=(n, 3))
+    return x, t
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def _cos(a, b):
+    return float(np.dot(a.ravel(), b.ravel()) / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+
+
+def test_param_count(g):
+    assert g.gr_mlp_num_params() == ref.num_params() == 200452
+
+
+def test_forward_matches_reference(g, net):
+    import torch
+    p = g.gr_mlp_get_params(net).astype(np.float64)
+    x, _ = _batch(333, 1)                          # not a multiple of the tile
+    y = torch.empty(333, 4, device="cuda")
+    g.gr_mlp_forward(net, _t(x), y)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().astype(np.float64)
+    want = ref.forward(p, x.astype(np.float64), bf16_mode=True)
+    assert _rel(got, want) < 1e-2 and _cos(got, want) > 0.9999
+
+
+def test_gradient_matches_reference(g, net):
+    import torch
+    # a trained-looking network: perturb the init so biases are not all zero
+    p = g.gr_mlp_get_params(net)
+    p = (p + np.random.default_rng(2).normal(scale=0.01, size=p.size)).astype(np.float32)
+    g.gr_mlp_set_params(net, p)
+    x, t = _batch(256, 3)
+    grad = torch.empty(g.gr_mlp_num_params(), device="cuda")
+    loss = torch.empty(1, device="cuda")
+    g.gr_mlp_loss_grad(net, _t(x), _t(t), grad, loss=loss, lam=10.0)
+    torch.cuda.synchronize()
+    L, gref = ref.loss_and_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64),
+                                lam=10.0, bf16_mode=True)
+    assert abs(loss.item() - L) <= 1e-3 * abs(L)
+    gg = grad.cpu().numpy().astype(np.float64)
+    o = 0
+    for a, b in zip(ref.SIZES[:-1], ref.SIZES[1:]):
+        for size in (a * b, b):
+            got, want = gg[o:o + size], gref[o:o + size]
+            o += size
+            assert _rel(got, want) < 1e-2 and _cos(got, want) > 0.9999, (a, b, size)
+
+
+def test_row_gather_equals_permuted_batch(g, net):
+    import torch
+    x, t = _batch(512, 4)
+    rows = np.random.default_rng(5).permutation(512)[:128].astype(np.int32)
+    g1 = torch.empty(g.gr_mlp_num_params(), device="cuda")
+    g2 = torch.empty_like(g1)
+    g.gr_mlp_loss_grad(net, _t(x), _t(t), g1, rows=_t(rows, torch.int32))
+    g.gr_mlp_loss_grad(net, _t(x[rows]), _t(t[rows]), g2)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
+
+
+def test_adam_step_matches_reference(g, net):
+    import torch
+    p0 = g.gr_mlp_get_params(net).astype(np.float64)
+    grad = np.random.default_rng(6).normal(size=p0.size).astype(np.float32)
+    g.gr_mlp_adam_step(net, _t(grad), lr=1e-3)
+    g.gr_mlp_adam_step(net, _t(grad * 0.5), lr=1e-3)
+    p = g.gr_mlp_get_params(net).astype(np.float64)
+    q, m, v = ref.adam_step(p0, grad.astype(np.float64), np.zeros_like(p0), np.zeros_like(p0), 1,
+                            1e-3)
+    q, m, v = ref.adam_step(q, 0.5 * grad.astype(np.float64), m, v, 2, 1e-3)
+    assert np.abs(p - q).max() < 1e-6
+    assert g.gr_mlp_steps(net) == 2
+
+
+def test_training_reduces_loss(g, net):
+    import torch
+    x, t = _batch(1024, 7)
+    t[:, 0] = (x[:, 0] + x[:, 1] > 0).astype(np.float32)        # a learnable rule
+    t[:, 1:] = 0.1 * np.tanh(x[:, 2:5])
+    grad = torch.empty(g.gr_mlp_num_params(), device="cuda")
+    loss = torch.empty(1, device="cuda")
+    X, T = _t(x), _t(t)
+    hist = []
+    for _ in range(300):
+        g.gr_mlp_loss_grad(net, X, T, grad, loss=loss, lam=100.0)
+        g.gr_mlp_adam_step(net, grad, lr=1e-3)
+        hist.append(loss.item())
+    assert hist[-1] < 0.1 * hist[0]
+
+
+def _flat_instance(g, W, H, out=None):
+    m = g.gr_metric(0.0, 0.0, 0.0)
+    c = g.gr_camera(20.0, 70 * DEG, 0.3, 75 * DEG, W, H)
+    return g.gr_instance(m, c, out if out is not None else g.gr_output(), None, -1)
+
+
+def test_surrogate_targets_vanish_in_flat_space(g):
+    """M = a = Q = 0: the traced ray is the straight line, so the direction
+    correction target is zero and every ray escapes."""
+    import torch
+    ctx = g.gr_trace_init(0, g.make_integrator(dt=0.01, max_steps=20000))
+    try:
+        W, H = 40, 30
+        out = g.alloc_outputs(W * H, fields=g.FIELDS)
+        inst = _flat_instance(g, W, H, out.struct)
+        g.gr_trace_batch(ctx, [inst])
+        x = torch.empty(W * H, 7, device="cuda")
+        u = torch.empty(W * H, 3, device="cuda")
+        t = torch.empty(W * H, 4, device="cuda")
+        g.gr_surrogate_inputs(ctx, [inst], x, u)
+        g.gr_surrogate_targets(ctx, [inst], u, t)
+        torch.cuda.synchronize()
+        t = t.cpu().numpy()
+        x = x.cpu().numpy()
+        assert np.all(t[:, 0] == 1.0)
+        assert np.abs(t[:, 1:]).max() < 2e-6                # binary32 of the unit vectors
+        assert np.allclose(np.linalg.norm(u.cpu().numpy(), axis=1), 1.0, atol=1e-6)
+        assert np.allclose(x[:, 4], 70 * DEG, atol=1e-6) and np.allclose(x[:, 6], 75 * DEG)
+    finally:
+        g.gr_trace_destroy(ctx)
+
+
+def test_surrogate_frame_full_fallback_equals_tracer(g):
+    """With every pixel sent to the fallback, the surrogate frame is the
+    binary64 tracer's frame."""
+    import torch
+
+    from paper_2310_15183_amd.evaluate import sky_at_escape, sky_direction
+    ctx = g.gr_trace_init(0, g.make_integrator(dt=0.01, max_steps=20000))
+    net = g.gr_mlp_create(0, 1024)
+    try:
+        g.gr_mlp_init(net, 7)
+        W, H = 48, 36
+        M, a, Q = 0.5, 0.3, 0.2
+        metric = g.gr_metric(M, a, Q)
+        cam = g.gr_camera(20.0, 75 * DEG, 0.0, 60 * DEG, W, H)
+        flag = torch.empty(W * H, dtype=torch.int8, device="cuda")
+        direc = torch.empty(W * H, 3, device="cuda")
+        fb = torch.empty(W * H, dtype=torch.int8, device="cuda")
+        nfb = g.gr_surrogate_frame(ctx, net, metric, cam, 1e30, 0, flag, direc, fb)
+        assert nfb == W * H
+        out = g.alloc_outputs(W * H, fields=g.FIELDS)
+        g.gr_trace_frame(ctx, metric, cam, out.struct)
+        torch.cuda.synchronize()
+        ref_res = {k: v.cpu().numpy() for k, v in out.tensors.items()}
+        np.testing.assert_array_equal(flag.cpu().numpy(), ref_res["flag"])
+        esc = ref_res["flag"] == g.GR_FLAG_ESCAPE
+        th, ph = sky_at_escape(M, a, Q, 30.0, {k: v[esc] for k, v in ref_res.items()})
+        want = sky_direction(th, ph)
+        got = direc.cpu().numpy()[esc]
+        assert np.abs(got - want).max() < 1e-5
+        # no fallback at all: the network's own classes
+        nfb0 = g.gr_surrogate_frame(ctx, net, metric, cam, 0.0, 0, flag, direc, fb)
+        torch.cuda.synchronize()
+        assert nfb0 == 0 and fb.cpu().numpy().sum() == 0
+    finally:
+        g.gr_mlp_destroy(net)
+        g.gr_trace_destroy(ctx)
