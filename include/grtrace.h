@@ -201,8 +201,9 @@ int gr_trace_autotune(gr_ctx *ctx, const gr_instance *inst, int32_t n, int32_t t
  * r = escape_factor * r0.  Parameters are one packed binary32 vector: for each
  * layer, W (in x out, row-major) then b (out).  Loss of a batch of n rays with
  * targets (escaped, d): mean of softplus(y0) - escaped*y0 +
- * lam*escaped*|y[1:4] - d|^2.  All array arguments are device pointers unless
- * named host_*; calls are asynchronous on the stream unless stated. */
+ * lam*escaped*sum_c huber(y[c] - d[c]), huber(e) = e^2 for |e| <= delta and
+ * 2 delta |e| - delta^2 beyond.  All array arguments are device pointers
+ * unless named host_*; calls are asynchronous on the stream unless stated. */
 typedef struct gr_mlp gr_mlp;
 
 /* Number of binary32 values in the packed parameter vector (200,452). */
@@ -230,9 +231,10 @@ int gr_mlp_forward(gr_mlp *mlp, const float *x, int64_t n, float *y, void *hip_s
  * (grad, gr_mlp_num_params floats, overwritten) over n rows, n a multiple of
  * 32 and <= max_batch.  rows (may be NULL) gathers row rows[i] of x (n_src x
  * 7) and target (n_src x 4); rows outside [0, n_src) read as zeros.  lam >= 0
- * weights the direction term. */
+ * weights the direction term, delta > 0 is its Huber threshold (a huge
+ * delta gives the squared error). */
 int gr_mlp_loss_grad(gr_mlp *mlp, const float *x, const float *target, const int32_t *rows,
-                     int64_t n, int64_t n_src, float lam, float *loss, float *grad,
+                     int64_t n, int64_t n_src, float lam, float delta, float *loss, float *grad,
                      void *hip_stream);
 
 /* One Adam step (Kingma and Ba, bias-corrected) on the binary32 master
@@ -259,12 +261,14 @@ int gr_surrogate_targets(gr_ctx *ctx, const gr_instance *inst, int32_t n, const 
 
 /* Surrogate frame with RK4 fallback.  Every pixel gets the network's class
  * (flag: GR_FLAG_ESCAPE or GR_FLAG_HORIZON) and end direction (dir, 3 floats,
- * zero unless escaped).  A pixel falls back (fallback[p] = 1) when |logit| <
- * logit_min or a pixel within Chebyshev distance edge_px has the other class;
- * fallback pixels are re-traced by the context's binary64 tracer and their
- * traced flag and escape-sphere direction replace the network's.  *n_fallback
- * (host, may be NULL) receives their number.  Workspace (about 120 B per
- * pixel) is kept in the context.  Blocks the calling thread once, to read the
+ * zero unless escaped), computed for the whole frame in one fused launch
+ * (inputs, the five layers, classification) with the same bfloat16 products
+ * and binary32 sums as gr_mlp_forward.  A pixel falls back (fallback[p] = 1)
+ * when |logit| < logit_min or a pixel within Chebyshev distance edge_px has
+ * the other class; fallback pixels are re-traced by the context's binary64
+ * tracer and their traced flag and escape-sphere direction replace the
+ * network's.  *n_fallback (host, may be NULL) receives their number.
+ * Workspace (about 65 B per pixel) is kept in the context.  Blocks the calling thread once, to read the
  * fallback count.  Errors: GR_EINVAL (also for networks on another device),
  * GR_EUNSUPPORTED (context not GR_FP64), GR_ENOMEM. */
 int gr_surrogate_frame(gr_ctx *ctx, gr_mlp *mlp, const gr_metric *m, const gr_camera *c,

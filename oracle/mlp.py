@@ -9,9 +9,11 @@ one packed float vector: for each layer, W (in x out, row-major) then b (out).
 
 Loss over a batch of n rays with targets (escaped, d_x, d_y, d_z):
     L = (1/n) sum [ softplus(y0) - escaped * y0
-                    + lam * escaped * |y[1:4] - d|^2 ]
-(binary cross-entropy with logits for the class; squared error of the
-direction correction on escaped rays only).
+                    + lam * escaped * sum_c huber(y[c] - d[c]) ]
+with huber(e) = e^2 for |e| <= delta and 2 delta |e| - delta^2 beyond
+(binary cross-entropy with logits for the class; a squared error of the
+direction correction that grows only linearly for outliers, on escaped rays
+only; delta = inf gives the plain squared error).
 
 bf16=True rounds, like the GPU kernels, the weights, every layer's input
 activations and the activation gradients fed to the backward products to
@@ -19,7 +21,8 @@ bfloat16 (round to nearest even); sums stay exact-ish (binary64 here, binary32
 on the GPU).
 
 Parity status: pinned by a central-difference gradient check (binary64, no
-rounding) and by the closed-form gradient of a one-layer case in the tests.
+rounding), closed-form loss values and gradients of an all-zero network, and
+Adam's closed-form first step.
 """
 from __future__ import annotations
 
@@ -79,7 +82,20 @@ def forward(params, x, bf16_mode=False, keep=False):
     return (h, cache) if keep else h
 
 
-def loss_and_grad(params, x, target, lam=100.0, bf16_mode=False):
+def huber(e, delta):
+    if not np.isfinite(delta):
+        return e * e
+    a = np.abs(e)
+    return np.where(a <= delta, e * e, 2.0 * delta * a - delta * delta)
+
+
+def huber_grad(e, delta):
+    if not np.isfinite(delta):
+        return 2.0 * e
+    return np.where(np.abs(e) <= delta, 2.0 * e, 2.0 * delta * np.sign(e))
+
+
+def loss_and_grad(params, x, target, lam=100.0, bf16_mode=False, delta=np.inf):
     """Mean loss over the batch and its gradient w.r.t. the packed params."""
     params = np.asarray(params, np.float64)
     layers = unpack(params)
@@ -88,10 +104,11 @@ def loss_and_grad(params, x, target, lam=100.0, bf16_mode=False):
     esc = target[:, 0]
     d = target[:, 1:4]
     sp = np.logaddexp(0.0, y[:, 0])
-    L = np.sum(sp - esc * y[:, 0] + lam * esc * np.sum((y[:, 1:4] - d) ** 2, axis=1)) / n
+    e = y[:, 1:4] - d
+    L = np.sum(sp - esc * y[:, 0] + lam * esc * np.sum(huber(e, delta), axis=1)) / n
     dy = np.zeros_like(y)
     dy[:, 0] = (sigmoid(y[:, 0]) - esc) / n
-    dy[:, 1:4] = 2.0 * lam * esc[:, None] * (y[:, 1:4] - d) / n
+    dy[:, 1:4] = lam * esc[:, None] * huber_grad(e, delta) / n
     grads = []
     dz = dy
     for li in range(len(layers) - 1, -1, -1):

@@ -91,7 +91,7 @@ def _load():
         "gr_mlp_get_params": (ctypes.c_int, [vp, vp]),
         "gr_mlp_forward": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp, vp]),
         "gr_mlp_loss_grad": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_int64,
-                                            ctypes.c_float, vp, vp, vp]),
+                                            ctypes.c_float, ctypes.c_float, vp, vp, vp]),
         "gr_mlp_adam_step": (ctypes.c_int, [vp, vp, ctypes.c_float, ctypes.c_float,
                                             ctypes.c_float, ctypes.c_float, vp]),
         "gr_mlp_steps": (ctypes.c_int64, [vp]),
@@ -289,11 +289,12 @@ def gr_mlp_forward(m, x, y, stream=None):
            "gr_mlp_forward")
 
 
-def gr_mlp_loss_grad(m, x, target, grad, loss=None, rows=None, n=None, lam=100.0, stream=None):
+def gr_mlp_loss_grad(m, x, target, grad, loss=None, rows=None, n=None, lam=100.0, delta=1e30,
+                     stream=None):
     n = int(rows.shape[0] if rows is not None else x.shape[0]) if n is None else int(n)
     _check(_lib.gr_mlp_loss_grad(m, _p(x), _p(target), _p(rows), n, int(x.shape[0]),
-                                 float(lam), _p(loss), _p(grad), _stream_handle(stream)),
-           "gr_mlp_loss_grad")
+                                 float(lam), float(delta), _p(loss), _p(grad),
+                                 _stream_handle(stream)), "gr_mlp_loss_grad")
 
 
 def gr_mlp_adam_step(m, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

@@ -14,8 +14,8 @@
 #include "internal.h"
 #include "surrogate_internal.h"
 
-extern "C" int gr_mlp_forward(gr_mlp* m, const float* x, int64_t n, float* y, void* stream);
 int gr_mlp_device_of(const gr_mlp* m);
+gr::mlp::NetView gr_mlp_view(const gr_mlp* m);
 
 struct gr_ctx {
     int device;
@@ -29,9 +29,7 @@ struct gr_ctx {
     int64_t table_cap;                // instances the device table holds
     // surrogate-frame workspace (grown on demand)
     int64_t sw_cap;                   // pixels it holds
-    float* sw_x;                      // cap x 7 network inputs
-    float* sw_u;                      // cap x 3 straight-line directions
-    float* sw_y;                      // cap x 4 network outputs
+    float* sw_logit;                  // cap escape logits
     int32_t* sw_list;                 // fallback pixel list
     unsigned long long* sw_count;
     double* sw_out[7];                // re-traced theta, phi, r, p_t, p_r, p_theta, p_phi
@@ -352,14 +350,12 @@ int check_instance_geometry(const gr_instance* inst, int32_t n) {
 }
 
 void free_surrogate_ws(gr_ctx* c) {
-    hipFree(c->sw_x);
-    hipFree(c->sw_u);
-    hipFree(c->sw_y);
+    hipFree(c->sw_logit);
     hipFree(c->sw_list);
     hipFree(c->sw_count);
     for (int k = 0; k < 7; ++k) hipFree(c->sw_out[k]);
     hipFree(c->sw_flag);
-    c->sw_x = c->sw_u = c->sw_y = nullptr;
+    c->sw_logit = nullptr;
     c->sw_list = nullptr;
     c->sw_count = nullptr;
     for (int k = 0; k < 7; ++k) c->sw_out[k] = nullptr;
@@ -371,9 +367,7 @@ int grow_surrogate_ws(gr_ctx* c, int64_t n) {
     if (n <= c->sw_cap) return GR_OK;
     hipDeviceSynchronize();
     free_surrogate_ws(c);
-    bool ok = hipMalloc(&c->sw_x, n * 7 * sizeof(float)) == hipSuccess &&
-              hipMalloc(&c->sw_u, n * 3 * sizeof(float)) == hipSuccess &&
-              hipMalloc(&c->sw_y, n * 4 * sizeof(float)) == hipSuccess &&
+    bool ok = hipMalloc(&c->sw_logit, n * sizeof(float)) == hipSuccess &&
               hipMalloc(&c->sw_list, n * sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&c->sw_count, sizeof(unsigned long long)) == hipSuccess &&
               hipMalloc(&c->sw_flag, n) == hipSuccess;
@@ -606,26 +600,24 @@ int gr_surrogate_frame(gr_ctx* ctx, gr_mlp* mlp, const gr_metric* m, const gr_ca
     hipStream_t s = (hipStream_t)hip_stream;
     rc = grow_surrogate_ws(ctx, npix);
     if (rc) return rc;
-    // 1. network inputs of every pixel, 2. network, 3. class and direction
+    // 1. inputs, network, class and direction of every pixel in one launch
     gr_instance frame;
     memset(&frame, 0, sizeof frame);
     frame.metric = *m;
     frame.camera = *c;
     frame.n_pixels = -1;
-    int32_t ninst = 0;
-    int64_t total = 0;
-    rc = upload_batch(ctx, &frame, 1, 0, s, &ninst, &total);
-    if (rc) return rc;
-    hipError_t e = gr::sur::inputs(ctx->table, ctx->firsts, ninst, total, ctx->sw_x, ctx->sw_u, s);
-    if (e != hipSuccess) return device_error(e, "surrogate inputs");
-    rc = gr_mlp_forward(mlp, ctx->sw_x, npix, ctx->sw_y, hip_stream);
-    if (rc) return rc;
-    e = gr::sur::classify(ctx->sw_y, ctx->sw_u, npix, flag, dir, s);
-    if (e == hipSuccess)
-        e = gr::sur::fallback(ctx->sw_y, flag, c->width, c->height, logit_min, edge_px, fallback,
-                              ctx->sw_list, ctx->sw_count, s);
+    gr::BatchInstance I;
+    memset(&I, 0, sizeof I);
+    I.hole = gr::make_hole(m->M, m->a, m->Q);
+    I.cam = gr::make_camera(I.hole, c->r0, c->theta0, c->phi0, c->fov, c->width, c->height);
+    I.r_esc = ctx->integ.escape_factor * c->r0;
+    hipError_t e = gr::sur::frame_net(I, npix, gr_mlp_view(mlp), flag, dir, ctx->sw_logit, s);
+    if (e != hipSuccess) return device_error(e, "surrogate network");
+    // 2. pixels to re-trace: small logits and class edges
+    e = gr::sur::fallback(ctx->sw_logit, flag, c->width, c->height, logit_min, edge_px, fallback,
+                          ctx->sw_list, ctx->sw_count, s);
     if (e != hipSuccess) return device_error(e, "surrogate fallback selection");
-    // 4. re-trace the fallback pixels with the binary64 tracer and merge
+    // 3. re-trace the fallback pixels with the binary64 tracer and merge
     unsigned long long count = 0;
     e = hipMemcpyAsync(&count, ctx->sw_count, sizeof count, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

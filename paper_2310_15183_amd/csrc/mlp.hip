@@ -110,8 +110,12 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs g) {
         }
 }
 
-// Packed binary32 parameters -> padded bfloat16 weights in both orientations
-// and padded binary32 biases.
+// Packed binary32 parameters -> padded bfloat16 weights in both orientations,
+// padded binary32 biases, and the weights as MFMA A fragments of W^T: the
+// 16 x 32 block (output features 16 ft.., inputs 32 ks..) is 64 lanes x 8
+// values, lane l holding feature 16 ft + l % 16 at inputs 32 ks + 8 (l / 16) + j,
+// stored at frag[((ft * (in_pad / 32) + ks) * 64 + l) * 8 + j] (16 contiguous
+// bytes per lane, 1 KiB per block).
 __global__ void pack_kernel(const float* __restrict__ params, Layer L, int64_t total) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= total) return;
@@ -122,6 +126,10 @@ __global__ void pack_kernel(const float* __restrict__ params, Layer L, int64_t t
     L.wf[(int64_t)n * L.in_pad + k] = w;       // forward: B(k=in, n=out)
     L.wb[(int64_t)k * L.out_pad + n] = w;      // backward: B(k=out, n=in)
     if (k == 0) L.bias[n] = n < L.out ? params[L.b_off + n] : 0.0f;
+    if (n < 16 * L.ftiles) {
+        const int ft = n >> 4, ks = k >> 5, lane = (n & 15) + 16 * ((k & 31) >> 3);
+        L.frag[(((int64_t)ft * (L.in_pad >> 5) + ks) * 64 + lane) * 8 + (k & 7)] = w;
+    }
 }
 
 // Inputs n x 7 binary32 (optionally gathered through rows[], each in
@@ -137,12 +145,14 @@ __global__ void input_kernel(const float* __restrict__ x, const int32_t* __restr
 }
 
 // Loss terms and output gradient (see the network description):
-//   l_i = softplus(y0) - esc y0 + lam esc |y[1:4] - d|^2,  L = sum l_i / n
+//   l_i = softplus(y0) - esc y0 + lam esc sum_c huber(y[c] - d[c]),  L = sum l_i / n
+// huber(e) = e^2 for |e| <= delta, 2 delta |e| - delta^2 beyond.
 // dy is written as bfloat16 n x 32 (zero beyond column 3); per-block partial
 // sums of l_i go to partial[blockIdx.x] (reduced by reduce_kernel).
 __global__ void loss_kernel(const float* __restrict__ y, const float* __restrict__ target,
                             const int32_t* __restrict__ rows, int64_t n, int64_t n_src, float lam,
-                            float inv_n, __bf16* __restrict__ dy, double* __restrict__ partial) {
+                            float delta, float inv_n, __bf16* __restrict__ dy,
+                            double* __restrict__ partial) {
     __shared__ double red[256];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double li = 0.0;
@@ -155,12 +165,18 @@ __global__ void loss_kernel(const float* __restrict__ y, const float* __restrict
         const float esc = t[0];
         const float y0 = yi[0];
         const float sp = fmaxf(y0, 0.0f) + log1pf(expf(-fabsf(y0)));
-        float sq = 0.0f;
-        for (int c = 1; c < OUT; ++c) sq += (yi[c] - t[c]) * (yi[c] - t[c]);
-        li = (double)(sp - esc * y0 + lam * esc * sq);
+        float hub = 0.0f;
+        for (int c = 1; c < OUT; ++c) {
+            const float e = yi[c] - t[c], a = fabsf(e);
+            hub += a <= delta ? e * e : 2.0f * delta * a - delta * delta;
+        }
+        li = (double)(sp - esc * y0 + lam * esc * hub);
         dy[i * OUT_PAD + 0] = (__bf16)((sigmoidf_(y0) - esc) * inv_n);
-        for (int c = 1; c < OUT; ++c)
-            dy[i * OUT_PAD + c] = (__bf16)(2.0f * lam * esc * (yi[c] - t[c]) * inv_n);
+        for (int c = 1; c < OUT; ++c) {
+            const float e = yi[c] - t[c];
+            const float ge = fabsf(e) <= delta ? 2.0f * e : copysignf(2.0f * delta, e);
+            dy[i * OUT_PAD + c] = (__bf16)(lam * esc * ge * inv_n);
+        }
         for (int c = OUT; c < OUT_PAD; ++c) dy[i * OUT_PAD + c] = (__bf16)0.0f;
     }
     red[threadIdx.x] = li;
@@ -246,12 +262,12 @@ hipError_t inputs(const float* x, const int32_t* rows, int64_t n, int64_t n_src,
 }
 
 hipError_t loss(const float* y, const float* target, const int32_t* rows, int64_t n,
-                int64_t n_src, float lam, __bf16* dy, double* partial, float* loss_out,
-                hipStream_t s) {
+                int64_t n_src, float lam, float delta, __bf16* dy, double* partial,
+                float* loss_out, hipStream_t s) {
     const unsigned blocks = (unsigned)((n + 255) / 256);
     const float inv_n = 1.0f / (float)n;
     hipLaunchKernelGGL(loss_kernel, dim3(blocks), dim3(256), 0, s, y, target, rows, n, n_src, lam,
-                       inv_n, dy, partial);
+                       delta, inv_n, dy, partial);
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)blocks, inv_n,
                        loss_out);
     return hipGetLastError();

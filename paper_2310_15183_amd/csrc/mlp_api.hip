@@ -69,6 +69,7 @@ void free_all(gr_mlp* m) {
         hipFree(m->layer[l].wf);
         hipFree(m->layer[l].wb);
         hipFree(m->layer[l].bias);
+        hipFree(m->layer[l].frag);
     }
     hipFree(m->X);
     for (int l = 0; l < NLAYER - 1; ++l) {
@@ -163,8 +164,10 @@ int gr_mlp_create(gr_mlp** out, int device, int64_t max_batch) {
         off += (int64_t)L.in * L.out;
         L.b_off = off;
         off += L.out;
+        L.ftiles = (L.out + 15) / 16;
         ok = dalloc(&L.wf, (int64_t)L.in_pad * L.out_pad) &&
-             dalloc(&L.wb, (int64_t)L.in_pad * L.out_pad) && dalloc(&L.bias, L.out_pad);
+             dalloc(&L.wb, (int64_t)L.in_pad * L.out_pad) && dalloc(&L.bias, L.out_pad) &&
+             dalloc(&L.frag, frag_elems(L.ftiles, L.in_pad));
     }
     ok = ok && dalloc(&m->X, max_batch * IN_PAD);
     for (int l = 0; l < NLAYER - 1 && ok; ++l)
@@ -249,17 +252,17 @@ int gr_mlp_forward(gr_mlp* m, const float* x, int64_t n, float* y, void* stream)
 }
 
 int gr_mlp_loss_grad(gr_mlp* m, const float* x, const float* target, const int32_t* rows,
-                     int64_t n, int64_t n_src, float lam, float* loss, float* grad,
+                     int64_t n, int64_t n_src, float lam, float delta, float* loss, float* grad,
                      void* stream) {
     if (!m || !x || !target || !grad) return GR_EINVAL;
     if (n < 32 || n > m->max_batch || n % 32) return GR_EINVAL;
     if (!rows) n_src = n;
-    if (n_src < 1 || !(lam >= 0.0f)) return GR_EINVAL;
+    if (n_src < 1 || !(lam >= 0.0f) || !(delta > 0.0f)) return GR_EINVAL;
     Guard guard(m->device);
     hipStream_t s = (hipStream_t)stream;
     if (inputs(x, rows, n, n_src, m->X, s) != hipSuccess) return GR_EDEVICE;
     if (forward_rows(m, n, true, s) != hipSuccess) return GR_EDEVICE;
-    if (gr::mlp::loss(m->Y, target, rows, n, n_src, lam, m->dY, m->partial,
+    if (gr::mlp::loss(m->Y, target, rows, n, n_src, lam, delta, m->dY, m->partial,
                       loss ? loss : m->loss, s) != hipSuccess)
         return GR_EDEVICE;
     // backward, last layer first
@@ -332,3 +335,12 @@ int64_t gr_mlp_steps(const gr_mlp* m) { return m ? m->step : -1; }
 }  // extern "C"
 
 int gr_mlp_device_of(const gr_mlp* m) { return m ? m->device : -1; }
+
+NetView gr_mlp_view(const gr_mlp* m) {
+    NetView v;
+    for (int l = 0; l < NLAYER; ++l) {
+        v.frag[l] = m->layer[l].frag;
+        v.bias[l] = m->layer[l].bias;
+    }
+    return v;
+}

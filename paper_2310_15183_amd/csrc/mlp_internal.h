@@ -38,15 +38,25 @@ struct Layer {
     __bf16* wf;     // out_pad x in_pad: forward operand B(k=in, n=out) at wf[n*in_pad + k]
     __bf16* wb;     // in_pad x out_pad: backward operand B(k=out, n=in) at wb[n*out_pad + k]
     float* bias;    // out_pad
+    __bf16* frag;   // MFMA A-operand fragments of W^T (see frag_pack in mlp.hip)
+    int ftiles;     // 16-row tiles of output features: ceil(out / 16)
+};
+
+// Read-only view of a packed network for kernels outside mlp.hip.
+struct NetView {
+    const __bf16* frag[NLAYER];
+    const float* bias[NLAYER];
 };
 
 hipError_t gemm(const GemmArgs& g, hipStream_t s);
 hipError_t pack(const float* params, const Layer& L, hipStream_t s);
+// Elements of Layer::frag for ftiles output tiles and padded input width in_pad.
+inline int64_t frag_elems(int ftiles, int in_pad) { return (int64_t)ftiles * (in_pad / 32) * 64 * 8; }
 hipError_t inputs(const float* x, const int32_t* rows, int64_t n, int64_t n_src, __bf16* out,
                   hipStream_t s);
 hipError_t loss(const float* y, const float* target, const int32_t* rows, int64_t n,
-                int64_t n_src, float lam, __bf16* dy, double* partial, float* loss_out,
-                hipStream_t s);
+                int64_t n_src, float lam, float delta, __bf16* dy, double* partial,
+                float* loss_out, hipStream_t s);
 hipError_t colsum(const __bf16* dz, int64_t nrows, int ld, int ncols, float* out, hipStream_t s);
 hipError_t adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
                 float b2, float eps, float c1, float c2, hipStream_t s);

@@ -11,6 +11,7 @@
 // ray's crossing of the same sphere (its end state moved back along its own
 // velocity to r_esc).
 #include "internal.h"
+#include "mlp_internal.h"
 #include "surrogate_internal.h"
 
 namespace gr {
@@ -120,35 +121,127 @@ __global__ void targets_kernel(const BatchInstance* __restrict__ inst,
     }
 }
 
-// Class and end direction of every pixel from the network output.
-__global__ void classify_kernel(const float* __restrict__ y, const float* __restrict__ uflat,
-                                int64_t n, int8_t* __restrict__ flag, float* __restrict__ dir) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const float* yi = y + p * 4;
-    const bool esc = yi[0] > 0.0f;
-    flag[p] = esc ? GR_FLAG_ESCAPE : GR_FLAG_HORIZON;
-    float u[3];
-    float nn = 0.0f;
-    for (int c = 0; c < 3; ++c) {
-        u[c] = uflat[p * 3 + c] + yi[1 + c];
-        nn += u[c] * u[c];
+// ---- fused frame kernel: inputs, the five layers and the class/direction of
+// FR consecutive pixels per workgroup.  The activations of the FR rays stay
+// in LDS (one row of HID bfloat16 per ray, padded by 8 values so that the 16
+// rows read by one MFMA operand fall in distinct banks); wave w computes the
+// output features 64 w .. 64 w + 63 of every layer for all FR rays as
+// D[feature][ray] = W^T (A fragments read from global memory, see
+// mlp::pack_kernel) times the activations (B operand from LDS), with
+// binary32 accumulation in the same k order as the training kernels.
+constexpr int FR = 128;                  // rays per workgroup
+constexpr int LDA = mlp::HID + 8;        // bfloat16 per LDS activation row
+constexpr int FRAME_THREADS = 256;
+
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf8;
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf4;
+
+__device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+// One SiLU layer of mlp::HID outputs over KS k-steps of 32 inputs, in place.
+template <int KS>
+__device__ __forceinline__ void frame_layer(__bf16* act, const __bf16* __restrict__ frag,
+                                            const float* __restrict__ bias, int wave, int lane) {
+    f4 acc[4][FR / 16];
+    for (int i = 0; i < 4; ++i)
+        for (int t = 0; t < FR / 16; ++t) acc[i][t] = f4{0.f, 0.f, 0.f, 0.f};
+    const bf8* A = reinterpret_cast<const bf8*>(frag);
+    const int rn = lane & 15, kq = (lane >> 4) * 8;
+#pragma unroll 2
+    for (int ks = 0; ks < KS; ++ks) {
+        bf8 a[4], b[FR / 16];
+        for (int i = 0; i < 4; ++i) a[i] = A[((4 * wave + i) * KS + ks) * 64 + lane];
+        for (int t = 0; t < FR / 16; ++t)
+            b[t] = *reinterpret_cast<const bf8*>(act + (16 * t + rn) * LDA + 32 * ks + kq);
+        for (int i = 0; i < 4; ++i)
+            for (int t = 0; t < FR / 16; ++t)
+                acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[t], acc[i][t], 0, 0, 0);
     }
-    const float inv = esc && nn > 0.0f ? 1.0f / sqrtf(nn) : 0.0f;
-    for (int c = 0; c < 3; ++c) dir[p * 3 + c] = u[c] * inv;
+    __syncthreads();                       // every wave has read this layer's inputs
+    // lane holds features f .. f + 3 (f = 16 (4 wave + i) + 4 (lane / 16)) of ray 16 t + lane % 16
+    for (int i = 0; i < 4; ++i) {
+        const int f = 16 * (4 * wave + i) + 4 * (lane >> 4);
+        const f4 bb = *reinterpret_cast<const f4*>(bias + f);
+        for (int t = 0; t < FR / 16; ++t) {
+            bf4 h;
+            for (int e = 0; e < 4; ++e) {
+                const float z = acc[i][t][e] + bb[e];
+                h[e] = (__bf16)(z * sigmoidf_(z));
+            }
+            *reinterpret_cast<bf4*>(act + (16 * t + rn) * LDA + f) = h;
+        }
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(FRAME_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+frame_net_kernel(const BatchInstance I, int64_t npix, const mlp::NetView net,
+                 int8_t* __restrict__ flag, float* __restrict__ dir, float* __restrict__ logit) {
+    __shared__ __attribute__((aligned(16))) __bf16 act[FR * LDA];
+    __shared__ float uf[FR][3];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t p0 = (int64_t)blockIdx.x * FR;
+
+    if (tid < FR) {                        // network inputs (rows past the frame are zero)
+        float x[mlp::IN] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, u[3] = {0.f, 0.f, 0.f};
+        if (p0 + tid < npix) ray_inputs(I, p0 + tid, x, u);
+        __bf16* row = act + tid * LDA;
+        for (int c = 0; c < mlp::IN_PAD; ++c) row[c] = c < mlp::IN ? (__bf16)x[c] : (__bf16)0.0f;
+        for (int c = 0; c < 3; ++c) uf[tid][c] = u[c];
+    }
+    __syncthreads();
+    frame_layer<mlp::IN_PAD / 32>(act, net.frag[0], net.bias[0], wave, lane);
+    frame_layer<mlp::HID / 32>(act, net.frag[1], net.bias[1], wave, lane);
+    frame_layer<mlp::HID / 32>(act, net.frag[2], net.bias[2], wave, lane);
+    frame_layer<mlp::HID / 32>(act, net.frag[3], net.bias[3], wave, lane);
+
+    // output layer: one 16-feature tile (features 0..3 real); wave w takes rays 32 w .. 32 w + 31
+    const bf8* A = reinterpret_cast<const bf8*>(net.frag[4]);
+    const int rn = lane & 15, kq = (lane >> 4) * 8;
+    f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+    for (int ks = 0; ks < mlp::HID / 32; ++ks) {
+        const bf8 a = A[ks * 64 + lane];
+        for (int t = 0; t < 2; ++t) {
+            const bf8 b =
+                *reinterpret_cast<const bf8*>(act + (32 * wave + 16 * t + rn) * LDA + 32 * ks + kq);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+        }
+    }
+    if (lane < 16) {                       // lanes 0..15 hold features 0..3 of their ray
+        const float* bo = net.bias[4];
+        for (int t = 0; t < 2; ++t) {
+            const int ray = 32 * wave + 16 * t + lane;
+            const int64_t p = p0 + ray;
+            if (p >= npix) continue;
+            const float y0 = acc[t][0] + bo[0];
+            const bool esc = y0 > 0.0f;
+            float u[3];
+            float nn = 0.0f;
+            for (int c = 0; c < 3; ++c) {
+                u[c] = uf[ray][c] + (acc[t][1 + c] + bo[1 + c]);
+                nn += u[c] * u[c];
+            }
+            const float inv = esc && nn > 0.0f ? 1.0f / sqrtf(nn) : 0.0f;
+            flag[p] = esc ? GR_FLAG_ESCAPE : GR_FLAG_HORIZON;
+            for (int c = 0; c < 3; ++c) dir[p * 3 + c] = u[c] * inv;
+            logit[p] = y0;
+        }
+    }
 }
 
 // A pixel falls back to RK4 when its logit is small or a pixel within
 // Chebyshev distance `edge` has the other class; fallback pixels are appended
 // to list (order unspecified).
-__global__ void fallback_kernel(const float* __restrict__ y, const int8_t* __restrict__ flag,
+__global__ void fallback_kernel(const float* __restrict__ logit, const int8_t* __restrict__ flag,
                                 int32_t W, int32_t H, float logit_min, int32_t edge,
                                 int8_t* __restrict__ fb, int32_t* __restrict__ list,
                                 unsigned long long* __restrict__ count) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= (int64_t)W * H) return;
     const int i = (int)(p % W), j = (int)(p / W);
-    bool f = fabsf(y[p * 4]) < logit_min;
+    bool f = fabsf(logit[p]) < logit_min;
     const int8_t mine = flag[p];
     for (int dj = -edge; dj <= edge && !f; ++dj) {
         const int jj = j + dj;
@@ -202,19 +295,21 @@ hipError_t targets(const BatchInstance* inst, const int64_t* firsts, int ninst, 
     return hipGetLastError();
 }
 
-hipError_t classify(const float* y, const float* uflat, int64_t n, int8_t* flag, float* dir,
-                    hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(classify_kernel, dim3(blocks(n)), dim3(256), 0, s, y, uflat, n, flag, dir);
+hipError_t frame_net(const BatchInstance& I, int64_t npix, const mlp::NetView& net,
+                     int8_t* flag, float* dir, float* logit, hipStream_t s) {
+    if (npix <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)((npix + FR - 1) / FR);
+    hipLaunchKernelGGL(frame_net_kernel, dim3(grid), dim3(FRAME_THREADS), 0, s, I, npix, net, flag,
+                       dir, logit);
     return hipGetLastError();
 }
 
-hipError_t fallback(const float* y, const int8_t* flag, int32_t W, int32_t H, float logit_min,
-                    int32_t edge, int8_t* fb, int32_t* list, unsigned long long* count,
-                    hipStream_t s) {
+hipError_t fallback(const float* logit, const int8_t* flag, int32_t W, int32_t H,
+                    float logit_min, int32_t edge, int8_t* fb, int32_t* list,
+                    unsigned long long* count, hipStream_t s) {
     hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, count);
-    hipLaunchKernelGGL(fallback_kernel, dim3(blocks((int64_t)W * H)), dim3(256), 0, s, y, flag, W,
-                       H, logit_min, edge, fb, list, count);
+    hipLaunchKernelGGL(fallback_kernel, dim3(blocks((int64_t)W * H)), dim3(256), 0, s, logit, flag,
+                       W, H, logit_min, edge, fb, list, count);
     return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "internal.h"
+#include "mlp_internal.h"
 
 namespace gr {
 namespace sur {
@@ -16,12 +17,14 @@ hipError_t inputs(const BatchInstance* inst, const int64_t* firsts, int ninst, i
 // Targets (n x 4: escaped, correction d) from the traced outputs of the table.
 hipError_t targets(const BatchInstance* inst, const int64_t* firsts, int ninst, int64_t total,
                    const float* uflat, float* target, hipStream_t s);
-// Frame pipeline.
-hipError_t classify(const float* y, const float* uflat, int64_t n, int8_t* flag, float* dir,
-                    hipStream_t s);
-hipError_t fallback(const float* y, const int8_t* flag, int32_t W, int32_t H, float logit_min,
-                    int32_t edge, int8_t* fb, int32_t* list, unsigned long long* count,
-                    hipStream_t s);
+// Frame pipeline.  frame_net: inputs, network, class and end direction of
+// every pixel of one frame (I.pixels is ignored: pixel k is ray k) in one
+// launch, keeping each escape logit for the fallback selection.
+hipError_t frame_net(const BatchInstance& I, int64_t npix, const mlp::NetView& net,
+                     int8_t* flag, float* dir, float* logit, hipStream_t s);
+hipError_t fallback(const float* logit, const int8_t* flag, int32_t W, int32_t H,
+                    float logit_min, int32_t edge, int8_t* fb, int32_t* list,
+                    unsigned long long* count, hipStream_t s);
 hipError_t merge(const BatchInstance* inst, const int32_t* list, int64_t n, int8_t* flag,
                  float* dir, hipStream_t s);
 

@@ -1,0 +1,132 @@
+"""Training and evaluation of the learned surrogate (marshalling only: every
+step runs in the library's kernels through the C ABI).
+
+Labels come from the binary64 tracer itself: rays of random black holes and
+cameras drawn over the ranges of the uneven batch (see workloads.py), each
+at random pixels of a virtual side x side image, traced with dt = 0.01 and at
+most 20000 steps.  Inputs and targets are built on the device
+(gr_surrogate_inputs / gr_surrogate_targets); training is Adam on shuffled
+mini-batches (rows gathered in-kernel) with a cosine learning-rate decay.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+import paper_2310_15183_amd as g
+from paper_2310_15183_amd.workloads import batch_instances
+
+LABEL_DT = 0.01
+LABEL_MAX_STEPS = 20000
+
+
+@dataclass
+class TrainingSet:
+    x: object          # (n, 7) float32 cuda tensor
+    u_flat: object     # (n, 3)
+    target: object     # (n, 4)
+    seconds: float
+    ray_steps: int
+
+
+def training_set(n_rays: int, seed: int = 1, rays_per_instance: int = 2048,
+                 side: int = 4096) -> TrainingSet:
+    """Trace n_rays labelled rays (rounded up to whole instances)."""
+    import torch
+    n_inst = max(1, math.ceil(n_rays / rays_per_instance))
+    n = n_inst * rays_per_instance
+    insts = batch_instances(n_inst, seed=seed)
+    rng = np.random.default_rng(seed + 7919)
+    pix = torch.as_tensor(rng.integers(0, side * side, n, dtype=np.int64).astype(np.int32),
+                          device="cuda")
+    cols = {f: torch.empty(n, dtype=torch.float64, device="cuda") for f in
+            ("theta", "phi", "r", "p_t", "p_r", "p_theta", "p_phi")}
+    flag = torch.empty(n, dtype=torch.int8, device="cuda")
+    steps = torch.empty(n, dtype=torch.int32, device="cuda")
+    structs = []
+    for k, I in enumerate(insts):
+        o = k * rays_per_instance
+
+        def at(t, o=o):
+            return t.data_ptr() + o * t.element_size()
+        out = g.gr_output(None, at(cols["r"]), at(cols["theta"]), at(cols["phi"]),
+                          at(cols["p_t"]), at(cols["p_r"]), at(cols["p_theta"]), at(cols["p_phi"]),
+                          at(flag), at(steps), g.GR_F64)
+        cam = g.gr_camera(I.r0, I.theta0, I.phi0, I.fov, side, side)
+        structs.append(g.gr_instance(g.gr_metric(I.M, I.a, I.Q), cam, out, at(pix),
+                                     rays_per_instance))
+    ctx = g.gr_trace_init(0, g.make_integrator(dt=LABEL_DT, max_steps=LABEL_MAX_STEPS))
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.gr_trace_batch(ctx, structs)
+        x = torch.empty(n, 7, device="cuda")
+        u = torch.empty(n, 3, device="cuda")
+        t = torch.empty(n, 4, device="cuda")
+        g.gr_surrogate_inputs(ctx, structs, x, u)
+        g.gr_surrogate_targets(ctx, structs, u, t)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+    finally:
+        g.gr_trace_destroy(ctx)
+    return TrainingSet(x, u, t, secs, int(steps.to(torch.int64).sum().item()))
+
+
+def train(net, data: TrainingSet, epochs: int = 20, batch: int = 8192, lr: float = 2e-3,
+          lr_min: float = 2e-5, lam: float = 100.0, delta: float = 0.02, seed: int = 1,
+          log=None):
+    """Adam with a cosine decay from lr to lr_min over all steps; returns the
+    mean loss of each epoch (read back once per epoch)."""
+    import torch
+    n = data.x.shape[0]
+    steps_per_epoch = n // batch
+    total = max(1, epochs * steps_per_epoch)
+    grad = torch.empty(g.gr_mlp_num_params(), device="cuda")
+    loss = torch.zeros(steps_per_epoch, device="cuda")
+    rng = np.random.default_rng(seed)
+    hist = []
+    step = 0
+    for ep in range(epochs):
+        perm = torch.as_tensor(rng.permutation(n).astype(np.int32), device="cuda")
+        for b in range(steps_per_epoch):
+            rows = perm[b * batch:(b + 1) * batch]
+            g.gr_mlp_loss_grad(net, data.x, data.target, grad, loss=loss[b:b + 1], rows=rows,
+                               lam=lam, delta=delta)
+            frac = step / total
+            g.gr_mlp_adam_step(net, grad, lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * frac)))
+            step += 1
+        hist.append(float(loss.mean().item()))
+        if log:
+            log(f"epoch {ep}: loss {hist[-1]:.5g}")
+    return hist
+
+
+def evaluate_network(net, data: TrainingSet, logit_min: float = 3.0):
+    """Accuracy of the network alone on labelled rays: class errors and the
+    great-circle error of the predicted end direction (escaped rays)."""
+    import torch
+    n = data.x.shape[0]
+    y = torch.empty(n, 4, device="cuda")
+    g.gr_mlp_forward(net, data.x, y)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy().astype(np.float64)
+    t = data.target.cpu().numpy().astype(np.float64)
+    u = data.u_flat.cpu().numpy().astype(np.float64)
+    esc_true = t[:, 0] > 0.5
+    esc_pred = y[:, 0] > 0
+    confident = np.abs(y[:, 0]) >= logit_min
+    both = esc_true & esc_pred
+    up = u[both] + y[both, 1:4]
+    up /= np.linalg.norm(up, axis=1, keepdims=True)
+    ut = u[both] + t[both, 1:4]
+    ut /= np.linalg.norm(ut, axis=1, keepdims=True)
+    ang = 2 * np.arctan2(np.linalg.norm(up - ut, axis=1), np.linalg.norm(up + ut, axis=1))
+    q = np.quantile(ang, [0.5, 0.9, 0.99, 0.999]) if ang.size else np.zeros(4)
+    return {"n": n, "class_error": float((esc_true != esc_pred).mean()),
+            "class_error_confident": float((esc_true != esc_pred)[confident].mean()),
+            "confident_frac": float(confident.mean()),
+            "angle_median": float(q[0]), "angle_p90": float(q[1]), "angle_p99": float(q[2]),
+            "angle_p999": float(q[3])}

@@ -20,7 +20,7 @@ def test_gradient_matches_central_differences():
     50 random parameters of every layer (binary64, no bf16 rounding)."""
     p = mlp.init_params(3) + np.random.default_rng(4).normal(scale=0.01, size=mlp.num_params())
     x, t = _batch(12, 5)
-    L, g = mlp.loss_and_grad(p, x, t, lam=3.0)
+    L, g = mlp.loss_and_grad(p, x, t, lam=3.0, delta=0.05)
     rng = np.random.default_rng(6)
     idx = rng.choice(p.size, 50, replace=False)
     # make sure every layer's weights and the last biases are represented
@@ -31,7 +31,8 @@ def test_gradient_matches_central_differences():
         pp, pm = p.copy(), p.copy()
         pp[i] += h
         pm[i] -= h
-        fd = (mlp.loss_and_grad(pp, x, t, lam=3.0)[0] - mlp.loss_and_grad(pm, x, t, lam=3.0)[0]) / (2 * h)
+        fd = (mlp.loss_and_grad(pp, x, t, lam=3.0, delta=0.05)[0]
+              - mlp.loss_and_grad(pm, x, t, lam=3.0, delta=0.05)[0]) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1e-3, abs(fd)), (i, fd, g[i])
 
 
@@ -81,3 +82,10 @@ def test_bf16_mode_stays_close_to_binary64():
     y64 = mlp.forward(p, x)
     y16 = mlp.forward(p, x, bf16_mode=True)
     assert np.linalg.norm(y16 - y64) / np.linalg.norm(y64) < 2e-2
+
+
+def test_huber_is_squared_error_inside_and_linear_outside():
+    e = np.array([-0.3, -0.05, 0.0, 0.02, 0.05, 1.0])
+    np.testing.assert_allclose(mlp.huber(e, np.inf), e * e)
+    np.testing.assert_allclose(mlp.huber(e, 0.05), [0.0275, 0.0025, 0.0, 0.0004, 0.0025, 0.0975])
+    np.testing.assert_allclose(mlp.huber_grad(e, 0.05), [-0.1, -0.1, 0.0, 0.04, 0.1, 0.1])
