@@ -24,10 +24,14 @@ __device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + expf
 // C[M x N] = A[M x K] B[K x N]; A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn].
 // 256 threads: the workgroup computes a 64x64 tile, each wave a 32x32 block
 // as 2x2 MFMA 16x16x32 tiles.  K must be a multiple of 32; rows >= M and
-// columns >= N are neither read nor written.
+// columns >= N are neither read nor written.  With gridDim.z = splits > 1
+// (EPI_F32 only) workgroup z sums k in [z kc, (z + 1) kc) and writes its
+// partial tile to part[z][M][N]; splitk_reduce_kernel adds the partials in
+// order of z.  Each thread stages 8 values of A and 8 of B per k-step with one
+// 16-byte load when they are contiguous and inside the matrix.
 __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs g) {
-    __shared__ __bf16 As[TM][LDK];
-    __shared__ __bf16 Bs[TN][LDK];
+    __shared__ __attribute__((aligned(16))) __bf16 As[TM][LDK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[TN][LDK];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int64_t m0 = (int64_t)blockIdx.x * TM;
@@ -36,40 +40,54 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs g) {
     f4 acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    const int64_t kbeg = (int64_t)blockIdx.z * g.kc;
+    const int64_t kend = kbeg + g.kc < g.K ? kbeg + g.kc : g.K;
 
-    for (int64_t k0 = 0; k0 < g.K; k0 += TK) {
+    for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
         // ---- stage A (64 x 32) and B (32 x 64) into LDS, rows = m / n, k contiguous
         if (g.sak == 1) {
             const int m = tid >> 2, kk = (tid & 3) * 8;
             const int64_t gm = m0 + m;
-            for (int j = 0; j < 8; ++j)
-                As[m][kk + j] = gm < g.M ? g.A[gm * g.sam + k0 + kk + j] : (__bf16)0.0f;
+            bf8 v;
+            if (gm < g.M) v = *reinterpret_cast<const bf8*>(g.A + gm * g.sam + k0 + kk);
+            else for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.0f;
+            *reinterpret_cast<bf8*>(&As[m][kk]) = v;
         } else {
             const int kk = tid >> 3, m = (tid & 7) * 8;
-            for (int j = 0; j < 8; ++j) {
-                const int64_t gm = m0 + m + j;
-                As[m + j][kk] = gm < g.M ? g.A[gm * g.sam + (k0 + kk) * g.sak] : (__bf16)0.0f;
+            const int64_t gm = m0 + m;
+            if (g.sam == 1 && gm + 8 <= g.M) {
+                const bf8 v = *reinterpret_cast<const bf8*>(g.A + gm + (k0 + kk) * g.sak);
+                for (int j = 0; j < 8; ++j) As[m + j][kk] = v[j];
+            } else {
+                for (int j = 0; j < 8; ++j)
+                    As[m + j][kk] = gm + j < g.M ? g.A[(gm + j) * g.sam + (k0 + kk) * g.sak]
+                                                 : (__bf16)0.0f;
             }
         }
         if (g.sbk == 1) {
             const int n = tid >> 2, kk = (tid & 3) * 8;
             const int64_t gn = n0 + n;
-            for (int j = 0; j < 8; ++j)
-                Bs[n][kk + j] = gn < g.N ? g.B[(k0 + kk + j) + gn * g.sbn] : (__bf16)0.0f;
+            bf8 v;
+            if (gn < g.N) v = *reinterpret_cast<const bf8*>(g.B + (k0 + kk) + gn * g.sbn);
+            else for (int j = 0; j < 8; ++j) v[j] = (__bf16)0.0f;
+            *reinterpret_cast<bf8*>(&Bs[n][kk]) = v;
         } else {
             const int kk = tid >> 3, n = (tid & 7) * 8;
-            for (int j = 0; j < 8; ++j) {
-                const int64_t gn = n0 + n + j;
-                Bs[n + j][kk] = gn < g.N ? g.B[(k0 + kk) * g.sbk + gn * g.sbn] : (__bf16)0.0f;
+            const int64_t gn = n0 + n;
+            if (g.sbn == 1 && gn + 8 <= g.N) {
+                const bf8 v = *reinterpret_cast<const bf8*>(g.B + (k0 + kk) * g.sbk + gn);
+                for (int j = 0; j < 8; ++j) Bs[n + j][kk] = v[j];
+            } else {
+                for (int j = 0; j < 8; ++j)
+                    Bs[n + j][kk] = gn + j < g.N ? g.B[(k0 + kk) * g.sbk + (gn + j) * g.sbn]
+                                                 : (__bf16)0.0f;
             }
         }
         __syncthreads();
         bf8 a[2], b[2];
         const int r = lane & 15, kq = (lane >> 4) * 8;
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 8; ++j) a[i][j] = As[wm + 16 * i + r][kq + j];
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 8; ++j) b[i][j] = Bs[wn + 16 * i + r][kq + j];
+        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf8*>(&As[wm + 16 * i + r][kq]);
+        for (int i = 0; i < 2; ++i) b[i] = *reinterpret_cast<const bf8*>(&Bs[wn + 16 * i + r][kq]);
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 2; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
@@ -77,6 +95,12 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs g) {
     }
 
     // ---- epilogue: lane holds rows 4*(lane/16)+e (e = 0..3), column lane%16 of each tile
+    float* outf = g.outf;
+    int64_t sof = g.sof;
+    if (gridDim.z > 1) {
+        outf = g.part + (int64_t)blockIdx.z * g.M * g.N;
+        sof = g.N;
+    }
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) {
             const int64_t col = n0 + wn + 16 * j + (lane & 15);
@@ -88,7 +112,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs g) {
                 const float v = acc[i][j][e];
                 switch (g.epi) {
                     case EPI_F32:
-                        g.outf[row * g.sof + col] = v;
+                        outf[row * sof + col] = v;
                         break;
                     case EPI_BIAS_F32:
                         g.outf[row * g.sof + col] = v + bias;
@@ -96,18 +120,28 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmArgs g) {
                     case EPI_BIAS_SILU: {
                         const float z = v + bias;
                         if (g.zout) g.zout[row * g.szo + col] = z;
-                        g.outh[row * g.soh + col] = (__bf16)(z * sigmoidf_(z));
+                        g.outh[row * g.soh + col] = (__bf16)(z * sigmoid_hw(z));
                         break;
                     }
                     case EPI_SILU_GRAD: {
                         const float z = g.zin[row * g.szi + col];
-                        const float s = sigmoidf_(z);
+                        const float s = sigmoid_hw(z);
                         g.outh[row * g.soh + col] = (__bf16)(v * (s * (1.0f + z * (1.0f - s))));
                         break;
                     }
                 }
             }
         }
+}
+
+// out[m * sof + n] = sum over z (in order) of part[z][m][n].
+__global__ void splitk_reduce_kernel(const float* __restrict__ part, int splits, int64_t M,
+                                     int64_t N, float* __restrict__ out, int64_t sof) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= M * N) return;
+    float s = part[idx];
+    for (int z = 1; z < splits; ++z) s += part[(int64_t)z * M * N + idx];
+    out[(idx / N) * sof + idx % N] = s;
 }
 
 // Packed binary32 parameters -> padded bfloat16 weights in both orientations,
@@ -202,19 +236,34 @@ __global__ void reduce_kernel(const double* __restrict__ partial, int64_t n, flo
     if (threadIdx.x == 0) loss[0] = (float)(red[0] * (double)inv_n);
 }
 
-// db[c] = sum over rows of dz[r][c] (bfloat16 rows of width ld), c < ncols.
-__global__ void colsum_kernel(const __bf16* __restrict__ dz, int64_t nrows, int ld, int ncols,
-                              float* __restrict__ out) {
+// db[c] = sum over rows of dz[r][c] (bfloat16 rows of width ld), c < ncols,
+// in two passes: COLSUM_CHUNKS row ranges into part[chunk][c], then the
+// chunks in order.
+__global__ void colsum_partial_kernel(const __bf16* __restrict__ dz, int64_t nrows, int ld,
+                                      int ncols, float* __restrict__ part) {
     __shared__ float red[4][64];
     const int c = blockIdx.x * 64 + (threadIdx.x & 63);
     const int grp = threadIdx.x >> 6;
+    const int64_t per = (nrows + COLSUM_CHUNKS - 1) / COLSUM_CHUNKS;
+    const int64_t r0 = (int64_t)blockIdx.y * per;
+    const int64_t r1 = r0 + per < nrows ? r0 + per : nrows;
     float s = 0.0f;
     if (c < ncols)
-        for (int64_t r = grp; r < nrows; r += 4) s += (float)dz[r * ld + c];
+        for (int64_t r = r0 + grp; r < r1; r += 4) s += (float)dz[r * ld + c];
     red[grp][threadIdx.x & 63] = s;
     __syncthreads();
     if (grp == 0 && c < ncols)
-        out[c] = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+        part[(int64_t)blockIdx.y * ncols + c] =
+            (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+__global__ void colsum_final_kernel(const float* __restrict__ part, int ncols,
+                                    float* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncols) return;
+    float s = 0.0f;
+    for (int k = 0; k < COLSUM_CHUNKS; ++k) s += part[k * ncols + c];
+    out[c] = s;
 }
 
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
@@ -239,10 +288,34 @@ __global__ void output_kernel(const float* __restrict__ y, int64_t n, float* __r
 
 }  // namespace
 
-hipError_t gemm(const GemmArgs& g, hipStream_t s) {
-    if (g.M <= 0 || g.N <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((g.M + TM - 1) / TM), (unsigned)((g.N + TN - 1) / TN));
+int splitk_count(int64_t M, int64_t N, int64_t K) {
+    const int64_t tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+    int64_t splits = (256 + tiles - 1) / tiles;
+    const int64_t max_splits = K / 128 > 1 ? K / 128 : 1;     // at least 128 k per split
+    if (splits > max_splits) splits = max_splits;
+    if (splits > SPLITK_MAX) splits = SPLITK_MAX;
+    return (int)(splits > 1 ? splits : 1);
+}
+
+hipError_t gemm(const GemmArgs& g0, hipStream_t s) {
+    if (g0.M <= 0 || g0.N <= 0) return hipSuccess;
+    // the 16-byte staging loads need 8-value aligned strides and operands
+    if (g0.K % TK || g0.sam % 8 && g0.sam != 1 || g0.sak % 8 && g0.sak != 1 ||
+        g0.sbk % 8 && g0.sbk != 1 || g0.sbn % 8 && g0.sbn != 1 ||
+        (reinterpret_cast<uintptr_t>(g0.A) | reinterpret_cast<uintptr_t>(g0.B)) & 15)
+        return hipErrorInvalidValue;
+    GemmArgs g = g0;
+    int splits = 1;
+    if (g.epi == EPI_F32 && g.part) splits = splitk_count(g.M, g.N, g.K);
+    g.kc = splits > 1 ? (((g.K + splits - 1) / splits + TK - 1) / TK) * TK : g.K;
+    const dim3 grid((unsigned)((g.M + TM - 1) / TM), (unsigned)((g.N + TN - 1) / TN),
+                    (unsigned)splits);
     hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, s, g);
+    if (splits > 1) {
+        const int64_t n = g.M * g.N;
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                           s, g.part, splits, g.M, g.N, g.outf, g.sof);
+    }
     return hipGetLastError();
 }
 
@@ -273,9 +346,12 @@ hipError_t loss(const float* y, const float* target, const int32_t* rows, int64_
     return hipGetLastError();
 }
 
-hipError_t colsum(const __bf16* dz, int64_t nrows, int ld, int ncols, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((ncols + 63) / 64)), dim3(256), 0, s, dz,
-                       nrows, ld, ncols, out);
+hipError_t colsum(const __bf16* dz, int64_t nrows, int ld, int ncols, float* part, float* out,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3((unsigned)((ncols + 63) / 64), COLSUM_CHUNKS),
+                       dim3(256), 0, s, dz, nrows, ld, ncols, part);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, s,
+                       part, ncols, out);
     return hipGetLastError();
 }
 

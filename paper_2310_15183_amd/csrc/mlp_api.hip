@@ -31,6 +31,8 @@ struct gr_mlp {
     __bf16* dY;                 // max_batch x OUT_PAD
     __bf16* dZ[2];              // ping-pong, x HID
     double* partial;            // loss partial sums
+    float* kpart;               // split-k partials of the weight gradients
+    float* colpart;             // partial bias-gradient sums
     float* loss;                // device scalar (when the caller passes none)
 };
 
@@ -81,6 +83,8 @@ void free_all(gr_mlp* m) {
     hipFree(m->dZ[0]);
     hipFree(m->dZ[1]);
     hipFree(m->partial);
+    hipFree(m->kpart);
+    hipFree(m->colpart);
     hipFree(m->loss);
 }
 
@@ -174,7 +178,9 @@ int gr_mlp_create(gr_mlp** out, int device, int64_t max_batch) {
         ok = dalloc(&m->H[l], max_batch * HID) && dalloc(&m->Z[l], max_batch * HID);
     ok = ok && dalloc(&m->Y, max_batch * OUT_PAD) && dalloc(&m->dY, max_batch * OUT_PAD) &&
          dalloc(&m->dZ[0], max_batch * HID) && dalloc(&m->dZ[1], max_batch * HID) &&
-         dalloc(&m->partial, max_batch / 256 + 2) && dalloc(&m->loss, 4);
+         dalloc(&m->partial, max_batch / 256 + 2) && dalloc(&m->loss, 4) &&
+         dalloc(&m->kpart, (int64_t)SPLITK_MAX * HID * HID) &&
+         dalloc(&m->colpart, (int64_t)COLSUM_CHUNKS * HID);
     if (!ok) {
         free_all(m);
         delete m;
@@ -287,8 +293,10 @@ int gr_mlp_loss_grad(gr_mlp* m, const float* x, const float* target, const int32
         g.epi = EPI_F32;
         g.outf = grad + L.w_off;
         g.sof = L.out;
+        g.part = m->kpart;
         if (gemm(g, s) != hipSuccess) return GR_EDEVICE;
-        if (colsum(dz, n, (int)ldz, L.out, grad + L.b_off, s) != hipSuccess) return GR_EDEVICE;
+        if (colsum(dz, n, (int)ldz, L.out, m->colpart, grad + L.b_off, s) != hipSuccess)
+            return GR_EDEVICE;
         if (l == 0) break;
         memset(&g, 0, sizeof g);
         g.A = dz;                   // dH = dz W^T, then times SiLU'(z of layer l-1)

@@ -8,8 +8,20 @@ namespace gr {
 namespace mlp {
 
 constexpr int IN = 7, IN_PAD = 32, HID = 256, OUT = 4, OUT_PAD = 32, NLAYER = 5;
+constexpr int COLSUM_CHUNKS = 64;   // row ranges of the bias-gradient sums
+constexpr int SPLITK_MAX = 64;      // k splits of a weight-gradient product
 
 enum { EPI_F32 = 0, EPI_BIAS_F32 = 1, EPI_BIAS_SILU = 2, EPI_SILU_GRAD = 3 };
+
+// Logistic function of the network's SiLU layers, 1 / (1 + 2^(-z log2 e)),
+// on the hardware base-2 exponential and reciprocal (about 1 ulp each; the
+// activations are rounded to bfloat16 afterwards).  Every kernel that applies
+// or differentiates SiLU uses this one definition, so that the fused frame
+// kernel reproduces the layer-by-layer forward pass bit for bit.  Saturates
+// to 0 and 1 for large |z|.
+__device__ __forceinline__ float sigmoid_hw(float z) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z * -1.44269504f));
+}
 
 // C = A B with strided bfloat16 operands and a fused epilogue (see mlp.hip).
 struct GemmArgs {
@@ -28,6 +40,8 @@ struct GemmArgs {
     int64_t szo;
     const float* zin;         // EPI_SILU_GRAD: pre-activation of the layer below
     int64_t szi;
+    float* part;              // EPI_F32: split-k partials (splitk_count(M, N, K) x M x N), or null
+    int64_t kc;               // set by gemm(): k per split
 };
 
 // One layer's parameters: offsets into the packed binary32 vector (W in x out
@@ -49,6 +63,8 @@ struct NetView {
 };
 
 hipError_t gemm(const GemmArgs& g, hipStream_t s);
+// k splits gemm() uses for an EPI_F32 product with a partial buffer.
+int splitk_count(int64_t M, int64_t N, int64_t K);
 hipError_t pack(const float* params, const Layer& L, hipStream_t s);
 // Elements of Layer::frag for ftiles output tiles and padded input width in_pad.
 inline int64_t frag_elems(int ftiles, int in_pad) { return (int64_t)ftiles * (in_pad / 32) * 64 * 8; }
@@ -57,7 +73,9 @@ hipError_t inputs(const float* x, const int32_t* rows, int64_t n, int64_t n_src,
 hipError_t loss(const float* y, const float* target, const int32_t* rows, int64_t n,
                 int64_t n_src, float lam, float delta, __bf16* dy, double* partial,
                 float* loss_out, hipStream_t s);
-hipError_t colsum(const __bf16* dz, int64_t nrows, int ld, int ncols, float* out, hipStream_t s);
+// part: COLSUM_CHUNKS x ncols scratch.
+hipError_t colsum(const __bf16* dz, int64_t nrows, int ld, int ncols, float* part, float* out,
+                  hipStream_t s);
 hipError_t adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
                 float b2, float eps, float c1, float c2, hipStream_t s);
 hipError_t outputs(const float* y, int64_t n, float* out, hipStream_t s);

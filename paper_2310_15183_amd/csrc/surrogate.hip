@@ -137,8 +137,6 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf8;
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf4;
 
-__device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + expf(-z)); }
-
 // One SiLU layer of mlp::HID outputs over KS k-steps of 32 inputs, in place.
 template <int KS>
 __device__ __forceinline__ void frame_layer(__bf16* act, const __bf16* __restrict__ frag,
@@ -167,7 +165,7 @@ __device__ __forceinline__ void frame_layer(__bf16* act, const __bf16* __restric
             bf4 h;
             for (int e = 0; e < 4; ++e) {
                 const float z = acc[i][t][e] + bb[e];
-                h[e] = (__bf16)(z * sigmoidf_(z));
+                h[e] = (__bf16)(z * mlp::sigmoid_hw(z));
             }
             *reinterpret_cast<bf4*>(act + (16 * t + rn) * LDA + f) = h;
         }
