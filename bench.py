@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 METRIC = "geodesic rays/s @1000² Kerr: FP64 vs mixed vs surrogate, ≤1e-4 rad err"
 FLOPS_PER_RAY_STEP = 693          # binary64 ops of one RK4 step (add/sub/mul/div 1, fma 2)
 FP64_PEAK_TFLOPS = 78.6           # MI355X FP64 vector (256 CU x 128 flop/clk x 2.4 GHz)
+BF16_PEAK_TFLOPS = 2500.0         # MI355X dense bfloat16 MFMA
 KERNEL_SOURCES = ["paper_2310_15183_amd/csrc/trace_fp64.hip",
                   "paper_2310_15183_amd/csrc/step_fp64.h",
                   "paper_2310_15183_amd/csrc/grmath.h"]
@@ -111,31 +112,34 @@ def time_frames(g, ctx, metric, cam, out, steps, warmup, stream):
     return wall, sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / 1e3 / steps
 
 
-def accuracy_pair(g, w, stream):
-    """Trace the frame once in binary64 and once mixed, with every output in
-    binary64, and compare where the rays cross the escape sphere."""
+def traced_frame(g, w, stream, precision):
+    """Trace the frame once with every output in binary64 (host arrays)."""
     import torch
+    ctx = g.gr_trace_init(0, g.make_integrator(dt=w["dt"], fd_eps=w["fd_eps"],
+                                               horizon_norm=w["horizon_norm"],
+                                               escape_factor=w["escape_factor"],
+                                               max_steps=w["max_steps"], precision=precision))
+    out = g.alloc_outputs(w["W"] * w["H"], dtype=g.GR_F64, fields=g.FIELDS)
+    g.gr_trace_frame(ctx, g.gr_metric(w["M"], w["a"], w["Q"]),
+                     g.gr_camera(w["r0"], w["theta0"], w["phi0"], w["fov"], w["W"], w["H"]),
+                     out.struct, stream)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.tensors.items()}
+    g.gr_trace_destroy(ctx)
+    return res
 
+
+def accuracy_pair(g, w, stream, ref):
+    """Mixed-precision frame against the binary64 one: where the rays cross
+    the escape sphere, and the flags."""
     from paper_2310_15183_amd.evaluate import mixed_errors
-    res = {}
-    for prec in (g.GR_FP64, g.GR_MIXED):
-        ctx = g.gr_trace_init(0, g.make_integrator(dt=w["dt"], fd_eps=w["fd_eps"],
-                                                   horizon_norm=w["horizon_norm"],
-                                                   escape_factor=w["escape_factor"],
-                                                   max_steps=w["max_steps"], precision=prec))
-        out = g.alloc_outputs(w["W"] * w["H"], dtype=g.GR_F64, fields=g.FIELDS)
-        g.gr_trace_frame(ctx, g.gr_metric(w["M"], w["a"], w["Q"]),
-                         g.gr_camera(w["r0"], w["theta0"], w["phi0"], w["fov"], w["W"], w["H"]),
-                         out.struct, stream)
-        torch.cuda.synchronize()
-        res[prec] = {k: v.cpu().numpy() for k, v in out.tensors.items()}
-        g.gr_trace_destroy(ctx)
-    return mixed_errors(w["M"], w["a"], w["Q"], w["escape_factor"] * w["r0"], res[g.GR_FP64],
-                        res[g.GR_MIXED])
+    got = traced_frame(g, w, stream, g.GR_MIXED)
+    return mixed_errors(w["M"], w["a"], w["Q"], w["escape_factor"] * w["r0"], ref, got)
 
 
-def mixed_variant(g, w, args, stream, fp64_rays_per_s):
-    """Mixed-precision form on the same frame: rays/s, speedup and accuracy."""
+def mixed_variant(g, w, args, stream, fp64_rays_per_s, ref):
+    """Mixed-precision form on the same frame: rays/s, speedup and accuracy
+    against the binary64 frame ref."""
     n = w["W"] * w["H"]
     ctx = g.gr_trace_init(0, g.make_integrator(dt=w["dt"], fd_eps=w["fd_eps"],
                                                horizon_norm=w["horizon_norm"],
@@ -146,7 +150,7 @@ def mixed_variant(g, w, args, stream, fp64_rays_per_s):
     cam = g.gr_camera(w["r0"], w["theta0"], w["phi0"], w["fov"], w["W"], w["H"])
     wall, launch_s = time_frames(g, ctx, metric, cam, out, args.steps, args.warmup, stream)
     g.gr_trace_destroy(ctx)
-    err = accuracy_pair(g, w, stream)
+    err = accuracy_pair(g, w, stream, ref)
     rays_s = n * args.steps / wall
     return {"rays_per_s": rays_s, "ms_per_step": wall / args.steps * 1e3,
             "launch_ms": launch_s * 1e3, "speedup_vs_fp64": rays_s / fp64_rays_per_s,
@@ -180,12 +184,131 @@ def bench_mixed(args):
                                      stream)
         g.gr_trace_destroy(ctx)
         fp64 = n * args.steps / wall
-        mixed = mixed_variant(g, w, args, stream, fp64)
+        mixed = mixed_variant(g, w, args, stream, fp64, traced_frame(g, w, stream, g.GR_FP64))
         lines.append({"workload": f"near-extremal kerr {side}x{side}", "fp64_rays_per_s": fp64,
                       "fp64_ms_per_step": wall / args.steps * 1e3, "mixed": mixed})
     print(json.dumps({"metric": "geodesic rays/s, near-extremal Kerr: FP64 vs mixed",
                       "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
                       "data": "synthetic", "results": lines}), flush=True)
+
+
+def train_surrogate(g, args):
+    """Label args.train_rays rays with the binary64 tracer over the batch
+    parameter ranges, train the network on them with the library's kernels,
+    and score it on 2e5 held-out rays."""
+    import torch
+
+    from paper_2310_15183_amd import surrogate as S
+    data = S.training_set(args.train_rays, seed=11)
+    net = g.gr_mlp_create(0, 8192)
+    g.gr_mlp_init(net, 11)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = S.train(net, data, epochs=args.train_epochs, seed=11)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    held = S.training_set(200_000, seed=12)
+    info = {"label_rays": int(data.x.shape[0]), "label_s": data.seconds,
+            "label_ray_steps": data.ray_steps, "epochs": args.train_epochs, "batch": 8192,
+            "train_s": train_s, "final_loss": hist[-1] if hist else None,
+            "held_out": S.evaluate_network(net, held)}
+    del data, held
+    return net, info
+
+
+def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3.0, edge=2):
+    """Surrogate + RK4 fallback on the frame w: rays/s, speedup over the
+    binary64 tracer on the same frame and integrator, the network-only frame
+    time against the MFMA peak, and the errors against the binary64 frame."""
+    import torch
+
+    from paper_2310_15183_amd import surrogate as S
+    n = w["W"] * w["H"]
+    ctx = g.gr_trace_init(0, g.make_integrator(dt=w["dt"], fd_eps=w["fd_eps"],
+                                               horizon_norm=w["horizon_norm"],
+                                               escape_factor=w["escape_factor"],
+                                               max_steps=w["max_steps"]))
+    metric = g.gr_metric(w["M"], w["a"], w["Q"])
+    cam = g.gr_camera(w["r0"], w["theta0"], w["phi0"], w["fov"], w["W"], w["H"])
+    flag = torch.empty(n, dtype=torch.int8, device="cuda")
+    direc = torch.empty(n, 3, device="cuda")
+    fb = torch.empty(n, dtype=torch.int8, device="cuda")
+
+    def run(lmin, e, steps, warmup):
+        nfb = 0
+        for _ in range(warmup):
+            nfb = g.gr_surrogate_frame(ctx, net, metric, cam, lmin, e, flag, direc, fb, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            nfb = g.gr_surrogate_frame(ctx, net, metric, cam, lmin, e, flag, direc, fb, stream)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, nfb
+
+    net_s, _ = run(0.0, 0, args.steps, args.warmup)          # network only, no fallback
+    wall, nfb = run(logit_min, edge, args.steps, args.warmup)
+    g.gr_trace_destroy(ctx)
+    err = S.frame_errors(w["M"], w["a"], w["Q"], w["escape_factor"] * w["r0"], ref,
+                         flag.cpu().numpy(), direc.cpu().numpy())
+    rays_s = n / wall
+    tflops = S.FLOPS_PER_RAY * n / net_s / 1e12
+    return {"rays_per_s": rays_s, "ms_per_step": wall * 1e3,
+            "speedup_vs_fp64": rays_s / fp64_rays_per_s,
+            "fallback": {"rule": f"|logit| < {logit_min} or a pixel within Chebyshev "
+                                 f"distance {edge} of the other predicted class",
+                         "pixels": int(nfb), "frac": nfb / n},
+            "network_only_ms": net_s * 1e3,
+            "network_mfma": {"achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": tflops / BF16_PEAK_TFLOPS,
+                             "flops_per_ray": S.FLOPS_PER_RAY},
+            **err,
+            "gate": "p99.9 <= 1e-4 rad, <= 0.1% misclassified",
+            "passes_gate": err["angle_err_rad"]["p999"] <= 1e-4
+            and err["misclassified_frac"] <= 1e-3}
+
+
+def bench_surrogate(args):
+    """Surrogate + fallback on 4096x4096 frames (the network trained first):
+    the Kerr-Newman point of the headline frame, near-extremal Kerr, and two
+    seeded draws from the batch parameter ranges; dt=0.01, 20000 steps."""
+    import torch
+
+    import paper_2310_15183_amd as g
+    from paper_2310_15183_amd.workloads import batch_instances
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    net, info = train_surrogate(g, args)
+    print(json.dumps({"training": info}), flush=True)
+    side = args.surrogate_side
+    base = dict(workload(), dt=0.01, max_steps=20000, W=side, H=side, phi0=0.0)
+    frames = [("kerr-newman a=0.24 Q=0.3 theta0=80deg", dict(base)),
+              ("near-extremal kerr a=0.49 theta0=60deg",
+               dict(base, a=0.49, Q=0.0, theta0=math.radians(60.0)))]
+    for k, I in enumerate(batch_instances(2, seed=777)):
+        frames.append((f"draw {k}: a={I.a:.3f} Q={I.Q:.3f} r0={I.r0:.1f} "
+                       f"theta0={math.degrees(I.theta0):.1f}deg fov={math.degrees(I.fov):.1f}deg",
+                       dict(base, M=I.M, a=I.a, Q=I.Q, r0=I.r0, theta0=I.theta0, fov=I.fov)))
+    lines = []
+    for name, w in frames:
+        n = side * side
+        ref = traced_frame(g, w, stream, g.GR_FP64)
+        ctx = g.gr_trace_init(0, g.make_integrator(dt=w["dt"], max_steps=w["max_steps"]))
+        out = g.alloc_outputs(n, dtype=g.GR_F32, fields=("t", "r", "theta", "phi"))
+        fp64_s, _ = time_frames(g, ctx, g.gr_metric(w["M"], w["a"], w["Q"]),
+                                g.gr_camera(w["r0"], w["theta0"], w["phi0"], w["fov"], side,
+                                            side), out, 1, 0, stream)
+        g.gr_trace_destroy(ctx)
+        del out
+        sur = surrogate_variant(g, net, w, args, stream, n / fp64_s, ref)
+        line = {"workload": f"{name} {side}x{side}", "fp64_rays_per_s": n / fp64_s,
+                "fp64_ms_per_step": fp64_s * 1e3, "surrogate": sur}
+        print(json.dumps(line), flush=True)
+        lines.append(line)
+        del ref
+    g.gr_mlp_destroy(net)
+    print(json.dumps({"metric": "geodesic rays/s, surrogate + RK4 fallback vs binary64",
+                      "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "data": "synthetic", "training": info, "results": lines}), flush=True)
 
 
 def copy_calibration(mib=256, reps=3):
@@ -272,10 +395,16 @@ def main():
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter scale)")
-    ap.add_argument("--workload", choices=["frame", "batch", "mixed"], default="frame",
+    ap.add_argument("--workload", choices=["frame", "batch", "mixed", "surrogate"],
+                    default="frame",
                     help="frame: the 1000x1000 Kerr-Newman frame (default, the headline "
                          "line); batch: the 256-instance uneven batch in one launch; mixed: "
-                         "near-extremal Kerr at 1000^2 and 2048^2, binary64 vs mixed")
+                         "near-extremal Kerr at 1000^2 and 2048^2, binary64 vs mixed; "
+                         "surrogate: 4096^2 frames, surrogate + fallback vs binary64")
+    ap.add_argument("--train-rays", type=int, default=10_000_000,
+                    help="surrogate: labelled rays to train on")
+    ap.add_argument("--train-epochs", type=int, default=12)
+    ap.add_argument("--surrogate-side", type=int, default=4096)
     ap.add_argument("--skip-variants", action="store_true",
                     help="frame workload: time only the binary64 path")
     args = ap.parse_args()
@@ -293,6 +422,9 @@ def main():
         return
     if args.workload == "mixed":
         bench_mixed(args)
+        return
+    if args.workload == "surrogate":
+        bench_surrogate(args)
         return
 
     import numpy as np
@@ -359,8 +491,14 @@ def main():
         "variants": {},
     }
     if not args.skip_variants:
-        result["variants"]["mixed"] = mixed_variant(g, w, args, stream, result["value"])
-        result["variants"]["surrogate"] = None
+        ref = traced_frame(g, w, stream, g.GR_FP64)
+        result["variants"]["mixed"] = mixed_variant(g, w, args, stream, result["value"], ref)
+        net, info = train_surrogate(g, args)
+        sur = surrogate_variant(g, net, w, args, stream, result["value"], ref)
+        g.gr_mlp_destroy(net)
+        sur["training"] = info
+        result["variants"]["surrogate"] = sur
+        del ref
     if not args.skip_cpu_baseline:
         import oracle
         threads = min(16, oracle.default_threads())

@@ -17,10 +17,13 @@ from dataclasses import dataclass
 import numpy as np
 
 import paper_2310_15183_amd as g
+from paper_2310_15183_amd.evaluate import angle_between, sky_at_escape, sky_direction
 from paper_2310_15183_amd.workloads import batch_instances
 
 LABEL_DT = 0.01
 LABEL_MAX_STEPS = 20000
+# multiply-adds of one ray through 7 -> 256 -> 256 -> 256 -> 256 -> 4, times 2
+FLOPS_PER_RAY = 2 * (7 * 256 + 3 * 256 * 256 + 256 * 4)
 
 
 @dataclass
@@ -130,3 +133,19 @@ def evaluate_network(net, data: TrainingSet, logit_min: float = 3.0):
             "confident_frac": float(confident.mean()),
             "angle_median": float(q[0]), "angle_p90": float(q[1]), "angle_p99": float(q[2]),
             "angle_p999": float(q[3])}
+
+
+def frame_errors(M, a, Q, r_esc, ref, flag, direc):
+    """A surrogate frame (flags, unit end directions) against a binary64
+    traced frame (all fields binary64): the fraction of pixels whose class
+    differs and the great-circle error of the end direction where both say
+    escaped (the reference direction is its crossing of r = r_esc)."""
+    flag = np.asarray(flag)
+    both = (ref["flag"] == g.GR_FLAG_ESCAPE) & (flag == g.GR_FLAG_ESCAPE)
+    th, ph = sky_at_escape(M, a, Q, r_esc, {k: v[both] for k, v in ref.items()})
+    ang = angle_between(sky_direction(th, ph), np.asarray(direc, np.float64)[both])
+    q = np.quantile(ang, [0.5, 0.9, 0.99, 0.999, 1.0]) if ang.size else np.zeros(5)
+    return {"misclassified_frac": float((flag != ref["flag"]).mean()),
+            "angle_err_rad": {"median": float(q[0]), "p90": float(q[1]), "p99": float(q[2]),
+                              "p999": float(q[3]), "max": float(q[4])},
+            "n_escaped_both": int(both.sum())}
