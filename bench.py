@@ -289,7 +289,7 @@ def bench_surrogate(args):
                        f"theta0={math.degrees(I.theta0):.1f}deg fov={math.degrees(I.fov):.1f}deg",
                        dict(base, M=I.M, a=I.a, Q=I.Q, r0=I.r0, theta0=I.theta0, fov=I.fov)))
     lines = []
-    for name, w in frames:
+    for name, w in frames[:args.surrogate_frames]:
         n = side * side
         ref = traced_frame(g, w, stream, g.GR_FP64)
         ctx = g.gr_trace_init(0, g.make_integrator(dt=w["dt"], max_steps=w["max_steps"]))
@@ -405,6 +405,8 @@ def main():
                     help="surrogate: labelled rays to train on")
     ap.add_argument("--train-epochs", type=int, default=12)
     ap.add_argument("--surrogate-side", type=int, default=4096)
+    ap.add_argument("--surrogate-frames", type=int, default=4,
+                    help="surrogate: how many of its frames to run (in order)")
     ap.add_argument("--skip-variants", action="store_true",
                     help="frame workload: time only the binary64 path")
     args = ap.parse_args()

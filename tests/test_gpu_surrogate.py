@@ -16,7 +16,6 @@ def test_trained_surrogate_gains_over_binary64_tracer():
 
     import paper_2310_15183_amd as g
     from paper_2310_15183_amd import surrogate as S
-    from paper_2310_15183_amd.evaluate import sky_at_escape  # noqa: F401  (import check)
 
     torch.cuda.set_device(0)
     data = S.training_set(1_000_000, seed=21)
