@@ -267,10 +267,14 @@ int gr_surrogate_targets(gr_ctx *ctx, const gr_instance *inst, int32_t n, const 
  * when |logit| < logit_min or a pixel within Chebyshev distance edge_px has
  * the other class; fallback pixels are re-traced by the context's binary64
  * tracer and their traced flag and escape-sphere direction replace the
- * network's.  *n_fallback (host, may be NULL) receives their number.
- * Workspace (about 65 B per pixel) is kept in the context.  Blocks the calling thread once, to read the
- * fallback count.  Errors: GR_EINVAL (also for networks on another device),
- * GR_EUNSUPPORTED (context not GR_FP64), GR_ENOMEM. */
+ * network's.  The whole frame is queued on hip_stream without waiting for
+ * the GPU (the fallback count stays on the device and sizes the retrace
+ * there) unless n_fallback (host) is non-NULL: then the call waits for the
+ * stream and stores the count.  Workspace (about 65 B per pixel) is kept in
+ * the context, so frames in flight at the same time need one context each;
+ * calls on one context must be ordered (same stream, or synchronised).
+ * Errors: GR_EINVAL (also for networks on another device), GR_EUNSUPPORTED
+ * (context not GR_FP64), GR_ENOMEM. */
 int gr_surrogate_frame(gr_ctx *ctx, gr_mlp *mlp, const gr_metric *m, const gr_camera *c,
                        float logit_min, int32_t edge_px, int8_t *flag, float *dir,
                        int8_t *fallback, int64_t *n_fallback, void *hip_stream);

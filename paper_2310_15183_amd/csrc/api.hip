@@ -211,6 +211,41 @@ int validate_batch(const gr_ctx* ctx, const gr_instance* inst, int32_t n) {
 }
 
 // Build and upload the instance table; returns the total ray count in *total.
+gr::BatchInstance batch_instance(const gr_ctx* ctx, const gr_instance* I) {
+    gr::BatchInstance B;
+    memset(&B, 0, sizeof B);
+    B.hole = gr::make_hole(I->metric.M, I->metric.a, I->metric.Q);
+    B.cam = gr::make_camera(B.hole, I->camera.r0, I->camera.theta0, I->camera.phi0,
+                            I->camera.fov, I->camera.width, I->camera.height);
+    B.r_esc = ctx->integ.escape_factor * I->camera.r0;
+    B.pixels = I->n_pixels < 0 ? nullptr : I->pixels;
+    B.out = out_ptrs(&I->out);
+    B.f32 = I->out.dtype == GR_F32;
+    return B;
+}
+
+// Device table capacity for m instances (m + 1 prefix offsets).
+int reserve_table(gr_ctx* ctx, int64_t m) {
+    if (m <= ctx->table_cap) return GR_OK;
+    const int64_t cap = std::max<int64_t>(m, 2 * ctx->table_cap);
+    gr::BatchInstance* t = nullptr;
+    int64_t* f = nullptr;
+    if (hipMalloc(&t, cap * sizeof(gr::BatchInstance)) != hipSuccess) return GR_ENOMEM;
+    if (hipMalloc(&f, (cap + 1) * sizeof(int64_t)) != hipSuccess) {
+        hipFree(t);
+        return GR_ENOMEM;
+    }
+    // the old table may still be read by queued work on another stream the
+    // caller synchronises; free after the device is idle for this context
+    hipDeviceSynchronize();
+    hipFree(ctx->table);
+    hipFree(ctx->firsts);
+    ctx->table = t;
+    ctx->firsts = f;
+    ctx->table_cap = cap;
+    return GR_OK;
+}
+
 int upload_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, int order,
                  hipStream_t s, int32_t* ninst, int64_t* total) {
     std::vector<int32_t> idx;
@@ -227,38 +262,14 @@ int upload_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, int order,
     std::vector<int64_t> firsts(m + 1, 0);
     for (int64_t q = 0; q < m; ++q) {
         const gr_instance* I = &inst[idx[q]];
-        gr::BatchInstance& B = tab[q];
-        memset(&B, 0, sizeof B);
-        B.hole = gr::make_hole(I->metric.M, I->metric.a, I->metric.Q);
-        B.cam = gr::make_camera(B.hole, I->camera.r0, I->camera.theta0, I->camera.phi0,
-                                I->camera.fov, I->camera.width, I->camera.height);
-        B.r_esc = ctx->integ.escape_factor * I->camera.r0;
-        B.pixels = I->n_pixels < 0 ? nullptr : I->pixels;
-        B.out = out_ptrs(&I->out);
-        B.f32 = I->out.dtype == GR_F32;
+        tab[q] = batch_instance(ctx, I);
         firsts[q + 1] = firsts[q] + instance_rays(I);
     }
     *ninst = (int32_t)m;
     *total = firsts[m];
     if (m == 0) return GR_OK;
-    if (m > ctx->table_cap) {
-        const int64_t cap = std::max<int64_t>(m, 2 * ctx->table_cap);
-        gr::BatchInstance* t = nullptr;
-        int64_t* f = nullptr;
-        if (hipMalloc(&t, cap * sizeof(gr::BatchInstance)) != hipSuccess) return GR_ENOMEM;
-        if (hipMalloc(&f, (cap + 1) * sizeof(int64_t)) != hipSuccess) {
-            hipFree(t);
-            return GR_ENOMEM;
-        }
-        // the old table may still be read by queued work on another stream the
-        // caller synchronises; free after the device is idle for this context
-        hipDeviceSynchronize();
-        hipFree(ctx->table);
-        hipFree(ctx->firsts);
-        ctx->table = t;
-        ctx->firsts = f;
-        ctx->table_cap = cap;
-    }
+    int rc = reserve_table(ctx, m);
+    if (rc) return rc;
     // pageable sources: the copies are staged before hipMemcpyAsync returns
     hipError_t e = hipMemcpyAsync(ctx->table, tab.data(), m * sizeof(gr::BatchInstance),
                                   hipMemcpyHostToDevice, s);
@@ -617,16 +628,11 @@ int gr_surrogate_frame(gr_ctx* ctx, gr_mlp* mlp, const gr_metric* m, const gr_ca
     e = gr::sur::fallback(ctx->sw_logit, flag, c->width, c->height, logit_min, edge_px, fallback,
                           ctx->sw_list, ctx->sw_count, s);
     if (e != hipSuccess) return device_error(e, "surrogate fallback selection");
-    // 3. re-trace the fallback pixels with the binary64 tracer and merge
-    unsigned long long count = 0;
-    e = hipMemcpyAsync(&count, ctx->sw_count, sizeof count, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return device_error(e, "fallback count");
-    if (n_fallback) *n_fallback = (int64_t)count;
-    if (count == 0) return GR_OK;
+    // 3. re-trace the fallback pixels with the binary64 tracer and merge, with
+    // the count left on the device: nothing here waits for the GPU
     gr_instance fb = frame;
     fb.pixels = ctx->sw_list;
-    fb.n_pixels = (int64_t)count;
+    fb.n_pixels = npix;                       // upper bound; the kernels read the count
     fb.out.theta = ctx->sw_out[0];
     fb.out.phi = ctx->sw_out[1];
     fb.out.r = ctx->sw_out[2];
@@ -636,10 +642,34 @@ int gr_surrogate_frame(gr_ctx* ctx, gr_mlp* mlp, const gr_metric* m, const gr_ca
     fb.out.p_phi = ctx->sw_out[6];
     fb.out.flag = ctx->sw_flag;
     fb.out.dtype = GR_F64;
-    rc = run_batch(ctx, &fb, 1, effective_launch(ctx), s);
+    rc = reserve_table(ctx, 1);
     if (rc) return rc;
-    e = gr::sur::merge(ctx->table, ctx->sw_list, (int64_t)count, flag, dir, s);
-    return e == hipSuccess ? GR_OK : device_error(e, "fallback merge");
+    const gr::BatchInstance B = batch_instance(ctx, &fb);
+    e = hipMemcpyAsync(ctx->table, &B, sizeof B, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = gr::sur::set_firsts(ctx->sw_count, ctx->firsts, s);
+    if (e != hipSuccess) return device_error(e, "fallback table");
+    gr::BatchArgs A;
+    memset(&A, 0, sizeof A);
+    A.in = device_integrator(ctx->integ);
+    A.inst = ctx->table;
+    A.firsts = ctx->firsts;
+    A.ninst = 1;
+    A.total = npix;
+    const gr_launch l = effective_launch(ctx);
+    const gr::LaunchShape L =
+        resident_shape(ctx, l, gr::occupancy_trace_fp64_batch(l.block), npix);
+    e = gr::launch_trace_fp64_batch(A, L, ctx->counter, s);
+    if (e != hipSuccess) return device_error(e, "fallback trace launch");
+    e = gr::sur::merge(ctx->table, ctx->sw_list, ctx->sw_count, npix, flag, dir, s);
+    if (e != hipSuccess) return device_error(e, "fallback merge");
+    if (n_fallback) {
+        unsigned long long count = 0;
+        e = hipMemcpyAsync(&count, ctx->sw_count, sizeof count, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return device_error(e, "fallback count");
+        *n_fallback = (int64_t)count;
+    }
+    return GR_OK;
 }
 
 int gr_trace_destroy(gr_ctx* ctx) {

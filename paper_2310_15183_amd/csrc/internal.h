@@ -58,7 +58,9 @@ struct BatchArgs {
     const BatchInstance* inst;  // device table, ninst entries
     const int64_t* firsts;      // device prefix offsets, ninst + 1 entries (firsts[0] = 0)
     int32_t ninst;
-    int64_t total;              // firsts[ninst]
+    int64_t total;              // rays on the host's side (launch shape; an upper bound when
+                                // firsts[ninst] is produced on the device); the kernel reads
+                                // the number of rays from firsts[ninst]
 };
 
 struct LaunchShape {

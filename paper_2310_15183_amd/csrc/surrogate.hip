@@ -12,6 +12,7 @@
 // velocity to r_esc).
 #include "internal.h"
 #include "mlp_internal.h"
+#include "step_fp64.h"
 #include "surrogate_internal.h"
 
 namespace gr {
@@ -231,44 +232,58 @@ frame_net_kernel(const BatchInstance I, int64_t npix, const mlp::NetView net,
 
 // A pixel falls back to RK4 when its logit is small or a pixel within
 // Chebyshev distance `edge` has the other class; fallback pixels are appended
-// to list (order unspecified).
+// to list with one atomic per wave (order unspecified).
 __global__ void fallback_kernel(const float* __restrict__ logit, const int8_t* __restrict__ flag,
                                 int32_t W, int32_t H, float logit_min, int32_t edge,
                                 int8_t* __restrict__ fb, int32_t* __restrict__ list,
                                 unsigned long long* __restrict__ count) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (int64_t)W * H) return;
-    const int i = (int)(p % W), j = (int)(p / W);
-    bool f = fabsf(logit[p]) < logit_min;
-    const int8_t mine = flag[p];
-    for (int dj = -edge; dj <= edge && !f; ++dj) {
-        const int jj = j + dj;
-        if (jj < 0 || jj >= H) continue;
-        for (int di = -edge; di <= edge; ++di) {
-            const int ii = i + di;
-            if (ii < 0 || ii >= W) continue;
-            if (flag[(int64_t)jj * W + ii] != mine) {
-                f = true;
-                break;
+    bool f = false;
+    if (p < (int64_t)W * H) {
+        const int i = (int)(p % W), j = (int)(p / W);
+        f = fabsf(logit[p]) < logit_min;
+        const int8_t mine = flag[p];
+        for (int dj = -edge; dj <= edge && !f; ++dj) {
+            const int jj = j + dj;
+            if (jj < 0 || jj >= H) continue;
+            for (int di = -edge; di <= edge; ++di) {
+                const int ii = i + di;
+                if (ii < 0 || ii >= W) continue;
+                if (flag[(int64_t)jj * W + ii] != mine) {
+                    f = true;
+                    break;
+                }
             }
         }
+        fb[p] = f ? 1 : 0;
     }
-    fb[p] = f ? 1 : 0;
-    if (f) list[atomicAdd(count, 1ull)] = (int32_t)p;
+    const int64_t slot = detail::take_ids(f, count);     // every lane of the wave takes part
+    if (f) list[slot] = (int32_t)p;
 }
 
-// Results of the re-traced pixels replace the network's.
+// Results of the re-traced pixels replace the network's; the number of
+// fallback pixels is read from the device (grid-stride over it).
 __global__ void merge_kernel(const BatchInstance* __restrict__ inst, const int32_t* __restrict__ list,
-                             int64_t n, int8_t* __restrict__ flag, float* __restrict__ dir) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
+                             const unsigned long long* __restrict__ count, int8_t* __restrict__ flag,
+                             float* __restrict__ dir) {
+    const int64_t n = (int64_t)*count;
     const BatchInstance& I = inst[0];
-    const int64_t p = list[k];
-    const int8_t f = I.out.flag[k];
-    flag[p] = f;
-    float u[3] = {0.f, 0.f, 0.f};
-    if (f == GR_FLAG_ESCAPE) escape_direction(I, k, u);
-    for (int c = 0; c < 3; ++c) dir[p * 3 + c] = u[c];
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = list[k];
+        const int8_t f = I.out.flag[k];
+        flag[p] = f;
+        float u[3] = {0.f, 0.f, 0.f};
+        if (f == GR_FLAG_ESCAPE) escape_direction(I, k, u);
+        for (int c = 0; c < 3; ++c) dir[p * 3 + c] = u[c];
+    }
+}
+
+// Prefix offsets of a one-instance batch whose size is the fallback count.
+__global__ void set_firsts_kernel(const unsigned long long* __restrict__ count,
+                                  int64_t* __restrict__ firsts) {
+    firsts[0] = 0;
+    firsts[1] = (int64_t)*count;
 }
 
 __global__ void zero_u64(unsigned long long* c) { *c = 0ull; }
@@ -311,10 +326,16 @@ hipError_t fallback(const float* logit, const int8_t* flag, int32_t W, int32_t H
     return hipGetLastError();
 }
 
-hipError_t merge(const BatchInstance* inst, const int32_t* list, int64_t n, int8_t* flag,
-                 float* dir, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(merge_kernel, dim3(blocks(n)), dim3(256), 0, s, inst, list, n, flag, dir);
+hipError_t set_firsts(const unsigned long long* count, int64_t* firsts, hipStream_t s) {
+    hipLaunchKernelGGL(set_firsts_kernel, dim3(1), dim3(1), 0, s, count, firsts);
+    return hipGetLastError();
+}
+
+hipError_t merge(const BatchInstance* inst, const int32_t* list, const unsigned long long* count,
+                 int64_t max_n, int8_t* flag, float* dir, hipStream_t s) {
+    if (max_n <= 0) return hipSuccess;
+    const unsigned grid = blocks(max_n) < 2048u ? blocks(max_n) : 2048u;
+    hipLaunchKernelGGL(merge_kernel, dim3(grid), dim3(256), 0, s, inst, list, count, flag, dir);
     return hipGetLastError();
 }
 

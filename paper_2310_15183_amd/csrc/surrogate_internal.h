@@ -25,8 +25,12 @@ hipError_t frame_net(const BatchInstance& I, int64_t npix, const mlp::NetView& n
 hipError_t fallback(const float* logit, const int8_t* flag, int32_t W, int32_t H,
                     float logit_min, int32_t edge, int8_t* fb, int32_t* list,
                     unsigned long long* count, hipStream_t s);
-hipError_t merge(const BatchInstance* inst, const int32_t* list, int64_t n, int8_t* flag,
-                 float* dir, hipStream_t s);
+// firsts[0] = 0, firsts[1] = *count (one-instance batch of the fallback list).
+hipError_t set_firsts(const unsigned long long* count, int64_t* firsts, hipStream_t s);
+// Traced flag and escape-sphere direction of the *count listed pixels
+// (count <= max_n) over the network's.
+hipError_t merge(const BatchInstance* inst, const int32_t* list, const unsigned long long* count,
+                 int64_t max_n, int8_t* flag, float* dir, hipStream_t s);
 
 }  // namespace sur
 }  // namespace gr

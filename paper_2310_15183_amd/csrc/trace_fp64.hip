@@ -101,6 +101,7 @@ __device__ __forceinline__ void write_batch(const BatchInstance& I, int64_t k, c
 
 __global__ void __launch_bounds__(256) trace_fp64_batch(const BatchArgs B,
                                                          unsigned long long* counter) {
+    const int64_t total = B.firsts[B.ninst];     // may be written on the device by an earlier kernel
     Ray y;
     Hole H;
     double r_esc = 0.0;
@@ -113,7 +114,7 @@ __global__ void __launch_bounds__(256) trace_fp64_batch(const BatchArgs B,
         const int64_t id = take_ids(want, counter);
         if (want) {
             want = false;
-            if (id < B.total) {
+            if (id < total) {
                 inst = find_instance(B, id);
                 const BatchInstance& I = B.inst[inst];
                 k = id - B.firsts[inst];

@@ -246,3 +246,42 @@ def test_fused_frame_network_matches_forward(g, net):
     nn = (v32[:, 0] * v32[:, 0] + v32[:, 1] * v32[:, 1]) + v32[:, 2] * v32[:, 2]
     exact = np.all(got_dir[both] == v32[both] * (np.float32(1) / np.sqrt(nn[both]))[:, None], axis=1)
     print(f"escaped {esc.mean():.3f}; directions bit-identical to the unfused path: {exact.mean():.4f}")
+
+
+def test_asynchronous_frames_on_two_streams_equal_the_synchronous_frame(g):
+    """Frames queued without waiting (count left on the device), two contexts
+    on two streams in flight at once, give the synchronous call's result."""
+    import torch
+    ctxs = [g.gr_trace_init(0, g.make_integrator(dt=0.01, max_steps=20000)) for _ in range(3)]
+    net = g.gr_mlp_create(0, 1024)
+    try:
+        g.gr_mlp_init(net, 5)
+        p = g.gr_mlp_get_params(net)
+        p[-4] = 0.0                                     # logit bias: both classes, some |logit| < 1
+        g.gr_mlp_set_params(net, p)
+        W, H = 64, 48
+        metric = g.gr_metric(0.5, 0.3, 0.2)
+        cam = g.gr_camera(20.0, 75 * DEG, 0.0, 60 * DEG, W, H)
+
+        def bufs():
+            return (torch.full((W * H,), 9, dtype=torch.int8, device="cuda"),
+                    torch.full((W * H, 3), 9.0, device="cuda"),
+                    torch.full((W * H,), 9, dtype=torch.int8, device="cuda"))
+        ref = bufs()
+        nfb = g.gr_surrogate_frame(ctxs[0], net, metric, cam, 1.0, 1, *ref)
+        assert 0 < nfb < W * H
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        outs = [bufs(), bufs()]
+        torch.cuda.synchronize()
+        for k in range(2):
+            assert g.gr_surrogate_frame(ctxs[1 + k], net, metric, cam, 1.0, 1, *outs[k],
+                                        streams[k], count=False) == -1
+        torch.cuda.synchronize()
+        for o in outs:
+            for a, b in zip(o, ref):
+                assert torch.equal(a, b)
+        assert int(ref[2].sum().item()) == nfb
+    finally:
+        g.gr_mlp_destroy(net)
+        for c in ctxs:
+            g.gr_trace_destroy(c)
