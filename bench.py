@@ -14,7 +14,7 @@ black-hole inputs of this configuration are binary32); state is binary64;
 end coordinates are stored as binary32 with an int8 flag.
 
 The roofline object reports the tracing kernel against the MI355X FP64
-vector peak: achieved = algorithmic flops per launch (693 per ray-step times
+vector peak: achieved = algorithmic flops per launch (697 per ray-step times
 the ray-steps of the launch, read from the kernel's own step counts) divided
 by the launch's duration measured with HIP events on the launch stream.
 """
@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "geodesic rays/s @1000² Kerr: FP64 vs mixed vs surrogate, ≤1e-4 rad err"
-FLOPS_PER_RAY_STEP = 693          # binary64 ops of one RK4 step (add/sub/mul/div 1, fma 2)
+FLOPS_PER_RAY_STEP = 697          # binary64 ops of one RK4 step (add/sub/mul/div 1, fma 2)
 FP64_PEAK_TFLOPS = 78.6           # MI355X FP64 vector (256 CU x 128 flop/clk x 2.4 GHz)
 BF16_PEAK_TFLOPS = 2500.0         # MI355X dense bfloat16 MFMA
 KERNEL_SOURCES = ["paper_2310_15183_amd/csrc/trace_fp64.hip",
@@ -216,7 +216,8 @@ def train_surrogate(g, args):
     return net, info
 
 
-def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3.0, edge=2):
+def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3.0, edge=2,
+                      max_turn=None):
     """Surrogate + RK4 fallback on the frame w: rays/s, speedup over the
     binary64 tracer on the same frame and integrator, the network-only frame
     time against the MFMA peak, and the errors against the binary64 frame."""
@@ -234,19 +235,25 @@ def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3
     direc = torch.empty(n, 3, device="cuda")
     fb = torch.empty(n, dtype=torch.int8, device="cuda")
 
-    def run(lmin, e, steps, warmup):
+    if max_turn is None:
+        max_turn = args.max_turn
+
+    def run(lmin, e, turn, steps, warmup):
         nfb = 0
         for _ in range(warmup):
-            nfb = g.gr_surrogate_frame(ctx, net, metric, cam, lmin, e, flag, direc, fb, stream)
+            nfb = g.gr_surrogate_frame(ctx, net, metric, cam, lmin, e, flag, direc, fb, stream,
+                                       max_turn=turn)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            nfb = g.gr_surrogate_frame(ctx, net, metric, cam, lmin, e, flag, direc, fb, stream)
+            nfb = g.gr_surrogate_frame(ctx, net, metric, cam, lmin, e, flag, direc, fb, stream,
+                                       max_turn=turn)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps, nfb
 
-    net_s, _ = run(0.0, 0, args.steps, args.warmup)          # network only, no fallback
-    wall, nfb = run(logit_min, edge, args.steps, args.warmup)
+    net_s, _ = run(0.0, 0, 0.0, args.steps, args.warmup)     # network only, no fallback
+    net_flag, net_dir = flag.cpu().numpy(), direc.cpu().numpy()
+    wall, nfb = run(logit_min, edge, max_turn, args.steps, args.warmup)
     g.gr_trace_destroy(ctx)
 
     # many frames in flight: one context and stream each, nothing waits for the
@@ -264,20 +271,23 @@ def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3
     torch.cuda.synchronize()
     for j in range(nstreams):
         g.gr_surrogate_frame(ctxs[j], net, metric, cam, logit_min, edge, *bufs[j], streams[j],
-                             count=False)
+                             count=False, max_turn=max_turn)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(nframes):
         j = k % nstreams
         g.gr_surrogate_frame(ctxs[j], net, metric, cam, logit_min, edge, *bufs[j], streams[j],
-                             count=False)
+                             count=False, max_turn=max_turn)
     torch.cuda.synchronize()
     pipe_s = (time.perf_counter() - t0) / nframes
     for c in ctxs:
         g.gr_trace_destroy(c)
     del bufs
-    err = S.frame_errors(w["M"], w["a"], w["Q"], w["escape_factor"] * w["r0"], ref,
-                         flag.cpu().numpy(), direc.cpu().numpy())
+    got_flag, got_dir, got_fb = flag.cpu().numpy(), direc.cpu().numpy(), fb.cpu().numpy()
+    err = S.frame_errors(w["M"], w["a"], w["Q"], w["escape_factor"] * w["r0"], ref, got_flag,
+                         got_dir)
+    # the network's own error on the pixels the fallback re-traced (known at run time)
+    online = S.online_errors(net_flag, net_dir, got_flag, got_dir, got_fb)
     rays_s = n / wall
     tflops = S.FLOPS_PER_RAY * n / net_s / 1e12
     return {"rays_per_s": rays_s, "ms_per_step": wall * 1e3,
@@ -285,9 +295,11 @@ def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3
             "pipelined": {"streams": nstreams, "frames": nframes, "ms_per_frame": pipe_s * 1e3,
                           "rays_per_s": n / pipe_s,
                           "speedup_vs_fp64": n / pipe_s / fp64_rays_per_s},
-            "fallback": {"rule": f"|logit| < {logit_min} or a pixel within Chebyshev "
-                                 f"distance {edge} of the other predicted class",
-                         "pixels": int(nfb), "frac": nfb / n},
+            "fallback": {"rule": f"|logit| < {logit_min}, a pixel within Chebyshev "
+                                 f"distance {edge} of the other predicted class"
+                                 + (f", or an escaping 8-neighbour's direction more than "
+                                    f"{max_turn} rad away" if max_turn > 0 else ""),
+                         "pixels": int(nfb), "frac": nfb / n, "online": online},
             "network_only_ms": net_s * 1e3,
             "network_mfma": {"achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                              "frac": tflops / BF16_PEAK_TFLOPS,
@@ -436,6 +448,9 @@ def main():
                     help="surrogate: labelled rays to train on")
     ap.add_argument("--train-epochs", type=int, default=12)
     ap.add_argument("--surrogate-side", type=int, default=4096)
+    ap.add_argument("--max-turn", type=float, default=0.0,
+                    help="surrogate: also re-trace pixels whose predicted direction differs "
+                         "from an escaping neighbour's by more than this (rad; 0: off)")
     ap.add_argument("--surrogate-frames", type=int, default=4,
                     help="surrogate: how many of its frames to run (in order)")
     ap.add_argument("--skip-variants", action="store_true",

@@ -63,6 +63,8 @@ def _load():
         lib.oracle_set_trig_mode.argtypes = [i]
         lib.oracle_sincos.restype = None
         lib.oracle_sincos.argtypes = [vp, i64, vp]
+        lib.oracle_recip_newton.restype = None
+        lib.oracle_recip_newton.argtypes = [vp, vp, i64, vp]
         lib.oracle_rhs.restype = None
         lib.oracle_rhs.argtypes = [d, d, d, d, d, d, d, d, d, d, vp, vp]
         _lib = lib
@@ -165,6 +167,16 @@ def rhs(M, a, Q, r, theta, p, eps=1e-8):
 def set_trig_mode(mode: int) -> None:
     """0: sin/cos from their series definition (default); 1: the C library."""
     _load().oracle_set_trig_mode(int(mode))
+
+
+def recip_newton(x, y0) -> np.ndarray:
+    """The oracle's Newton-refined reciprocal of x from y0 (an exact 1/x0 of a
+    nearby x0), elementwise."""
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    y0 = np.ascontiguousarray(y0, dtype=np.float64).ravel()
+    out = np.empty_like(x)
+    _load().oracle_recip_newton(_ptr(x), _ptr(y0), x.size, _ptr(out))
+    return out
 
 
 def sincos(x) -> tuple[np.ndarray, np.ndarray]:

@@ -136,24 +136,54 @@ static void sincos_mode(int mode, double x, double *s, double *c)
  *
  * The sequence of roundings is fixed (it matters: the forward difference
  * divides rounding noise by eps).  sin^2 and cos^2 are passed in so that the
- * same rounded values serve every evaluation at one theta. */
-static void inverse_metric(const oracle_params *P, double r, double s2, double c2,
-                           double g[5])
+ * same rounded values serve every evaluation at one theta.  The components
+ * share the reciprocals inv = 1/(rho^2 Delta) and is = inv / sin^2 (see
+ * metric_recips for how they are formed). */
+static void metric_from(const oracle_params *P, double r, double s2, double inv, double is,
+                        double g[5])
 {
     const double a2 = P->a * P->a;
     const double r2 = r * r;
     const double ra = r2 + a2;                                 /* r^2 + a^2 */
-    const double rho2 = fma(a2, c2, r2);                       /* r^2 + a^2 cos^2 */
     const double Delta = fma(r, r - 2.0 * P->M, a2 + P->Q * P->Q);
     const double w = a2 * s2;                                  /* a^2 sin^2 */
     const double Sigma2 = fma(-w, Delta, ra * ra);
-    const double inv = 1.0 / (rho2 * Delta);                   /* 1/(rho^2 Delta) */
-    const double is2 = 1.0 / s2;
     g[0] = -(Sigma2 * inv);
     g[1] = -((P->a * fma(2.0 * P->M, r, -(P->Q * P->Q))) * inv);
     g[2] = (Delta * Delta) * inv;
     g[3] = Delta * inv;
-    g[4] = ((Delta - w) * inv) * is2;
+    g[4] = (Delta - w) * is;
+}
+
+/* rho^2 Delta at (r, theta). */
+static double rho2_delta(const oracle_params *P, double r, double c2)
+{
+    const double a2 = P->a * P->a;
+    const double rho2 = fma(a2, c2, r * r);                    /* r^2 + a^2 cos^2 */
+    const double Delta = fma(r, r - 2.0 * P->M, a2 + P->Q * P->Q);
+    return rho2 * Delta;
+}
+
+/* 1/x from y0 = 1/x0 for a nearby x0: two Newton steps y <- y + y (1 - x y).
+ * Each squares the relative error e0 = 1 - x y0; for the displacements of the
+ * forward differences |e0| is about eps times a logarithmic derivative of
+ * rho^2 Delta (below 1e-4 even at the horizon cutoff), so e0^4 is at or below
+ * the rounding of the result. */
+static double recip_newton(double x, double y0)
+{
+    double e = fma(-x, y0, 1.0);
+    const double y = fma(y0, e, y0);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+/* Full inverse metric at one point: is = 1/(rho^2 Delta sin^2) divided,
+ * inv = is sin^2. */
+static void inverse_metric(const oracle_params *P, double r, double s2, double c2,
+                           double g[5])
+{
+    const double is = 1.0 / (rho2_delta(P, r, c2) * s2);
+    metric_from(P, r, s2, is * s2, is, g);
 }
 
 /* g^{mu nu} at (r, theta) from the angle itself (the listing's metricAtPoint). */
@@ -179,11 +209,21 @@ static void hamilton_rhs(const oracle_params *P, const double eps_sc[2], double 
 {
     double s, c, g[5], gr[5], gth[5];
     sincos_mode(P->trig_mode, theta, &s, &c);
-    inverse_metric(P, r, s * s, c * c, g);
-    inverse_metric(P, r + P->eps, s * s, c * c, gr);
     const double se = fma(c, eps_sc[0], s * eps_sc[1]);      /* sin(theta + eps) */
     const double ce = fma(-s, eps_sc[0], c * eps_sc[1]);     /* cos(theta + eps) */
-    inverse_metric(P, r, se * se, ce * ce, gth);
+    const double s2 = s * s, c2 = c * c, se2 = se * se, ce2 = ce * ce;
+    /* reciprocals (two divisions): at (r, theta) is = 1/(rho^2 Delta sin^2)
+     * and inv = is sin^2; at (r + eps, theta) is refined from the base point's;
+     * at (r, theta + eps) 1/(rho^2 Delta) is refined from inv and multiplied
+     * by a divided 1/sin^2 (near the axis sin^2 changes by a large factor
+     * over eps, rho^2 Delta never does) */
+    const double is = 1.0 / (rho2_delta(P, r, c2) * s2);
+    const double inv = is * s2;
+    const double is_r = recip_newton(rho2_delta(P, r + P->eps, c2) * s2, is);
+    const double inv_t = recip_newton(rho2_delta(P, r, ce2), inv);
+    metric_from(P, r, s2, inv, is, g);
+    metric_from(P, r + P->eps, s2, is_r * s2, is_r, gr);
+    metric_from(P, r, se2, inv_t, inv_t * (1.0 / se2), gth);
 
     /* weights p_nu p_sigma of the five independent components */
     const double wtt = pt * pt, wtp = (2.0 * pt) * pph, wpp = pph * pph;
@@ -406,6 +446,12 @@ void oracle_sincos(const double *x, int64_t n, double *sc)
 {
     pthread_once(&trig_once, trig_init);
     for (int64_t k = 0; k < n; ++k) trig_sincos(x[k], sc + 2 * k, sc + 2 * k + 1);
+}
+
+/* Accuracy checks of the Newton-refined reciprocal: out[k] = recip_newton(x[k], y0[k]). */
+void oracle_recip_newton(const double *x, const double *y0, int64_t n, double *out)
+{
+    for (int64_t k = 0; k < n; ++k) out[k] = recip_newton(x[k], y0[k]);
 }
 
 static oracle_params make_params(double M, double a, double Q, double dt, double eps,

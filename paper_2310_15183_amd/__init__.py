@@ -98,7 +98,7 @@ def _load():
         "gr_surrogate_inputs": (ctypes.c_int, [vp, P(gr_instance), ctypes.c_int32, vp, vp, vp]),
         "gr_surrogate_targets": (ctypes.c_int, [vp, P(gr_instance), ctypes.c_int32, vp, vp, vp]),
         "gr_surrogate_frame": (ctypes.c_int, [vp, vp, P(gr_metric), P(gr_camera), ctypes.c_float,
-                                              ctypes.c_int32, vp, vp, vp,
+                                              ctypes.c_int32, ctypes.c_float, vp, vp, vp,
                                               P(ctypes.c_int64), vp]),
     }
     for name, (res, args) in sig.items():
@@ -319,12 +319,13 @@ def gr_surrogate_targets(ctx, instances, u_flat, target, stream=None):
 
 
 def gr_surrogate_frame(ctx, mlp, metric, camera, logit_min, edge_px, flag, direction, fallback,
-                       stream=None, count=True) -> int:
+                       stream=None, count=True, max_turn=0.0) -> int:
     """Returns the number of fallback pixels; with count=False the call does not
     wait for the GPU and returns -1."""
     nfb = ctypes.c_int64(-1)
     _check(_lib.gr_surrogate_frame(ctx, mlp, ctypes.byref(metric), ctypes.byref(camera),
-                                   float(logit_min), int(edge_px), _p(flag), _p(direction),
+                                   float(logit_min), int(edge_px), float(max_turn), _p(flag),
+                                   _p(direction),
                                    _p(fallback), ctypes.byref(nfb) if count else None,
                                    _stream_handle(stream)),
            "gr_surrogate_frame")

@@ -596,13 +596,15 @@ int gr_surrogate_targets(gr_ctx* ctx, const gr_instance* inst, int32_t n, const 
 }
 
 int gr_surrogate_frame(gr_ctx* ctx, gr_mlp* mlp, const gr_metric* m, const gr_camera* c,
-                       float logit_min, int32_t edge_px, int8_t* flag, float* dir,
+                       float logit_min, int32_t edge_px, float max_turn, int8_t* flag, float* dir,
                        int8_t* fallback, int64_t* n_fallback, void* hip_stream) {
     if (!ctx || !mlp || !flag || !dir || !fallback) return GR_EINVAL;
     int rc = check_metric(m);
     if (!rc) rc = check_camera(m, c);
     if (rc) return rc;
     if (!(logit_min >= 0.0f) || edge_px < 0 || edge_px > 16) return GR_EINVAL;
+    if (!(max_turn >= 0.0f && max_turn <= 3.14159265f)) return GR_EINVAL;
+    const float chord = max_turn > 0.0f ? 2.0f * sinf(0.5f * max_turn) : 0.0f;
     if (ctx->integ.precision != GR_FP64) return GR_EUNSUPPORTED;
     if (gr_mlp_device_of(mlp) != ctx->device) return GR_EINVAL;
     const int64_t npix = (int64_t)c->width * c->height;
@@ -625,8 +627,8 @@ int gr_surrogate_frame(gr_ctx* ctx, gr_mlp* mlp, const gr_metric* m, const gr_ca
     hipError_t e = gr::sur::frame_net(I, npix, gr_mlp_view(mlp), flag, dir, ctx->sw_logit, s);
     if (e != hipSuccess) return device_error(e, "surrogate network");
     // 2. pixels to re-trace: small logits and class edges
-    e = gr::sur::fallback(ctx->sw_logit, flag, c->width, c->height, logit_min, edge_px, fallback,
-                          ctx->sw_list, ctx->sw_count, s);
+    e = gr::sur::fallback(ctx->sw_logit, flag, dir, c->width, c->height, logit_min, edge_px,
+                          chord * chord, fallback, ctx->sw_list, ctx->sw_count, s);
     if (e != hipSuccess) return device_error(e, "surrogate fallback selection");
     // 3. re-trace the fallback pixels with the binary64 tracer and merge, with
     // the count left on the device: nothing here waits for the GPU

@@ -89,14 +89,13 @@ GR_HD Hole make_hole(double M, double a, double Q) {
 
 // Terms of the metric that depend on theta only.
 struct ThetaTerms {
-    double s2, c2, is2, w;     // sin^2, cos^2, 1/sin^2, a^2 sin^2
+    double s2, c2, w;          // sin^2, cos^2, a^2 sin^2
 };
 
 GR_HD ThetaTerms theta_terms_sc(const Hole& H, double s, double c) {
     ThetaTerms T;
     T.s2 = s * s;
     T.c2 = c * c;
-    T.is2 = 1.0 / T.s2;
     T.w = H.a2 * T.s2;
     return T;
 }
@@ -132,17 +131,41 @@ struct InvMetric {
     double tt, tp, rr, hh, pp;
 };
 
-GR_HD InvMetric inverse_metric(const Hole& H, const RadialTerms& R, const ThetaTerms& T) {
-    const double rho2 = fma(H.a2, T.c2, R.r2);
+// rho2 Delta at (r-terms, theta-terms).
+GR_HD double rho2_delta(const Hole& H, const RadialTerms& R, const ThetaTerms& T) {
+    return fma(H.a2, T.c2, R.r2) * R.Delta;
+}
+
+// The five components from the shared reciprocals inv = 1/(rho2 Delta) and
+// is = 1/(rho2 Delta sin^2).
+GR_HD InvMetric metric_from(const Hole& H, const RadialTerms& R, const ThetaTerms& T,
+                            double inv, double is) {
     const double Sigma2 = fma(-T.w, R.Delta, R.rara);
-    const double inv = 1.0 / (rho2 * R.Delta);
     InvMetric g;
     g.tt = -(Sigma2 * inv);
     g.tp = -(R.aF * inv);
     g.rr = R.DD * inv;
     g.hh = R.Delta * inv;
-    g.pp = ((R.Delta - T.w) * inv) * T.is2;
+    g.pp = (R.Delta - T.w) * is;
     return g;
+}
+
+// Full inverse metric at one point: is divided, inv = is sin^2.
+GR_HD InvMetric inverse_metric(const Hole& H, const RadialTerms& R, const ThetaTerms& T) {
+    const double is = 1.0 / (rho2_delta(H, R, T) * T.s2);
+    return metric_from(H, R, T, is * T.s2, is);
+}
+
+// 1/x from y0 = 1/x0 for a nearby x0: two Newton steps y <- y + y (1 - x y).
+// Each squares the relative error e0 = 1 - x y0; for the displacements of the
+// forward differences |e0| is about eps times a logarithmic derivative of
+// rho2 Delta (below 1e-4 even at the horizon cutoff), so e0^4 is at or below
+// the rounding of the result.
+GR_HD double recip_newton(double x, double y0) {
+    double e = fma(-x, y0, 1.0);
+    const double y = fma(y0, e, y0);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
 }
 
 // ----------------------------------------------------------------- camera

@@ -19,6 +19,11 @@ struct Deriv {
 // (r, th+eps), sin/cos at th+eps by angle addition from those at th and eps;
 // p-dot = -1/(2 eps) times the sum of the five component differences times
 // p_nu p_sigma, in the order tt, tphi (weight 2 p_t p_phi), rr, thth, phph.
+// Two divisions per stage: is = 1/(rho2 Delta sin^2) at (r, th), inv = is
+// sin^2; at (r+eps, th) is refined from the base point's by Newton steps; at
+// (r, th+eps) 1/(rho2 Delta) is refined from inv and multiplied by a divided
+// 1/sin^2 (near the axis sin^2 changes by a large factor over eps, rho2 Delta
+// never does).
 static __device__ __forceinline__ Deriv rhs(const Hole& H, const Integrator& in, double r,
                                             double th, double pt, double pr, double pth,
                                             double pph, double wtt, double wtp, double wpp) {
@@ -29,9 +34,13 @@ static __device__ __forceinline__ Deriv rhs(const Hole& H, const Integrator& in,
                                          fma(-s, in.sin_eps, c * in.cos_eps));
     const RadialTerms R0 = radial_terms(H, r);
     const RadialTerms R1 = radial_terms(H, r + in.eps);
-    const InvMetric g = inverse_metric(H, R0, T0);
-    const InvMetric gr = inverse_metric(H, R1, T0);
-    const InvMetric gh = inverse_metric(H, R0, T1);
+    const double is = 1.0 / (rho2_delta(H, R0, T0) * T0.s2);
+    const double inv = is * T0.s2;
+    const double is_r = recip_newton(rho2_delta(H, R1, T0) * T0.s2, is);
+    const double inv_t = recip_newton(rho2_delta(H, R0, T1), inv);
+    const InvMetric g = metric_from(H, R0, T0, inv, is);
+    const InvMetric gr = metric_from(H, R1, T0, is_r * T0.s2, is_r);
+    const InvMetric gh = metric_from(H, R0, T1, inv_t, inv_t * (1.0 / T1.s2));
 
     const double wrr = pr * pr, wth = pth * pth;
     double acc = (gr.tt - g.tt) * wtt;

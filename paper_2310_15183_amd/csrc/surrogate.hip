@@ -230,11 +230,15 @@ frame_net_kernel(const BatchInstance I, int64_t npix, const mlp::NetView net,
     }
 }
 
-// A pixel falls back to RK4 when its logit is small or a pixel within
-// Chebyshev distance `edge` has the other class; fallback pixels are appended
-// to list with one atomic per wave (order unspecified).
+// A pixel falls back to RK4 when its logit is small, a pixel within
+// Chebyshev distance `edge` has the other class, or (max_chord2 > 0) an
+// escaping pixel and an escaping 8-neighbour have predicted directions more
+// than sqrt(max_chord2) apart (chord of unit vectors): the image is strongly
+// magnified there and the network's direction least reliable.  Fallback
+// pixels are appended to list with one atomic per wave (order unspecified).
 __global__ void fallback_kernel(const float* __restrict__ logit, const int8_t* __restrict__ flag,
-                                int32_t W, int32_t H, float logit_min, int32_t edge,
+                                const float* __restrict__ dir, int32_t W, int32_t H,
+                                float logit_min, int32_t edge, float max_chord2,
                                 int8_t* __restrict__ fb, int32_t* __restrict__ list,
                                 unsigned long long* __restrict__ count) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -252,6 +256,25 @@ __global__ void fallback_kernel(const float* __restrict__ logit, const int8_t* _
                 if (flag[(int64_t)jj * W + ii] != mine) {
                     f = true;
                     break;
+                }
+            }
+        }
+        if (!f && max_chord2 > 0.0f && mine == GR_FLAG_ESCAPE) {
+            const float u0 = dir[p * 3], u1 = dir[p * 3 + 1], u2 = dir[p * 3 + 2];
+            for (int dj = -1; dj <= 1 && !f; ++dj) {
+                const int jj = j + dj;
+                if (jj < 0 || jj >= H) continue;
+                for (int di = -1; di <= 1; ++di) {
+                    const int ii = i + di;
+                    if (ii < 0 || ii >= W) continue;
+                    const int64_t q = (int64_t)jj * W + ii;
+                    if (flag[q] != GR_FLAG_ESCAPE) continue;
+                    const float d0 = dir[q * 3] - u0, d1 = dir[q * 3 + 1] - u1,
+                                d2 = dir[q * 3 + 2] - u2;
+                    if ((d0 * d0 + d1 * d1) + d2 * d2 > max_chord2) {
+                        f = true;
+                        break;
+                    }
                 }
             }
         }
@@ -317,12 +340,12 @@ hipError_t frame_net(const BatchInstance& I, int64_t npix, const mlp::NetView& n
     return hipGetLastError();
 }
 
-hipError_t fallback(const float* logit, const int8_t* flag, int32_t W, int32_t H,
-                    float logit_min, int32_t edge, int8_t* fb, int32_t* list,
-                    unsigned long long* count, hipStream_t s) {
+hipError_t fallback(const float* logit, const int8_t* flag, const float* dir, int32_t W,
+                    int32_t H, float logit_min, int32_t edge, float max_chord2, int8_t* fb,
+                    int32_t* list, unsigned long long* count, hipStream_t s) {
     hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, s, count);
     hipLaunchKernelGGL(fallback_kernel, dim3(blocks((int64_t)W * H)), dim3(256), 0, s, logit, flag,
-                       W, H, logit_min, edge, fb, list, count);
+                       dir, W, H, logit_min, edge, max_chord2, fb, list, count);
     return hipGetLastError();
 }
 

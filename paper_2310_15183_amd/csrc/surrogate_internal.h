@@ -22,9 +22,9 @@ hipError_t targets(const BatchInstance* inst, const int64_t* firsts, int ninst, 
 // launch, keeping each escape logit for the fallback selection.
 hipError_t frame_net(const BatchInstance& I, int64_t npix, const mlp::NetView& net,
                      int8_t* flag, float* dir, float* logit, hipStream_t s);
-hipError_t fallback(const float* logit, const int8_t* flag, int32_t W, int32_t H,
-                    float logit_min, int32_t edge, int8_t* fb, int32_t* list,
-                    unsigned long long* count, hipStream_t s);
+hipError_t fallback(const float* logit, const int8_t* flag, const float* dir, int32_t W,
+                    int32_t H, float logit_min, int32_t edge, float max_chord2, int8_t* fb,
+                    int32_t* list, unsigned long long* count, hipStream_t s);
 // firsts[0] = 0, firsts[1] = *count (one-instance batch of the fallback list).
 hipError_t set_firsts(const unsigned long long* count, int64_t* firsts, hipStream_t s);
 // Traced flag and escape-sphere direction of the *count listed pixels

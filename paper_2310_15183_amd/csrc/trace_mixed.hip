@@ -17,7 +17,9 @@
 //    identity in binary64 (cos eps rounds to 1, sin eps to eps), so both
 //    evaluations of the theta difference see one consistent angle and the
 //    step is exactly eps;
-//  - reciprocals use v_rcp_f64 refined by two Newton steps (about 1 ulp);
+//  - the metric's reciprocals follow the binary64 tracer's scheme with
+//    v_rcp_f64 refined by two Newton steps (about 1 ulp) in place of its two
+//    divisions per stage;
 //    the binary32 step divides by |dt/dtau| with v_rcp_f32;
 //  - 1/eps is folded into the binary32 contraction weights.
 // A ray switches to whole binary64 steps (the binary64 tracer's own step)
@@ -47,23 +49,8 @@ __device__ __forceinline__ ThetaTerms theta_from(const Hole& H, double s, double
     ThetaTerms T;
     T.s2 = s * s;
     T.c2 = c * c;
-    T.is2 = rcp_nr(T.s2);
     T.w = H.a2 * T.s2;
     return T;
-}
-
-__device__ __forceinline__ InvMetric metric_fast(const Hole& H, const RadialTerms& R,
-                                                 const ThetaTerms& T) {
-    const double rho2 = fma(H.a2, T.c2, R.r2);
-    const double Sigma2 = fma(-T.w, R.Delta, R.rara);
-    const double inv = rcp_nr(rho2 * R.Delta);
-    InvMetric g;
-    g.tt = -(Sigma2 * inv);
-    g.tp = -(R.aF * inv);
-    g.rr = R.DD * inv;
-    g.hh = R.Delta * inv;
-    g.pp = ((R.Delta - T.w) * inv) * T.is2;
-    return g;
 }
 
 struct DerivF {
@@ -112,9 +99,15 @@ __device__ __forceinline__ DerivF rhs_mixed(const Hole& H, double eps, float r, 
     const ThetaTerms T1 = theta_from(H, fma(eps, c, s), fma(-eps, s, c));
     const RadialTerms R0 = radial_terms(H, (double)r);
     const RadialTerms R1 = radial_terms(H, (double)r + eps);
-    const InvMetric g = metric_fast(H, R0, T0);
-    const InvMetric gr = metric_fast(H, R1, T0);
-    const InvMetric gh = metric_fast(H, R0, T1);
+    // the binary64 tracer's reciprocal scheme, with v_rcp_f64 and two Newton
+    // steps in place of its two divisions
+    const double is = rcp_nr(rho2_delta(H, R0, T0) * T0.s2);
+    const double inv = is * T0.s2;
+    const double is_r = recip_newton(rho2_delta(H, R1, T0) * T0.s2, is);
+    const double inv_t = recip_newton(rho2_delta(H, R0, T1), inv);
+    const InvMetric g = metric_from(H, R0, T0, inv, is);
+    const InvMetric gr = metric_from(H, R1, T0, is_r * T0.s2, is_r);
+    const InvMetric gh = metric_from(H, R0, T1, inv_t, inv_t * rcp_nr(T1.s2));
 
     const float wrr = (pr * pr) * K.ie, wth = (pth * pth) * K.ie;
     float acc = dq(gr.tt, g.tt) * K.wtt;

@@ -149,3 +149,19 @@ def frame_errors(M, a, Q, r_esc, ref, flag, direc):
             "angle_err_rad": {"median": float(q[0]), "p90": float(q[1]), "p99": float(q[2]),
                               "p999": float(q[3]), "max": float(q[4])},
             "n_escaped_both": int(both.sum())}
+
+
+def online_errors(net_flag, net_dir, flag, direc, fallback):
+    """The network's own error where the fallback re-traced: class changes and
+    the great-circle error of its direction on re-traced pixels that escaped
+    in both (what a run can report without a reference frame)."""
+    fbm = np.asarray(fallback) == 1
+    if not fbm.any():
+        return {"pixels": 0}
+    nf, f = np.asarray(net_flag)[fbm], np.asarray(flag)[fbm]
+    both = (nf == g.GR_FLAG_ESCAPE) & (f == g.GR_FLAG_ESCAPE)
+    ang = angle_between(np.asarray(net_dir, np.float64)[fbm][both],
+                        np.asarray(direc, np.float64)[fbm][both])
+    q = np.quantile(ang, [0.5, 0.99]) if ang.size else np.zeros(2)
+    return {"pixels": int(fbm.sum()), "class_changed_frac": float((nf != f).mean()),
+            "angle_err_rad": {"median": float(q[0]), "p99": float(q[1])}}

@@ -46,6 +46,27 @@ def test_sincos_definition_is_within_1p5_ulp():
     assert s0[0] == 0.0 and c0[0] == 1.0
 
 
+def test_newton_reciprocal_is_correctly_rounded_for_small_displacements():
+    """The displaced points' reciprocals (two Newton steps from the base
+    point's exact reciprocal) are correctly rounded for relative
+    displacements up to 3e-5 and within 1.5 ulp up to 1e-4, the largest the
+    forward differences produce (at the horizon cutoff)."""
+    rng = np.random.default_rng(3)
+    x0 = 10.0 ** rng.uniform(-6, 6, 4000)
+    rel = np.concatenate([rng.uniform(-1e-4, 1e-4, 2000), 10.0 ** rng.uniform(-12, -4, 2000)])
+    x = x0 * (1.0 + rel)
+    y0 = 1.0 / x0
+    got = oracle.recip_newton(x, y0)
+    mp.mp.prec = 120
+    err = np.array([float(abs(mp.mpf(g) - 1 / mp.mpf(xi))) / np.spacing(float(1 / mp.mpf(xi)))
+                    for g, xi in zip(got, x)])
+    assert err[np.abs(rel) <= 3e-5].max() <= 0.5 + 1e-9
+    assert err.max() <= 1.5
+    # a large displacement is not what the refinement is for: two steps leave e0^4
+    far = oracle.recip_newton(np.array([1.1]), np.array([1.0]))
+    assert abs(far[0] - 1 / 1.1) > 1e-5
+
+
 # --------------------------------------------------------------------------- metric
 @pytest.mark.parametrize("M,a,Q", [(0.5, 0.24, 0.0), (0.5, 0.24, 0.3), (0.5, 0.49, 0.0),
                                    (0.0, 0.3, 0.0), (0.5, 0.0, 0.0)])
