@@ -36,6 +36,7 @@ METRIC = "geodesic rays/s @1000² Kerr: FP64 vs mixed vs surrogate, ≤1e-4 rad 
 FLOPS_PER_RAY_STEP = 697          # binary64 ops of one RK4 step (add/sub/mul/div 1, fma 2)
 FP64_PEAK_TFLOPS = 78.6           # MI355X FP64 vector (256 CU x 128 flop/clk x 2.4 GHz)
 BF16_PEAK_TFLOPS = 2500.0         # MI355X dense bfloat16 MFMA
+STRICT_GAIN = 40.0                # surrogate_strict: also re-trace above 40x local magnification
 KERNEL_SOURCES = ["paper_2310_15183_amd/csrc/trace_fp64.hip",
                   "paper_2310_15183_amd/csrc/step_fp64.h",
                   "paper_2310_15183_amd/csrc/grmath.h"]
@@ -217,7 +218,7 @@ def train_surrogate(g, args):
 
 
 def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3.0, edge=2,
-                      max_turn=None):
+                      max_gain=None):
     """Surrogate + RK4 fallback on the frame w: rays/s, speedup over the
     binary64 tracer on the same frame and integrator, the network-only frame
     time against the MFMA peak, and the errors against the binary64 frame."""
@@ -235,25 +236,25 @@ def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3
     direc = torch.empty(n, 3, device="cuda")
     fb = torch.empty(n, dtype=torch.int8, device="cuda")
 
-    if max_turn is None:
-        max_turn = args.max_turn
+    if max_gain is None:
+        max_gain = args.max_gain
 
     def run(lmin, e, turn, steps, warmup):
         nfb = 0
         for _ in range(warmup):
             nfb = g.gr_surrogate_frame(ctx, net, metric, cam, lmin, e, flag, direc, fb, stream,
-                                       max_turn=turn)
+                                       max_gain=turn)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
             nfb = g.gr_surrogate_frame(ctx, net, metric, cam, lmin, e, flag, direc, fb, stream,
-                                       max_turn=turn)
+                                       max_gain=turn)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps, nfb
 
     net_s, _ = run(0.0, 0, 0.0, args.steps, args.warmup)     # network only, no fallback
     net_flag, net_dir = flag.cpu().numpy(), direc.cpu().numpy()
-    wall, nfb = run(logit_min, edge, max_turn, args.steps, args.warmup)
+    wall, nfb = run(logit_min, edge, max_gain, args.steps, args.warmup)
     g.gr_trace_destroy(ctx)
 
     # many frames in flight: one context and stream each, nothing waits for the
@@ -271,13 +272,13 @@ def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3
     torch.cuda.synchronize()
     for j in range(nstreams):
         g.gr_surrogate_frame(ctxs[j], net, metric, cam, logit_min, edge, *bufs[j], streams[j],
-                             count=False, max_turn=max_turn)
+                             count=False, max_gain=max_gain)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(nframes):
         j = k % nstreams
         g.gr_surrogate_frame(ctxs[j], net, metric, cam, logit_min, edge, *bufs[j], streams[j],
-                             count=False, max_turn=max_turn)
+                             count=False, max_gain=max_gain)
     torch.cuda.synchronize()
     pipe_s = (time.perf_counter() - t0) / nframes
     for c in ctxs:
@@ -298,7 +299,7 @@ def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3
             "fallback": {"rule": f"|logit| < {logit_min}, a pixel within Chebyshev "
                                  f"distance {edge} of the other predicted class"
                                  + (f", or an escaping 8-neighbour's direction more than "
-                                    f"{max_turn} rad away" if max_turn > 0 else ""),
+                                    f"{max_gain} pixel widths away" if max_gain > 0 else ""),
                          "pixels": int(nfb), "frac": nfb / n, "online": online},
             "network_only_ms": net_s * 1e3,
             "network_mfma": {"achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -343,8 +344,10 @@ def bench_surrogate(args):
         g.gr_trace_destroy(ctx)
         del out
         sur = surrogate_variant(g, net, w, args, stream, n / fp64_s, ref)
+        strict = surrogate_variant(g, net, w, args, stream, n / fp64_s, ref,
+                                   max_gain=STRICT_GAIN)
         line = {"workload": f"{name} {side}x{side}", "fp64_rays_per_s": n / fp64_s,
-                "fp64_ms_per_step": fp64_s * 1e3, "surrogate": sur}
+                "fp64_ms_per_step": fp64_s * 1e3, "surrogate": sur, "surrogate_strict": strict}
         print(json.dumps(line), flush=True)
         lines.append(line)
         del ref
@@ -448,9 +451,10 @@ def main():
                     help="surrogate: labelled rays to train on")
     ap.add_argument("--train-epochs", type=int, default=12)
     ap.add_argument("--surrogate-side", type=int, default=4096)
-    ap.add_argument("--max-turn", type=float, default=0.0,
+    ap.add_argument("--max-gain", type=float, default=0.0,
                     help="surrogate: also re-trace pixels whose predicted direction differs "
-                         "from an escaping neighbour's by more than this (rad; 0: off)")
+                         "from an escaping neighbour's by more than this many pixel widths "
+                         "(0: off)")
     ap.add_argument("--surrogate-frames", type=int, default=4,
                     help="surrogate: how many of its frames to run (in order)")
     ap.add_argument("--skip-variants", action="store_true",
@@ -543,9 +547,12 @@ def main():
         result["variants"]["mixed"] = mixed_variant(g, w, args, stream, result["value"], ref)
         net, info = train_surrogate(g, args)
         sur = surrogate_variant(g, net, w, args, stream, result["value"], ref)
+        strict = surrogate_variant(g, net, w, args, stream, result["value"], ref,
+                                   max_gain=STRICT_GAIN)
         g.gr_mlp_destroy(net)
         sur["training"] = info
         result["variants"]["surrogate"] = sur
+        result["variants"]["surrogate_strict"] = strict
         del ref
     if not args.skip_cpu_baseline:
         import oracle

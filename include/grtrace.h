@@ -265,10 +265,11 @@ int gr_surrogate_targets(gr_ctx *ctx, const gr_instance *inst, int32_t n, const 
  * (inputs, the five layers, classification) with the same bfloat16 products
  * and binary32 sums as gr_mlp_forward.  A pixel falls back (fallback[p] = 1)
  * when |logit| < logit_min, a pixel within Chebyshev distance edge_px
- * (0..16) has the other class, or (max_turn > 0, radians, at most pi) the
- * predicted end directions of the pixel and an 8-neighbour, both escaping,
- * differ by more than max_turn (strong lensing, where the network's
- * direction is least reliable); fallback pixels are re-traced by the context's binary64
+ * (0..16) has the other class, or (max_gain > 0) the predicted end
+ * directions of the pixel and an 8-neighbour, both escaping, differ by more
+ * than max_gain pixel widths (fov / width radians each): a local
+ * magnification above max_gain, where the network's direction is least
+ * reliable; fallback pixels are re-traced by the context's binary64
  * tracer and their traced flag and escape-sphere direction replace the
  * network's.  The whole frame is queued on hip_stream without waiting for
  * the GPU (the fallback count stays on the device and sizes the retrace
@@ -279,7 +280,7 @@ int gr_surrogate_targets(gr_ctx *ctx, const gr_instance *inst, int32_t n, const 
  * Errors: GR_EINVAL (also for networks on another device), GR_EUNSUPPORTED
  * (context not GR_FP64), GR_ENOMEM. */
 int gr_surrogate_frame(gr_ctx *ctx, gr_mlp *mlp, const gr_metric *m, const gr_camera *c,
-                       float logit_min, int32_t edge_px, float max_turn, int8_t *flag,
+                       float logit_min, int32_t edge_px, float max_gain, int8_t *flag,
                        float *dir, int8_t *fallback, int64_t *n_fallback, void *hip_stream);
 
 /* Free the context (waits for nothing: the caller synchronises its streams

@@ -319,12 +319,12 @@ def gr_surrogate_targets(ctx, instances, u_flat, target, stream=None):
 
 
 def gr_surrogate_frame(ctx, mlp, metric, camera, logit_min, edge_px, flag, direction, fallback,
-                       stream=None, count=True, max_turn=0.0) -> int:
+                       stream=None, count=True, max_gain=0.0) -> int:
     """Returns the number of fallback pixels; with count=False the call does not
     wait for the GPU and returns -1."""
     nfb = ctypes.c_int64(-1)
     _check(_lib.gr_surrogate_frame(ctx, mlp, ctypes.byref(metric), ctypes.byref(camera),
-                                   float(logit_min), int(edge_px), float(max_turn), _p(flag),
+                                   float(logit_min), int(edge_px), float(max_gain), _p(flag),
                                    _p(direction),
                                    _p(fallback), ctypes.byref(nfb) if count else None,
                                    _stream_handle(stream)),

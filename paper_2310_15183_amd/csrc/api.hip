@@ -596,15 +596,17 @@ int gr_surrogate_targets(gr_ctx* ctx, const gr_instance* inst, int32_t n, const 
 }
 
 int gr_surrogate_frame(gr_ctx* ctx, gr_mlp* mlp, const gr_metric* m, const gr_camera* c,
-                       float logit_min, int32_t edge_px, float max_turn, int8_t* flag, float* dir,
+                       float logit_min, int32_t edge_px, float max_gain, int8_t* flag, float* dir,
                        int8_t* fallback, int64_t* n_fallback, void* hip_stream) {
     if (!ctx || !mlp || !flag || !dir || !fallback) return GR_EINVAL;
     int rc = check_metric(m);
     if (!rc) rc = check_camera(m, c);
     if (rc) return rc;
     if (!(logit_min >= 0.0f) || edge_px < 0 || edge_px > 16) return GR_EINVAL;
-    if (!(max_turn >= 0.0f && max_turn <= 3.14159265f)) return GR_EINVAL;
-    const float chord = max_turn > 0.0f ? 2.0f * sinf(0.5f * max_turn) : 0.0f;
+    if (!(max_gain >= 0.0f && max_gain <= 1e6f)) return GR_EINVAL;
+    // a turn of max_gain pixel widths (fov / width) as a chord of unit vectors
+    const double turn = std::min((double)max_gain * (c->fov / c->width), M_PI);
+    const float chord = max_gain > 0.0f ? (float)(2.0 * sin(0.5 * turn)) : 0.0f;
     if (ctx->integ.precision != GR_FP64) return GR_EUNSUPPORTED;
     if (gr_mlp_device_of(mlp) != ctx->device) return GR_EINVAL;
     const int64_t npix = (int64_t)c->width * c->height;

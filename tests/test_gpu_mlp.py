@@ -285,3 +285,49 @@ def test_asynchronous_frames_on_two_streams_equal_the_synchronous_frame(g):
         g.gr_mlp_destroy(net)
         for c in ctxs:
             g.gr_trace_destroy(c)
+
+
+def test_direction_jump_trigger_marks_the_magnified_pixels(g, net):
+    """max_gain re-traces exactly the escaping pixels whose predicted direction
+    differs from an escaping 8-neighbour's by more than max_gain pixel widths
+    (the rule evaluated on the host from the network-only frame, in the same
+    binary32 arithmetic)."""
+    import torch
+    p = g.gr_mlp_get_params(net)
+    p[-4] = 2.0                                          # mostly escaping
+    g.gr_mlp_set_params(net, p)
+    ctx = g.gr_trace_init(0, g.make_integrator(dt=0.01, max_steps=20000))
+    try:
+        W, H = 96, 80
+        fov = 70 * DEG
+        metric = g.gr_metric(0.5, 0.2, 0.1)
+        cam = g.gr_camera(20.0, 80 * DEG, 0.0, fov, W, H)
+        flag = torch.empty(W * H, dtype=torch.int8, device="cuda")
+        direc = torch.empty(W * H, 3, device="cuda")
+        fb = torch.empty(W * H, dtype=torch.int8, device="cuda")
+        assert g.gr_surrogate_frame(ctx, net, metric, cam, 0.0, 0, flag, direc, fb) == 0
+        f0, d0 = flag.cpu().numpy().reshape(H, W), direc.cpu().numpy().reshape(H, W, 3)
+        # largest squared chord to an escaping 8-neighbour, binary32 as in the kernel
+        J2 = np.full((H, W), -1.0, np.float32)
+        for j in range(H):
+            for i in range(W):
+                if f0[j, i] != g.GR_FLAG_ESCAPE:
+                    continue
+                for dj in (-1, 0, 1):
+                    for di in (-1, 0, 1):
+                        jj, ii = j + dj, i + di
+                        if 0 <= jj < H and 0 <= ii < W and f0[jj, ii] == g.GR_FLAG_ESCAPE:
+                            dd = d0[jj, ii] - d0[j, i]
+                            J2[j, i] = max(J2[j, i], (dd[0] * dd[0] + dd[1] * dd[1]) + dd[2] * dd[2])
+        # a gain at the median jump marks about half of the escaping pixels
+        m = float(np.median(J2[J2 >= 0]))
+        gain = 2.0 * math.asin(0.5 * math.sqrt(m)) / (fov / W)
+        g.gr_surrogate_frame(ctx, net, metric, cam, 0.0, 0, flag, direc, fb, max_gain=gain)
+        got = fb.cpu().numpy().reshape(H, W)
+    finally:
+        g.gr_trace_destroy(ctx)
+    turn = min(float(np.float32(gain)) * (fov / W), math.pi)
+    chord = np.float32(2.0 * math.sin(0.5 * turn))
+    want = J2 > chord * chord
+    assert 0.2 * want.size < want.sum() < 0.8 * want.size
+    np.testing.assert_array_equal(got.astype(bool), want)
