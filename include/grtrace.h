@@ -134,9 +134,14 @@ typedef struct gr_ctx gr_ctx;
  * residency used to size the persistent grid (1..8, 0 = as many as fit);
  * refill: 1 = lanes that finish take the next ray from the work queue,
  * 0 = each lane traces one ray and the grid covers every ray (frames only;
- * batches always refill); order (batches): 0 = instances are queued in the
- * order given, 1 = instances with the longest expected rays (largest
- * escape radius over dt) are queued first, which shortens the tail. */
+ * batches always refill); order: 0 = rays are queued in the order given;
+ * 1 = batches queue the instances with the longest expected rays (largest
+ * escape radius) first, which shortens the tail; 2 = as 1, and frames of at
+ * least 4096 pixels traced with refill queue their pixels sorted by how close
+ * the camera ray's impact parameter sqrt(Carter Q + L_z^2)/E is to the
+ * critical one (16 bytes per pixel of context workspace).  The default
+ * launch uses 1 for GR_FP64 contexts and 2 for GR_MIXED ones (measured
+ * faster there). */
 typedef struct {
     int32_t block;
     int32_t waves_per_simd;

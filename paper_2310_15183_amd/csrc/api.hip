@@ -34,6 +34,12 @@ struct gr_ctx {
     unsigned long long* sw_count;
     double* sw_out[7];                // re-traced theta, phi, r, p_t, p_r, p_theta, p_phi
     int8_t* sw_flag;                  // re-traced flags
+    // frame queue order (grown on demand)
+    int64_t ord_cap;                  // pixels it holds
+    float* ord_keys;                  // 2 x cap
+    int32_t* ord_vals;                // 2 x cap
+    void* ord_temp;
+    size_t ord_temp_bytes;
 };
 
 namespace {
@@ -99,7 +105,8 @@ gr_launch effective_launch(const gr_ctx* ctx) {
         l.block = 256;
         l.waves_per_simd = 0;
         l.refill = 1;
-        l.order = 1;
+        // frames in near-critical-first order only where it measured faster (mixed)
+        l.order = ctx->integ.precision == GR_MIXED ? 2 : 1;
     }
     return l;
 }
@@ -374,6 +381,45 @@ void free_surrogate_ws(gr_ctx* c) {
     c->sw_cap = 0;
 }
 
+void free_order_ws(gr_ctx* c) {
+    hipFree(c->ord_keys);
+    hipFree(c->ord_vals);
+    hipFree(c->ord_temp);
+    c->ord_keys = nullptr;
+    c->ord_vals = nullptr;
+    c->ord_temp = nullptr;
+    c->ord_cap = 0;
+    c->ord_temp_bytes = 0;
+}
+
+int grow_order_ws(gr_ctx* c, int64_t n) {
+    if (n <= c->ord_cap) return GR_OK;
+    hipDeviceSynchronize();
+    free_order_ws(c);
+    const size_t tb = gr::frame_order_temp(n);
+    bool ok = hipMalloc(&c->ord_keys, 2 * n * sizeof(float)) == hipSuccess &&
+              hipMalloc(&c->ord_vals, 2 * n * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&c->ord_temp, tb > 0 ? tb : 1) == hipSuccess;
+    if (!ok) {
+        free_order_ws(c);
+        return GR_ENOMEM;
+    }
+    c->ord_cap = n;
+    c->ord_temp_bytes = tb;
+    return GR_OK;
+}
+
+// Critical impact parameter of the Reissner-Nordstrom hole with the same M
+// and Q (photon sphere r_ph = (3M + sqrt(9M^2 - 8Q^2))/2): the centre of the
+// ring of longest rays, used only to order the queue.
+double critical_impact(const gr_metric* m) {
+    if (!(m->M > 0.0)) return 0.0;
+    const double M = m->M, Q2 = m->Q * m->Q;
+    const double rph = 0.5 * (3.0 * M + sqrt(std::max(9.0 * M * M - 8.0 * Q2, 0.0)));
+    const double f = 1.0 - 2.0 * M / rph + Q2 / (rph * rph);
+    return f > 0.0 ? rph / sqrt(f) : 0.0;
+}
+
 int grow_surrogate_ws(gr_ctx* c, int64_t n) {
     if (n <= c->sw_cap) return GR_OK;
     hipDeviceSynchronize();
@@ -447,7 +493,7 @@ int gr_trace_set_launch(gr_ctx* ctx, const gr_launch* l) {
     if (l->block != 64 && l->block != 128 && l->block != 256) return GR_EINVAL;
     if (l->waves_per_simd < 0 || l->waves_per_simd > 8) return GR_EINVAL;
     if (l->refill != 0 && l->refill != 1) return GR_EINVAL;
-    if (l->order != 0 && l->order != 1) return GR_EINVAL;
+    if (l->order < 0 || l->order > 2) return GR_EINVAL;
     ctx->launch = *l;
     return GR_OK;
 }
@@ -468,8 +514,19 @@ int gr_trace_frame(gr_ctx* ctx, const gr_metric* m, const gr_camera* c, const gr
     DeviceGuard guard(ctx->device);
     const int64_t nray = (int64_t)c->width * c->height;
     const bool f32 = out->dtype == GR_F32;
-    const gr::FrameArgs A = frame_args(ctx, m, c, out, nullptr, nray);
+    gr::FrameArgs A = frame_args(ctx, m, c, out, nullptr, nray);
     hipError_t e;
+    const gr_launch l0 = effective_launch(ctx);
+    if (l0.refill && l0.order == 2 && nray >= 4096) {
+        // near-critical rays first (results do not depend on the order)
+        rc = grow_order_ws(ctx, nray);
+        if (rc) return rc;
+        e = gr::frame_order(A.hole, A.cam, critical_impact(m), nray, ctx->ord_keys,
+                            ctx->ord_vals, ctx->ord_temp, ctx->ord_temp_bytes,
+                            (hipStream_t)hip_stream);
+        if (e != hipSuccess) return device_error(e, "frame order");
+        A.order = ctx->ord_vals + nray;
+    }
     if (ctx->integ.precision == GR_MIXED) {
         const gr_launch l = effective_launch(ctx);
         const gr::LaunchShape L =
@@ -680,6 +737,7 @@ int gr_trace_destroy(gr_ctx* ctx) {
     if (!ctx) return GR_OK;
     DeviceGuard guard(ctx->device);
     free_surrogate_ws(ctx);
+    free_order_ws(ctx);
     hipFree(ctx->counter);
     hipFree(ctx->table);
     hipFree(ctx->firsts);

@@ -40,6 +40,8 @@ struct FrameArgs {
     double r_esc;           // esc_factor * r0
     int64_t nray;           // rays to trace
     const int32_t* pixels;  // null: ray k is pixel k
+    const int32_t* order;   // null: the queue hands out ray k as its k-th id; else
+                            // id -> ray k = order[id] (a permutation of 0..nray-1)
     OutPtrs out;
 };
 
@@ -68,6 +70,15 @@ struct LaunchShape {
     int grid;            // workgroups
     int refill;          // persistent lanes pull rays from the queue
 };
+
+// Queue order of a frame: the permutation of its pixels sorted by
+// |b - b_c|, the distance of each camera ray's impact parameter
+// b = sqrt(Carter Q + L_z^2)/E from b_c, so that the near-critical rays, the
+// longest, are traced first.  keys/vals: 2 x npix each; temp: frame_order_temp
+// bytes.  The sorted permutation is left in vals + npix.
+hipError_t frame_order(const Hole& H, const Camera& C, double b_crit, int64_t npix, float* keys,
+                       int32_t* vals, void* temp, size_t temp_bytes, hipStream_t s);
+size_t frame_order_temp(int64_t npix);
 
 // Fill the queue counter with zero (a kernel, so that it can sit in a
 // captured graph).

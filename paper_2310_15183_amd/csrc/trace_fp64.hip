@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(256) trace_fp64_refill(const FrameArgs A,
         if (want) {
             want = false;
             if (id < A.nray) {
-                k = id;
+                k = A.order ? (int64_t)A.order[id] : id;
                 start_ray(A.cam, A.pixels ? (int64_t)A.pixels[k] : k, y);
                 s = 0;
                 const int f = start_flag(A.in, y);

@@ -186,7 +186,7 @@ trace_mixed_refill(const MixedArgs X,
         if (want) {
             want = false;
             if (id < A.nray) {
-                k = id;
+                k = A.order ? (int64_t)A.order[id] : id;
                 start_ray(A.cam, A.pixels ? (int64_t)A.pixels[k] : k, y);
                 s = 0;
                 in64 = false;
