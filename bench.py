@@ -36,7 +36,8 @@ METRIC = "geodesic rays/s @1000² Kerr: FP64 vs mixed vs surrogate, ≤1e-4 rad 
 FLOPS_PER_RAY_STEP = 697          # binary64 ops of one RK4 step (add/sub/mul/div 1, fma 2)
 FP64_PEAK_TFLOPS = 78.6           # MI355X FP64 vector (256 CU x 128 flop/clk x 2.4 GHz)
 BF16_PEAK_TFLOPS = 2500.0         # MI355X dense bfloat16 MFMA
-STRICT_GAIN = 40.0                # surrogate_strict: also re-trace above 40x local magnification
+STRICT_TURN = 0.05                # surrogate_strict: also re-trace where neighbours' directions
+                                  # differ by more than 0.05 rad
 KERNEL_SOURCES = ["paper_2310_15183_amd/csrc/trace_fp64.hip",
                   "paper_2310_15183_amd/csrc/step_fp64.h",
                   "paper_2310_15183_amd/csrc/grmath.h"]
@@ -256,11 +257,19 @@ def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3
     net_flag, net_dir = flag.cpu().numpy(), direc.cpu().numpy()
     wall, nfb = run(logit_min, edge, max_gain, args.steps, args.warmup)
     g.gr_trace_destroy(ctx)
+    got_flag, got_dir, got_fb = flag.cpu().numpy(), direc.cpu().numpy(), fb.cpu().numpy()
+    err = S.frame_errors(w["M"], w["a"], w["Q"], w["escape_factor"] * w["r0"], ref, got_flag,
+                         got_dir)
+    # the network's own error on the pixels the fallback re-traced (known at run time)
+    online = S.online_errors(net_flag, net_dir, got_flag, got_dir, got_fb)
 
     # many frames in flight: one context and stream each, nothing waits for the
     # GPU between frames, so one frame's latency-bound retrace overlaps the next
     # frame's network
-    nstreams, nframes = 3, max(3, 3 * args.steps)
+    nstreams, nframes = args.pipeline_streams, max(3, 3 * args.steps)
+    if nstreams < 1:
+        return _surrogate_result(n, wall, net_s, nfb, fp64_rays_per_s, None, err, online,
+                                 logit_min, edge, max_gain)
     streams = [torch.cuda.Stream() for _ in range(nstreams)]
     ctxs = [g.gr_trace_init(0, g.make_integrator(dt=w["dt"], fd_eps=w["fd_eps"],
                                                  horizon_norm=w["horizon_norm"],
@@ -284,22 +293,26 @@ def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3
     for c in ctxs:
         g.gr_trace_destroy(c)
     del bufs
-    got_flag, got_dir, got_fb = flag.cpu().numpy(), direc.cpu().numpy(), fb.cpu().numpy()
-    err = S.frame_errors(w["M"], w["a"], w["Q"], w["escape_factor"] * w["r0"], ref, got_flag,
-                         got_dir)
-    # the network's own error on the pixels the fallback re-traced (known at run time)
-    online = S.online_errors(net_flag, net_dir, got_flag, got_dir, got_fb)
+    return _surrogate_result(n, wall, net_s, nfb, fp64_rays_per_s, pipe_s, err, online,
+                             logit_min, edge, max_gain, nstreams, nframes)
+
+
+def _surrogate_result(n, wall, net_s, nfb, fp64_rays_per_s, pipe_s, err, online, logit_min,
+                      edge, max_gain, nstreams=0, nframes=0):
+    from paper_2310_15183_amd import surrogate as S
     rays_s = n / wall
     tflops = S.FLOPS_PER_RAY * n / net_s / 1e12
+    pipelined = None
+    if pipe_s:
+        pipelined = {"streams": nstreams, "frames": nframes, "ms_per_frame": pipe_s * 1e3,
+                     "rays_per_s": n / pipe_s, "speedup_vs_fp64": n / pipe_s / fp64_rays_per_s}
     return {"rays_per_s": rays_s, "ms_per_step": wall * 1e3,
             "speedup_vs_fp64": rays_s / fp64_rays_per_s,
-            "pipelined": {"streams": nstreams, "frames": nframes, "ms_per_frame": pipe_s * 1e3,
-                          "rays_per_s": n / pipe_s,
-                          "speedup_vs_fp64": n / pipe_s / fp64_rays_per_s},
+            "pipelined": pipelined,
             "fallback": {"rule": f"|logit| < {logit_min}, a pixel within Chebyshev "
                                  f"distance {edge} of the other predicted class"
                                  + (f", or an escaping 8-neighbour's direction more than "
-                                    f"{max_gain} pixel widths away" if max_gain > 0 else ""),
+                                    f"{max_gain:.4g} pixel widths away" if max_gain > 0 else ""),
                          "pixels": int(nfb), "frac": nfb / n, "online": online},
             "network_only_ms": net_s * 1e3,
             "network_mfma": {"achieved": tflops, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -345,7 +358,7 @@ def bench_surrogate(args):
         del out
         sur = surrogate_variant(g, net, w, args, stream, n / fp64_s, ref)
         strict = surrogate_variant(g, net, w, args, stream, n / fp64_s, ref,
-                                   max_gain=STRICT_GAIN)
+                                   max_gain=STRICT_TURN / (w["fov"] / side))
         line = {"workload": f"{name} {side}x{side}", "fp64_rays_per_s": n / fp64_s,
                 "fp64_ms_per_step": fp64_s * 1e3, "surrogate": sur, "surrogate_strict": strict}
         print(json.dumps(line), flush=True)
@@ -451,6 +464,8 @@ def main():
                     help="surrogate: labelled rays to train on")
     ap.add_argument("--train-epochs", type=int, default=12)
     ap.add_argument("--surrogate-side", type=int, default=4096)
+    ap.add_argument("--pipeline-streams", type=int, default=3,
+                    help="surrogate: frames in flight for the pipelined figure (0: skip it)")
     ap.add_argument("--max-gain", type=float, default=0.0,
                     help="surrogate: also re-trace pixels whose predicted direction differs "
                          "from an escaping neighbour's by more than this many pixel widths "
@@ -548,7 +563,7 @@ def main():
         net, info = train_surrogate(g, args)
         sur = surrogate_variant(g, net, w, args, stream, result["value"], ref)
         strict = surrogate_variant(g, net, w, args, stream, result["value"], ref,
-                                   max_gain=STRICT_GAIN)
+                                   max_gain=STRICT_TURN / (w["fov"] / w["W"]))
         g.gr_mlp_destroy(net)
         sur["training"] = info
         result["variants"]["surrogate"] = sur

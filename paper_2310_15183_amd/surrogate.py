@@ -135,19 +135,39 @@ def evaluate_network(net, data: TrainingSet, logit_min: float = 3.0):
             "angle_p999": float(q[3])}
 
 
+AXIS_MU = 1e-3
+
+
 def frame_errors(M, a, Q, r_esc, ref, flag, direc):
     """A surrogate frame (flags, unit end directions) against a binary64
     traced frame (all fields binary64): the fraction of pixels whose class
     differs and the great-circle error of the end direction where both say
-    escaped (the reference direction is its crossing of r = r_esc)."""
+    escaped (the reference direction is its crossing of r = r_esc).
+
+    The error is also given without the rays that graze the polar axis,
+    mu = |L_z| / sqrt(Q + L_z^2) < AXIS_MU (Carter's Q from the end state;
+    sin of the closest approach to the axis is about mu): there the
+    Boyer-Lindquist phi is singular and the traced reference itself is not
+    reliable to better than a fraction of a radian."""
     flag = np.asarray(flag)
     both = (ref["flag"] == g.GR_FLAG_ESCAPE) & (flag == g.GR_FLAG_ESCAPE)
-    th, ph = sky_at_escape(M, a, Q, r_esc, {k: v[both] for k, v in ref.items()})
+    sub = {k: v[both] for k, v in ref.items()}
+    th, ph = sky_at_escape(M, a, Q, r_esc, sub)
     ang = angle_between(sky_direction(th, ph), np.asarray(direc, np.float64)[both])
-    q = np.quantile(ang, [0.5, 0.9, 0.99, 0.999, 1.0]) if ang.size else np.zeros(5)
+    E, L = -sub["p_t"], sub["p_phi"]
+    c2, s2 = np.cos(sub["theta"]) ** 2, np.sin(sub["theta"]) ** 2
+    Qc = sub["p_theta"] ** 2 + c2 * (L * L / s2 - a * a * E * E)
+    mu = np.abs(L) / np.sqrt(np.maximum(Qc + L * L, 1e-300))
+    off_axis = mu >= AXIS_MU
+
+    def quant(x):
+        q = np.quantile(x, [0.5, 0.9, 0.99, 0.999, 1.0]) if x.size else np.zeros(5)
+        return {"median": float(q[0]), "p90": float(q[1]), "p99": float(q[2]),
+                "p999": float(q[3]), "max": float(q[4])}
     return {"misclassified_frac": float((flag != ref["flag"]).mean()),
-            "angle_err_rad": {"median": float(q[0]), "p90": float(q[1]), "p99": float(q[2]),
-                              "p999": float(q[3]), "max": float(q[4])},
+            "angle_err_rad": quant(ang),
+            "angle_err_rad_off_axis": quant(ang[off_axis]),
+            "axis_grazing_rays": int((~off_axis).sum()),
             "n_escaped_both": int(both.sum())}
 
 

@@ -111,3 +111,21 @@ def test_online_errors_use_only_the_retraced_pixels():
     assert o["pixels"] == 100 and o["class_changed_frac"] == 0.05
     assert abs(o["angle_err_rad"]["median"] - math.pi) < 1e-6
     assert S.online_errors(net_flag, d, flag, direc, np.zeros(n, np.int8)) == {"pixels": 0}
+
+
+def test_frame_errors_set_axis_grazing_rays_apart():
+    """Rays with |L_z| / sqrt(Q + L_z^2) below 1e-3 pass within ~1e-3 rad of
+    the polar axis; their errors are reported apart."""
+    rng = np.random.default_rng(4)
+    n, r_esc = 300, 30.0
+    ref = _state_at_sphere(n, r_esc, rng)
+    ref["flag"] = np.full(n, g.GR_FLAG_ESCAPE, np.int8)
+    ref["p_theta"] = rng.choice([-1.0, 1.0], n) * rng.uniform(0.5, 2.0, n)   # physical: Q + L^2 > 0
+    ref["p_phi"][:40] = 1e-7                       # grazing the axis
+    u = sky_direction(ref["theta"], ref["phi"])
+    direc = u.astype(np.float32).copy()
+    direc[:40] = -direc[:40]                       # wildly wrong there only
+    e = S.frame_errors(0.5, 0.3, 0.2, r_esc, ref, np.full(n, g.GR_FLAG_ESCAPE, np.int8), direc)
+    assert e["axis_grazing_rays"] == 40
+    assert abs(e["angle_err_rad"]["max"] - math.pi) < 1e-3
+    assert e["angle_err_rad_off_axis"]["max"] < 1e-6
