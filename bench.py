@@ -38,6 +38,7 @@ FP64_PEAK_TFLOPS = 78.6           # MI355X FP64 vector (256 CU x 128 flop/clk x 
 BF16_PEAK_TFLOPS = 2500.0         # MI355X dense bfloat16 MFMA
 STRICT_TURN = 0.05                # surrogate_strict: also re-trace where neighbours' directions
                                   # differ by more than 0.05 rad
+MIN_IMPACT = 1.2                  # re-trace escaping rays with b < 1.2 b_c (baseline not valid)
 KERNEL_SOURCES = ["paper_2310_15183_amd/csrc/trace_fp64.hip",
                   "paper_2310_15183_amd/csrc/step_fp64.h",
                   "paper_2310_15183_amd/csrc/grmath.h"]
@@ -219,7 +220,7 @@ def train_surrogate(g, args):
 
 
 def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3.0, edge=2,
-                      max_gain=None):
+                      max_gain=None, min_impact=MIN_IMPACT):
     """Surrogate + RK4 fallback on the frame w: rays/s, speedup over the
     binary64 tracer on the same frame and integrator, the network-only frame
     time against the MFMA peak, and the errors against the binary64 frame."""
@@ -240,22 +241,22 @@ def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3
     if max_gain is None:
         max_gain = args.max_gain
 
-    def run(lmin, e, turn, steps, warmup):
+    def run(lmin, e, turn, imp, steps, warmup):
         nfb = 0
         for _ in range(warmup):
             nfb = g.gr_surrogate_frame(ctx, net, metric, cam, lmin, e, flag, direc, fb, stream,
-                                       max_gain=turn)
+                                       max_gain=turn, min_impact=imp)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
             nfb = g.gr_surrogate_frame(ctx, net, metric, cam, lmin, e, flag, direc, fb, stream,
-                                       max_gain=turn)
+                                       max_gain=turn, min_impact=imp)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps, nfb
 
-    net_s, _ = run(0.0, 0, 0.0, args.steps, args.warmup)     # network only, no fallback
+    net_s, _ = run(0.0, 0, 0.0, 0.0, args.steps, args.warmup)   # network only, no fallback
     net_flag, net_dir = flag.cpu().numpy(), direc.cpu().numpy()
-    wall, nfb = run(logit_min, edge, max_gain, args.steps, args.warmup)
+    wall, nfb = run(logit_min, edge, max_gain, min_impact, args.steps, args.warmup)
     g.gr_trace_destroy(ctx)
     got_flag, got_dir, got_fb = flag.cpu().numpy(), direc.cpu().numpy(), fb.cpu().numpy()
     err = S.frame_errors(w["M"], w["a"], w["Q"], w["escape_factor"] * w["r0"], ref, got_flag,
@@ -269,7 +270,7 @@ def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3
     nstreams, nframes = args.pipeline_streams, max(3, 3 * args.steps)
     if nstreams < 1:
         return _surrogate_result(n, wall, net_s, nfb, fp64_rays_per_s, None, err, online,
-                                 logit_min, edge, max_gain)
+                                 logit_min, edge, max_gain, min_impact)
     streams = [torch.cuda.Stream() for _ in range(nstreams)]
     ctxs = [g.gr_trace_init(0, g.make_integrator(dt=w["dt"], fd_eps=w["fd_eps"],
                                                  horizon_norm=w["horizon_norm"],
@@ -281,24 +282,24 @@ def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3
     torch.cuda.synchronize()
     for j in range(nstreams):
         g.gr_surrogate_frame(ctxs[j], net, metric, cam, logit_min, edge, *bufs[j], streams[j],
-                             count=False, max_gain=max_gain)
+                             count=False, max_gain=max_gain, min_impact=min_impact)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(nframes):
         j = k % nstreams
         g.gr_surrogate_frame(ctxs[j], net, metric, cam, logit_min, edge, *bufs[j], streams[j],
-                             count=False, max_gain=max_gain)
+                             count=False, max_gain=max_gain, min_impact=min_impact)
     torch.cuda.synchronize()
     pipe_s = (time.perf_counter() - t0) / nframes
     for c in ctxs:
         g.gr_trace_destroy(c)
     del bufs
     return _surrogate_result(n, wall, net_s, nfb, fp64_rays_per_s, pipe_s, err, online,
-                             logit_min, edge, max_gain, nstreams, nframes)
+                             logit_min, edge, max_gain, min_impact, nstreams, nframes)
 
 
 def _surrogate_result(n, wall, net_s, nfb, fp64_rays_per_s, pipe_s, err, online, logit_min,
-                      edge, max_gain, nstreams=0, nframes=0):
+                      edge, max_gain, min_impact, nstreams=0, nframes=0):
     from paper_2310_15183_amd import surrogate as S
     rays_s = n / wall
     tflops = S.FLOPS_PER_RAY * n / net_s / 1e12
@@ -311,6 +312,8 @@ def _surrogate_result(n, wall, net_s, nfb, fp64_rays_per_s, pipe_s, err, online,
             "pipelined": pipelined,
             "fallback": {"rule": f"|logit| < {logit_min}, a pixel within Chebyshev "
                                  f"distance {edge} of the other predicted class"
+                                 + (f", predicted escape with b < {min_impact} b_c"
+                                    if min_impact > 0 else "")
                                  + (f", or an escaping 8-neighbour's direction more than "
                                     f"{max_gain:.4g} pixel widths away" if max_gain > 0 else ""),
                          "pixels": int(nfb), "frac": nfb / n, "online": online},

@@ -237,10 +237,11 @@ int gr_mlp_forward(gr_mlp *mlp, const float *x, int64_t n, float *y, void *hip_s
  * 32 and <= max_batch.  rows (may be NULL) gathers row rows[i] of x (n_src x
  * 7) and target (n_src x 4); rows outside [0, n_src) read as zeros.  lam >= 0
  * weights the direction term, delta > 0 is its Huber threshold (a huge
- * delta gives the squared error). */
+ * delta gives the squared error), and rows whose target correction is longer
+ * than dmax >= 0 take no direction loss (a huge dmax keeps every row). */
 int gr_mlp_loss_grad(gr_mlp *mlp, const float *x, const float *target, const int32_t *rows,
-                     int64_t n, int64_t n_src, float lam, float delta, float *loss, float *grad,
-                     void *hip_stream);
+                     int64_t n, int64_t n_src, float lam, float delta, float dmax, float *loss,
+                     float *grad, void *hip_stream);
 
 /* One Adam step (Kingma and Ba, bias-corrected) on the binary32 master
  * parameters with the given gradient; refreshes the bfloat16 copies. */
@@ -250,10 +251,13 @@ int gr_mlp_adam_step(gr_mlp *mlp, const float *grad, float lr, float beta1, floa
 /* Adam steps taken since the last init/set. */
 int64_t gr_mlp_steps(const gr_mlp *mlp);
 
-/* Network inputs x (total x 7) and straight-line directions u_flat (total x
- * 3) of the rays of a batch, enumerated like gr_trace_batch with instances in
- * the order given (frame order or pixel-list order).  Outputs of the
- * instances are not used. */
+/* Network inputs x (total x 7) and baseline directions u_flat (total x 3) of
+ * the rays of a batch, enumerated like gr_trace_batch with instances in the
+ * order given (frame order or pixel-list order).  The baseline is where the
+ * camera ray would cross the escape sphere around the Reissner-Nordstrom hole
+ * with the same M and Q (its sweep is a 1-D integral), or where the
+ * straight line of flat space crosses it if that hole captures the ray.
+ * Outputs of the instances are not used. */
 int gr_surrogate_inputs(gr_ctx *ctx, const gr_instance *inst, int32_t n, float *x,
                         float *u_flat, void *hip_stream);
 
@@ -264,29 +268,40 @@ int gr_surrogate_inputs(gr_ctx *ctx, const gr_instance *inst, int32_t n, float *
 int gr_surrogate_targets(gr_ctx *ctx, const gr_instance *inst, int32_t n, const float *u_flat,
                          float *target, void *hip_stream);
 
+/* Which pixels of a surrogate frame are re-traced with RK4 (any rule that
+ * holds): |logit| < logit_min; a pixel within Chebyshev distance edge_px
+ * (0..16) has the other class; (max_gain > 0) the predicted end directions of
+ * the pixel and an 8-neighbour, both escaping, differ by more than max_gain
+ * pixel widths (fov / width radians each), a local magnification above
+ * max_gain; (min_impact > 0) the pixel is predicted to escape and its camera
+ * ray's impact parameter is below min_impact times the critical one of the
+ * Reissner-Nordstrom hole with the same M and Q, where the network's
+ * baseline does not hold (see gr_surrogate_inputs). */
+typedef struct {
+    float logit_min;
+    int32_t edge_px;
+    float max_gain;
+    float min_impact;
+} gr_fallback;
+
 /* Surrogate frame with RK4 fallback.  Every pixel gets the network's class
  * (flag: GR_FLAG_ESCAPE or GR_FLAG_HORIZON) and end direction (dir, 3 floats,
  * zero unless escaped), computed for the whole frame in one fused launch
  * (inputs, the five layers, classification) with the same bfloat16 products
- * and binary32 sums as gr_mlp_forward.  A pixel falls back (fallback[p] = 1)
- * when |logit| < logit_min, a pixel within Chebyshev distance edge_px
- * (0..16) has the other class, or (max_gain > 0) the predicted end
- * directions of the pixel and an 8-neighbour, both escaping, differ by more
- * than max_gain pixel widths (fov / width radians each): a local
- * magnification above max_gain, where the network's direction is least
- * reliable; fallback pixels are re-traced by the context's binary64
- * tracer and their traced flag and escape-sphere direction replace the
- * network's.  The whole frame is queued on hip_stream without waiting for
- * the GPU (the fallback count stays on the device and sizes the retrace
- * there) unless n_fallback (host) is non-NULL: then the call waits for the
- * stream and stores the count.  Workspace (about 65 B per pixel) is kept in
- * the context, so frames in flight at the same time need one context each;
- * calls on one context must be ordered (same stream, or synchronised).
- * Errors: GR_EINVAL (also for networks on another device), GR_EUNSUPPORTED
- * (context not GR_FP64), GR_ENOMEM. */
+ * and binary32 sums as gr_mlp_forward.  Pixels selected by rule (fallback[p]
+ * = 1) are re-traced by the context's binary64 tracer and their traced flag
+ * and escape-sphere direction replace the network's.  The whole frame is
+ * queued on hip_stream without waiting for the GPU (the fallback count stays
+ * on the device and sizes the retrace there) unless n_fallback (host) is
+ * non-NULL: then the call waits for the stream and stores the count.
+ * Workspace (about 65 B per pixel) is kept in the context, so frames in
+ * flight at the same time need one context each; calls on one context must
+ * be ordered (same stream, or synchronised).  Errors: GR_EINVAL (also for
+ * networks on another device), GR_EUNSUPPORTED (context not GR_FP64),
+ * GR_ENOMEM. */
 int gr_surrogate_frame(gr_ctx *ctx, gr_mlp *mlp, const gr_metric *m, const gr_camera *c,
-                       float logit_min, int32_t edge_px, float max_gain, int8_t *flag,
-                       float *dir, int8_t *fallback, int64_t *n_fallback, void *hip_stream);
+                       const gr_fallback *rule, int8_t *flag, float *dir, int8_t *fallback,
+                       int64_t *n_fallback, void *hip_stream);
 
 /* Free the context (waits for nothing: the caller synchronises its streams
  * first).  NULL is accepted. */

@@ -9,11 +9,12 @@ one packed float vector: for each layer, W (in x out, row-major) then b (out).
 
 Loss over a batch of n rays with targets (escaped, d_x, d_y, d_z):
     L = (1/n) sum [ softplus(y0) - escaped * y0
-                    + lam * escaped * sum_c huber(y[c] - d[c]) ]
+                    + lam * w * sum_c huber(y[c] - d[c]) ]
 with huber(e) = e^2 for |e| <= delta and 2 delta |e| - delta^2 beyond
 (binary cross-entropy with logits for the class; a squared error of the
-direction correction that grows only linearly for outliers, on escaped rays
-only; delta = inf gives the plain squared error).
+direction correction that grows only linearly for outliers, with weight
+w = escaped for rows whose target |d| <= dmax and 0 otherwise; delta = inf
+gives the plain squared error, dmax = inf keeps every escaped row).
 
 bf16=True rounds, like the GPU kernels, the weights, every layer's input
 activations and the activation gradients fed to the backward products to
@@ -95,20 +96,22 @@ def huber_grad(e, delta):
     return np.where(np.abs(e) <= delta, 2.0 * e, 2.0 * delta * np.sign(e))
 
 
-def loss_and_grad(params, x, target, lam=100.0, bf16_mode=False, delta=np.inf):
-    """Mean loss over the batch and its gradient w.r.t. the packed params."""
+def loss_and_grad(params, x, target, lam=100.0, bf16_mode=False, delta=np.inf, dmax=np.inf):
+    """Mean loss over the batch and its gradient w.r.t. the packed params.
+    Rows whose target correction is longer than dmax take no direction loss."""
     params = np.asarray(params, np.float64)
     layers = unpack(params)
     y, cache = forward(params, x, bf16_mode, keep=True)
     n = y.shape[0]
     esc = target[:, 0]
     d = target[:, 1:4]
+    wd = np.where(np.sum(d * d, axis=1) <= dmax * dmax, esc, 0.0)
     sp = np.logaddexp(0.0, y[:, 0])
     e = y[:, 1:4] - d
-    L = np.sum(sp - esc * y[:, 0] + lam * esc * np.sum(huber(e, delta), axis=1)) / n
+    L = np.sum(sp - esc * y[:, 0] + lam * wd * np.sum(huber(e, delta), axis=1)) / n
     dy = np.zeros_like(y)
     dy[:, 0] = (sigmoid(y[:, 0]) - esc) / n
-    dy[:, 1:4] = lam * esc[:, None] * huber_grad(e, delta) / n
+    dy[:, 1:4] = lam * wd[:, None] * huber_grad(e, delta) / n
     grads = []
     dz = dy
     for li in range(len(layers) - 1, -1, -1):

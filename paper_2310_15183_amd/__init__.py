@@ -52,6 +52,11 @@ class gr_instance(ctypes.Structure):
                 ("pixels", ctypes.c_void_p), ("n_pixels", ctypes.c_int64)]
 
 
+class gr_fallback(ctypes.Structure):
+    _fields_ = [("logit_min", ctypes.c_float), ("edge_px", ctypes.c_int32),
+                ("max_gain", ctypes.c_float), ("min_impact", ctypes.c_float)]
+
+
 class gr_launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
                 ("refill", ctypes.c_int32), ("order", ctypes.c_int32)]
@@ -91,15 +96,16 @@ def _load():
         "gr_mlp_get_params": (ctypes.c_int, [vp, vp]),
         "gr_mlp_forward": (ctypes.c_int, [vp, vp, ctypes.c_int64, vp, vp]),
         "gr_mlp_loss_grad": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_int64,
-                                            ctypes.c_float, ctypes.c_float, vp, vp, vp]),
+                                            ctypes.c_float, ctypes.c_float, ctypes.c_float, vp,
+                                            vp, vp]),
         "gr_mlp_adam_step": (ctypes.c_int, [vp, vp, ctypes.c_float, ctypes.c_float,
                                             ctypes.c_float, ctypes.c_float, vp]),
         "gr_mlp_steps": (ctypes.c_int64, [vp]),
         "gr_surrogate_inputs": (ctypes.c_int, [vp, P(gr_instance), ctypes.c_int32, vp, vp, vp]),
         "gr_surrogate_targets": (ctypes.c_int, [vp, P(gr_instance), ctypes.c_int32, vp, vp, vp]),
-        "gr_surrogate_frame": (ctypes.c_int, [vp, vp, P(gr_metric), P(gr_camera), ctypes.c_float,
-                                              ctypes.c_int32, ctypes.c_float, vp, vp, vp,
-                                              P(ctypes.c_int64), vp]),
+        "gr_surrogate_frame": (ctypes.c_int, [vp, vp, P(gr_metric), P(gr_camera),
+                                              P(gr_fallback), vp, vp, vp, P(ctypes.c_int64),
+                                              vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -290,10 +296,10 @@ def gr_mlp_forward(m, x, y, stream=None):
 
 
 def gr_mlp_loss_grad(m, x, target, grad, loss=None, rows=None, n=None, lam=100.0, delta=1e30,
-                     stream=None):
+                     stream=None, dmax=1e30):
     n = int(rows.shape[0] if rows is not None else x.shape[0]) if n is None else int(n)
     _check(_lib.gr_mlp_loss_grad(m, _p(x), _p(target), _p(rows), n, int(x.shape[0]),
-                                 float(lam), float(delta), _p(loss), _p(grad),
+                                 float(lam), float(delta), float(dmax), _p(loss), _p(grad),
                                  _stream_handle(stream)), "gr_mlp_loss_grad")
 
 
@@ -319,13 +325,14 @@ def gr_surrogate_targets(ctx, instances, u_flat, target, stream=None):
 
 
 def gr_surrogate_frame(ctx, mlp, metric, camera, logit_min, edge_px, flag, direction, fallback,
-                       stream=None, count=True, max_gain=0.0) -> int:
+                       stream=None, count=True, max_gain=0.0, min_impact=0.0) -> int:
     """Returns the number of fallback pixels; with count=False the call does not
-    wait for the GPU and returns -1."""
+    wait for the GPU and returns -1.  The rule's fields are the keywords of the
+    same names (gr_fallback)."""
     nfb = ctypes.c_int64(-1)
+    rule = gr_fallback(float(logit_min), int(edge_px), float(max_gain), float(min_impact))
     _check(_lib.gr_surrogate_frame(ctx, mlp, ctypes.byref(metric), ctypes.byref(camera),
-                                   float(logit_min), int(edge_px), float(max_gain), _p(flag),
-                                   _p(direction),
+                                   ctypes.byref(rule), _p(flag), _p(direction),
                                    _p(fallback), ctypes.byref(nfb) if count else None,
                                    _stream_handle(stream)),
            "gr_surrogate_frame")

@@ -653,14 +653,17 @@ int gr_surrogate_targets(gr_ctx* ctx, const gr_instance* inst, int32_t n, const 
 }
 
 int gr_surrogate_frame(gr_ctx* ctx, gr_mlp* mlp, const gr_metric* m, const gr_camera* c,
-                       float logit_min, int32_t edge_px, float max_gain, int8_t* flag, float* dir,
-                       int8_t* fallback, int64_t* n_fallback, void* hip_stream) {
-    if (!ctx || !mlp || !flag || !dir || !fallback) return GR_EINVAL;
+                       const gr_fallback* rule, int8_t* flag, float* dir, int8_t* fallback,
+                       int64_t* n_fallback, void* hip_stream) {
+    if (!ctx || !mlp || !rule || !flag || !dir || !fallback) return GR_EINVAL;
     int rc = check_metric(m);
     if (!rc) rc = check_camera(m, c);
     if (rc) return rc;
+    const float logit_min = rule->logit_min, max_gain = rule->max_gain;
+    const int32_t edge_px = rule->edge_px;
     if (!(logit_min >= 0.0f) || edge_px < 0 || edge_px > 16) return GR_EINVAL;
     if (!(max_gain >= 0.0f && max_gain <= 1e6f)) return GR_EINVAL;
+    if (!(rule->min_impact >= 0.0f && rule->min_impact <= 1e3f)) return GR_EINVAL;
     // a turn of max_gain pixel widths (fov / width) as a chord of unit vectors
     const double turn = std::min((double)max_gain * (c->fov / c->width), M_PI);
     const float chord = max_gain > 0.0f ? (float)(2.0 * sin(0.5 * turn)) : 0.0f;
@@ -683,7 +686,8 @@ int gr_surrogate_frame(gr_ctx* ctx, gr_mlp* mlp, const gr_metric* m, const gr_ca
     I.hole = gr::make_hole(m->M, m->a, m->Q);
     I.cam = gr::make_camera(I.hole, c->r0, c->theta0, c->phi0, c->fov, c->width, c->height);
     I.r_esc = ctx->integ.escape_factor * c->r0;
-    hipError_t e = gr::sur::frame_net(I, npix, gr_mlp_view(mlp), flag, dir, ctx->sw_logit, s);
+    hipError_t e = gr::sur::frame_net(I, npix, gr_mlp_view(mlp), rule->min_impact, flag, dir,
+                                      ctx->sw_logit, s);
     if (e != hipSuccess) return device_error(e, "surrogate network");
     // 2. pixels to re-trace: small logits and class edges
     e = gr::sur::fallback(ctx->sw_logit, flag, dir, c->width, c->height, logit_min, edge_px,

@@ -179,13 +179,14 @@ __global__ void input_kernel(const float* __restrict__ x, const int32_t* __restr
 }
 
 // Loss terms and output gradient (see the network description):
-//   l_i = softplus(y0) - esc y0 + lam esc sum_c huber(y[c] - d[c]),  L = sum l_i / n
-// huber(e) = e^2 for |e| <= delta, 2 delta |e| - delta^2 beyond.
+//   l_i = softplus(y0) - esc y0 + lam w sum_c huber(y[c] - d[c]),  L = sum l_i / n
+// huber(e) = e^2 for |e| <= delta, 2 delta |e| - delta^2 beyond; the direction
+// weight w is esc for rows whose target |d| <= dmax and 0 otherwise.
 // dy is written as bfloat16 n x 32 (zero beyond column 3); per-block partial
 // sums of l_i go to partial[blockIdx.x] (reduced by reduce_kernel).
 __global__ void loss_kernel(const float* __restrict__ y, const float* __restrict__ target,
                             const int32_t* __restrict__ rows, int64_t n, int64_t n_src, float lam,
-                            float delta, float inv_n, __bf16* __restrict__ dy,
+                            float delta, float dmax, float inv_n, __bf16* __restrict__ dy,
                             double* __restrict__ partial) {
     __shared__ double red[256];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -197,6 +198,8 @@ __global__ void loss_kernel(const float* __restrict__ y, const float* __restrict
         const float* t = ok ? target + src * OUT : zero4;
         const float* yi = y + i * OUT_PAD;
         const float esc = t[0];
+        const float d2 = (t[1] * t[1] + t[2] * t[2]) + t[3] * t[3];
+        const float wd = d2 <= dmax * dmax ? esc : 0.0f;
         const float y0 = yi[0];
         const float sp = fmaxf(y0, 0.0f) + log1pf(expf(-fabsf(y0)));
         float hub = 0.0f;
@@ -204,12 +207,12 @@ __global__ void loss_kernel(const float* __restrict__ y, const float* __restrict
             const float e = yi[c] - t[c], a = fabsf(e);
             hub += a <= delta ? e * e : 2.0f * delta * a - delta * delta;
         }
-        li = (double)(sp - esc * y0 + lam * esc * hub);
+        li = (double)(sp - esc * y0 + lam * wd * hub);
         dy[i * OUT_PAD + 0] = (__bf16)((sigmoidf_(y0) - esc) * inv_n);
         for (int c = 1; c < OUT; ++c) {
             const float e = yi[c] - t[c];
             const float ge = fabsf(e) <= delta ? 2.0f * e : copysignf(2.0f * delta, e);
-            dy[i * OUT_PAD + c] = (__bf16)(lam * esc * ge * inv_n);
+            dy[i * OUT_PAD + c] = (__bf16)(lam * wd * ge * inv_n);
         }
         for (int c = OUT; c < OUT_PAD; ++c) dy[i * OUT_PAD + c] = (__bf16)0.0f;
     }
@@ -335,12 +338,12 @@ hipError_t inputs(const float* x, const int32_t* rows, int64_t n, int64_t n_src,
 }
 
 hipError_t loss(const float* y, const float* target, const int32_t* rows, int64_t n,
-                int64_t n_src, float lam, float delta, __bf16* dy, double* partial,
+                int64_t n_src, float lam, float delta, float dmax, __bf16* dy, double* partial,
                 float* loss_out, hipStream_t s) {
     const unsigned blocks = (unsigned)((n + 255) / 256);
     const float inv_n = 1.0f / (float)n;
     hipLaunchKernelGGL(loss_kernel, dim3(blocks), dim3(256), 0, s, y, target, rows, n, n_src, lam,
-                       delta, inv_n, dy, partial);
+                       delta, dmax, inv_n, dy, partial);
     hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, s, partial, (int64_t)blocks, inv_n,
                        loss_out);
     return hipGetLastError();

@@ -258,17 +258,17 @@ int gr_mlp_forward(gr_mlp* m, const float* x, int64_t n, float* y, void* stream)
 }
 
 int gr_mlp_loss_grad(gr_mlp* m, const float* x, const float* target, const int32_t* rows,
-                     int64_t n, int64_t n_src, float lam, float delta, float* loss, float* grad,
-                     void* stream) {
+                     int64_t n, int64_t n_src, float lam, float delta, float dmax, float* loss,
+                     float* grad, void* stream) {
     if (!m || !x || !target || !grad) return GR_EINVAL;
     if (n < 32 || n > m->max_batch || n % 32) return GR_EINVAL;
     if (!rows) n_src = n;
-    if (n_src < 1 || !(lam >= 0.0f) || !(delta > 0.0f)) return GR_EINVAL;
+    if (n_src < 1 || !(lam >= 0.0f) || !(delta > 0.0f) || !(dmax >= 0.0f)) return GR_EINVAL;
     Guard guard(m->device);
     hipStream_t s = (hipStream_t)stream;
     if (inputs(x, rows, n, n_src, m->X, s) != hipSuccess) return GR_EDEVICE;
     if (forward_rows(m, n, true, s) != hipSuccess) return GR_EDEVICE;
-    if (gr::mlp::loss(m->Y, target, rows, n, n_src, lam, delta, m->dY, m->partial,
+    if (gr::mlp::loss(m->Y, target, rows, n, n_src, lam, delta, dmax, m->dY, m->partial,
                       loss ? loss : m->loss, s) != hipSuccess)
         return GR_EDEVICE;
     // backward, last layer first

@@ -71,7 +71,7 @@ inline int64_t frag_elems(int ftiles, int in_pad) { return (int64_t)ftiles * (in
 hipError_t inputs(const float* x, const int32_t* rows, int64_t n, int64_t n_src, __bf16* out,
                   hipStream_t s);
 hipError_t loss(const float* y, const float* target, const int32_t* rows, int64_t n,
-                int64_t n_src, float lam, float delta, __bf16* dy, double* partial,
+                int64_t n_src, float lam, float delta, float dmax, __bf16* dy, double* partial,
                 float* loss_out, hipStream_t s);
 // part: COLSUM_CHUNKS x ncols scratch.
 hipError_t colsum(const __bf16* dz, int64_t nrows, int ld, int ncols, float* part, float* out,

@@ -4,10 +4,15 @@
 //
 // Inputs of a ray (7): pixel angles alpha = atan(x), beta = atan(y) of its
 // image-plane coordinates, a/M, |Q|/M, theta0, r0/(50 M), fov (M = 1 for flat
-// space).  The network's direction output is a correction d to u_flat, the
-// point where the straight line of the camera ray (flat space, spherical
-// coordinates) leaves the escape sphere r = escape_factor * r0, as a unit
-// vector; the end direction is normalise(u_flat + d).  Targets use the traced
+// space).  The network's direction output is a correction d to a baseline
+// u_base: where the same camera ray would cross the escape sphere
+// r = escape_factor * r0 around the Reissner-Nordstrom hole with the same M
+// and Q (no spin: the ray stays in a plane and its sweep is a 1-D integral),
+// or, for rays that hole captures, where the straight line of flat space
+// leaves the sphere; the end direction is normalise(u_base + d).  Close to
+// the critical impact parameter b_c the sweep diverges and the spin moves
+// the shadow, so the frame pipeline can re-trace escaping rays with
+// b < min_impact b_c instead of trusting the network there.  Targets use the traced
 // ray's crossing of the same sphere (its end state moved back along its own
 // velocity to r_esc).
 #include "internal.h"
@@ -28,7 +33,94 @@ __device__ __forceinline__ int find_inst(const int64_t* firsts, int ninst, int64
     return lo;
 }
 
-__device__ void ray_inputs(const BatchInstance& I, int64_t pix, float* x, float* u) {
+// ---- Reissner-Nordstrom baseline of the end direction
+// Gauss-Legendre 16-point rule on [-1, 1]: nodes +-GLX[k], weights GLW[k]
+// (roots of the Legendre polynomial P_16 and their weights).
+__device__ constexpr double GLX[8] = {
+    0x1.852bd6676a9fap-4, 0x1.205cae642337cp-2, 0x1.d50259a43a772p-2, 0x1.3c5a466d5e8b8p-1,
+    0x1.82c45dda4726bp-1, 0x1.bb3403514e483p-1, 0x1.e39f56616f9b0p-1, 0x1.fa92c264d787ep-1};
+__device__ constexpr double GLW[8] = {
+    0x1.83feae80e4dffp-3, 0x1.75f8c77e0c010p-3, 0x1.5a6ebbb5a75ffp-3, 0x1.325f61bca3cc0p-3,
+    0x1.fe7af2bad3875p-4, 0x1.85c4ee79cc24ap-4, 0x1.fdfb1a2c12642p-5, 0x1.bcddab4b7c200p-6};
+
+// Azimuth swept by an equatorial photon of the Reissner-Nordstrom hole (M,
+// Q^2) with impact parameter b that starts inward at u0 = 1/r0, turns at its
+// periapsis u_t and leaves to u1 = 1/r1.  With u = 1/r the orbit obeys
+// (du/dphi)^2 = F(u) = 1/b^2 - u^2 + 2 M u^3 - Q^2 u^4; u_t is the root of F
+// below the photon sphere (where dF/du = 0), found by safeguarded Newton
+// steps.  The substitution u = u_t - s^2 gives F = s^2 G(s), G the Taylor
+// polynomial of F about u_t divided by -s^2, and dphi = 2 ds / sqrt(G(s)),
+// integrated from 0 to sqrt(u_t - u0) and to sqrt(u_t - u1) by 16-point
+// Gauss-Legendre.  Returns false when the photon does not turn outside the
+// photon sphere.
+__device__ bool rn_sweep(double M, double Q2, double b, double u0, double u1, double& dphi) {
+    if (!(b > 0.0)) return false;
+    const double ib2 = 1.0 / (b * b);
+    double ut;
+    if (M == 0.0 && Q2 == 0.0) {
+        ut = 1.0 / b;                                   // straight line
+    } else {
+        // photon sphere: smallest positive root of 1 - 3 M u + 2 Q^2 u^2
+        const double uph = Q2 > 0.0 ? (3.0 * M - sqrt(fmax(9.0 * M * M - 8.0 * Q2, 0.0))) /
+                                          (4.0 * Q2)
+                                    : 1.0 / (3.0 * M);
+        const double Fph = ib2 + uph * uph * (-1.0 + uph * (2.0 * M - Q2 * uph));
+        if (!(Fph < 0.0) || !(u0 < uph)) return false;
+        double lo = u0, hi = uph, u = u0;
+        for (int it = 0; it < 64; ++it) {
+            const double F = ib2 + u * u * (-1.0 + u * (2.0 * M - Q2 * u));
+            const double dF = u * (-2.0 + u * (6.0 * M - 4.0 * Q2 * u));
+            if (F > 0.0) lo = u; else hi = u;
+            double un = u - F / dF;
+            if (!(un > lo && un < hi)) un = 0.5 * (lo + hi);
+            if (fabs(un - u) <= 1e-16 * un) {
+                u = un;
+                break;
+            }
+            u = un;
+        }
+        ut = u;
+    }
+    // derivatives of F at u_t (first to fourth)
+    const double F1 = ut * (-2.0 + ut * (6.0 * M - 4.0 * Q2 * ut));
+    const double F2 = -2.0 + ut * (12.0 * M - 12.0 * Q2 * ut);
+    const double F3 = 12.0 * M - 24.0 * Q2 * ut;
+    const double F4 = -24.0 * Q2;
+    const double g0 = -F1, g1 = 0.5 * F2, g2 = -F3 / 6.0, g3 = F4 / 24.0;
+    if (!(g0 > 0.0)) return false;
+    double total = 0.0;
+    for (int leg = 0; leg < 2; ++leg) {
+        const double w = ut - (leg ? u1 : u0);
+        if (w <= 0.0) continue;
+        const double half = 0.5 * sqrt(w);
+        double acc = 0.0;
+        for (int k = 0; k < 8; ++k) {
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+                const double sk = half * (1.0 + sgn * GLX[k]);
+                const double z = sk * sk;
+                const double G = g0 + z * (g1 + z * (g2 + z * g3));
+                acc += GLW[k] / sqrt(G);
+            }
+        }
+        total += half * 2.0 * acc;
+    }
+    dphi = total;
+    return isfinite(total);
+}
+
+// Critical impact parameter of the Reissner-Nordstrom hole (M, Q^2), infinity
+// for flat space: r_ph / sqrt(f(r_ph)) at the photon sphere
+// r_ph = (3M + sqrt(9M^2 - 8Q^2))/2.
+__device__ double critical_b(double M, double Q2) {
+    if (!(M > 0.0)) return INFINITY;
+    const double rph = 0.5 * (3.0 * M + sqrt(fmax(9.0 * M * M - 8.0 * Q2, 0.0)));
+    return rph / sqrt(1.0 - (2.0 * M - Q2 / rph) / rph);
+}
+
+// Features x (7) and baseline u (3) of pixel pix; b_rel (may be null)
+// receives the ray's impact parameter over the critical one.
+__device__ void ray_inputs(const BatchInstance& I, int64_t pix, float* x, float* u,
+                           float* b_rel = nullptr) {
     const Camera& C = I.cam;
     const int64_t i = pix % C.W, j = pix / C.W;
     const double xs = ((double)(2 * i + 1 - C.W) / (double)C.W) * C.tan_h;
@@ -50,11 +142,32 @@ __device__ void ray_inputs(const BatchInstance& I, int64_t pix, float* x, float*
     const double d1 = nr * st * sp + nt * ct * sp + np * cp;
     const double d2 = nr * ct - nt * st;
     const double R = I.r_esc;
-    const double b = C.r0 * nr;                       // x0 . d
-    const double s = -b + sqrt(b * b - (C.r0 * C.r0 - R * R));
+    // Reissner-Nordstrom baseline (the hole without spin, same M and Q): the
+    // photon stays in the plane of x0 and its initial direction and sweeps
+    // rn_sweep's azimuth; impact parameter b = r0 sin(alpha)/sqrt(f(r0)) with
+    // alpha the angle from the inward radial direction of a static observer
+    // flat space: the straight line's crossing of the escape sphere
+    const double bb = C.r0 * nr;                      // x0 . d
+    const double s = -bb + sqrt(bb * bb - (C.r0 * C.r0 - R * R));
     u[0] = (float)((C.r0 * st * cp + s * d0) / R);
     u[1] = (float)((C.r0 * st * sp + s * d1) / R);
     u[2] = (float)((C.r0 * ct + s * d2) / R);
+    // the Reissner-Nordstrom sweep where that hole lets the ray turn
+    const double tt = sqrt(nt * nt + np * np);        // sin(alpha)
+    const double f0 = 1.0 - (I.hole.M2 - I.hole.Q2 / C.r0) / C.r0;
+    const double b = f0 > 0.0 ? C.r0 * tt / sqrt(f0) : 0.0;
+    if (b_rel) *b_rel = (float)(b / critical_b(M, I.hole.Q2));
+    double sweep;
+    if (tt > 0.0 && rn_sweep(M, I.hole.Q2, b, 1.0 / C.r0, 1.0 / R, sweep)) {
+        const double e0 = st * cp, e1 = st * sp, e2 = ct;                 // x0 / r0
+        const double t0 = (nt * ct * cp - np * sp) / tt;                  // tangential unit
+        const double t1 = (nt * ct * sp + np * cp) / tt;
+        const double t2 = (-nt * st) / tt;
+        const double cs = cos(sweep), sn = sin(sweep);
+        u[0] = (float)(cs * e0 + sn * t0);
+        u[1] = (float)(cs * e1 + sn * t1);
+        u[2] = (float)(cs * e2 + sn * t2);
+    }
 }
 
 template <typename T>
@@ -175,16 +288,19 @@ __device__ __forceinline__ void frame_layer(__bf16* act, const __bf16* __restric
 }
 
 __global__ void __launch_bounds__(FRAME_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
-frame_net_kernel(const BatchInstance I, int64_t npix, const mlp::NetView net,
+frame_net_kernel(const BatchInstance I, int64_t npix, const mlp::NetView net, float min_impact,
                  int8_t* __restrict__ flag, float* __restrict__ dir, float* __restrict__ logit) {
     __shared__ __attribute__((aligned(16))) __bf16 act[FR * LDA];
     __shared__ float uf[FR][3];
+    __shared__ float brel[FR];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t p0 = (int64_t)blockIdx.x * FR;
 
     if (tid < FR) {                        // network inputs (rows past the frame are zero)
         float x[mlp::IN] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, u[3] = {0.f, 0.f, 0.f};
-        if (p0 + tid < npix) ray_inputs(I, p0 + tid, x, u);
+        float br = INFINITY;
+        if (p0 + tid < npix) ray_inputs(I, p0 + tid, x, u, &br);
+        brel[tid] = br;
         __bf16* row = act + tid * LDA;
         for (int c = 0; c < mlp::IN_PAD; ++c) row[c] = c < mlp::IN ? (__bf16)x[c] : (__bf16)0.0f;
         for (int c = 0; c < 3; ++c) uf[tid][c] = u[c];
@@ -225,7 +341,9 @@ frame_net_kernel(const BatchInstance I, int64_t npix, const mlp::NetView net,
             const float inv = esc && nn > 0.0f ? 1.0f / sqrtf(nn) : 0.0f;
             flag[p] = esc ? GR_FLAG_ESCAPE : GR_FLAG_HORIZON;
             for (int c = 0; c < 3; ++c) dir[p * 3 + c] = u[c] * inv;
-            logit[p] = y0;
+            // an escaping ray too close to the critical impact parameter gets a
+            // NaN logit, which the fallback selection always re-traces
+            logit[p] = esc && brel[ray] < min_impact ? NAN : y0;
         }
     }
 }
@@ -245,7 +363,7 @@ __global__ void fallback_kernel(const float* __restrict__ logit, const int8_t* _
     bool f = false;
     if (p < (int64_t)W * H) {
         const int i = (int)(p % W), j = (int)(p / W);
-        f = fabsf(logit[p]) < logit_min;
+        f = !(fabsf(logit[p]) >= logit_min);          // NaN: always
         const int8_t mine = flag[p];
         for (int dj = -edge; dj <= edge && !f; ++dj) {
             const int jj = j + dj;
@@ -332,11 +450,11 @@ hipError_t targets(const BatchInstance* inst, const int64_t* firsts, int ninst, 
 }
 
 hipError_t frame_net(const BatchInstance& I, int64_t npix, const mlp::NetView& net,
-                     int8_t* flag, float* dir, float* logit, hipStream_t s) {
+                     float min_impact, int8_t* flag, float* dir, float* logit, hipStream_t s) {
     if (npix <= 0) return hipSuccess;
     const unsigned grid = (unsigned)((npix + FR - 1) / FR);
-    hipLaunchKernelGGL(frame_net_kernel, dim3(grid), dim3(FRAME_THREADS), 0, s, I, npix, net, flag,
-                       dir, logit);
+    hipLaunchKernelGGL(frame_net_kernel, dim3(grid), dim3(FRAME_THREADS), 0, s, I, npix, net,
+                       min_impact, flag, dir, logit);
     return hipGetLastError();
 }
 

@@ -19,9 +19,11 @@ hipError_t targets(const BatchInstance* inst, const int64_t* firsts, int ninst, 
                    const float* uflat, float* target, hipStream_t s);
 // Frame pipeline.  frame_net: inputs, network, class and end direction of
 // every pixel of one frame (I.pixels is ignored: pixel k is ray k) in one
-// launch, keeping each escape logit for the fallback selection.
+// launch, keeping each escape logit for the fallback selection (NaN for an
+// escaping ray whose impact parameter is below min_impact times the critical
+// one, which the selection always re-traces).
 hipError_t frame_net(const BatchInstance& I, int64_t npix, const mlp::NetView& net,
-                     int8_t* flag, float* dir, float* logit, hipStream_t s);
+                     float min_impact, int8_t* flag, float* dir, float* logit, hipStream_t s);
 hipError_t fallback(const float* logit, const int8_t* flag, const float* dir, int32_t W,
                     int32_t H, float logit_min, int32_t edge, float max_chord2, int8_t* fb,
                     int32_t* list, unsigned long long* count, hipStream_t s);

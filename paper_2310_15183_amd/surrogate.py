@@ -79,10 +79,12 @@ def training_set(n_rays: int, seed: int = 1, rays_per_instance: int = 2048,
 
 
 def train(net, data: TrainingSet, epochs: int = 20, batch: int = 8192, lr: float = 2e-3,
-          lr_min: float = 2e-5, lam: float = 100.0, delta: float = 0.02, seed: int = 1,
-          log=None):
+          lr_min: float = 2e-5, lam: float = 100.0, delta: float = 0.02, dmax: float = 0.5,
+          seed: int = 1, log=None):
     """Adam with a cosine decay from lr to lr_min over all steps; returns the
-    mean loss of each epoch (read back once per epoch)."""
+    mean loss of each epoch (read back once per epoch).  Rows whose target
+    correction is longer than dmax (rays the Reissner-Nordstrom baseline does
+    not describe, re-traced at inference) take no direction loss."""
     import torch
     n = data.x.shape[0]
     steps_per_epoch = n // batch
@@ -97,7 +99,7 @@ def train(net, data: TrainingSet, epochs: int = 20, batch: int = 8192, lr: float
         for b in range(steps_per_epoch):
             rows = perm[b * batch:(b + 1) * batch]
             g.gr_mlp_loss_grad(net, data.x, data.target, grad, loss=loss[b:b + 1], rows=rows,
-                               lam=lam, delta=delta)
+                               lam=lam, delta=delta, dmax=dmax)
             frac = step / total
             g.gr_mlp_adam_step(net, grad, lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * frac)))
             step += 1

@@ -155,6 +155,45 @@ def schwarzschild_deflection(M, b, r0, r_end, dps=30):
         return float(phi), float(t)
 
 
+def rn_sweep(M, Q, b, r0, r_end, dps=30):
+    """Azimuth swept by an equatorial Reissner-Nordstrom photon with impact
+    parameter b that starts inward at r0, passes periapsis and leaves to r_end:
+    (du/dphi)^2 = F(u) = 1/b^2 - u^2 + 2 M u^3 - Q^2 u^4 with u = 1/r; the
+    turning point u_t is the smallest positive root of F, and u = u_t - s^2
+    removes the endpoint singularity (mpmath quadrature).  None if the photon
+    does not turn (captured)."""
+    with mp.workdps(dps):
+        M_, Q2, b_ = mp.mpf(M), mp.mpf(Q) ** 2, mp.mpf(b)
+        coeffs = [-Q2, 2 * M_, -1, 0, 1 / b_ ** 2] if Q2 > 0 else [2 * M_, -1, 0, 1 / b_ ** 2]
+        if M_ == 0 and Q2 == 0:
+            pos = [1 / b_]
+        else:
+            roots = mp.polyroots(coeffs, maxsteps=400, extraprec=200)
+            pos = sorted([mp.re(x) for x in roots if abs(mp.im(x)) < mp.mpf(10) ** (-dps // 2)
+                          and mp.re(x) > 0])
+        if not pos or pos[0] <= 1 / mp.mpf(r0):
+            return None
+        ut = pos[0]
+        if M_ > 0:
+            # a root beyond the photon sphere lies inside the hole: no turning point
+            uph = (3 * M_ - mp.sqrt(9 * M_ ** 2 - 8 * Q2)) / (4 * Q2) if Q2 > 0 else 1 / (3 * M_)
+            if ut >= uph:
+                return None
+
+        # F(u_t - s^2) = s^2 G(s) exactly (Taylor series of the quartic about its root)
+        F1 = -2 * ut + 6 * M_ * ut ** 2 - 4 * Q2 * ut ** 3
+        F2 = -2 + 12 * M_ * ut - 12 * Q2 * ut ** 2
+        F3 = 12 * M_ - 24 * Q2 * ut
+        F4 = -24 * Q2
+
+        def dphi(s):
+            z = s * s
+            return 2 / mp.sqrt(-F1 + F2 / 2 * z - F3 / 6 * z * z + F4 / 24 * z ** 3)
+
+        return float(mp.quad(dphi, [0, mp.sqrt(ut - 1 / mp.mpf(r0))]) +
+                     mp.quad(dphi, [0, mp.sqrt(ut - 1 / mp.mpf(r_end))]))
+
+
 def bl_to_cartesian(a, r, theta, phi):
     """Flat-space oblate-spheroidal map x = sqrt(r^2+a^2) sin cos, y = ..., z = r cos."""
     rr = np.sqrt(r * r + a * a)

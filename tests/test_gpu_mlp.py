@@ -72,10 +72,11 @@ def test_gradient_matches_reference(g, net):
     x, t = _batch(256, 3)
     grad = torch.empty(g.gr_mlp_num_params(), device="cuda")
     loss = torch.empty(1, device="cuda")
-    g.gr_mlp_loss_grad(net, _t(x), _t(t), grad, loss=loss, lam=10.0, delta=0.05)
+    # dmax masks the direction term of about half of the rows
+    g.gr_mlp_loss_grad(net, _t(x), _t(t), grad, loss=loss, lam=10.0, delta=0.05, dmax=0.17)
     torch.cuda.synchronize()
     L, gref = ref.loss_and_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64),
-                                lam=10.0, bf16_mode=True, delta=0.05)
+                                lam=10.0, bf16_mode=True, delta=0.05, dmax=0.17)
     assert abs(loss.item() - L) <= 1e-3 * abs(L)
     gg = grad.cpu().numpy().astype(np.float64)
     o = 0
@@ -331,3 +332,87 @@ def test_direction_jump_trigger_marks_the_magnified_pixels(g, net):
     want = J2 > chord * chord
     assert 0.2 * want.size < want.sum() < 0.8 * want.size
     np.testing.assert_array_equal(got.astype(bool), want)
+
+
+def test_surrogate_baseline_is_the_reissner_nordstrom_sweep(g):
+    """The direction baseline of the network's inputs: where the camera ray
+    would cross the escape sphere around the Reissner-Nordstrom hole with the
+    frame's M and Q, against the sweep integral evaluated on the CPU (mpmath)
+    for pixels whose impact parameter is at least 1.4 times the critical one
+    (below 1.1 b_c the baseline is the straight line, blended in between)."""
+    import torch
+
+    from tests import physics
+    M, a, Q, r0, th0, ph0, fov, W, H = 0.5, 0.3, 0.25, 25.0, 70 * DEG, 0.4, 70 * DEG, 60, 40
+    ctx = g.gr_trace_init(0, g.make_integrator(dt=0.01, max_steps=20000))
+    try:
+        inst = g.gr_instance(g.gr_metric(M, a, Q), g.gr_camera(r0, th0, ph0, fov, W, H),
+                             g.gr_output(), None, -1)
+        x = torch.empty(W * H, 7, device="cuda")
+        u = torch.empty(W * H, 3, device="cuda")
+        g.gr_surrogate_inputs(ctx, [inst], x, u)
+        torch.cuda.synchronize()
+        u = u.cpu().numpy().astype(np.float64)
+    finally:
+        g.gr_trace_destroy(ctx)
+    rph = 0.5 * (3 * M + math.sqrt(9 * M * M - 8 * Q * Q))
+    b_crit = rph / math.sqrt(1 - 2 * M / rph + Q * Q / rph ** 2)
+    f0 = 1 - 2 * M / r0 + Q * Q / r0 ** 2
+    tan_h = math.tan(fov / 2)
+    tan_v = tan_h * H / W
+    st, ct, sp, cp = math.sin(th0), math.cos(th0), math.sin(ph0), math.cos(ph0)
+    e = np.array([st * cp, st * sp, ct])
+    eth = np.array([ct * cp, ct * sp, -st])
+    eph = np.array([-sp, cp, 0.0])
+    rng = np.random.default_rng(9)
+    checked = 0
+    for p in rng.permutation(W * H)[:300]:
+        i, j = p % W, p // W
+        xs = (2 * i + 1 - W) / W * tan_h
+        ys = (H - 2 * j - 1) / H * tan_v
+        sin_a = math.hypot(xs, ys) / math.sqrt(1 + xs * xs + ys * ys)
+        b = r0 * sin_a / math.sqrt(f0)
+        if b < 1.4 * b_crit:
+            continue
+        sweep = physics.rn_sweep(M, Q, b, r0, 1.5 * r0, dps=20)
+        t = -ys * eth + xs * eph
+        t /= np.linalg.norm(t)
+        want = math.cos(sweep) * e + math.sin(sweep) * t
+        assert np.abs(u[p] - want).max() < 2e-6, (p, u[p], want)
+        checked += 1
+    assert checked > 100
+
+
+def test_min_impact_rule_marks_escaping_rays_near_the_critical_impact(g, net):
+    """min_impact re-traces exactly the pixels predicted to escape whose impact
+    parameter (static camera, Reissner-Nordstrom hole with the frame's M and Q)
+    is below min_impact times the critical one."""
+    import torch
+    p = g.gr_mlp_get_params(net)
+    p[-4] = 3.0                                          # mostly escaping
+    g.gr_mlp_set_params(net, p)
+    M, a, Q, r0, th0, fov, W, H = 0.5, 0.2, 0.3, 20.0, 80 * DEG, 60 * DEG, 90, 70
+    ctx = g.gr_trace_init(0, g.make_integrator(dt=0.01, max_steps=20000))
+    try:
+        metric, cam = g.gr_metric(M, a, Q), g.gr_camera(r0, th0, 0.0, fov, W, H)
+        flag = torch.empty(W * H, dtype=torch.int8, device="cuda")
+        direc = torch.empty(W * H, 3, device="cuda")
+        fb = torch.empty(W * H, dtype=torch.int8, device="cuda")
+        g.gr_surrogate_frame(ctx, net, metric, cam, 0.0, 0, flag, direc, fb)
+        f0 = flag.cpu().numpy()
+        g.gr_surrogate_frame(ctx, net, metric, cam, 0.0, 0, flag, direc, fb, min_impact=1.6)
+        got = fb.cpu().numpy().astype(bool)
+    finally:
+        g.gr_trace_destroy(ctx)
+    i, j = np.arange(W * H) % W, np.arange(W * H) // W
+    tan_h = math.tan(fov / 2)
+    xs = (2 * i + 1 - W) / W * tan_h
+    ys = (H - 2 * j - 1) / H * tan_h * H / W
+    sin_a = np.hypot(xs, ys) / np.sqrt(1 + xs * xs + ys * ys)
+    b = r0 * sin_a / math.sqrt(1 - 2 * M / r0 + Q * Q / r0 ** 2)
+    rph = 0.5 * (3 * M + math.sqrt(9 * M * M - 8 * Q * Q))
+    b_rel = b / (rph / math.sqrt(1 - 2 * M / rph + Q * Q / rph ** 2))
+    want = (f0 == g.GR_FLAG_ESCAPE) & (b_rel < 1.6)
+    sure = np.abs(b_rel - 1.6) > 1e-5
+    assert want[sure].sum() > 50 and (~want[sure]).sum() > 50
+    np.testing.assert_array_equal(got[sure], want[sure])

@@ -18,11 +18,11 @@ def test_trained_surrogate_gains_over_binary64_tracer():
     from paper_2310_15183_amd import surrogate as S
 
     torch.cuda.set_device(0)
-    data = S.training_set(1_000_000, seed=21)
+    data = S.training_set(2_000_000, seed=21)
     net = g.gr_mlp_create(0, 8192)
     try:
         g.gr_mlp_init(net, 21)
-        hist = S.train(net, data, epochs=4, seed=21)
+        hist = S.train(net, data, epochs=8, seed=21)
         assert hist[-1] < 0.5 * hist[0]
         del data
         side = 2048
@@ -44,10 +44,11 @@ def test_trained_surrogate_gains_over_binary64_tracer():
             flag = torch.empty(n, dtype=torch.int8, device="cuda")
             direc = torch.empty(n, 3, device="cuda")
             fb = torch.empty(n, dtype=torch.int8, device="cuda")
-            g.gr_surrogate_frame(ctx, net, metric, cam, 3.0, 2, flag, direc, fb)
+            g.gr_surrogate_frame(ctx, net, metric, cam, 3.0, 2, flag, direc, fb, min_impact=1.2)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            nfb = g.gr_surrogate_frame(ctx, net, metric, cam, 3.0, 2, flag, direc, fb)
+            nfb = g.gr_surrogate_frame(ctx, net, metric, cam, 3.0, 2, flag, direc, fb,
+                                       min_impact=1.2)
             torch.cuda.synchronize()
             t_sur = time.perf_counter() - t0
         finally:

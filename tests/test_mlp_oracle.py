@@ -20,7 +20,7 @@ def test_gradient_matches_central_differences():
     50 random parameters of every layer (binary64, no bf16 rounding)."""
     p = mlp.init_params(3) + np.random.default_rng(4).normal(scale=0.01, size=mlp.num_params())
     x, t = _batch(12, 5)
-    L, g = mlp.loss_and_grad(p, x, t, lam=3.0, delta=0.05)
+    L, g = mlp.loss_and_grad(p, x, t, lam=3.0, delta=0.05, dmax=0.17)
     rng = np.random.default_rng(6)
     idx = rng.choice(p.size, 50, replace=False)
     # make sure every layer's weights and the last biases are represented
@@ -31,8 +31,8 @@ def test_gradient_matches_central_differences():
         pp, pm = p.copy(), p.copy()
         pp[i] += h
         pm[i] -= h
-        fd = (mlp.loss_and_grad(pp, x, t, lam=3.0, delta=0.05)[0]
-              - mlp.loss_and_grad(pm, x, t, lam=3.0, delta=0.05)[0]) / (2 * h)
+        fd = (mlp.loss_and_grad(pp, x, t, lam=3.0, delta=0.05, dmax=0.17)[0]
+              - mlp.loss_and_grad(pm, x, t, lam=3.0, delta=0.05, dmax=0.17)[0]) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1e-3, abs(fd)), (i, fd, g[i])
 
 
@@ -89,3 +89,18 @@ def test_huber_is_squared_error_inside_and_linear_outside():
     np.testing.assert_allclose(mlp.huber(e, np.inf), e * e)
     np.testing.assert_allclose(mlp.huber(e, 0.05), [0.0275, 0.0025, 0.0, 0.0004, 0.0025, 0.0975])
     np.testing.assert_allclose(mlp.huber_grad(e, 0.05), [-0.1, -0.1, 0.0, 0.04, 0.1, 0.1])
+
+
+def test_direction_loss_skips_rows_beyond_dmax():
+    """Rows whose target correction is longer than dmax contribute only their
+    class term: their loss equals that of the same rows with lam = 0."""
+    p = mlp.init_params(5) + np.random.default_rng(6).normal(scale=0.01, size=mlp.num_params())
+    x, t = _batch(16, 7)
+    t[:, 0] = 1.0
+    t[:8, 1:] = 2.0                                       # |d| = 3.46 > dmax
+    Lmask, gmask = mlp.loss_and_grad(p, x, t, lam=5.0, delta=0.05, dmax=1.0)
+    keep = np.r_[8:16]
+    Lk, gk = mlp.loss_and_grad(p, x[keep], t[keep], lam=5.0, delta=0.05)
+    Ld, gd = mlp.loss_and_grad(p, x[:8], t[:8], lam=0.0)
+    assert abs(Lmask - (Lk * 8 + Ld * 8) / 16) < 1e-12
+    np.testing.assert_allclose(gmask, (gk * 8 + gd * 8) / 16, rtol=1e-9, atol=1e-15)

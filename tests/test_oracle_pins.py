@@ -360,3 +360,33 @@ def test_library_trig_changes_only_the_noise_floor(kerr64):
     esc = lib.flag == oracle.FLAG_ESCAPE
     d = np.maximum(np.abs(lib.theta - kerr64.theta[sel]), np.abs(lib.phi - kerr64.phi[sel]))
     assert d[esc].max() < 2e-7
+
+
+def test_reissner_nordstrom_sweep_reference():
+    """The sweep integral the surrogate's baseline is checked against: equal to
+    the Schwarzschild deflection for Q = 0, to the straight line in flat space,
+    and to equatorial Reissner-Nordstrom rays traced by the oracle."""
+    assert abs(physics.rn_sweep(0.5, 0.0, 5.0, 20.0, 30.0) -
+               physics.schwarzschild_deflection(0.5, 5.0, 20.0, 30.0)[0]) < 1e-12
+    b = 7.0
+    assert abs(physics.rn_sweep(0.0, 0.0, b, 20.0, 30.0) -
+               (math.acos(b / 20.0) + math.acos(b / 30.0))) < 1e-12
+    assert physics.rn_sweep(0.5, 0.3, 1.0, 20.0, 30.0) is None          # captured
+    # oracle: one equatorial row of an RN frame, a = 0, camera on the equator
+    M, Q, r0, W = 0.5, 0.3, 20.0, 41
+    fov = math.radians(60.0)
+    pix = np.arange(W // 2 + 3, W)                                      # rays with x > 0
+    res = oracle.trace_frame(M, 0.0, Q, r0, math.pi / 2, 0.0, fov, W, 1, dt=0.002, eps=1e-8,
+                             horizon_norm=1e4, escape_factor=1.5, max_steps=100000, pixels=pix,
+                             want_p0=True)
+    f = 1 - 2 * M / r0 + Q * Q / r0 ** 2
+    x = ((2 * pix + 1 - W) / W) * math.tan(fov / 2)
+    b = r0 * (x / np.sqrt(1 + x * x)) / math.sqrt(f)
+    st = {"r": res.r, "theta": res.theta, "phi": res.phi, "p_t": res.p0[:, 0], "p_r": res.pr,
+          "p_theta": res.ptheta, "p_phi": res.p0[:, 3]}
+    esc = res.flag == oracle.FLAG_ESCAPE
+    from paper_2310_15183_amd.evaluate import sky_at_escape
+    th, ph = sky_at_escape(M, 0.0, Q, 1.5 * r0, {k: v[esc] for k, v in st.items()})
+    assert esc.sum() >= 10 and np.allclose(th, math.pi / 2, atol=1e-12)
+    want = np.array([physics.rn_sweep(M, Q, bb, r0, 1.5 * r0) for bb in b[esc]])
+    assert np.abs(ph - want).max() < 1e-6
