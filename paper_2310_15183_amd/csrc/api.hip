@@ -218,6 +218,47 @@ int validate_batch(const gr_ctx* ctx, const gr_instance* inst, int32_t n) {
 }
 
 // Build and upload the instance table; returns the total ray count in *total.
+// Critical impact parameter of the Reissner-Nordstrom hole with the same M
+// and Q (photon sphere r_ph = (3M + sqrt(9M^2 - 8Q^2))/2): the centre of the
+// ring of longest rays (queue order; the surrogate's impact rule).
+double critical_impact(const gr_metric* m) {
+    if (!(m->M > 0.0)) return 0.0;
+    const double M = m->M, Q2 = m->Q * m->Q;
+    const double rph = 0.5 * (3.0 * M + sqrt(std::max(9.0 * M * M - 8.0 * Q2, 0.0)));
+    const double f = 1.0 - 2.0 * M / rph + Q2 / (rph * rph);
+    return f > 0.0 ? rph / sqrt(f) : 0.0;
+}
+
+// Constants of the surrogate's features and Reissner-Nordstrom baseline.
+gr::SurConst sur_constants(const gr_metric* m, const gr_camera* c, double r_esc) {
+    gr::SurConst S;
+    memset(&S, 0, sizeof S);
+    const double M = m->M, Q2 = m->Q * m->Q, Mn = M > 0.0 ? M : 1.0;
+    S.feat[0] = (float)(m->a / Mn);
+    S.feat[1] = (float)(fabs(m->Q) / Mn);
+    S.feat[2] = (float)c->theta0;
+    S.feat[3] = (float)(c->r0 / (50.0 * Mn));
+    S.feat[4] = (float)c->fov;
+    S.st = sin(c->theta0);
+    S.ct = cos(c->theta0);
+    S.sp = sin(c->phi0);
+    S.cp = cos(c->phi0);
+    S.r0 = c->r0;
+    S.R = r_esc;
+    S.u0 = 1.0 / c->r0;
+    S.u1 = 1.0 / r_esc;
+    S.M = M;
+    S.Q2 = Q2;
+    const double f0 = 1.0 - (2.0 * M - Q2 / c->r0) / c->r0;
+    S.bscale = f0 > 0.0 ? c->r0 / sqrt(f0) : 0.0;
+    const double bc = critical_impact(m);
+    S.inv_bc = bc > 0.0 ? 1.0 / bc : 0.0;
+    if (M > 0.0)
+        S.uph = Q2 > 0.0 ? (3.0 * M - sqrt(std::max(9.0 * M * M - 8.0 * Q2, 0.0))) / (4.0 * Q2)
+                         : 1.0 / (3.0 * M);
+    return S;
+}
+
 gr::BatchInstance batch_instance(const gr_ctx* ctx, const gr_instance* I) {
     gr::BatchInstance B;
     memset(&B, 0, sizeof B);
@@ -228,6 +269,7 @@ gr::BatchInstance batch_instance(const gr_ctx* ctx, const gr_instance* I) {
     B.pixels = I->n_pixels < 0 ? nullptr : I->pixels;
     B.out = out_ptrs(&I->out);
     B.f32 = I->out.dtype == GR_F32;
+    B.sur = sur_constants(&I->metric, &I->camera, B.r_esc);
     return B;
 }
 
@@ -407,17 +449,6 @@ int grow_order_ws(gr_ctx* c, int64_t n) {
     c->ord_cap = n;
     c->ord_temp_bytes = tb;
     return GR_OK;
-}
-
-// Critical impact parameter of the Reissner-Nordstrom hole with the same M
-// and Q (photon sphere r_ph = (3M + sqrt(9M^2 - 8Q^2))/2): the centre of the
-// ring of longest rays, used only to order the queue.
-double critical_impact(const gr_metric* m) {
-    if (!(m->M > 0.0)) return 0.0;
-    const double M = m->M, Q2 = m->Q * m->Q;
-    const double rph = 0.5 * (3.0 * M + sqrt(std::max(9.0 * M * M - 8.0 * Q2, 0.0)));
-    const double f = 1.0 - 2.0 * M / rph + Q2 / (rph * rph);
-    return f > 0.0 ? rph / sqrt(f) : 0.0;
 }
 
 int grow_surrogate_ws(gr_ctx* c, int64_t n) {
@@ -681,11 +712,7 @@ int gr_surrogate_frame(gr_ctx* ctx, gr_mlp* mlp, const gr_metric* m, const gr_ca
     frame.metric = *m;
     frame.camera = *c;
     frame.n_pixels = -1;
-    gr::BatchInstance I;
-    memset(&I, 0, sizeof I);
-    I.hole = gr::make_hole(m->M, m->a, m->Q);
-    I.cam = gr::make_camera(I.hole, c->r0, c->theta0, c->phi0, c->fov, c->width, c->height);
-    I.r_esc = ctx->integ.escape_factor * c->r0;
+    const gr::BatchInstance I = batch_instance(ctx, &frame);
     hipError_t e = gr::sur::frame_net(I, npix, gr_mlp_view(mlp), rule->min_impact, flag, dir,
                                       ctx->sw_logit, s);
     if (e != hipSuccess) return device_error(e, "surrogate network");

@@ -45,6 +45,17 @@ struct FrameArgs {
     OutPtrs out;
 };
 
+// Per-instance constants of the surrogate's features and baseline (host-made).
+struct SurConst {
+    float feat[5];          // a/M, |Q|/M, theta0, r0/(50 M), fov (M = 1 for flat space)
+    double st, ct, sp, cp;  // sin/cos of theta0 and phi0
+    double r0, R, u0, u1;   // camera radius, escape radius, 1/r0, 1/R
+    double M, Q2;
+    double bscale;          // b = bscale sin(alpha): r0 / sqrt(f(r0)) of the charged hole
+    double inv_bc;          // 1 / critical impact parameter (0 for flat space)
+    double uph;             // 1 / photon-sphere radius (0 for flat space)
+};
+
 // One instance of a batch (device table entry).
 struct BatchInstance {
     Hole hole;
@@ -53,6 +64,7 @@ struct BatchInstance {
     const int32_t* pixels;  // null: ray k is pixel k
     OutPtrs out;
     int32_t f32;
+    SurConst sur;
 };
 
 struct BatchArgs {

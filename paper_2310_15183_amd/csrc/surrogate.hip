@@ -47,37 +47,37 @@ __device__ constexpr double GLW[8] = {
 // Q^2) with impact parameter b that starts inward at u0 = 1/r0, turns at its
 // periapsis u_t and leaves to u1 = 1/r1.  With u = 1/r the orbit obeys
 // (du/dphi)^2 = F(u) = 1/b^2 - u^2 + 2 M u^3 - Q^2 u^4; u_t is the root of F
-// below the photon sphere (where dF/du = 0), found by safeguarded Newton
-// steps.  The substitution u = u_t - s^2 gives F = s^2 G(s), G the Taylor
-// polynomial of F about u_t divided by -s^2, and dphi = 2 ds / sqrt(G(s)),
-// integrated from 0 to sqrt(u_t - u0) and to sqrt(u_t - u1) by 16-point
-// Gauss-Legendre.  Returns false when the photon does not turn outside the
-// photon sphere.
-__device__ bool rn_sweep(double M, double Q2, double b, double u0, double u1, double& dphi) {
-    if (!(b > 0.0)) return false;
-    const double ib2 = 1.0 / (b * b);
+// below the photon sphere u_ph (where dF/du = 0), which exists when b exceeds
+// the critical impact parameter b_c (rn_turn).  The substitution u = u_t - s^2
+// gives F = s^2 G(s), G the Taylor polynomial of F about u_t divided by -s^2,
+// and dphi = 2 ds / sqrt(G(s)), integrated from 0 to sqrt(u_t - u) for each
+// leg (rn_leg) by 16-point Gauss-Legendre; the sweep is rn_leg(u0) + rn_leg(u1).
+struct RnTurn {
+    double ut, g0, g1, g2, g3;          // turning point and G's coefficients in s^2
+};
+
+// u_t starts from the Schwarzschild periapsis of a hole whose photon sphere
+// and critical impact parameter are those of (M, Q^2) -- the trigonometric
+// root 1/u = 2 r_ph b_rel cos(arccos(-1/b_rel)/3) of the cubic, b_rel = b/b_c,
+// exact for Q = 0 up to binary32 rounding -- and takes four Newton steps on F
+// (relative error below 1e-12 for b_rel > 1 + 1e-6 and |Q| < M).  False when
+// the photon does not turn outside the photon sphere.
+__device__ bool rn_turn(const SurConst& S, double b, double b_rel, RnTurn& T) {
+    const double M = S.M, Q2 = S.Q2;
     double ut;
     if (M == 0.0 && Q2 == 0.0) {
+        if (!(b > 0.0)) return false;
         ut = 1.0 / b;                                   // straight line
     } else {
-        // photon sphere: smallest positive root of 1 - 3 M u + 2 Q^2 u^2
-        const double uph = Q2 > 0.0 ? (3.0 * M - sqrt(fmax(9.0 * M * M - 8.0 * Q2, 0.0))) /
-                                          (4.0 * Q2)
-                                    : 1.0 / (3.0 * M);
-        const double Fph = ib2 + uph * uph * (-1.0 + uph * (2.0 * M - Q2 * uph));
-        if (!(Fph < 0.0) || !(u0 < uph)) return false;
-        double lo = u0, hi = uph, u = u0;
-        for (int it = 0; it < 64; ++it) {
+        if (!(b_rel > 1.0) || !(S.u0 < S.uph)) return false;
+        const float c = cosf(acosf(-1.0f / (float)b_rel) * (1.0f / 3.0f));
+        double u = (0.5 * S.uph) / (b_rel * (double)c);
+        u = fmin(fmax(u, S.u0), S.uph);
+        const double ib2 = 1.0 / (b * b);
+        for (int it = 0; it < 4; ++it) {
             const double F = ib2 + u * u * (-1.0 + u * (2.0 * M - Q2 * u));
             const double dF = u * (-2.0 + u * (6.0 * M - 4.0 * Q2 * u));
-            if (F > 0.0) lo = u; else hi = u;
-            double un = u - F / dF;
-            if (!(un > lo && un < hi)) un = 0.5 * (lo + hi);
-            if (fabs(un - u) <= 1e-16 * un) {
-                u = un;
-                break;
-            }
-            u = un;
+            u -= F / dF;
         }
         ut = u;
     }
@@ -86,88 +86,114 @@ __device__ bool rn_sweep(double M, double Q2, double b, double u0, double u1, do
     const double F2 = -2.0 + ut * (12.0 * M - 12.0 * Q2 * ut);
     const double F3 = 12.0 * M - 24.0 * Q2 * ut;
     const double F4 = -24.0 * Q2;
-    const double g0 = -F1, g1 = 0.5 * F2, g2 = -F3 / 6.0, g3 = F4 / 24.0;
-    if (!(g0 > 0.0)) return false;
-    double total = 0.0;
-    for (int leg = 0; leg < 2; ++leg) {
-        const double w = ut - (leg ? u1 : u0);
-        if (w <= 0.0) continue;
-        const double half = 0.5 * sqrt(w);
-        double acc = 0.0;
-        for (int k = 0; k < 8; ++k) {
-            for (int sgn = -1; sgn <= 1; sgn += 2) {
-                const double sk = half * (1.0 + sgn * GLX[k]);
-                const double z = sk * sk;
-                const double G = g0 + z * (g1 + z * (g2 + z * g3));
-                acc += GLW[k] / sqrt(G);
-            }
-        }
-        total += half * 2.0 * acc;
-    }
-    dphi = total;
-    return isfinite(total);
+    T.ut = ut;
+    T.g0 = -F1;
+    T.g1 = 0.5 * F2;
+    T.g2 = -F3 / 6.0;
+    T.g3 = F4 / 24.0;
+    return T.g0 > 0.0 && ut > S.u0;
 }
 
-// Critical impact parameter of the Reissner-Nordstrom hole (M, Q^2), infinity
-// for flat space: r_ph / sqrt(f(r_ph)) at the photon sphere
-// r_ph = (3M + sqrt(9M^2 - 8Q^2))/2.
-__device__ double critical_b(double M, double Q2) {
-    if (!(M > 0.0)) return INFINITY;
-    const double rph = 0.5 * (3.0 * M + sqrt(fmax(9.0 * M * M - 8.0 * Q2, 0.0)));
-    return rph / sqrt(1.0 - (2.0 * M - Q2 / rph) / rph);
+// One leg; G in binary64, 1/sqrt(G) and the weighted sum in binary32 (the
+// baseline is rounded to binary32 and its error only has to be small against
+// the network's).
+__device__ double rn_leg(const RnTurn& T, double u_end) {
+    const double w = T.ut - u_end;
+    if (!(w > 0.0)) return 0.0;
+    const double half = 0.5 * sqrt(w);
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+#pragma unroll
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            const double sk = half * (1.0 + sgn * GLX[k]);
+            const double z = sk * sk;
+            const double G = T.g0 + z * (T.g1 + z * (T.g2 + z * T.g3));
+            acc += (float)GLW[k] * rsqrtf((float)G);
+        }
+    }
+    return half * 2.0 * (double)acc;
+}
+
+// Everything about a pixel's ray but the sweep integrals: the features, the
+// straight-line baseline, the orbit plane and the Reissner-Nordstrom turning
+// point (turns: whether there is one outside the photon sphere).
+struct RayGeom {
+    float x[7];
+    double flat[3];                   // straight-line crossing of the escape sphere
+    double e[3], t[3];                // x0 / r0 and the tangential unit of the orbit plane
+    double u0, u1;                    // 1/r0, 1/r_esc
+    float b_rel;                      // impact parameter over the critical one (inf: flat space)
+    bool turns;
+    RnTurn T;
+};
+
+__device__ void ray_geom(const BatchInstance& I, int64_t pix, RayGeom& G) {
+    const Camera& C = I.cam;
+    const SurConst& S = I.sur;
+    const int64_t i = pix % C.W, j = pix / C.W;
+    const double xs = ((double)(2 * i + 1 - C.W) / (double)C.W) * C.tan_h;
+    const double ys = ((double)(C.H - 2 * j - 1) / (double)C.H) * C.tan_v;
+    G.x[0] = atanf((float)xs);
+    G.x[1] = atanf((float)ys);
+    for (int c = 0; c < 5; ++c) G.x[2 + c] = S.feat[c];
+    // the camera ray's line of sight n = (-1, -y, x) in (e_r, e_theta, e_phi)
+    const double inv = 1.0 / sqrt(1.0 + xs * xs + ys * ys);
+    const double nr = -inv, nt = -ys * inv, np = xs * inv;
+    const double d0 = nr * S.st * S.cp + nt * S.ct * S.cp - np * S.sp;
+    const double d1 = nr * S.st * S.sp + nt * S.ct * S.sp + np * S.cp;
+    const double d2 = nr * S.ct - nt * S.st;
+    G.e[0] = S.st * S.cp;
+    G.e[1] = S.st * S.sp;
+    G.e[2] = S.ct;
+    // flat space: the straight line's crossing of the escape sphere
+    const double bb = S.r0 * nr;                      // x0 . d
+    const double s = -bb + sqrt(bb * bb - (S.r0 * S.r0 - S.R * S.R));
+    G.flat[0] = (S.r0 * G.e[0] + s * d0) * S.u1;
+    G.flat[1] = (S.r0 * G.e[1] + s * d1) * S.u1;
+    G.flat[2] = (S.r0 * G.e[2] + s * d2) * S.u1;
+    // the orbit plane of x0 and the initial direction, impact parameter
+    // b = r0 sin(alpha)/sqrt(f(r0)) for a static observer
+    const double tt = sqrt(nt * nt + np * np);        // sin(alpha)
+    const double b = S.bscale * tt;
+    const double b_rel = b * S.inv_bc;
+    G.b_rel = S.inv_bc > 0.0 ? (float)b_rel : INFINITY;
+    G.u0 = S.u0;
+    G.u1 = S.u1;
+    G.turns = tt > 0.0 && rn_turn(S, b, b_rel, G.T);
+    if (G.turns) {
+        const double it = 1.0 / tt;
+        G.t[0] = (nt * S.ct * S.cp - np * S.sp) * it;
+        G.t[1] = (nt * S.ct * S.sp + np * S.cp) * it;
+        G.t[2] = (-nt * S.st) * it;
+    }
+}
+
+// Baseline from the geometry and the sweep (rn_leg(u0) + rn_leg(u1)): the
+// Reissner-Nordstrom crossing when the ray turns, else the straight line.
+__device__ void ray_baseline(const RayGeom& G, double sweep, float* u) {
+    if (G.turns && isfinite(sweep)) {
+        const double cs = cos(sweep), sn = sin(sweep);
+        for (int c = 0; c < 3; ++c) u[c] = (float)(cs * G.e[c] + sn * G.t[c]);
+    } else {
+        for (int c = 0; c < 3; ++c) u[c] = (float)G.flat[c];
+    }
 }
 
 // Features x (7) and baseline u (3) of pixel pix; b_rel (may be null)
 // receives the ray's impact parameter over the critical one.
 __device__ void ray_inputs(const BatchInstance& I, int64_t pix, float* x, float* u,
                            float* b_rel = nullptr) {
-    const Camera& C = I.cam;
-    const int64_t i = pix % C.W, j = pix / C.W;
-    const double xs = ((double)(2 * i + 1 - C.W) / (double)C.W) * C.tan_h;
-    const double ys = ((double)(C.H - 2 * j - 1) / (double)C.H) * C.tan_v;
-    const double M = 0.5 * I.hole.M2;
-    const double Mn = M > 0.0 ? M : 1.0;
-    x[0] = (float)atan(xs);
-    x[1] = (float)atan(ys);
-    x[2] = (float)(I.hole.a / Mn);
-    x[3] = (float)(sqrt(I.hole.Q2) / Mn);
-    x[4] = (float)C.th0;
-    x[5] = (float)(C.r0 / (50.0 * Mn));
-    x[6] = (float)(2.0 * atan(C.tan_h));
-    // straight line from the camera along its line of sight n = (-1, -y, x)
-    const double inv = 1.0 / sqrt(1.0 + xs * xs + ys * ys);
-    const double nr = -inv, nt = -ys * inv, np = xs * inv;
-    const double st = sin(C.th0), ct = cos(C.th0), sp = sin(C.ph0), cp = cos(C.ph0);
-    const double d0 = nr * st * cp + nt * ct * cp - np * sp;
-    const double d1 = nr * st * sp + nt * ct * sp + np * cp;
-    const double d2 = nr * ct - nt * st;
-    const double R = I.r_esc;
-    // Reissner-Nordstrom baseline (the hole without spin, same M and Q): the
-    // photon stays in the plane of x0 and its initial direction and sweeps
-    // rn_sweep's azimuth; impact parameter b = r0 sin(alpha)/sqrt(f(r0)) with
-    // alpha the angle from the inward radial direction of a static observer
-    // flat space: the straight line's crossing of the escape sphere
-    const double bb = C.r0 * nr;                      // x0 . d
-    const double s = -bb + sqrt(bb * bb - (C.r0 * C.r0 - R * R));
-    u[0] = (float)((C.r0 * st * cp + s * d0) / R);
-    u[1] = (float)((C.r0 * st * sp + s * d1) / R);
-    u[2] = (float)((C.r0 * ct + s * d2) / R);
-    // the Reissner-Nordstrom sweep where that hole lets the ray turn
-    const double tt = sqrt(nt * nt + np * np);        // sin(alpha)
-    const double f0 = 1.0 - (I.hole.M2 - I.hole.Q2 / C.r0) / C.r0;
-    const double b = f0 > 0.0 ? C.r0 * tt / sqrt(f0) : 0.0;
-    if (b_rel) *b_rel = (float)(b / critical_b(M, I.hole.Q2));
-    double sweep;
-    if (tt > 0.0 && rn_sweep(M, I.hole.Q2, b, 1.0 / C.r0, 1.0 / R, sweep)) {
-        const double e0 = st * cp, e1 = st * sp, e2 = ct;                 // x0 / r0
-        const double t0 = (nt * ct * cp - np * sp) / tt;                  // tangential unit
-        const double t1 = (nt * ct * sp + np * cp) / tt;
-        const double t2 = (-nt * st) / tt;
-        const double cs = cos(sweep), sn = sin(sweep);
-        u[0] = (float)(cs * e0 + sn * t0);
-        u[1] = (float)(cs * e1 + sn * t1);
-        u[2] = (float)(cs * e2 + sn * t2);
+    RayGeom G;
+    ray_geom(I, pix, G);
+    double sweep = 0.0;
+    if (G.turns) {
+        sweep += rn_leg(G.T, G.u0);
+        sweep += rn_leg(G.T, G.u1);
     }
+    ray_baseline(G, sweep, u);
+    for (int c = 0; c < 7; ++c) x[c] = G.x[c];
+    if (b_rel) *b_rel = G.b_rel;
 }
 
 template <typename T>
@@ -293,17 +319,39 @@ frame_net_kernel(const BatchInstance I, int64_t npix, const mlp::NetView net, fl
     __shared__ __attribute__((aligned(16))) __bf16 act[FR * LDA];
     __shared__ float uf[FR][3];
     __shared__ float brel[FR];
+    __shared__ double legsum[FR];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t p0 = (int64_t)blockIdx.x * FR;
 
-    if (tid < FR) {                        // network inputs (rows past the frame are zero)
-        float x[mlp::IN] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, u[3] = {0.f, 0.f, 0.f};
-        float br = INFINITY;
-        if (p0 + tid < npix) ray_inputs(I, p0 + tid, x, u, &br);
-        brel[tid] = br;
-        __bf16* row = act + tid * LDA;
-        for (int c = 0; c < mlp::IN_PAD; ++c) row[c] = c < mlp::IN ? (__bf16)x[c] : (__bf16)0.0f;
-        for (int c = 0; c < 3; ++c) uf[tid][c] = u[c];
+    // network inputs: two threads per pixel, each integrating one leg of the
+    // sweep (summed in the same order as ray_inputs); rows past the frame are zero
+    {
+        const int px = tid % FR, leg = tid / FR;
+        const bool inside = p0 + px < npix;
+        RayGeom G;
+        double part = 0.0;
+        if (inside) {
+            ray_geom(I, p0 + px, G);
+            if (G.turns) part = rn_leg(G.T, leg ? G.u1 : G.u0);
+        }
+        if (leg) legsum[px] = part;
+        __syncthreads();
+        if (!leg) {
+            float u[3] = {0.f, 0.f, 0.f};
+            __bf16* row = act + px * LDA;
+            brel[px] = inside ? G.b_rel : INFINITY;
+            if (inside) {
+                double sweep = 0.0;
+                if (G.turns) {
+                    sweep += part;
+                    sweep += legsum[px];
+                }
+                ray_baseline(G, sweep, u);
+            }
+            for (int c = 0; c < mlp::IN_PAD; ++c)
+                row[c] = (inside && c < mlp::IN) ? (__bf16)G.x[c] : (__bf16)0.0f;
+            for (int c = 0; c < 3; ++c) uf[px][c] = u[c];
+        }
     }
     __syncthreads();
     frame_layer<mlp::IN_PAD / 32>(act, net.frag[0], net.bias[0], wave, lane);

@@ -339,7 +339,7 @@ def test_surrogate_baseline_is_the_reissner_nordstrom_sweep(g):
     would cross the escape sphere around the Reissner-Nordstrom hole with the
     frame's M and Q, against the sweep integral evaluated on the CPU (mpmath)
     for pixels whose impact parameter is at least 1.4 times the critical one
-    (below 1.1 b_c the baseline is the straight line, blended in between)."""
+    (the sweep diverges logarithmically as b approaches b_c)."""
     import torch
 
     from tests import physics
