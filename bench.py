@@ -38,7 +38,7 @@ FP64_PEAK_TFLOPS = 78.6           # MI355X FP64 vector (256 CU x 128 flop/clk x 
 BF16_PEAK_TFLOPS = 2500.0         # MI355X dense bfloat16 MFMA
 STRICT_TURN = 0.05                # surrogate_strict: also re-trace where neighbours' directions
                                   # differ by more than 0.05 rad
-MIN_IMPACT = 1.2                  # re-trace escaping rays with b < 1.2 b_c (baseline not valid)
+MIN_IMPACT = 1.2                  # surrogate_strict: also re-trace escaping rays with b < 1.2 b_c
 KERNEL_SOURCES = ["paper_2310_15183_amd/csrc/trace_fp64.hip",
                   "paper_2310_15183_amd/csrc/step_fp64.h",
                   "paper_2310_15183_amd/csrc/grmath.h"]
@@ -220,7 +220,7 @@ def train_surrogate(g, args):
 
 
 def surrogate_variant(g, net, w, args, stream, fp64_rays_per_s, ref, logit_min=3.0, edge=2,
-                      max_gain=None, min_impact=MIN_IMPACT):
+                      max_gain=None, min_impact=0.0):
     """Surrogate + RK4 fallback on the frame w: rays/s, speedup over the
     binary64 tracer on the same frame and integrator, the network-only frame
     time against the MFMA peak, and the errors against the binary64 frame."""
@@ -361,7 +361,8 @@ def bench_surrogate(args):
         del out
         sur = surrogate_variant(g, net, w, args, stream, n / fp64_s, ref)
         strict = surrogate_variant(g, net, w, args, stream, n / fp64_s, ref,
-                                   max_gain=STRICT_TURN / (w["fov"] / side))
+                                   max_gain=STRICT_TURN / (w["fov"] / side),
+                                   min_impact=MIN_IMPACT)
         line = {"workload": f"{name} {side}x{side}", "fp64_rays_per_s": n / fp64_s,
                 "fp64_ms_per_step": fp64_s * 1e3, "surrogate": sur, "surrogate_strict": strict}
         print(json.dumps(line), flush=True)
@@ -566,7 +567,8 @@ def main():
         net, info = train_surrogate(g, args)
         sur = surrogate_variant(g, net, w, args, stream, result["value"], ref)
         strict = surrogate_variant(g, net, w, args, stream, result["value"], ref,
-                                   max_gain=STRICT_TURN / (w["fov"] / w["W"]))
+                                   max_gain=STRICT_TURN / (w["fov"] / w["W"]),
+                                   min_impact=MIN_IMPACT)
         g.gr_mlp_destroy(net)
         sur["training"] = info
         result["variants"]["surrogate"] = sur
