@@ -2,7 +2,7 @@
 
 One step = one complete trace of the frame: camera rays built in-kernel,
 metric and forward differences, Hamilton right-hand side, RK4 with the
-coordinate-time normaliser, termination, lane refill and the per-ray stores.
+coordinate-time normaliser, termination and the per-ray stores.
 Inputs are synthetic (an analytic camera grid); nothing is cached between
 steps.  Prints one JSON line.
 

@@ -139,9 +139,11 @@ typedef struct gr_ctx gr_ctx;
  * escape radius) first, which shortens the tail; 2 = as 1, and frames of at
  * least 4096 pixels traced with refill queue their pixels sorted by how close
  * the camera ray's impact parameter sqrt(Carter Q + L_z^2)/E is to the
- * critical one (16 bytes per pixel of context workspace).  The default
- * launch uses 1 for GR_FP64 contexts and 2 for GR_MIXED ones (measured
- * faster there). */
+ * critical one (16 bytes per pixel of context workspace).  Without refill a
+ * frame is traced one ray per lane over 8x8 pixel tiles, one tile per wave.
+ * Until a shape is set, frames use {64, 0, 0, 0} (neighbouring pixels take
+ * nearly the same number of steps, so waves stay full without refill) and
+ * batches {256, 0, 1, 1}, the fastest measured for each. */
 typedef struct {
     int32_t block;
     int32_t waves_per_simd;
@@ -176,12 +178,13 @@ int gr_trace_set_integrator(gr_ctx *ctx, const gr_integrator *integ);
 /* Override (or with launch == NULL restore) the launch shape. */
 int gr_trace_set_launch(gr_ctx *ctx, const gr_launch *launch);
 
-/* Launch shape the next call will use. */
+/* Launch shape the next frame call will use (batches: see gr_launch). */
 int gr_trace_get_launch(const gr_ctx *ctx, gr_launch *launch);
 
 /* Pick the launch shape for a batch by measurement, store it in the context
- * and trace the batch with it.  Candidate shapes (block 64/128/256, residency
- * 2 or as many as fit, both queue orders) are timed on the batch with the
+ * and trace the batch with it.  Candidate shapes (persistent: block
+ * 64/128/256 and residency 2 or as many as fit; one ray per lane: block
+ * 64/128/256; both queue orders) are timed on the batch with the
  * step limit lowered to trial_steps (0 = no lowering); every candidate gives
  * identical results, so the outputs hold the final full run, made with the
  * winner.  If cache_path is non-NULL, a winner recorded there for the same

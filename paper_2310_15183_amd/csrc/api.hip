@@ -99,14 +99,24 @@ int check_output(const gr_output* o) {
     return GR_OK;
 }
 
-gr_launch effective_launch(const gr_ctx* ctx) {
+// The context's launch shape, else the default for frames or batches: frames
+// one ray per lane over 8x8 pixel tiles in workgroups of 64 (neighbouring
+// pixels take nearly the same number of steps, so a wave's lanes stay busy
+// without refill, and the step needs fewer registers); batches refill in
+// workgroups of 256, instances with the longest rays first.
+gr_launch effective_launch(const gr_ctx* ctx, bool batch = false) {
     gr_launch l = ctx->launch;
     if (l.block == 0) {
-        l.block = 256;
         l.waves_per_simd = 0;
-        l.refill = 1;
-        // frames in near-critical-first order only where it measured faster (mixed)
-        l.order = ctx->integ.precision == GR_MIXED ? 2 : 1;
+        if (batch) {
+            l.block = 256;
+            l.refill = 1;
+            l.order = 1;
+        } else {
+            l.block = 64;
+            l.refill = 0;
+            l.order = 0;
+        }
     }
     return l;
 }
@@ -130,16 +140,26 @@ gr::LaunchShape resident_shape(const gr_ctx* ctx, const gr_launch& l, int per_cu
     return L;
 }
 
-gr::LaunchShape frame_shape(const gr_ctx* ctx, int64_t nray, bool f32_out) {
+// Grid of a frame launch: persistent, or (no refill) one lane per ray with
+// whole 8x8 pixel tiles per wave when the frame has no pixel list.
+gr::LaunchShape frame_shape(const gr_ctx* ctx, const gr::FrameArgs& A, bool f32_out) {
     const gr_launch l = effective_launch(ctx);
-    if (!l.refill) {
+    const bool mixed = ctx->integ.precision == GR_MIXED;
+    const int64_t nray = A.nray;
+    int64_t lanes = nray;
+    if (!A.pixels) lanes = 64 * (((int64_t)A.cam.W + 7) / 8) * (((int64_t)A.cam.H + 7) / 8);
+    const int64_t blocks = (lanes + l.block - 1) / l.block;
+    if (!l.refill && blocks <= INT32_MAX) {    // larger grids take the persistent form
         gr::LaunchShape L;
         L.block = l.block;
         L.refill = 0;
-        L.grid = (int)std::max<int64_t>(1, (nray + L.block - 1) / L.block);
+        L.grid = (int)std::max<int64_t>(1, blocks);
         return L;
     }
-    return resident_shape(ctx, l, gr::occupancy_trace_fp64(l.block, f32_out), nray);
+    return resident_shape(ctx, l,
+                          mixed ? gr::occupancy_trace_mixed(l.block, f32_out)
+                                : gr::occupancy_trace_fp64(l.block, f32_out),
+                          nray);
 }
 
 struct DeviceGuard {
@@ -280,7 +300,7 @@ int reserve_table(gr_ctx* ctx, int64_t m) {
     gr::BatchInstance* t = nullptr;
     int64_t* f = nullptr;
     if (hipMalloc(&t, cap * sizeof(gr::BatchInstance)) != hipSuccess) return GR_ENOMEM;
-    if (hipMalloc(&f, (cap + 1) * sizeof(int64_t)) != hipSuccess) {
+    if (hipMalloc(&f, 2 * (cap + 1) * sizeof(int64_t)) != hipSuccess) {
         hipFree(t);
         return GR_ENOMEM;
     }
@@ -296,7 +316,7 @@ int reserve_table(gr_ctx* ctx, int64_t m) {
 }
 
 int upload_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, int order,
-                 hipStream_t s, int32_t* ninst, int64_t* total) {
+                 hipStream_t s, int32_t* ninst, int64_t* total, int64_t* waves = nullptr) {
     std::vector<int32_t> idx;
     for (int32_t k = 0; k < n; ++k)
         if (instance_rays(&inst[k]) > 0) idx.push_back(k);
@@ -308,14 +328,22 @@ int upload_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, int order,
     }
     const int64_t m = (int64_t)idx.size();
     std::vector<gr::BatchInstance> tab(m);
-    std::vector<int64_t> firsts(m + 1, 0);
+    // ray offsets, then wave offsets (8x8 tiles of a frame, 64 list entries)
+    std::vector<int64_t> firsts(2 * (m + 1), 0);
+    int64_t* wf = firsts.data() + m + 1;
     for (int64_t q = 0; q < m; ++q) {
         const gr_instance* I = &inst[idx[q]];
         tab[q] = batch_instance(ctx, I);
-        firsts[q + 1] = firsts[q] + instance_rays(I);
+        const int64_t n = instance_rays(I);
+        firsts[q + 1] = firsts[q] + n;
+        const int64_t nw = I->n_pixels < 0 ? ((int64_t)I->camera.width + 7) / 8 *
+                                                 (((int64_t)I->camera.height + 7) / 8)
+                                           : (n + 63) / 64;
+        wf[q + 1] = wf[q] + nw;
     }
     *ninst = (int32_t)m;
     *total = firsts[m];
+    if (waves) *waves = wf[m];
     if (m == 0) return GR_OK;
     int rc = reserve_table(ctx, m);
     if (rc) return rc;
@@ -323,7 +351,7 @@ int upload_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, int order,
     hipError_t e = hipMemcpyAsync(ctx->table, tab.data(), m * sizeof(gr::BatchInstance),
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(ctx->firsts, firsts.data(), (m + 1) * sizeof(int64_t),
+        e = hipMemcpyAsync(ctx->firsts, firsts.data(), 2 * (m + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return device_error(e, "batch table upload");
     return GR_OK;
@@ -332,8 +360,8 @@ int upload_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, int order,
 int run_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, const gr_launch& l,
               hipStream_t s) {
     int32_t ninst = 0;
-    int64_t total = 0;
-    int rc = upload_batch(ctx, inst, n, l.order, s, &ninst, &total);
+    int64_t total = 0, waves = 0;
+    int rc = upload_batch(ctx, inst, n, l.order, s, &ninst, &total, &waves);
     if (rc) return rc;
     if (total == 0) return GR_OK;
     gr::BatchArgs B;
@@ -341,10 +369,18 @@ int run_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, const gr_launch& 
     B.in = device_integrator(ctx->integ);
     B.inst = ctx->table;
     B.firsts = ctx->firsts;
+    B.wfirsts = ctx->firsts + ninst + 1;
     B.ninst = ninst;
     B.total = total;
-    const gr::LaunchShape L =
-        resident_shape(ctx, l, gr::occupancy_trace_fp64_batch(l.block), total);
+    gr::LaunchShape L;
+    const int64_t blocks = (64 * waves + l.block - 1) / l.block;
+    if (!l.refill && blocks <= INT32_MAX) {
+        L.block = l.block;
+        L.refill = 0;
+        L.grid = (int)blocks;
+    } else {
+        L = resident_shape(ctx, l, gr::occupancy_trace_fp64_batch(l.block), total);
+    }
     hipError_t e = gr::launch_trace_fp64_batch(B, L, ctx->counter, s);
     if (e != hipSuccess) return device_error(e, "trace_fp64_batch launch");
     return GR_OK;
@@ -352,7 +388,7 @@ int run_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, const gr_launch& 
 
 // ---------------------------------------------------------------- autotune cache
 // One JSON object per line:
-// {"key": "...", "block": B, "waves_per_simd": W, "refill": 1, "order": O, "ms": T}
+// {"key": "...", "block": B, "waves_per_simd": W, "refill": R, "order": O, "ms": T}
 std::string cache_key(const gr_ctx* ctx, int64_t total, int32_t ninst) {
     int lg = 0;
     while (((int64_t)1 << (lg + 1)) <= total) ++lg;
@@ -378,6 +414,9 @@ bool cache_lookup(const char* path, const std::string& key, gr_launch* out) {
             sscanf(p, "\"waves_per_simd\": %d", &l.waves_per_simd) == 1 &&
             (p = strstr(line, "\"order\": ")) && sscanf(p, "\"order\": %d", &l.order) == 1) {
             l.refill = 1;
+            if ((p = strstr(line, "\"refill\": ")) && sscanf(p, "\"refill\": %d", &l.refill) == 1 &&
+                l.refill != 0)
+                l.refill = 1;
             *out = l;      // the last matching line wins
             found = true;
         }
@@ -390,9 +429,9 @@ void cache_append(const char* path, const std::string& key, const gr_launch& l, 
     FILE* f = fopen(path, "a");
     if (!f) return;
     fprintf(f,
-            "{\"key\": \"%s\", \"block\": %d, \"waves_per_simd\": %d, \"refill\": 1, "
+            "{\"key\": \"%s\", \"block\": %d, \"waves_per_simd\": %d, \"refill\": %d, "
             "\"order\": %d, \"ms\": %.3f}\n",
-            key.c_str(), l.block, l.waves_per_simd, l.order, ms);
+            key.c_str(), l.block, l.waves_per_simd, l.refill, l.order, ms);
     fclose(f);
 }
 
@@ -559,15 +598,13 @@ int gr_trace_frame(gr_ctx* ctx, const gr_metric* m, const gr_camera* c, const gr
         A.order = ctx->ord_vals + nray;
     }
     if (ctx->integ.precision == GR_MIXED) {
-        const gr_launch l = effective_launch(ctx);
-        const gr::LaunchShape L =
-            resident_shape(ctx, l, gr::occupancy_trace_mixed(l.block, f32), nray);
+        const gr::LaunchShape L = frame_shape(ctx, A, f32);
         e = gr::launch_trace_mixed(A, horizon(m), f32, L, ctx->counter,
                                    (hipStream_t)hip_stream);
         if (e != hipSuccess) return device_error(e, "trace_mixed launch");
         return GR_OK;
     }
-    const gr::LaunchShape L = frame_shape(ctx, nray, f32);
+    const gr::LaunchShape L = frame_shape(ctx, A, f32);
     e = gr::launch_trace_fp64(A, f32, L, ctx->counter, (hipStream_t)hip_stream);
     if (e != hipSuccess) return device_error(e, "trace_fp64 launch");
     return GR_OK;
@@ -577,7 +614,7 @@ int gr_trace_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, void* hip_st
     const int rc = validate_batch(ctx, inst, n);
     if (rc) return rc;
     DeviceGuard guard(ctx->device);
-    return run_batch(ctx, inst, n, effective_launch(ctx), (hipStream_t)hip_stream);
+    return run_batch(ctx, inst, n, effective_launch(ctx, true), (hipStream_t)hip_stream);
 }
 
 int gr_trace_autotune(gr_ctx* ctx, const gr_instance* inst, int32_t n, int32_t trial_steps,
@@ -607,13 +644,15 @@ int gr_trace_autotune(gr_ctx* ctx, const gr_instance* inst, int32_t n, int32_t t
         double best_ms = 1e300;
         const int blocks[3] = {64, 128, 256};
         const int waves[2] = {2, 0};
+        // persistent shapes, then one ray per lane (waves_per_simd does not apply)
+        for (int refill = 1; refill >= 0 && !rc; --refill)
         for (int order = 0; order <= 1 && !rc; ++order)
             for (int b = 0; b < 3 && !rc; ++b)
-                for (int w = 0; w < 2 && !rc; ++w) {
+                for (int w = 0; w < (refill ? 2 : 1) && !rc; ++w) {
                     gr_launch l;
                     l.block = blocks[b];
-                    l.waves_per_simd = waves[w];
-                    l.refill = 1;
+                    l.waves_per_simd = refill ? waves[w] : 0;
+                    l.refill = refill;
                     l.order = order;
                     hipEventRecord(e0, s);
                     rc = run_batch(ctx, inst, n, l, s);
@@ -747,7 +786,7 @@ int gr_surrogate_frame(gr_ctx* ctx, gr_mlp* mlp, const gr_metric* m, const gr_ca
     A.firsts = ctx->firsts;
     A.ninst = 1;
     A.total = npix;
-    const gr_launch l = effective_launch(ctx);
+    const gr_launch l = effective_launch(ctx, true);
     const gr::LaunchShape L =
         resident_shape(ctx, l, gr::occupancy_trace_fp64_batch(l.block), npix);
     e = gr::launch_trace_fp64_batch(A, L, ctx->counter, s);

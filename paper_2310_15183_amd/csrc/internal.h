@@ -41,7 +41,8 @@ struct FrameArgs {
     int64_t nray;           // rays to trace
     const int32_t* pixels;  // null: ray k is pixel k
     const int32_t* order;   // null: the queue hands out ray k as its k-th id; else
-                            // id -> ray k = order[id] (a permutation of 0..nray-1)
+                            // id -> ray k = order[id] (a permutation of 0..nray-1);
+                            // persistent tracers only
     OutPtrs out;
 };
 
@@ -71,6 +72,8 @@ struct BatchArgs {
     Integrator in;
     const BatchInstance* inst;  // device table, ninst entries
     const int64_t* firsts;      // device prefix offsets, ninst + 1 entries (firsts[0] = 0)
+    const int64_t* wfirsts;     // one ray per lane: prefix offsets of the instances' waves
+                                // (8x8 tiles of a frame, 64 entries of a pixel list)
     int32_t ninst;
     int64_t total;              // rays on the host's side (launch shape; an upper bound when
                                 // firsts[ninst] is produced on the device); the kernel reads
@@ -110,7 +113,8 @@ hipError_t launch_trace_mixed(const FrameArgs& A, double r_plus, bool f32_out,
                               hipStream_t s);
 int occupancy_trace_mixed(int block, bool f32_out);
 
-// All instances of a batch in one persistent launch.
+// All instances of a batch in one launch: persistent (L.refill), or one ray
+// per lane over the waves of B.wfirsts.
 hipError_t launch_trace_fp64_batch(const BatchArgs& B, const LaunchShape& L,
                                    unsigned long long* counter, hipStream_t s);
 int occupancy_trace_fp64_batch(int block);

@@ -10,6 +10,33 @@ namespace detail {
 
 enum { RUNNING = -1 };
 
+// Correctly rounded 1/x and a/x for the step's operands (finite, normal, with
+// a normal quotient): the hardware reciprocal estimate, two Newton-Raphson
+// refinements y <- y + y (1 - x y), then Markstein's correction q + (a - x q) y
+// with the residual exact in fma.  IEEE division wraps the same steps in
+// operand scaling and special-value fixup, which leave such operands
+// untouched; a zero, infinite or NaN divisor gives NaN here, on a ray that is
+// invalid either way.
+static __device__ __forceinline__ double rcp_rn(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(e, y, y);
+}
+
+static __device__ __forceinline__ double div_rn(double a, double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    const double q = a * y;
+    return fma(fma(-x, q, a), y, q);
+}
+
 struct Deriv {
     double qt, qr, qh, qp;   // dq^mu/dtau
     double pr, ph;           // dp_r/dtau, dp_theta/dtau
@@ -34,13 +61,13 @@ static __device__ __forceinline__ Deriv rhs(const Hole& H, const Integrator& in,
                                          fma(-s, in.sin_eps, c * in.cos_eps));
     const RadialTerms R0 = radial_terms(H, r);
     const RadialTerms R1 = radial_terms(H, r + in.eps);
-    const double is = 1.0 / (rho2_delta(H, R0, T0) * T0.s2);
+    const double is = rcp_rn(rho2_delta(H, R0, T0) * T0.s2);
     const double inv = is * T0.s2;
     const double is_r = recip_newton(rho2_delta(H, R1, T0) * T0.s2, is);
     const double inv_t = recip_newton(rho2_delta(H, R0, T1), inv);
     const InvMetric g = metric_from(H, R0, T0, inv, is);
     const InvMetric gr = metric_from(H, R1, T0, is_r * T0.s2, is_r);
-    const InvMetric gh = metric_from(H, R0, T1, inv_t, inv_t * (1.0 / T1.s2));
+    const InvMetric gh = metric_from(H, R0, T1, inv_t, inv_t * rcp_rn(T1.s2));
 
     const double wrr = pr * pr, wth = pth * pth;
     double acc = (gr.tt - g.tt) * wtt;
@@ -90,7 +117,7 @@ static __device__ __forceinline__ bool finite6(const Ray& y) {
 static __device__ __forceinline__ double rk4_step(const Hole& H, const Integrator& in, Ray& y) {
     Deriv k = rhs(H, in, y.r, y.th, y.pt, y.pr, y.pth, y.pph, y.wtt, y.wtp, y.wpp);
     const double nu = fabs(k.qt);
-    const double h = in.dt / nu;
+    const double h = div_rn(in.dt, nu);
     const double hh = 0.5 * h;
     double st = k.qt, sr = k.qr, sh = k.qh, sp = k.qp, spr = k.pr, sph = k.ph;
     k = rhs(H, in, fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), y.pt,
@@ -142,6 +169,31 @@ static __device__ __forceinline__ void write_ray(const OutPtrs& o, int64_t k, co
     put<T>(o.pph, k, y.pph);
     o.flag[k] = (int8_t)flag;
     if (o.steps) o.steps[k] = s;
+}
+
+// Ray of lane g in a one-ray-per-lane launch, false for a lane without one.
+// A frame is cut into 8x8 pixel tiles, one per wave (row-major over the
+// tiles), so that a wave's rays start side by side and take nearly the same
+// number of steps; lanes of a ragged edge tile that fall outside the frame
+// have no ray, and the grid needs 64 lanes per tile.  With a pixel list, lane
+// g traces list entry g.  k: output index, pix: pixel.
+static __device__ __forceinline__ bool static_ray(const FrameArgs& A, int64_t g, int64_t& k,
+                                                  int64_t& pix) {
+    if (A.pixels) {
+        k = g;
+        if (k >= A.nray) return false;
+        pix = (int64_t)A.pixels[k];
+        return true;
+    }
+    const int64_t W = A.cam.W, H = A.cam.H;
+    const int64_t tiles_x = (W + 7) >> 3;
+    const int64_t wave = g >> 6;
+    const int lane = (int)(g & 63);
+    const int64_t i = (wave % tiles_x) * 8 + (lane & 7);
+    const int64_t j = (wave / tiles_x) * 8 + (lane >> 3);
+    if (i >= W || j >= H) return false;
+    k = pix = j * W + i;
+    return true;
 }
 
 // Flag for a freshly started ray: invalid start or a zero step limit end it.

@@ -24,13 +24,13 @@ namespace {
 
 using namespace detail;
 
-// One lane, one ray; the grid covers every ray.
+// One lane, one ray (static_ray); the grid covers every ray.
 template <typename T>
 __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.nray) return;
+    int64_t k, pix;
+    if (!static_ray(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, k, pix)) return;
     Ray y;
-    start_ray(A.cam, A.pixels ? (int64_t)A.pixels[k] : k, y);
+    start_ray(A.cam, pix, y);
     int s = 0;
     int f = start_flag(A.in, y);
     while (f == RUNNING) {
@@ -145,6 +145,48 @@ __global__ void __launch_bounds__(256) trace_fp64_batch(const BatchArgs B,
     }
 }
 
+// Many instances in one launch, one ray per lane: wave w finds its instance
+// by binary search of the wave offsets and takes the instance's 8x8 tile (or
+// 64 pixel-list entries) w - wfirsts[instance].
+__global__ void __launch_bounds__(256) trace_fp64_batch_static(const BatchArgs B) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t wave = g >> 6;
+    if (wave >= B.wfirsts[B.ninst]) return;
+    int lo = 0, hi = B.ninst;                     // wfirsts[lo] <= wave < wfirsts[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (B.wfirsts[mid] <= wave) lo = mid; else hi = mid;
+    }
+    const BatchInstance& I = B.inst[lo];
+    const int64_t t = wave - B.wfirsts[lo];
+    const int lane = (int)(g & 63);
+    int64_t k, pix;
+    if (I.pixels) {
+        k = t * 64 + lane;
+        if (k >= B.firsts[lo + 1] - B.firsts[lo]) return;
+        pix = (int64_t)I.pixels[k];
+    } else {
+        const int64_t W = I.cam.W, H = I.cam.H;
+        const int64_t tiles_x = (W + 7) >> 3;
+        const int64_t i = (t % tiles_x) * 8 + (lane & 7);
+        const int64_t j = (t / tiles_x) * 8 + (lane >> 3);
+        if (i >= W || j >= H) return;
+        k = pix = j * W + i;
+    }
+    const Hole H = I.hole;
+    const double r_esc = I.r_esc;
+    Ray y;
+    start_ray(I.cam, pix, y);
+    int s = 0;
+    int f = start_flag(B.in, y);
+    while (f == RUNNING) {
+        const double nu = rk4_step(H, B.in, y);
+        ++s;
+        f = exit_flag(B.in, r_esc, y, nu, s);
+    }
+    write_batch(I, k, y, f, s);
+}
+
 __global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
 
 }  // namespace
@@ -176,6 +218,10 @@ hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, const LaunchShape
 
 hipError_t launch_trace_fp64_batch(const BatchArgs& B, const LaunchShape& L,
                                    unsigned long long* counter, hipStream_t s) {
+    if (!L.refill) {
+        hipLaunchKernelGGL(trace_fp64_batch_static, dim3(L.grid), dim3(L.block), 0, s, B);
+        return hipGetLastError();
+    }
     hipError_t e = launch_reset_counter(counter, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(trace_fp64_batch, dim3(L.grid), dim3(L.block), 0, s, B, counter);

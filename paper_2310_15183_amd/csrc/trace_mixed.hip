@@ -170,6 +170,49 @@ struct MixedArgs {
     double r_enter, r_leave;   // binary64 mode boundaries (R64_* times r_+)
 };
 
+// Constants of ray y's binary32 right-hand side.
+__device__ __forceinline__ void mixed_constants(const FrameArgs& A, const Ray& y, ConstF& K) {
+    K.pt = (float)y.pt;
+    K.pph = (float)y.pph;
+    K.ie = (float)A.in.inv_eps;
+    K.wtt = (K.pt * K.pt) * K.ie;
+    K.wtp = ((2.0f * K.pt) * K.pph) * K.ie;
+    K.wpp = (K.pph * K.pph) * K.ie;
+}
+
+// One step of ray y in its current mode; in64 switches with hysteresis.
+__device__ __forceinline__ double mixed_step(const MixedArgs& X, const ConstF& K, float dtf,
+                                             bool& in64, Ray& y) {
+    const FrameArgs& A = X.f;
+    const double apr = fabs(y.pr);
+    if (!in64 && (y.r < X.r_enter || apr < PR_ENTER)) in64 = true;
+    else if (in64 && y.r > X.r_leave && apr > PR_LEAVE) in64 = false;
+    return in64 ? rk4_step(A.hole, A.in, y) : rk4_step_mixed(A.hole, A.in, K, dtf, y);
+}
+
+// One lane, one ray (static_ray: 8x8 pixel tiles per wave); the grid covers
+// every ray.
+template <typename T>
+__global__ void __launch_bounds__(256) trace_mixed_static(const MixedArgs X) {
+    const FrameArgs& A = X.f;
+    int64_t k, pix;
+    if (!static_ray(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, k, pix)) return;
+    const float dtf = (float)A.in.dt;
+    Ray y;
+    ConstF K;
+    start_ray(A.cam, pix, y);
+    mixed_constants(A, y, K);
+    bool in64 = false;
+    int s = 0;
+    int f = start_flag(A.in, y);
+    while (f == RUNNING) {
+        const double nu = mixed_step(X, K, dtf, in64, y);
+        ++s;
+        f = exit_flag(A.in, A.r_esc, y, nu, s);
+    }
+    write_ray<T>(A.out, k, y, f, s);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 trace_mixed_refill(const MixedArgs X,
@@ -190,12 +233,7 @@ trace_mixed_refill(const MixedArgs X,
                 start_ray(A.cam, A.pixels ? (int64_t)A.pixels[k] : k, y);
                 s = 0;
                 in64 = false;
-                K.pt = (float)y.pt;
-                K.pph = (float)y.pph;
-                K.ie = (float)A.in.inv_eps;
-                K.wtt = (K.pt * K.pt) * K.ie;
-                K.wtp = ((2.0f * K.pt) * K.pph) * K.ie;
-                K.wpp = (K.pph * K.pph) * K.ie;
+                mixed_constants(A, y, K);
                 const int f = start_flag(A.in, y);
                 if (f == RUNNING) {
                     live = true;
@@ -207,11 +245,7 @@ trace_mixed_refill(const MixedArgs X,
         }
         if (!__any(live || want)) break;
         if (live) {
-            const double apr = fabs(y.pr);
-            if (!in64 && (y.r < X.r_enter || apr < PR_ENTER)) in64 = true;
-            else if (in64 && y.r > X.r_leave && apr > PR_LEAVE) in64 = false;
-            const double nu = in64 ? rk4_step(A.hole, A.in, y)
-                                   : rk4_step_mixed(A.hole, A.in, K, dtf, y);
+            const double nu = mixed_step(X, K, dtf, in64, y);
             ++s;
             const int f = exit_flag(A.in, A.r_esc, y, nu, s);
             if (f != RUNNING) {
@@ -232,6 +266,13 @@ hipError_t launch_trace_mixed(const FrameArgs& A, double r_plus, bool f32_out,
     X.f = A;
     X.r_enter = R64_ENTER * r_plus;
     X.r_leave = R64_LEAVE * r_plus;
+    if (!L.refill) {
+        if (f32_out)
+            hipLaunchKernelGGL(trace_mixed_static<float>, dim3(L.grid), dim3(L.block), 0, s, X);
+        else
+            hipLaunchKernelGGL(trace_mixed_static<double>, dim3(L.grid), dim3(L.block), 0, s, X);
+        return hipGetLastError();
+    }
     hipError_t e = launch_reset_counter(counter, s);
     if (e != hipSuccess) return e;
     if (f32_out)

@@ -100,17 +100,22 @@ def test_launch_shape_does_not_change_results(g, ctx):
 
 def test_queue_order_does_not_change_results(g, ctx):
     """Frames of at least 4096 pixels queued near-critical rays first give
-    the outputs of pixel order, bit for bit (binary64 and mixed)."""
-    case = (0.5, 0.24, 0.3, 20.0, 80 * DEG, 0.0, 75 * DEG, 80, 64)
-    for prec in (g.GR_FP64, g.GR_MIXED):
-        g.gr_trace_set_integrator(ctx, g.make_integrator(dt=0.01, max_steps=20000,
-                                                         precision=prec))
-        g.gr_trace_set_launch(ctx, g.gr_launch(256, 0, 1, 2))
-        ordered = gpu_trace(ctx, *case)
-        g.gr_trace_set_launch(ctx, g.gr_launch(256, 0, 1, 0))
-        plain = gpu_trace(ctx, *case)
-        for k in plain:
-            np.testing.assert_array_equal(ordered[k], plain[k], err_msg=f"{k} {prec}")
+    the outputs of pixel order, bit for bit (binary64 and mixed), and so do
+    one-ray-per-lane launches (which take 8x8 tiles in row-major order and
+    ignore the queue order; the 81x63 frame has ragged edge tiles)."""
+    for case in [(0.5, 0.24, 0.3, 20.0, 80 * DEG, 0.0, 75 * DEG, 80, 64),
+                 (0.5, 0.3, 0.2, 20.0, 70 * DEG, 0.0, 70 * DEG, 81, 63)]:
+        for prec in (g.GR_FP64, g.GR_MIXED):
+            g.gr_trace_set_integrator(ctx, g.make_integrator(dt=0.01, max_steps=20000,
+                                                             precision=prec))
+            g.gr_trace_set_launch(ctx, g.gr_launch(256, 0, 1, 0))
+            plain = gpu_trace(ctx, *case)
+            for shape in [(256, 0, 1, 2), (64, 0, 0, 2), (128, 0, 0, 2)]:
+                g.gr_trace_set_launch(ctx, g.gr_launch(*shape))
+                ordered = gpu_trace(ctx, *case)
+                for k in plain:
+                    np.testing.assert_array_equal(ordered[k], plain[k],
+                                                  err_msg=f"{k} {prec} {shape}")
     g.gr_trace_set_launch(ctx, None)
     g.gr_trace_set_integrator(ctx, g.make_integrator(dt=0.01, max_steps=20000))
 
