@@ -67,6 +67,16 @@ def _load():
         lib.oracle_recip_newton.argtypes = [vp, vp, i64, vp]
         lib.oracle_rhs.restype = None
         lib.oracle_rhs.argtypes = [d, d, d, d, d, d, d, d, d, d, vp, vp]
+        lib.oracle_trace_frame_mn.restype = i64
+        lib.oracle_trace_frame_mn.argtypes = lib.oracle_trace_frame.argtypes
+        lib.oracle_inverse_metric_mn.restype = None
+        lib.oracle_inverse_metric_mn.argtypes = [d, d, d, d, d, vp]
+        lib.oracle_rhs_mn.restype = None
+        lib.oracle_rhs_mn.argtypes = [d, d, d, d, d, d, d, d, d, d, vp, vp]
+        lib.oracle_exp.restype = None
+        lib.oracle_exp.argtypes = [vp, i64, vp]
+        lib.oracle_mn_consts.restype = None
+        lib.oracle_mn_consts.argtypes = [d, d, d, vp]
         _lib = lib
     return _lib
 
@@ -185,3 +195,57 @@ def sincos(x) -> tuple[np.ndarray, np.ndarray]:
     sc = np.empty((x.size, 2), np.float64)
     _load().oracle_sincos(_ptr(x), x.size, _ptr(sc))
     return sc[:, 0], sc[:, 1]
+
+
+# ---------------------------------------------------------------- Manko-Novikov
+def trace_frame_mn(M, S, q, r0, theta0, phi0, fov, width, height, dt=0.01, eps=1e-8,
+                   horizon_norm=1e4, escape_factor=1.5, max_steps=20000, pixels=None,
+                   threads=None, want_p0=False) -> Result:
+    """trace_frame for the Manko-Novikov spacetime (mass M, spin S, quadrupole
+    deviation q; paper Sec. 2.2.3)."""
+    lib = _load()
+    if pixels is not None:
+        pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+        n = int(pixels.size)
+    else:
+        n = int(width) * int(height)
+    t, r, th, ph, pr, pth, flag, steps = _alloc(n)
+    p0 = np.empty((n, 4), np.float64) if want_p0 else None
+    lib.oracle_trace_frame_mn(M, S, q, r0, theta0, phi0, fov, int(width), int(height), dt, eps,
+                              horizon_norm, escape_factor, int(max_steps), _ptr(pixels), n,
+                              _ptr(t), _ptr(r), _ptr(th), _ptr(ph), _ptr(pr), _ptr(pth),
+                              _ptr(p0), _ptr(flag), _ptr(steps), int(threads or default_threads()))
+    return Result(t, r, th, ph, pr, pth, flag, steps, p0)
+
+
+def inverse_metric_mn(M, S, q, r, theta) -> np.ndarray:
+    """Manko-Novikov (g^tt, g^tphi, g^rr, g^thth, g^phph) at (r, theta)."""
+    lib = _load()
+    g = np.empty(5, np.float64)
+    lib.oracle_inverse_metric_mn(M, S, q, float(r), float(theta), _ptr(g))
+    return g
+
+
+def rhs_mn(M, S, q, r, theta, p, eps=1e-8):
+    """Manko-Novikov Hamilton right-hand side: (qdot[4], (pdot_r, pdot_theta))."""
+    lib = _load()
+    qd = np.empty(4, np.float64)
+    pd = np.empty(2, np.float64)
+    lib.oracle_rhs_mn(M, S, q, eps, float(r), float(theta), float(p[0]), float(p[1]),
+                      float(p[2]), float(p[3]), _ptr(qd), _ptr(pd))
+    return qd, pd
+
+
+def mn_consts(M, S, q) -> tuple[float, float, float]:
+    """(alpha, k, beta) of the Manko-Novikov spacetime (M, S, q)."""
+    out = np.empty(3, np.float64)
+    _load().oracle_mn_consts(M, S, q, _ptr(out))
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+def exp_def(x) -> np.ndarray:
+    """The oracle's exp definition applied elementwise."""
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    out = np.empty_like(x)
+    _load().oracle_exp(_ptr(x), x.size, _ptr(out))
+    return out

@@ -1,6 +1,7 @@
 /*
  * CPU reference ("oracle") for backward null-geodesic ray tracing around a
- * Kerr-Newman black hole in Boyer-Lindquist coordinates.
+ * Kerr-Newman black hole in Boyer-Lindquist coordinates, and around the
+ * quadrupole Manko-Novikov spacetime (paper Sec. 2.2.3).
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call this file;
  * only the test suite, the smoke check and the benchmark's CPU-baseline leg
@@ -37,7 +38,9 @@
  *
  * Parity status: pinned (flat space, Schwarzschild critical impact parameter
  * and deflection integral, Kerr/Kerr-Newman capture by the radial potential,
- * conserved p_t, p_phi, H and Carter constant, mirror symmetries).
+ * conserved p_t, p_phi, H and Carter constant, mirror symmetries; for
+ * Manko-Novikov: the Kerr limit q = 0, vacuum field equations, asymptotic
+ * flatness, the far-field quadrupole, equatorial symmetry, H along rays).
  */
 #include <math.h>
 #include <pthread.h>
@@ -47,6 +50,19 @@
 
 enum { FLAG_TIMEOUT = 0, FLAG_ESCAPE = 1, FLAG_HORIZON = 2, FLAG_INVALID = 3 };
 
+/* Constants of a Manko-Novikov spacetime (mass M, spin S, quadrupole
+ * deviation q; see mn_inverse_metric). */
+typedef struct {
+    double M, alpha, k, beta;
+    double ik;                   /* 1/k */
+    double k2;                   /* k^2 */
+    double twok;                 /* 2k */
+    double om0;                  /* 4 k alpha / (1 - alpha^2) */
+    double iw2;                  /* 1 / (1 - alpha^2)^2 */
+} mn_consts;
+
+enum { METRIC_KN = 0, METRIC_MN = 1 };
+
 typedef struct {
     double M, a, Q;              /* mass, spin length a = J/M, charge (G=c=1) */
     double dt, eps;              /* coordinate-time step, finite-difference step */
@@ -54,6 +70,8 @@ typedef struct {
     double escape_factor;        /* stop when r > escape_factor * r_start */
     int max_steps;
     int trig_mode;               /* 0: trig_sincos below; 1: C library sin/cos */
+    int kind;                    /* METRIC_KN or METRIC_MN */
+    mn_consts mn;                /* METRIC_MN only */
 } oracle_params;
 
 /* ------------------------------------------------------------------------ */
@@ -74,8 +92,11 @@ static const double PIO2_LO = 0x1.1a62633145c07p-54;      /* fl(pi/2 - PIO2_HI) 
 static double SIN_C[9], COS_C[9];                          /* index n = 1..8 */
 static pthread_once_t trig_once = PTHREAD_ONCE_INIT;
 
+static void exp_init(void);
+
 static void trig_init(void)
 {
+    exp_init();
     double fact = 1.0;                                     /* m! */
     for (int m = 1; m <= 17; ++m) {
         fact *= (double)m;
@@ -115,6 +136,144 @@ static void sincos_mode(int mode, double x, double *s, double *c)
     } else {
         trig_sincos(x, s, c);               /* tables set by make_params */
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* exp from its definition (the Manko-Novikov metric needs it; as with sin and
+ * cos, a library exp would make the forward differences irreproducible).
+ *   x = k ln2 + r with k the integer nearest to x / ln2, |r| <= ln2 / 2;
+ *   ln2 is split as LN2_HI + LN2_LO (LN2_HI = fl(ln2)), r = (x - k LN2_HI) -
+ *   k LN2_LO in two fma;
+ *   exp r = sum_{n=0}^{13} r^n / n!  (Horner in fma; truncation below 5e-18
+ *   relative on |r| <= ln2/2), then exp x = 2^k exp r (exact scaling).
+ * Overflow gives +inf, x < -746 gives 0, NaN stays NaN. */
+static const double LOG2E = 0x1.71547652b82fep+0;         /* fl(1/ln2) */
+static const double LN2_HI = 0x1.62e42fefa39efp-1;        /* fl(ln2) */
+static const double LN2_LO = 0x1.abc9e3b39803fp-56;       /* fl(ln2 - LN2_HI) */
+static double EXP_C[14];                                   /* 1/n!, n = 0..13 */
+
+static void exp_init(void)
+{
+    double fact = 1.0;
+    EXP_C[0] = 1.0;
+    for (int n = 1; n <= 13; ++n) {
+        fact *= (double)n;
+        EXP_C[n] = 1.0 / fact;
+    }
+}
+
+static double exp_def(double x)
+{
+    if (x != x) return x;
+    if (x > 710.0) return INFINITY;
+    if (x < -746.0) return 0.0;
+    const double k = rint(x * LOG2E);
+    double r = fma(-k, LN2_HI, x);
+    r = fma(-k, LN2_LO, r);
+    double p = EXP_C[13];
+    for (int n = 12; n >= 0; --n) p = fma(p, r, EXP_C[n]);
+    return ldexp(p, (int)k);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Inverse Manko-Novikov metric (paper Sec. 2.2.3, the quadrupole member of
+ * the family; the inverse components as in the appendix listing's
+ * metricAtPoint).  In Boyer-Lindquist-like coordinates the line element is
+ *   ds^2 = -f (dt - omega dphi)^2
+ *          + f^{-1} [ e^{2 gamma} rho^2 (dr^2 / Delta + dtheta^2)
+ *                     + Delta sin^2(theta) dphi^2 ],
+ *   rho^2 = (r - M)^2 - k^2 cos^2(theta) = k^2 (x^2 - y^2),
+ *   Delta = (r - M)^2 - k^2             = k^2 (x^2 - 1),
+ * with prolate spheroidal x = (r - M)/k, y = cos(theta), and
+ *   alpha = (-M + sqrt(M^2 - (S/M)^2)) / (S/M),  k = M (1 - alpha^2)/(1 + alpha^2),
+ *   beta = q M^3 / k^3,  R = sqrt(x^2 + y^2 - 1),  P_l = P_l(x y / R),
+ *   a_ = -alpha exp(-2 beta (-1 + sum_{l=0}^2 (x - y) P_l / R^{l+1})),
+ *   b_ =  alpha exp( 2 beta ( 1 + sum_{l=0}^2 (-1)^{3-l} (x + y) P_l / R^{l+1})),
+ *   A = (x^2 - 1)(1 + a_ b_)^2 - (1 - y^2)(b_ - a_)^2,
+ *   B = [x + 1 + (x - 1) a_ b_]^2 + [(1 + y) a_ + (1 - y) b_]^2,
+ *   C = (x^2 - 1)(1 + a_ b_)[b_ - a_ - y (a_ + b_)]
+ *       + (1 - y^2)(b_ - a_)[1 + a_ b_ + x (1 - a_ b_)],
+ *   psi = beta P_2 / R^3,   f = e^{2 psi} A / B,
+ *   omega = 2 k e^{-2 psi} C / A - 4 k alpha / (1 - alpha^2),
+ *   gamma' = ln sqrt((x^2 - 1)/(x^2 - y^2)) + 3 beta^2 (P_3^2 - P_2^2) / (2 R^6)
+ *            + beta (-2 + sum_{l=0}^2 [x - y + (-1)^{2-l} (x + y)] P_l / R^{l+1}),
+ *   e^{2 gamma} = e^{2 gamma'} A / ((x^2 - 1)(1 - alpha^2)^2).
+ * Readings of the printed formulas (garbled in places): the first term of
+ * the line element is squared, the theta term is e^{2 gamma} rho^2 dtheta^2 / f,
+ * B is a sum of two squares, and the beta term of gamma' is beta (-2 + sum):
+ * these are the forms for which q = 0 gives Kerr and the metric is a vacuum
+ * solution (both are tested), and with them gamma' vanishes at infinity.
+ * The logarithm cancels: e^{2 gamma} rho^2 = k^2 e^{2 G} A / (1 - alpha^2)^2
+ * with G = gamma' - ln sqrt((x^2 - 1)/(x^2 - y^2)).  Inverse components
+ * (D = Delta sin^2 theta):
+ *   g^{tt} = -1/f + f omega^2 / D,  g^{t phi} = f omega / D,
+ *   g^{rr} = f Delta / (e^{2 gamma} rho^2),  g^{theta theta} = f / (e^{2 gamma} rho^2),
+ *   g^{phi phi} = f / D.
+ * y = cos(theta) and s2 = sin^2(theta) are passed in (the forward difference
+ * in theta evaluates them by angle addition). */
+static void mn_consts_make(double M, double S, double q, mn_consts *K)
+{
+    const double chi = S / M;                                  /* a = S/M */
+    K->M = M;
+    K->alpha = (-M + sqrt(M * M - chi * chi)) / chi;
+    const double al2 = K->alpha * K->alpha;
+    K->k = M * ((1.0 - al2) / (1.0 + al2));
+    K->beta = (q * (M * M * M)) / (K->k * K->k * K->k);
+    K->ik = 1.0 / K->k;
+    K->k2 = K->k * K->k;
+    K->twok = 2.0 * K->k;
+    K->om0 = (4.0 * K->k * K->alpha) / (1.0 - al2);
+    K->iw2 = 1.0 / ((1.0 - al2) * (1.0 - al2));
+}
+
+static void mn_inverse_metric(const mn_consts *K, double r, double y, double s2, double g[5])
+{
+    const double beta = K->beta;
+    const double x = (r - K->M) * K->ik;
+    const double x2 = x * x, y2 = y * y;
+    const double R = sqrt((x2 + y2) - 1.0);
+    const double iR = 1.0 / R;
+    const double iR2 = iR * iR, iR3 = iR2 * iR;
+    const double u = (x * y) * iR;                             /* argument of P_l */
+    const double P1 = u;
+    const double P2 = fma(1.5 * u, u, -0.5);                   /* (3u^2 - 1)/2 */
+    const double P3 = u * fma(2.5 * u, u, -1.5);               /* (5u^3 - 3u)/2 */
+    /* the l = 0..2 sums: L1 = sum P_l / R^{l+1}, L2 = sum (-1)^l P_l / R^{l+1} */
+    const double L1 = fma(P2, iR3, fma(P1, iR2, iR));
+    const double L2 = fma(P2, iR3, fma(-P1, iR2, iR));
+    const double Sa = (x - y) * L1;                            /* sum (x - y) P_l / R^{l+1} */
+    const double Sb = -((x + y) * L2);                         /* sum (-1)^{3-l} (x + y) ... */
+    const double Sg = fma(x - y, L1, (x + y) * L2);            /* sum [x - y + (-1)^l (x + y)] ... */
+    const double ea = exp_def((-2.0 * beta) * (Sa - 1.0));
+    const double eb = exp_def((2.0 * beta) * (1.0 + Sb));
+    const double am = -(K->alpha * ea);                        /* a_ */
+    const double bm = K->alpha * eb;                           /* b_ */
+    const double psi = (beta * P2) * iR3;
+    const double iR6 = iR3 * iR3;
+    const double G = fma((1.5 * (beta * beta)) * iR6, (P3 * P3) - (P2 * P2), beta * (Sg - 2.0));
+    const double ab = am * bm;
+    const double opab = 1.0 + ab, omab = 1.0 - ab;
+    const double bma = bm - am, apb = am + bm;
+    const double xm1 = x2 - 1.0, ym1 = 1.0 - y2;
+    const double A = fma(xm1, opab * opab, -(ym1 * (bma * bma)));
+    const double B1 = fma(x - 1.0, ab, x + 1.0);
+    const double B2 = fma(1.0 + y, am, (1.0 - y) * bm);
+    const double B = fma(B1, B1, B2 * B2);
+    const double C = fma(xm1 * opab, fma(-y, apb, bma), (ym1 * bma) * fma(x, omab, opab));
+    const double e2psi = exp_def(2.0 * psi);
+    const double fA = e2psi * A;
+    const double f = fA / B;
+    const double omega = (K->twok * C) / fA - K->om0;
+    const double e2g_rho2 = ((K->k2 * exp_def(2.0 * G)) * A) * K->iw2;
+    const double Delta = K->k2 * xm1;
+    const double iD = 1.0 / (Delta * s2);
+    const double ie = 1.0 / e2g_rho2;
+    const double fo = f * omega;
+    g[0] = fma(fo * omega, iD, -(1.0 / f));                   /* g^{tt} */
+    g[1] = fo * iD;                                            /* g^{t phi} */
+    g[2] = (f * Delta) * ie;                                   /* g^{rr} */
+    g[3] = f * ie;                                             /* g^{theta theta} */
+    g[4] = f * iD;                                             /* g^{phi phi} */
 }
 
 /* ------------------------------------------------------------------------ */
@@ -191,13 +350,16 @@ static void metric_at_point(const oracle_params *P, double r, double theta, doub
 {
     double s, c;
     sincos_mode(P->trig_mode, theta, &s, &c);
-    inverse_metric(P, r, s * s, c * c, g);
+    if (P->kind == METRIC_MN)
+        mn_inverse_metric(&P->mn, r, c, s * s, g);
+    else
+        inverse_metric(P, r, s * s, c * c, g);
 }
 
 /* Right-hand side of Hamilton's equations at one RK4 stage point.
  * Paper eq. hamGeodesic with the factor 1/2 of Appendix A; derivatives by
- * forward differences of step eps as in the listing: the metric at (r,theta),
- * (r+eps,theta) and (r,theta+eps).  sin and cos at theta+eps are the
+ * forward differences of step eps as in the listing: the metric (Kerr-Newman
+ * or Manko-Novikov) at (r,theta), (r+eps,theta) and (r,theta+eps).  sin and cos at theta+eps are the
  * angle-addition identity applied to those at theta and at eps (for eps =
  * 1e-8, cos eps rounds to 1 and sin eps to eps), so the theta step is eps
  * itself.  The contraction sums the differences of the five independent
@@ -217,13 +379,20 @@ static void hamilton_rhs(const oracle_params *P, const double eps_sc[2], double 
      * at (r, theta + eps) 1/(rho^2 Delta) is refined from inv and multiplied
      * by a divided 1/sin^2 (near the axis sin^2 changes by a large factor
      * over eps, rho^2 Delta never does) */
-    const double is = 1.0 / (rho2_delta(P, r, c2) * s2);
-    const double inv = is * s2;
-    const double is_r = recip_newton(rho2_delta(P, r + P->eps, c2) * s2, is);
-    const double inv_t = recip_newton(rho2_delta(P, r, ce2), inv);
-    metric_from(P, r, s2, inv, is, g);
-    metric_from(P, r + P->eps, s2, is_r * s2, is_r, gr);
-    metric_from(P, r, se2, inv_t, inv_t * (1.0 / se2), gth);
+    if (P->kind == METRIC_MN) {
+        /* full evaluations at the three points */
+        mn_inverse_metric(&P->mn, r, c, s2, g);
+        mn_inverse_metric(&P->mn, r + P->eps, c, s2, gr);
+        mn_inverse_metric(&P->mn, r, ce, se2, gth);
+    } else {
+        const double is = 1.0 / (rho2_delta(P, r, c2) * s2);
+        const double inv = is * s2;
+        const double is_r = recip_newton(rho2_delta(P, r + P->eps, c2) * s2, is);
+        const double inv_t = recip_newton(rho2_delta(P, r, ce2), inv);
+        metric_from(P, r, s2, inv, is, g);
+        metric_from(P, r + P->eps, s2, is_r * s2, is_r, gr);
+        metric_from(P, r, se2, inv_t, inv_t * (1.0 / se2), gth);
+    }
 
     /* weights p_nu p_sigma of the five independent components */
     const double wtt = pt * pt, wtp = (2.0 * pt) * pph, wpp = pph * pph;
@@ -331,6 +500,15 @@ static void camera_setup(const oracle_params *P, double r0, double th0, double f
     C->tan_half_v = (C->tan_half * (double)H) / (double)W;
     sincos_mode(P->trig_mode, th0, &s, &c);
     const double s2 = s * s, c2 = c * c;
+    if (P->kind == METRIC_MN) {
+        /* covariant g_rr = 1/g^rr, g_thth = 1/g^thth and, from the inverse of
+         * the (t, phi) block, g_phph = g^tt / (g^tt g^phph - (g^tphi)^2) */
+        mn_inverse_metric(&P->mn, r0, c, s2, C->g);
+        C->er = sqrt(1.0 / C->g[2]);
+        C->eth = sqrt(1.0 / C->g[3]);
+        C->eph = sqrt(C->g[0] / ((C->g[0] * C->g[4]) - (C->g[1] * C->g[1])));
+        return;
+    }
     const double a2 = P->a * P->a;
     const double r2 = r0 * r0;
     const double ra = r2 + a2;
@@ -461,7 +639,21 @@ static oracle_params make_params(double M, double a, double Q, double dt, double
     P.M = M; P.a = a; P.Q = Q; P.dt = dt; P.eps = eps;
     P.horizon_norm = horizon_norm; P.escape_factor = escape_factor;
     P.max_steps = max_steps; P.trig_mode = g_trig_mode;
+    P.kind = METRIC_KN;
+    memset(&P.mn, 0, sizeof P.mn);
     pthread_once(&trig_once, trig_init);
+    return P;
+}
+
+/* Parameters of a Manko-Novikov spacetime (mass M, spin S with 0 < |S| < M^2,
+ * quadrupole deviation q). */
+static oracle_params make_params_mn(double M, double S, double q, double dt, double eps,
+                                    double horizon_norm, double escape_factor, int max_steps)
+{
+    oracle_params P = make_params(M, S / M, 0.0, dt, eps, horizon_norm, escape_factor,
+                                  max_steps);
+    P.kind = METRIC_MN;
+    mn_consts_make(M, S, q, &P.mn);
     return P;
 }
 
@@ -539,4 +731,64 @@ void oracle_rhs(double M, double a, double Q, double eps, double r, double theta
     double eps_sc[2];
     sincos_mode(P.trig_mode, eps, &eps_sc[0], &eps_sc[1]);
     hamilton_rhs(&P, eps_sc, r, theta, pt, pr, pth, pph, qdot, pdot);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Manko-Novikov entry points: as oracle_trace_frame / oracle_inverse_metric
+ * with (M, S, q) in place of (M, a, Q). */
+int64_t oracle_trace_frame_mn(double M, double S, double q,
+                              double r0, double th0, double ph0, double fov, int W, int H,
+                              double dt, double eps, double horizon_norm,
+                              double escape_factor, int max_steps,
+                              const int64_t *pixels, int64_t n,
+                              double *t, double *r, double *th, double *ph,
+                              double *pr, double *pth, double *p0,
+                              int8_t *flag, int32_t *steps, int nthreads)
+{
+    oracle_params P = make_params_mn(M, S, q, dt, eps, horizon_norm, escape_factor, max_steps);
+    camera_consts C;
+    camera_setup(&P, r0, th0, fov, W, H, &C);
+    job J;
+    memset(&J, 0, sizeof J);
+    J.P = &P; J.C = &C; J.r0 = r0; J.th0 = th0; J.ph0 = ph0; J.W = W; J.H = H;
+    J.pixels = pixels;
+    J.n = pixels ? n : (int64_t)W * H;
+    J.t = t; J.r = r; J.th = th; J.ph = ph; J.pr = pr; J.pth = pth; J.p0 = p0;
+    J.flag = flag; J.steps = steps;
+    run_job(&J, nthreads);
+    return J.n;
+}
+
+void oracle_inverse_metric_mn(double M, double S, double q, double r, double theta,
+                              double *g5)
+{
+    oracle_params P = make_params_mn(M, S, q, 0.01, 1e-8, 1e4, 1.5, 1);
+    metric_at_point(&P, r, theta, g5);
+}
+
+/* Right-hand side at a state (tests), Manko-Novikov. */
+void oracle_rhs_mn(double M, double S, double q, double eps, double r, double theta,
+                   double pt, double pr, double pth, double pph, double *qdot, double *pdot)
+{
+    oracle_params P = make_params_mn(M, S, q, 0.01, eps, 1e4, 1.5, 1);
+    double eps_sc[2];
+    sincos_mode(P.trig_mode, eps, &eps_sc[0], &eps_sc[1]);
+    hamilton_rhs(&P, eps_sc, r, theta, pt, pr, pth, pph, qdot, pdot);
+}
+
+/* Accuracy checks of the exp definition. */
+void oracle_exp(const double *x, int64_t n, double *out)
+{
+    pthread_once(&trig_once, trig_init);
+    for (int64_t k = 0; k < n; ++k) out[k] = exp_def(x[k]);
+}
+
+/* Constants (alpha, k, beta) of a Manko-Novikov spacetime (tests). */
+void oracle_mn_consts(double M, double S, double q, double *out3)
+{
+    mn_consts K;
+    mn_consts_make(M, S, q, &K);
+    out3[0] = K.alpha;
+    out3[1] = K.k;
+    out3[2] = K.beta;
 }

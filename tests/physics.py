@@ -222,3 +222,58 @@ def sky_direction(theta, phi):
 def angle_between(u, v):
     """Great-circle angle between unit vectors (accurate for tiny angles)."""
     return 2.0 * np.arctan2(np.linalg.norm(u - v, axis=-1), np.linalg.norm(u + v, axis=-1))
+
+
+# ------------------------------------------------------------------ curvature
+def covariant_from_inverse(g5):
+    """4x4 covariant metric (t, r, theta, phi) from the five independent
+    inverse components (g^tt, g^tphi, g^rr, g^thth, g^phph)."""
+    gtt, gtp, grr, ghh, gpp = g5
+    det = gtt * gpp - gtp * gtp
+    g = np.zeros((4, 4))
+    g[0, 0] = gpp / det
+    g[0, 3] = g[3, 0] = -gtp / det
+    g[3, 3] = gtt / det
+    g[1, 1] = 1.0 / grr
+    g[2, 2] = 1.0 / ghh
+    return g
+
+
+def _d(fn, x, h):
+    """Fourth-order central difference of fn at x."""
+    return (8.0 * (fn(x + h) - fn(x - h)) - (fn(x + 2 * h) - fn(x - 2 * h))) / (12.0 * h)
+
+
+def ricci(inverse_fn, r, theta, h=2e-3):
+    """Ricci tensor R_{mu nu} at (r, theta) of a stationary axisymmetric metric
+    given by inverse_fn(r, theta) -> (g^tt, g^tphi, g^rr, g^thth, g^phph),
+    from Christoffel symbols and their derivatives by nested fourth-order
+    central differences in r and theta (the metric depends on no other
+    coordinate).  R = d_l G^l_mn - d_n G^l_lm + G^l_ls G^s_mn - G^l_ns G^s_lm."""
+    def gcov(rr, tt):
+        return covariant_from_inverse(inverse_fn(rr, tt))
+
+    def christoffel(rr, tt):
+        g = gcov(rr, tt)
+        gi = np.linalg.inv(g)
+        dg = np.zeros((4, 4, 4))                   # dg[s, m, n] = d_s g_mn
+        dg[1] = _d(lambda x: gcov(x, tt), rr, h)
+        dg[2] = _d(lambda x: gcov(rr, x), tt, h)
+        # G^l_mn = 1/2 g^ls (d_m g_sn + d_n g_sm - d_s g_mn)
+        t1 = np.einsum('msn->smn', dg)             # d_m g_sn indexed [s, m, n]
+        t2 = np.einsum('nsm->smn', dg)             # d_n g_sm
+        return 0.5 * np.einsum('ls,smn->lmn', gi, t1 + t2 - dg)
+
+    G = christoffel(r, theta)
+    dG = np.zeros((4, 4, 4, 4))                    # dG[s, l, m, n] = d_s G^l_mn
+    dG[1] = _d(lambda x: christoffel(x, theta), r, h)
+    dG[2] = _d(lambda x: christoffel(r, x), theta, h)
+    R = (np.einsum('llmn->mn', dG) - np.einsum('nllm->mn', dG)
+         + np.einsum('lls,smn->mn', G, G) - np.einsum('lns,slm->mn', G, G))
+    return R
+
+
+def mn_quadrupole_moment(M, S, q):
+    """Mass quadrupole of the Manko-Novikov spacetime: the Kerr value -S^2/M
+    plus the deviation -q M^3."""
+    return -(S * S) / M - q * M ** 3
