@@ -388,6 +388,98 @@ def copy_calibration(mib=256, reps=3):
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": reps}))
 
 
+FLOPS_PER_RAY_STEP_MN = 3365     # binary64 ops of one Manko-Novikov RK4 step (same counting)
+
+
+def mn_workload():
+    """The appendix listing's spacetime and camera radius: Manko-Novikov with
+    M=0.5, S=0.24 (a = 0.96 M), q=2, camera r0=8 on the equator, fov 75 deg,
+    1000x1000; dt=0.005, at most 50000 steps (binary32 parameters)."""
+    import numpy as np
+    f = lambda x: float(np.float32(x))          # noqa: E731
+    return dict(M=f(0.5), S=f(0.24), q=f(2.0), r0=f(8.0), theta0=f(math.pi / 2), phi0=0.0,
+                fov=f(75 * math.pi / 180), W=1000, H=1000, dt=0.005, fd_eps=1e-8,
+                horizon_norm=1e4, escape_factor=1.5, max_steps=50000)
+
+
+def bench_mn(args):
+    """Manko-Novikov frame (paper Sec. 2.2.3): binary64 rays/s, roofline,
+    and the oracle on a sample of the same frame."""
+    import numpy as np
+    import torch
+
+    import paper_2310_15183_amd as g
+    w = mn_workload()
+    torch.cuda.set_device(0)
+    n = w["W"] * w["H"]
+    ctx = g.gr_trace_init(0, g.make_integrator(dt=w["dt"], fd_eps=w["fd_eps"],
+                                               horizon_norm=w["horizon_norm"],
+                                               escape_factor=w["escape_factor"],
+                                               max_steps=w["max_steps"]))
+    metric = g.gr_metric_mn(w["M"], w["S"], w["q"])
+    cam = g.gr_camera(w["r0"], w["theta0"], w["phi0"], w["fov"], w["W"], w["H"])
+    out = g.alloc_outputs(n, dtype=g.GR_F32, fields=("t", "r", "theta", "phi"))
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        g.gr_trace_frame_mn(ctx, metric, cam, out.struct, stream)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        g.gr_trace_frame_mn(ctx, metric, cam, out.struct, stream)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_s = sum(a.elapsed_time(b) for a, b in zip(starts, ends)) / 1e3 / args.steps
+    steps = out["steps"].cpu().numpy().astype(np.int64)
+    flags = out["flag"].cpu().numpy()
+    ray_steps = int(steps.sum())
+    g.gr_trace_destroy(ctx)
+    achieved = FLOPS_PER_RAY_STEP_MN * ray_steps / launch_s / 1e12
+    result = {
+        "metric": "geodesic rays/s, Manko-Novikov 1000x1000 (binary64)",
+        "value": n * args.steps / wall, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "manko-novikov 1000x1000 fp64: M=0.5 S=0.24 q=2 r0=8 "
+                               "theta0=90deg fov=75deg dt=0.005 eps=1e-8 max_steps=50000 "
+                               "(binary32 params, binary32 end coordinates + int8 flag)",
+                   "rays_per_step": n, "ray_steps_per_step": ray_steps,
+                   "mean_steps_per_ray": ray_steps / n,
+                   "flags": {"timeout": int((flags == 0).sum()),
+                             "escape": int((flags == 1).sum()),
+                             "horizon": int((flags == 2).sum()),
+                             "invalid": int((flags == 3).sum())}},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "trace_mn", "flops_per_ray_step": FLOPS_PER_RAY_STEP_MN,
+                     "launch_ms": launch_s * 1e3},
+        "cpu_baseline": None,
+    }
+    if not args.skip_cpu_baseline:
+        import oracle
+        stride = 16
+        ii = np.arange(stride // 2, w["W"], stride)
+        pix = (ii[:, None] * w["W"] + ii[None, :]).ravel()
+        threads = oracle.default_threads()
+        t0 = time.perf_counter()
+        res = oracle.trace_frame_mn(w["M"], w["S"], w["q"], w["r0"], w["theta0"], w["phi0"],
+                                    w["fov"], w["W"], w["H"], dt=w["dt"], eps=w["fd_eps"],
+                                    horizon_norm=w["horizon_norm"],
+                                    escape_factor=w["escape_factor"],
+                                    max_steps=w["max_steps"], pixels=pix, threads=threads)
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {
+            "value": pix.size / dt, "unit": "rays/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}th pixel in both axes of the same frame ({pix.size} rays, "
+                      f"mean {res.steps.mean():.0f} steps/ray vs {ray_steps / n:.0f} for the "
+                      f"full frame), {dt:.1f} s"}
+    print(json.dumps(result), flush=True)
+
+
 def bench_batch(args):
     """All 256 seeded instances (uneven sizes, spins, charges, cameras) traced
     in one persistent launch per step, with the autotuned launch shape."""
@@ -458,12 +550,13 @@ def main():
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter scale)")
-    ap.add_argument("--workload", choices=["frame", "batch", "mixed", "surrogate"],
+    ap.add_argument("--workload", choices=["frame", "batch", "mixed", "surrogate", "mn"],
                     default="frame",
                     help="frame: the 1000x1000 Kerr-Newman frame (default, the headline "
                          "line); batch: the 256-instance uneven batch in one launch; mixed: "
                          "near-extremal Kerr at 1000^2 and 2048^2, binary64 vs mixed; "
-                         "surrogate: 4096^2 frames, surrogate + fallback vs binary64")
+                         "surrogate: 4096^2 frames, surrogate + fallback vs binary64; "
+                         "mn: the 1000x1000 Manko-Novikov frame")
     ap.add_argument("--train-rays", type=int, default=10_000_000,
                     help="surrogate: labelled rays to train on")
     ap.add_argument("--train-epochs", type=int, default=12)
@@ -496,6 +589,9 @@ def main():
         return
     if args.workload == "surrogate":
         bench_surrogate(args)
+        return
+    if args.workload == "mn":
+        bench_mn(args)
         return
 
     import numpy as np

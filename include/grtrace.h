@@ -79,6 +79,16 @@ typedef struct {
     double M, a, Q;
 } gr_metric;
 
+/* Manko-Novikov spacetime with a mass quadrupole (arXiv 2310.15183,
+ * Sec. 2.2.3): mass M > 0, spin S (angular momentum; a = S/M) with
+ * 0 < |S| < M^2 (S = 0 is excluded, as in the paper: the construction divides
+ * by it), and quadrupole deviation q from Kerr (mass quadrupole
+ * -S^2/M - q M^3; q = 0 is Kerr, q < 0 prolate, q > 0 oblate).  The horizon
+ * sits at r = M + k, k = sqrt(M^2 - (S/M)^2). */
+typedef struct {
+    double M, S, q;
+} gr_metric_mn;
+
 /* Static pinhole camera at Boyer-Lindquist (r0, theta0, phi0) looking toward
  * the hole.  fov is the full horizontal field of view in radians, pixels are
  * square, image right is +phi and image up is -theta.  Requires
@@ -162,6 +172,18 @@ int gr_trace_init(gr_ctx **ctx, int device, const gr_integrator *integ);
  * out->flag), GR_EDEVICE (launch failed). */
 int gr_trace_frame(gr_ctx *ctx, const gr_metric *m, const gr_camera *c,
                    const gr_output *out, void *hip_stream);
+
+/* gr_trace_frame for a Manko-Novikov spacetime (Sec. 2.2.3; the inverse
+ * components of the appendix listing's metricAtPoint): the same camera
+ * (orthonormal scale factors from the metric at the camera), integrator and
+ * exits, the metric evaluated in full at the three points of every stage
+ * (its exponentials from their series definition, so results are
+ * reproducible bit for bit).  One ray per lane over 8x8 pixel tiles whatever
+ * the context's launch shape.  The camera needs r0 > M + k.  Errors:
+ * GR_EINVAL (validation, NULL arguments), GR_EUNSUPPORTED (a GR_MIXED
+ * context), GR_EDEVICE. */
+int gr_trace_frame_mn(gr_ctx *ctx, const gr_metric_mn *m, const gr_camera *c,
+                      const gr_output *out, void *hip_stream);
 
 /* Trace n >= 1 instances (possibly different black holes, cameras and image
  * sizes) in one persistent launch fed by one work queue (GR_FP64 only:

@@ -27,6 +27,10 @@ class gr_metric(ctypes.Structure):
     _fields_ = [("M", ctypes.c_double), ("a", ctypes.c_double), ("Q", ctypes.c_double)]
 
 
+class gr_metric_mn(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_double), ("S", ctypes.c_double), ("q", ctypes.c_double)]
+
+
 class gr_camera(ctypes.Structure):
     _fields_ = [("r0", ctypes.c_double), ("theta0", ctypes.c_double),
                 ("phi0", ctypes.c_double), ("fov", ctypes.c_double),
@@ -76,6 +80,8 @@ def _load():
     sig = {
         "gr_trace_init": (ctypes.c_int, [P(vp), ctypes.c_int, P(gr_integrator)]),
         "gr_trace_frame": (ctypes.c_int, [vp, P(gr_metric), P(gr_camera), P(gr_output), vp]),
+        "gr_trace_frame_mn": (ctypes.c_int, [vp, P(gr_metric_mn), P(gr_camera), P(gr_output),
+                                             vp]),
         "gr_trace_batch": (ctypes.c_int, [vp, P(gr_instance), ctypes.c_int32, vp]),
         "gr_trace_set_integrator": (ctypes.c_int, [vp, P(gr_integrator)]),
         "gr_trace_set_launch": (ctypes.c_int, [vp, P(gr_launch)]),
@@ -115,7 +121,8 @@ def _load():
 
 
 _lib = _load()
-EXPORTED = ["gr_trace_init", "gr_trace_frame", "gr_trace_batch", "gr_trace_set_integrator",
+EXPORTED = ["gr_trace_init", "gr_trace_frame", "gr_trace_frame_mn", "gr_trace_batch",
+            "gr_trace_set_integrator",
             "gr_trace_set_launch", "gr_trace_get_launch", "gr_trace_autotune", "gr_trace_destroy",
             "gr_trace_strerror", "gr_trace_last_device_error", "gr_horizon_radius",
             "gr_trace_validate", "gr_mlp_num_params", "gr_mlp_create", "gr_mlp_destroy",
@@ -159,6 +166,13 @@ def gr_trace_init(device: int = 0, integrator: gr_integrator | None = None) -> c
 def gr_trace_frame(ctx, metric: gr_metric, camera: gr_camera, out: gr_output, stream=None):
     _check(_lib.gr_trace_frame(ctx, ctypes.byref(metric), ctypes.byref(camera),
                                ctypes.byref(out), _stream_handle(stream)), "gr_trace_frame")
+
+
+def gr_trace_frame_mn(ctx, metric: gr_metric_mn, camera: gr_camera, out: gr_output,
+                      stream=None):
+    _check(_lib.gr_trace_frame_mn(ctx, ctypes.byref(metric), ctypes.byref(camera),
+                                  ctypes.byref(out), _stream_handle(stream)),
+           "gr_trace_frame_mn")
 
 
 def gr_trace_batch(ctx, instances, stream=None):

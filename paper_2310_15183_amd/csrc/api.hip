@@ -1,6 +1,8 @@
 // C-ABI entry points of libgrtrace: argument validation, context, launch
 // shape, batch tables, autotuning and dispatch to the kernels.  Host code.
 #include <math.h>
+
+#include <cmath>
 #include <stdio.h>
 #include <string.h>
 
@@ -607,6 +609,46 @@ int gr_trace_frame(gr_ctx* ctx, const gr_metric* m, const gr_camera* c, const gr
     const gr::LaunchShape L = frame_shape(ctx, A, f32);
     e = gr::launch_trace_fp64(A, f32, L, ctx->counter, (hipStream_t)hip_stream);
     if (e != hipSuccess) return device_error(e, "trace_fp64 launch");
+    return GR_OK;
+}
+
+int gr_trace_frame_mn(gr_ctx* ctx, const gr_metric_mn* m, const gr_camera* c,
+                      const gr_output* out, void* hip_stream) {
+    if (!ctx || !m || !c) return GR_EINVAL;
+    if (!(std::isfinite(m->M) && std::isfinite(m->S) && std::isfinite(m->q))) return GR_EINVAL;
+    if (!(m->M > 0.0) || m->S == 0.0 || !(fabs(m->S) < m->M * m->M)) return GR_EINVAL;
+    const gr::MnHole K = gr::make_mn_hole(m->M, m->S, m->q);
+    if (!(K.k > 0.0 && std::isfinite(K.beta))) return GR_EINVAL;
+    if (!(std::isfinite(c->r0) && std::isfinite(c->theta0) && std::isfinite(c->phi0) &&
+          std::isfinite(c->fov)))
+        return GR_EINVAL;
+    if (!(c->r0 > m->M + K.k)) return GR_EINVAL;
+    if (!(c->theta0 > 0.0 && c->theta0 < M_PI) || !(c->fov > 0.0 && c->fov < M_PI))
+        return GR_EINVAL;
+    if (c->width < 1 || c->height < 1 ||
+        (int64_t)c->width * (int64_t)c->height > ((int64_t)1 << 40))
+        return GR_EINVAL;
+    int rc = check_output(out);
+    if (rc) return rc;
+    if (ctx->integ.precision != GR_FP64) return GR_EUNSUPPORTED;
+    DeviceGuard guard(ctx->device);
+    const int64_t nray = (int64_t)c->width * c->height;
+    gr::FrameArgs A;
+    memset(&A, 0, sizeof A);
+    A.cam = gr::make_camera_mn(K, c->r0, c->theta0, c->phi0, c->fov, c->width, c->height);
+    A.in = device_integrator(ctx->integ);
+    A.r_esc = ctx->integ.escape_factor * c->r0;
+    A.nray = nray;
+    A.out = out_ptrs(out);
+    gr::LaunchShape L;
+    L.block = 64;
+    L.refill = 0;
+    const int64_t blocks = ((int64_t)c->width + 7) / 8 * (((int64_t)c->height + 7) / 8);
+    if (blocks > INT32_MAX) return GR_EINVAL;
+    L.grid = (int)blocks;
+    const hipError_t e =
+        gr::launch_trace_mn(A, K, out->dtype == GR_F32, L, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return device_error(e, "trace_mn launch");
     return GR_OK;
 }
 

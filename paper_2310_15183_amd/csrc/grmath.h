@@ -168,6 +168,144 @@ GR_HD double recip_newton(double x, double y0) {
     return fma(y, e, y);
 }
 
+// -------------------------------------------------------------------- exp
+// x = k ln2 + r, k = rint(x * fl(1/ln2)), r = (x - k LN2_HI) - k LN2_LO via
+// two fma (|r| <= ln2/2); exp r = sum_{n=0}^{13} r^n/n! by Horner in fma
+// (truncation below 5e-18 relative), exp x = 2^k exp r.  Within 1 ulp.
+// Overflow gives +inf, x < -746 gives 0, NaN stays NaN.
+constexpr double LOG2E = 0x1.71547652b82fep+0;         // fl(1/ln2)
+constexpr double LN2_HI = 0x1.62e42fefa39efp-1;        // fl(ln2)
+constexpr double LN2_LO = 0x1.abc9e3b39803fp-56;       // fl(ln2 - LN2_HI)
+constexpr double exp_coef(int n) { return 1.0 / factorial(n); }   // one rounding
+
+GR_HD double exp_def(double x) {
+    // no branches: x is clamped to [-746, 710], where exp(710) overflows to
+    // inf and exp(-746) rounds to 0 through the scaling, as the out-of-range
+    // values should; NaN is restored at the end
+    const double xr = fmin(fmax(x, -746.0), 710.0);
+    const double k = rint(xr * LOG2E);
+    double r = fma(-k, LN2_HI, xr);
+    r = fma(-k, LN2_LO, r);
+    double p = exp_coef(13);
+    p = fma(p, r, exp_coef(12));
+    p = fma(p, r, exp_coef(11));
+    p = fma(p, r, exp_coef(10));
+    p = fma(p, r, exp_coef(9));
+    p = fma(p, r, exp_coef(8));
+    p = fma(p, r, exp_coef(7));
+    p = fma(p, r, exp_coef(6));
+    p = fma(p, r, exp_coef(5));
+    p = fma(p, r, exp_coef(4));
+    p = fma(p, r, exp_coef(3));
+    p = fma(p, r, exp_coef(2));
+    p = fma(p, r, exp_coef(1));
+    p = fma(p, r, 1.0);
+    const double e = ldexp(p, (int)k);
+    return x != x ? x : e;
+}
+
+// ----------------------------------------------------------- Manko-Novikov
+// The quadrupole Manko-Novikov spacetime (arXiv 2310.15183, Sec. 2.2.3;
+// inverse components of the appendix listing's metricAtPoint):
+//   ds^2 = -f (dt - omega dphi)^2
+//          + f^{-1} [e^{2 gamma} rho^2 (dr^2/Delta + dtheta^2) + Delta sin^2 dphi^2]
+// in prolate spheroidal x = (r - M)/k, y = cos(theta), with rho^2 = k^2 (x^2 - y^2),
+// Delta = k^2 (x^2 - 1) and, R = sqrt(x^2 + y^2 - 1), P_l = P_l(x y / R),
+//   a_ = -alpha exp(-2 beta (sum_l (x - y) P_l / R^{l+1} - 1)),
+//   b_ =  alpha exp( 2 beta (1 + sum_l (-1)^{3-l} (x + y) P_l / R^{l+1})),
+//   A = (x^2-1)(1+a_b_)^2 - (1-y^2)(b_-a_)^2,
+//   B = [x+1 + (x-1) a_b_]^2 + [(1+y) a_ + (1-y) b_]^2,
+//   C = (x^2-1)(1+a_b_)[b_-a_ - y(a_+b_)] + (1-y^2)(b_-a_)[1+a_b_ + x(1-a_b_)],
+//   f = e^{2 psi} A/B, psi = beta P_2/R^3,
+//   omega = 2k e^{-2 psi} C/A - 4k alpha/(1-alpha^2),
+//   e^{2 gamma} rho^2 = k^2 e^{2G} A/(1-alpha^2)^2,
+//   G = 3 beta^2 (P_3^2 - P_2^2)/(2 R^6) + beta (sum_l [x-y + (-1)^l (x+y)] P_l/R^{l+1} - 2),
+// sums over l = 0..2; alpha = (-M + sqrt(M^2 - (S/M)^2))/(S/M),
+// k = M (1-alpha^2)/(1+alpha^2), beta = q M^3/k^3.
+struct MnHole {
+    double M, alpha, k, beta;
+    double ik, k2, twok;   // 1/k, k^2, 2k
+    double om0;            // 4 k alpha / (1 - alpha^2)
+    double iw2;            // 1 / (1 - alpha^2)^2
+};
+
+inline MnHole make_mn_hole(double M, double S, double q) {
+    MnHole h;
+    const double chi = S / M;
+    h.M = M;
+    h.alpha = (-M + sqrt(M * M - chi * chi)) / chi;
+    const double al2 = h.alpha * h.alpha;
+    h.k = M * ((1.0 - al2) / (1.0 + al2));
+    h.beta = (q * (M * M * M)) / (h.k * h.k * h.k);
+    h.ik = 1.0 / h.k;
+    h.k2 = h.k * h.k;
+    h.twok = 2.0 * h.k;
+    h.om0 = (4.0 * h.k * h.alpha) / (1.0 - al2);
+    h.iw2 = 1.0 / ((1.0 - al2) * (1.0 - al2));
+    return h;
+}
+
+// IEEE division (correctly rounded, with IEEE special values: near the
+// singular ring of the Manko-Novikov horizon the exponentials overflow and
+// 1/inf = 0 has to stay 0).
+struct IeeeDiv {
+    GR_HD static double rcp(double x) { return 1.0 / x; }
+    GR_HD static double div(double a, double x) { return a / x; }
+};
+
+// The five inverse components at (r, theta) from y = cos(theta) and
+// s2 = sin^2(theta); Div supplies correctly rounded 1/x and a/x.
+template <class Div>
+GR_HD InvMetric mn_inverse_metric(const MnHole& K, double r, double y, double s2) {
+    const double beta = K.beta;
+    const double x = (r - K.M) * K.ik;
+    const double x2 = x * x, y2 = y * y;
+    const double R = sqrt((x2 + y2) - 1.0);
+    const double iR = Div::rcp(R);
+    const double iR2 = iR * iR, iR3 = iR2 * iR;
+    const double u = (x * y) * iR;
+    const double P1 = u;
+    const double P2 = fma(1.5 * u, u, -0.5);
+    const double P3 = u * fma(2.5 * u, u, -1.5);
+    const double L1 = fma(P2, iR3, fma(P1, iR2, iR));      // sum P_l / R^{l+1}
+    const double L2 = fma(P2, iR3, fma(-P1, iR2, iR));     // sum (-1)^l P_l / R^{l+1}
+    const double Sa = (x - y) * L1;
+    const double Sb = -((x + y) * L2);
+    const double Sg = fma(x - y, L1, (x + y) * L2);
+    const double ea = exp_def((-2.0 * beta) * (Sa - 1.0));
+    const double eb = exp_def((2.0 * beta) * (1.0 + Sb));
+    const double am = -(K.alpha * ea);
+    const double bm = K.alpha * eb;
+    const double psi = (beta * P2) * iR3;
+    const double iR6 = iR3 * iR3;
+    const double G = fma((1.5 * (beta * beta)) * iR6, (P3 * P3) - (P2 * P2), beta * (Sg - 2.0));
+    const double ab = am * bm;
+    const double opab = 1.0 + ab, omab = 1.0 - ab;
+    const double bma = bm - am, apb = am + bm;
+    const double xm1 = x2 - 1.0, ym1 = 1.0 - y2;
+    const double A = fma(xm1, opab * opab, -(ym1 * (bma * bma)));
+    const double B1 = fma(x - 1.0, ab, x + 1.0);
+    const double B2 = fma(1.0 + y, am, (1.0 - y) * bm);
+    const double B = fma(B1, B1, B2 * B2);
+    const double C = fma(xm1 * opab, fma(-y, apb, bma), (ym1 * bma) * fma(x, omab, opab));
+    const double e2psi = exp_def(2.0 * psi);
+    const double fA = e2psi * A;
+    const double f = Div::div(fA, B);
+    const double omega = Div::div(K.twok * C, fA) - K.om0;
+    const double e2g_rho2 = ((K.k2 * exp_def(2.0 * G)) * A) * K.iw2;
+    const double Delta = K.k2 * xm1;
+    const double iD = Div::rcp(Delta * s2);
+    const double ie = Div::rcp(e2g_rho2);
+    const double fo = f * omega;
+    InvMetric g;
+    g.tt = fma(fo * omega, iD, -Div::rcp(f));
+    g.tp = fo * iD;
+    g.rr = (f * Delta) * ie;
+    g.hh = f * ie;
+    g.pp = f * iD;
+    return g;
+}
+
 // ----------------------------------------------------------------- camera
 // Frame constants of the pinhole camera (host side, once per frame):
 // half-extents tan(fov/2) and tan(fov/2) H/W, the orthonormal-frame scale
@@ -201,6 +339,31 @@ inline Camera make_camera(const Hole& Hh, double r0, double th0, double ph0, dou
     C.eth = sqrt(rho2);                          // sqrt(g_thth)
     C.eph = sqrt((Sigma2 * T.s2) / rho2);        // sqrt(g_phph)
     C.g = inverse_metric(Hh, R, T);
+    return C;
+}
+
+// The same frame constants for a Manko-Novikov spacetime: the orthonormal
+// scale factors from the inverse metric at the camera, g_rr = 1/g^rr,
+// g_thth = 1/g^thth and g_phph = g^tt / (g^tt g^phph - (g^tphi)^2) (inverse of
+// the (t, phi) block).
+inline Camera make_camera_mn(const MnHole& K, double r0, double th0, double ph0, double fov,
+                             int32_t W, int32_t H) {
+    Camera C;
+    C.r0 = r0;
+    C.th0 = th0;
+    C.ph0 = ph0;
+    C.W = W;
+    C.H = H;
+    double sf, cf;
+    sincos_def(0.5 * fov, sf, cf);
+    C.tan_h = sf / cf;
+    C.tan_v = (C.tan_h * (double)H) / (double)W;
+    double s, c;
+    sincos_def(th0, s, c);
+    C.g = mn_inverse_metric<IeeeDiv>(K, r0, c, s * s);
+    C.er = sqrt(1.0 / C.g.rr);
+    C.eth = sqrt(1.0 / C.g.hh);
+    C.eph = sqrt(C.g.tt / ((C.g.tt * C.g.pp) - (C.g.tp * C.g.tp)));
     return C;
 }
 

@@ -113,6 +113,11 @@ hipError_t launch_trace_mixed(const FrameArgs& A, double r_plus, bool f32_out,
                               hipStream_t s);
 int occupancy_trace_mixed(int block, bool f32_out);
 
+// A Manko-Novikov frame, one ray per lane over 8x8 pixel tiles (L.refill
+// must be 0); A.hole is not used.
+hipError_t launch_trace_mn(const FrameArgs& A, const MnHole& K, bool f32_out,
+                           const LaunchShape& L, hipStream_t s);
+
 // All instances of a batch in one launch: persistent (L.refill), or one ray
 // per lane over the waves of B.wfirsts.
 hipError_t launch_trace_fp64_batch(const BatchArgs& B, const LaunchShape& L,

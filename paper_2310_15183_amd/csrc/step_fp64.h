@@ -42,6 +42,35 @@ struct Deriv {
     double pr, ph;           // dp_r/dtau, dp_theta/dtau
 };
 
+// Hamilton's equations from the inverse metric g at the stage point and gr,
+// gh at (r + eps, theta) and (r, theta + eps): p-dot = -1/(2 eps) times the
+// sum of the five component differences times p_nu p_sigma, in the order
+// tt, tphi (weight 2 p_t p_phi), rr, thth, phph.
+static __device__ __forceinline__ Deriv deriv_from(const InvMetric& g, const InvMetric& gr,
+                                                   const InvMetric& gh, const Integrator& in,
+                                                   double pt, double pr, double pth, double pph,
+                                                   double wtt, double wtp, double wpp) {
+    const double wrr = pr * pr, wth = pth * pth;
+    double acc = (gr.tt - g.tt) * wtt;
+    acc = fma(gr.tp - g.tp, wtp, acc);
+    acc = fma(gr.rr - g.rr, wrr, acc);
+    acc = fma(gr.hh - g.hh, wth, acc);
+    acc = fma(gr.pp - g.pp, wpp, acc);
+    Deriv d;
+    d.pr = acc * in.scale;
+    acc = (gh.tt - g.tt) * wtt;
+    acc = fma(gh.tp - g.tp, wtp, acc);
+    acc = fma(gh.rr - g.rr, wrr, acc);
+    acc = fma(gh.hh - g.hh, wth, acc);
+    acc = fma(gh.pp - g.pp, wpp, acc);
+    d.ph = acc * in.scale;
+    d.qt = fma(g.tt, pt, g.tp * pph);
+    d.qr = g.rr * pr;
+    d.qh = g.hh * pth;
+    d.qp = fma(g.tp, pt, g.pp * pph);
+    return d;
+}
+
 // Right-hand side at one stage point: metric at (r, th), (r+eps, th) and
 // (r, th+eps), sin/cos at th+eps by angle addition from those at th and eps;
 // p-dot = -1/(2 eps) times the sum of the five component differences times
@@ -68,27 +97,24 @@ static __device__ __forceinline__ Deriv rhs(const Hole& H, const Integrator& in,
     const InvMetric g = metric_from(H, R0, T0, inv, is);
     const InvMetric gr = metric_from(H, R1, T0, is_r * T0.s2, is_r);
     const InvMetric gh = metric_from(H, R0, T1, inv_t, inv_t * rcp_rn(T1.s2));
+    return deriv_from(g, gr, gh, in, pt, pr, pth, pph, wtt, wtp, wpp);
+}
 
-    const double wrr = pr * pr, wth = pth * pth;
-    double acc = (gr.tt - g.tt) * wtt;
-    acc = fma(gr.tp - g.tp, wtp, acc);
-    acc = fma(gr.rr - g.rr, wrr, acc);
-    acc = fma(gr.hh - g.hh, wth, acc);
-    acc = fma(gr.pp - g.pp, wpp, acc);
-    Deriv d;
-    d.pr = acc * in.scale;
-    acc = (gh.tt - g.tt) * wtt;
-    acc = fma(gh.tp - g.tp, wtp, acc);
-    acc = fma(gh.rr - g.rr, wrr, acc);
-    acc = fma(gh.hh - g.hh, wth, acc);
-    acc = fma(gh.pp - g.pp, wpp, acc);
-    d.ph = acc * in.scale;
-
-    d.qt = fma(g.tt, pt, g.tp * pph);
-    d.qr = g.rr * pr;
-    d.qh = g.hh * pth;
-    d.qp = fma(g.tp, pt, g.pp * pph);
-    return d;
+// The same right-hand side for the Manko-Novikov spacetime: three full
+// evaluations of its inverse metric (y = cos theta, sin and cos at theta+eps
+// by angle addition as above).
+static __device__ __forceinline__ Deriv rhs_mn(const MnHole& K, const Integrator& in, double r,
+                                               double th, double pt, double pr, double pth,
+                                               double pph, double wtt, double wtp, double wpp) {
+    double s, c;
+    sincos_def(th, s, c);
+    const double se = fma(c, in.sin_eps, s * in.cos_eps);
+    const double ce = fma(-s, in.sin_eps, c * in.cos_eps);
+    const double s2 = s * s;
+    const InvMetric g = mn_inverse_metric<IeeeDiv>(K, r, c, s2);
+    const InvMetric gr = mn_inverse_metric<IeeeDiv>(K, r + in.eps, c, s2);
+    const InvMetric gh = mn_inverse_metric<IeeeDiv>(K, r, ce, se * se);
+    return deriv_from(g, gr, gh, in, pt, pr, pth, pph, wtt, wtp, wpp);
 }
 
 struct Ray {
@@ -113,23 +139,25 @@ static __device__ __forceinline__ bool finite6(const Ray& y) {
            isfinite(y.pr) && isfinite(y.pth);
 }
 
-// One RK4 step; returns nu = |dt/dtau| of the first stage.
-static __device__ __forceinline__ double rk4_step(const Hole& H, const Integrator& in, Ray& y) {
-    Deriv k = rhs(H, in, y.r, y.th, y.pt, y.pr, y.pth, y.pph, y.wtt, y.wtp, y.wpp);
+// One RK4 step with the right-hand side rhs_at(r, theta, p_r, p_theta);
+// returns nu = |dt/dtau| of the first stage.
+template <class Rhs>
+static __device__ __forceinline__ double rk4_generic(const Rhs& rhs_at, const Integrator& in,
+                                                     Ray& y) {
+    Deriv k = rhs_at(y.r, y.th, y.pr, y.pth);
     const double nu = fabs(k.qt);
     const double h = div_rn(in.dt, nu);
     const double hh = 0.5 * h;
     double st = k.qt, sr = k.qr, sh = k.qh, sp = k.qp, spr = k.pr, sph = k.ph;
-    k = rhs(H, in, fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), y.pt,
-            fma(hh, k.pr, y.pr), fma(hh, k.ph, y.pth), y.pph, y.wtt, y.wtp, y.wpp);
+    k = rhs_at(fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), fma(hh, k.pr, y.pr),
+               fma(hh, k.ph, y.pth));
     st = st + 2.0 * k.qt; sr = sr + 2.0 * k.qr; sh = sh + 2.0 * k.qh; sp = sp + 2.0 * k.qp;
     spr = spr + 2.0 * k.pr; sph = sph + 2.0 * k.ph;
-    k = rhs(H, in, fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), y.pt,
-            fma(hh, k.pr, y.pr), fma(hh, k.ph, y.pth), y.pph, y.wtt, y.wtp, y.wpp);
+    k = rhs_at(fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), fma(hh, k.pr, y.pr),
+               fma(hh, k.ph, y.pth));
     st = st + 2.0 * k.qt; sr = sr + 2.0 * k.qr; sh = sh + 2.0 * k.qh; sp = sp + 2.0 * k.qp;
     spr = spr + 2.0 * k.pr; sph = sph + 2.0 * k.ph;
-    k = rhs(H, in, fma(h, k.qr, y.r), fma(h, k.qh, y.th), y.pt,
-            fma(h, k.pr, y.pr), fma(h, k.ph, y.pth), y.pph, y.wtt, y.wtp, y.wpp);
+    k = rhs_at(fma(h, k.qr, y.r), fma(h, k.qh, y.th), fma(h, k.pr, y.pr), fma(h, k.ph, y.pth));
     st = st + k.qt; sr = sr + k.qr; sh = sh + k.qh; sp = sp + k.qp;
     spr = spr + k.pr; sph = sph + k.ph;
     const double h6 = h * (1.0 / 6.0);
@@ -140,6 +168,25 @@ static __device__ __forceinline__ double rk4_step(const Hole& H, const Integrato
     y.pr = fma(h6, spr, y.pr);
     y.pth = fma(h6, sph, y.pth);
     return nu;
+}
+
+// One Kerr-Newman RK4 step.
+static __device__ __forceinline__ double rk4_step(const Hole& H, const Integrator& in, Ray& y) {
+    return rk4_generic(
+        [&](double r, double th, double pr, double pth) {
+            return rhs(H, in, r, th, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
+        },
+        in, y);
+}
+
+// One Manko-Novikov RK4 step.
+static __device__ __forceinline__ double rk4_step_mn(const MnHole& K, const Integrator& in,
+                                                     Ray& y) {
+    return rk4_generic(
+        [&](double r, double th, double pr, double pth) {
+            return rhs_mn(K, in, r, th, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
+        },
+        in, y);
 }
 
 static __device__ __forceinline__ int exit_flag(const Integrator& in, double r_esc, const Ray& y,

@@ -58,7 +58,9 @@ def compare(gpu, ref, angle_tol=1e-9, f32=False):
         same &= (got == want) | (np.isnan(got) & np.isnan(want))
     for k in ("theta", "phi"):
         want = ref[k].astype(np.float32).astype(np.float64) if f32 else ref[k]
-        d = np.abs(gpu[k].astype(np.float64) - want)
+        got = gpu[k].astype(np.float64)
+        both_nan = np.isnan(got) & np.isnan(want)           # invalid rays on both sides
+        d = np.abs(got - want)[~both_nan]
         stats[f"max_d{k}"] = float(d.max()) if d.size else 0.0
         assert d.size == 0 or d.max() <= angle_tol, (k, float(d.max()))
     stats["bit_identical"] = int(same.sum())
