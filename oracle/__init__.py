@@ -51,7 +51,7 @@ def _load():
         vp = ctypes.c_void_p
         lib.oracle_trace_frame.restype = i64
         lib.oracle_trace_frame.argtypes = [d, d, d, d, d, d, d, i, i, d, d, d, d, i,
-                                           vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, i]
+                                           vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, i, i]
         lib.oracle_trace_rays.restype = i64
         lib.oracle_trace_rays.argtypes = [d, d, d, d, d, d, d, i, vp, i64,
                                           vp, vp, vp, vp, vp, vp, vp, vp, i]
@@ -112,8 +112,9 @@ def _alloc(n):
 
 def trace_frame(M, a, Q, r0, theta0, phi0, fov, width, height, dt=0.01, eps=1e-8,
                 horizon_norm=1e4, escape_factor=1.5, max_steps=20000, pixels=None,
-                threads=None, want_p0=False) -> Result:
-    """Trace the camera rays of a width x height frame (or the listed pixels)."""
+                threads=None, want_p0=False, method=0) -> Result:
+    """Trace the camera rays of a width x height frame (or the listed pixels);
+    method 0 is RK4, 1 explicit Euler."""
     lib = _load()
     if pixels is not None:
         pixels = np.ascontiguousarray(pixels, dtype=np.int64)
@@ -125,7 +126,8 @@ def trace_frame(M, a, Q, r0, theta0, phi0, fov, width, height, dt=0.01, eps=1e-8
     lib.oracle_trace_frame(M, a, Q, r0, theta0, phi0, fov, int(width), int(height), dt, eps,
                            horizon_norm, escape_factor, int(max_steps), _ptr(pixels), n,
                            _ptr(t), _ptr(r), _ptr(th), _ptr(ph), _ptr(pr), _ptr(pth), _ptr(p0),
-                           _ptr(flag), _ptr(steps), int(threads or default_threads()))
+                           _ptr(flag), _ptr(steps), int(threads or default_threads()),
+                           int(method))
     return Result(t, r, th, ph, pr, pth, flag, steps, p0)
 
 
@@ -200,7 +202,7 @@ def sincos(x) -> tuple[np.ndarray, np.ndarray]:
 # ---------------------------------------------------------------- Manko-Novikov
 def trace_frame_mn(M, S, q, r0, theta0, phi0, fov, width, height, dt=0.01, eps=1e-8,
                    horizon_norm=1e4, escape_factor=1.5, max_steps=20000, pixels=None,
-                   threads=None, want_p0=False) -> Result:
+                   threads=None, want_p0=False, method=0) -> Result:
     """trace_frame for the Manko-Novikov spacetime (mass M, spin S, quadrupole
     deviation q; paper Sec. 2.2.3)."""
     lib = _load()
@@ -214,7 +216,8 @@ def trace_frame_mn(M, S, q, r0, theta0, phi0, fov, width, height, dt=0.01, eps=1
     lib.oracle_trace_frame_mn(M, S, q, r0, theta0, phi0, fov, int(width), int(height), dt, eps,
                               horizon_norm, escape_factor, int(max_steps), _ptr(pixels), n,
                               _ptr(t), _ptr(r), _ptr(th), _ptr(ph), _ptr(pr), _ptr(pth),
-                              _ptr(p0), _ptr(flag), _ptr(steps), int(threads or default_threads()))
+                              _ptr(p0), _ptr(flag), _ptr(steps), int(threads or default_threads()),
+                              int(method))
     return Result(t, r, th, ph, pr, pth, flag, steps, p0)
 
 

@@ -18,7 +18,8 @@
  *
  * integrated with classical RK4 whose step h = dt / |dq^t/dtau| is fixed for
  * the whole step from the first stage, so that coordinate time advances by
- * about dt per step.  d_r g and d_theta g are one-sided forward differences
+ * about dt per step (or, on request, with explicit Euler and the same h,
+ * Sec. 3.1.1).  d_r g and d_theta g are one-sided forward differences
  * with step eps; the t and phi derivatives vanish (stationary, axisymmetric),
  * so p_t and p_phi never change.  A ray stops when r exceeds escape_factor
  * times its starting radius (escape), else when |dq^t/dtau| exceeds
@@ -71,6 +72,7 @@ typedef struct {
     int max_steps;
     int trig_mode;               /* 0: trig_sincos below; 1: C library sin/cos */
     int kind;                    /* METRIC_KN or METRIC_MN */
+    int method;                  /* 0: RK4 (Sec. 3.1.2); 1: explicit Euler (Sec. 3.1.1) */
     mn_consts mn;                /* METRIC_MN only */
 } oracle_params;
 
@@ -443,6 +445,19 @@ int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nste
 
     for (s = 1; s <= P->max_steps; ++s) {
         double k1q[4], k1p[2], k2q[4], k2p[2], k3q[4], k3p[2], k4q[4], k4p[2];
+        if (P->method == 1) {
+            /* explicit Euler: x += h f(x), h = dt / |dt/dtau| from f(x) */
+            hamilton_rhs(P, eps_sc, q[1], q[2], pt, pr, pth, pph, k1q, k1p);
+            const double nu = fabs(k1q[0]);
+            const double h = P->dt / nu;
+            for (int m = 0; m < 4; ++m) q[m] = fma(h, k1q[m], q[m]);
+            pr = fma(h, k1p[0], pr);
+            pth = fma(h, k1p[1], pth);
+            if (q[1] > r_esc) { flag = FLAG_ESCAPE; break; }
+            if (nu > P->horizon_norm) { flag = FLAG_HORIZON; break; }
+            if (!all_finite(q, pr, pth)) { flag = FLAG_INVALID; break; }
+            continue;
+        }
         /* K1 at the current point; its dt/dtau fixes the step. */
         hamilton_rhs(P, eps_sc, q[1], q[2], pt, pr, pth, pph, k1q, k1p);
         const double nu = fabs(k1q[0]);
@@ -640,6 +655,7 @@ static oracle_params make_params(double M, double a, double Q, double dt, double
     P.horizon_norm = horizon_norm; P.escape_factor = escape_factor;
     P.max_steps = max_steps; P.trig_mode = g_trig_mode;
     P.kind = METRIC_KN;
+    P.method = 0;
     memset(&P.mn, 0, sizeof P.mn);
     pthread_once(&trig_once, trig_init);
     return P;
@@ -667,9 +683,10 @@ int64_t oracle_trace_frame(double M, double a, double Q,
                            const int64_t *pixels, int64_t n,
                            double *t, double *r, double *th, double *ph,
                            double *pr, double *pth, double *p0,
-                           int8_t *flag, int32_t *steps, int nthreads)
+                           int8_t *flag, int32_t *steps, int nthreads, int method)
 {
     oracle_params P = make_params(M, a, Q, dt, eps, horizon_norm, escape_factor, max_steps);
+    P.method = method;
     camera_consts C;
     camera_setup(&P, r0, th0, fov, W, H, &C);
     job J;
@@ -743,9 +760,10 @@ int64_t oracle_trace_frame_mn(double M, double S, double q,
                               const int64_t *pixels, int64_t n,
                               double *t, double *r, double *th, double *ph,
                               double *pr, double *pth, double *p0,
-                              int8_t *flag, int32_t *steps, int nthreads)
+                              int8_t *flag, int32_t *steps, int nthreads, int method)
 {
     oracle_params P = make_params_mn(M, S, q, dt, eps, horizon_norm, escape_factor, max_steps);
+    P.method = method;
     camera_consts C;
     camera_setup(&P, r0, th0, fov, W, H, &C);
     job J;
