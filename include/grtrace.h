@@ -99,15 +99,26 @@ typedef struct {
     int32_t width, height;
 } gr_camera;
 
+/* Integration method (arXiv 2310.15183, Sec. 3.1).
+ * GR_RK4: classical Runge-Kutta with the step h = dt / |dt/dtau| fixed from
+ *   the first stage (Sec. 3.1.2).
+ * GR_EULER: explicit Euler, x += h f(x) with the same h (Sec. 3.1.1); first
+ *   order, for the accuracy/cost comparison of Sec. 3.2.  Binary64 frames
+ *   only (gr_trace_frame, gr_trace_frame_mn): batches, the surrogate and
+ *   GR_MIXED return GR_EUNSUPPORTED. */
+enum { GR_RK4 = 0, GR_EULER = 1 };
+
 /* Integrator settings.  dt > 0 is the coordinate-time step, fd_eps > 0 the
  * forward-difference step, horizon_norm > 0 the |dt/dtau| at which a ray is
  * declared captured, escape_factor > 1 the escape radius in units of r0,
  * max_steps >= 0 the step limit (0 returns the initial state), precision
- * GR_FP64.  Suggested: 0.01, 1e-8, 1e4, 1.5, 20000, GR_FP64. */
+ * GR_FP64 or GR_MIXED, method GR_RK4 or GR_EULER.
+ * Suggested: 0.01, 1e-8, 1e4, 1.5, 20000, GR_FP64, GR_RK4. */
 typedef struct {
     double dt, fd_eps, horizon_norm, escape_factor;
     int32_t max_steps;
     int32_t precision;
+    int32_t method;
 } gr_integrator;
 
 /* Per-ray outputs (device pointers).  The eight floating-point arrays hold

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libgrtrace.so")
 GR_OK, GR_EINVAL, GR_ENOMEM, GR_EDEVICE, GR_EUNSUPPORTED = 0, -1, -2, -3, -4
 GR_FLAG_TIMEOUT, GR_FLAG_ESCAPE, GR_FLAG_HORIZON, GR_FLAG_INVALID = 0, 1, 2, 3
 GR_FP64, GR_MIXED = 0, 1
+GR_RK4, GR_EULER = 0, 1
 GR_F64, GR_F32 = 0, 1
 
 
@@ -40,7 +41,8 @@ class gr_camera(ctypes.Structure):
 class gr_integrator(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("fd_eps", ctypes.c_double),
                 ("horizon_norm", ctypes.c_double), ("escape_factor", ctypes.c_double),
-                ("max_steps", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("max_steps", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("method", ctypes.c_int32)]
 
 
 class gr_output(ctypes.Structure):
@@ -233,9 +235,9 @@ def gr_horizon_radius(metric: gr_metric) -> float:
 
 # ---------------------------------------------------------------- marshalling helpers
 def make_integrator(dt=0.01, fd_eps=1e-8, horizon_norm=1e4, escape_factor=1.5,
-                    max_steps=20000, precision=GR_FP64) -> gr_integrator:
+                    max_steps=20000, precision=GR_FP64, method=None) -> gr_integrator:
     return gr_integrator(dt, fd_eps, horizon_norm, escape_factor, int(max_steps),
-                         int(precision))
+                         int(precision), GR_RK4 if method is None else int(method))
 
 
 FIELDS = ("t", "r", "theta", "phi", "p_t", "p_r", "p_theta", "p_phi")

@@ -63,6 +63,8 @@ int check_integrator(const gr_integrator* in) {
     if (!(finite(in->escape_factor) && in->escape_factor > 1.0)) return GR_EINVAL;
     if (in->max_steps < 0) return GR_EINVAL;
     if (in->precision != GR_FP64 && in->precision != GR_MIXED) return GR_EINVAL;
+    if (in->method != GR_RK4 && in->method != GR_EULER) return GR_EINVAL;
+    if (in->method == GR_EULER && in->precision != GR_FP64) return GR_EUNSUPPORTED;
     return GR_OK;
 }
 
@@ -224,6 +226,7 @@ int64_t instance_rays(const gr_instance* I) {
 
 int validate_batch(const gr_ctx* ctx, const gr_instance* inst, int32_t n) {
     if (!ctx || !inst || n < 1) return GR_EINVAL;
+    if (ctx->integ.method != GR_RK4) return GR_EUNSUPPORTED;
     for (int32_t k = 0; k < n; ++k) {
         const gr_instance* I = &inst[k];
         int rc = check_metric(&I->metric);
@@ -606,8 +609,17 @@ int gr_trace_frame(gr_ctx* ctx, const gr_metric* m, const gr_camera* c, const gr
         if (e != hipSuccess) return device_error(e, "trace_mixed launch");
         return GR_OK;
     }
-    const gr::LaunchShape L = frame_shape(ctx, A, f32);
-    e = gr::launch_trace_fp64(A, f32, L, ctx->counter, (hipStream_t)hip_stream);
+    gr::LaunchShape L = frame_shape(ctx, A, f32);
+    const bool euler = ctx->integ.method == GR_EULER;
+    if (euler && L.refill) {
+        // Euler steps exist in the one-ray-per-lane kernel only
+        const int64_t tiles = ((int64_t)c->width + 7) / 8 * (((int64_t)c->height + 7) / 8);
+        if (tiles > INT32_MAX) return GR_EUNSUPPORTED;
+        L.block = 64;
+        L.refill = 0;
+        L.grid = (int)tiles;
+    }
+    e = gr::launch_trace_fp64(A, f32, euler, L, ctx->counter, (hipStream_t)hip_stream);
     if (e != hipSuccess) return device_error(e, "trace_fp64 launch");
     return GR_OK;
 }
@@ -646,8 +658,9 @@ int gr_trace_frame_mn(gr_ctx* ctx, const gr_metric_mn* m, const gr_camera* c,
     const int64_t blocks = ((int64_t)c->width + 7) / 8 * (((int64_t)c->height + 7) / 8);
     if (blocks > INT32_MAX) return GR_EINVAL;
     L.grid = (int)blocks;
-    const hipError_t e =
-        gr::launch_trace_mn(A, K, out->dtype == GR_F32, L, (hipStream_t)hip_stream);
+    const hipError_t e = gr::launch_trace_mn(A, K, out->dtype == GR_F32,
+                                             ctx->integ.method == GR_EULER, L,
+                                             (hipStream_t)hip_stream);
     if (e != hipSuccess) return device_error(e, "trace_mn launch");
     return GR_OK;
 }
@@ -779,7 +792,7 @@ int gr_surrogate_frame(gr_ctx* ctx, gr_mlp* mlp, const gr_metric* m, const gr_ca
     // a turn of max_gain pixel widths (fov / width) as a chord of unit vectors
     const double turn = std::min((double)max_gain * (c->fov / c->width), M_PI);
     const float chord = max_gain > 0.0f ? (float)(2.0 * sin(0.5 * turn)) : 0.0f;
-    if (ctx->integ.precision != GR_FP64) return GR_EUNSUPPORTED;
+    if (ctx->integ.precision != GR_FP64 || ctx->integ.method != GR_RK4) return GR_EUNSUPPORTED;
     if (gr_mlp_device_of(mlp) != ctx->device) return GR_EINVAL;
     const int64_t npix = (int64_t)c->width * c->height;
     if (npix > ((int64_t)1 << 31) - 1) return GR_EINVAL;

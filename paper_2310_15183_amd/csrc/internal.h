@@ -100,8 +100,8 @@ size_t frame_order_temp(int64_t npix);
 hipError_t launch_reset_counter(unsigned long long* counter, hipStream_t s);
 
 // FP64 frame tracer.  f32_out selects binary32 outputs.
-hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, const LaunchShape& L,
-                             unsigned long long* counter, hipStream_t s);
+hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, bool euler,
+                             const LaunchShape& L, unsigned long long* counter, hipStream_t s);
 
 // Workgroups of `block` threads that fit on one CU for the FP64 tracer.
 int occupancy_trace_fp64(int block, bool f32_out);
@@ -115,7 +115,7 @@ int occupancy_trace_mixed(int block, bool f32_out);
 
 // A Manko-Novikov frame, one ray per lane over 8x8 pixel tiles (L.refill
 // must be 0); A.hole is not used.
-hipError_t launch_trace_mn(const FrameArgs& A, const MnHole& K, bool f32_out,
+hipError_t launch_trace_mn(const FrameArgs& A, const MnHole& K, bool f32_out, bool euler,
                            const LaunchShape& L, hipStream_t s);
 
 // All instances of a batch in one launch: persistent (L.refill), or one ray

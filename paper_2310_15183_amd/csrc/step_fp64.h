@@ -170,6 +170,23 @@ static __device__ __forceinline__ double rk4_generic(const Rhs& rhs_at, const In
     return nu;
 }
 
+// One explicit Euler step x += h f(x) with the same h = dt/|dt/dtau| (paper
+// Sec. 3.1.1); returns nu.
+template <class Rhs>
+static __device__ __forceinline__ double euler_generic(const Rhs& rhs_at, const Integrator& in,
+                                                       Ray& y) {
+    const Deriv k = rhs_at(y.r, y.th, y.pr, y.pth);
+    const double nu = fabs(k.qt);
+    const double h = div_rn(in.dt, nu);
+    y.t = fma(h, k.qt, y.t);
+    y.r = fma(h, k.qr, y.r);
+    y.th = fma(h, k.qh, y.th);
+    y.ph = fma(h, k.qp, y.ph);
+    y.pr = fma(h, k.pr, y.pr);
+    y.pth = fma(h, k.ph, y.pth);
+    return nu;
+}
+
 // One Kerr-Newman RK4 step.
 static __device__ __forceinline__ double rk4_step(const Hole& H, const Integrator& in, Ray& y) {
     return rk4_generic(
@@ -179,14 +196,23 @@ static __device__ __forceinline__ double rk4_step(const Hole& H, const Integrato
         in, y);
 }
 
-// One Manko-Novikov RK4 step.
-static __device__ __forceinline__ double rk4_step_mn(const MnHole& K, const Integrator& in,
-                                                     Ray& y) {
-    return rk4_generic(
-        [&](double r, double th, double pr, double pth) {
-            return rhs_mn(K, in, r, th, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
-        },
-        in, y);
+// One step of the chosen method (EULER: explicit Euler, else RK4).
+template <bool EULER>
+static __device__ __forceinline__ double kn_step(const Hole& H, const Integrator& in, Ray& y) {
+    const auto f = [&](double r, double th, double pr, double pth) {
+        return rhs(H, in, r, th, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
+    };
+    if constexpr (EULER) return euler_generic(f, in, y);
+    else return rk4_generic(f, in, y);
+}
+
+template <bool EULER>
+static __device__ __forceinline__ double mn_step(const MnHole& K, const Integrator& in, Ray& y) {
+    const auto f = [&](double r, double th, double pr, double pth) {
+        return rhs_mn(K, in, r, th, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
+    };
+    if constexpr (EULER) return euler_generic(f, in, y);
+    else return rk4_generic(f, in, y);
 }
 
 static __device__ __forceinline__ int exit_flag(const Integrator& in, double r_esc, const Ray& y,

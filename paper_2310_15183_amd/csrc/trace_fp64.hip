@@ -24,8 +24,9 @@ namespace {
 
 using namespace detail;
 
-// One lane, one ray (static_ray); the grid covers every ray.
-template <typename T>
+// One lane, one ray (static_ray); the grid covers every ray.  EULER selects
+// explicit Euler steps in place of RK4.
+template <typename T, bool EULER>
 __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
     int64_t k, pix;
     if (!static_ray(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, k, pix)) return;
@@ -34,7 +35,7 @@ __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
     int s = 0;
     int f = start_flag(A.in, y);
     while (f == RUNNING) {
-        const double nu = rk4_step(A.hole, A.in, y);
+        const double nu = kn_step<EULER>(A.hole, A.in, y);
         ++s;
         f = exit_flag(A.in, A.r_esc, y, nu, s);
     }
@@ -196,8 +197,18 @@ hipError_t launch_reset_counter(unsigned long long* counter, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, const LaunchShape& L,
-                             unsigned long long* counter, hipStream_t s) {
+hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, bool euler,
+                             const LaunchShape& L, unsigned long long* counter, hipStream_t s) {
+    if (euler) {                                  // one ray per lane only
+        if (L.refill) return hipErrorInvalidValue;
+        if (f32_out)
+            hipLaunchKernelGGL((trace_fp64_static<float, true>), dim3(L.grid), dim3(L.block), 0,
+                               s, A);
+        else
+            hipLaunchKernelGGL((trace_fp64_static<double, true>), dim3(L.grid), dim3(L.block),
+                               0, s, A);
+        return hipGetLastError();
+    }
     if (L.refill) {
         hipError_t e = launch_reset_counter(counter, s);
         if (e != hipSuccess) return e;
@@ -209,9 +220,11 @@ hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, const LaunchShape
                                counter);
     } else {
         if (f32_out)
-            hipLaunchKernelGGL(trace_fp64_static<float>, dim3(L.grid), dim3(L.block), 0, s, A);
+            hipLaunchKernelGGL((trace_fp64_static<float, false>), dim3(L.grid), dim3(L.block), 0,
+                               s, A);
         else
-            hipLaunchKernelGGL(trace_fp64_static<double>, dim3(L.grid), dim3(L.block), 0, s, A);
+            hipLaunchKernelGGL((trace_fp64_static<double, false>), dim3(L.grid), dim3(L.block), 0,
+                               s, A);
     }
     return hipGetLastError();
 }

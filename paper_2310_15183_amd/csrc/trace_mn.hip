@@ -18,7 +18,7 @@ struct MnArgs {
     MnHole mn;
 };
 
-template <typename T>
+template <typename T, bool EULER>
 __global__ void __launch_bounds__(256) trace_mn_static(const MnArgs X) {
     const FrameArgs& A = X.f;
     int64_t k, pix;
@@ -28,7 +28,7 @@ __global__ void __launch_bounds__(256) trace_mn_static(const MnArgs X) {
     int s = 0;
     int f = start_flag(A.in, y);
     while (f == RUNNING) {
-        const double nu = rk4_step_mn(X.mn, A.in, y);
+        const double nu = mn_step<EULER>(X.mn, A.in, y);
         ++s;
         f = exit_flag(A.in, A.r_esc, y, nu, s);
     }
@@ -37,15 +37,20 @@ __global__ void __launch_bounds__(256) trace_mn_static(const MnArgs X) {
 
 }  // namespace
 
-hipError_t launch_trace_mn(const FrameArgs& A, const MnHole& K, bool f32_out,
+hipError_t launch_trace_mn(const FrameArgs& A, const MnHole& K, bool f32_out, bool euler,
                            const LaunchShape& L, hipStream_t s) {
     MnArgs X;
     X.f = A;
     X.mn = K;
-    if (f32_out)
-        hipLaunchKernelGGL(trace_mn_static<float>, dim3(L.grid), dim3(L.block), 0, s, X);
+    if (f32_out && euler)
+        hipLaunchKernelGGL((trace_mn_static<float, true>), dim3(L.grid), dim3(L.block), 0, s, X);
+    else if (f32_out)
+        hipLaunchKernelGGL((trace_mn_static<float, false>), dim3(L.grid), dim3(L.block), 0, s, X);
+    else if (euler)
+        hipLaunchKernelGGL((trace_mn_static<double, true>), dim3(L.grid), dim3(L.block), 0, s, X);
     else
-        hipLaunchKernelGGL(trace_mn_static<double>, dim3(L.grid), dim3(L.block), 0, s, X);
+        hipLaunchKernelGGL((trace_mn_static<double, false>), dim3(L.grid), dim3(L.block), 0, s,
+                           X);
     return hipGetLastError();
 }
 
