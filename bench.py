@@ -480,6 +480,64 @@ def bench_mn(args):
     print(json.dumps(result), flush=True)
 
 
+FLOPS_PER_RAY_STEP_EULER = 170   # one stage (157), h (1), update (6 fma)
+
+
+def bench_euler(args):
+    """RK4 against explicit Euler (paper Sec. 3.1.1, the comparison of Sec.
+    3.2) on the 1000x1000 Kerr-Newman frame: rays/s and the end-direction
+    difference from the RK4 frame at the same dt, for Euler at dt and dt/4."""
+    import numpy as np
+    import torch
+
+    import paper_2310_15183_amd as g
+    from paper_2310_15183_amd.evaluate import mixed_errors
+    w = workload()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    n = w["W"] * w["H"]
+    metric = g.gr_metric(w["M"], w["a"], w["Q"])
+    cam = g.gr_camera(w["r0"], w["theta0"], w["phi0"], w["fov"], w["W"], w["H"])
+
+    def run(dt, max_steps, method):
+        ctx = g.gr_trace_init(0, g.make_integrator(dt=dt, fd_eps=w["fd_eps"],
+                                                   horizon_norm=w["horizon_norm"],
+                                                   escape_factor=w["escape_factor"],
+                                                   max_steps=max_steps, method=method))
+        out = g.alloc_outputs(n, dtype=g.GR_F32, fields=("t", "r", "theta", "phi"))
+        wall, launch_s = time_frames(g, ctx, metric, cam, out, args.steps, args.warmup, stream)
+        ray_steps = int(out["steps"].cpu().numpy().astype(np.int64).sum())
+        full = g.alloc_outputs(n, dtype=g.GR_F64, fields=g.FIELDS)
+        g.gr_trace_frame(ctx, metric, cam, full.struct, stream)
+        torch.cuda.synchronize()
+        res = {k: v.cpu().numpy() for k, v in full.tensors.items()}
+        g.gr_trace_destroy(ctx)
+        return wall / args.steps, launch_s, ray_steps, res
+
+    rk_s, rk_launch, rk_steps, ref = run(w["dt"], w["max_steps"], g.GR_RK4)
+    lines = {"rk4": {"dt": w["dt"], "ms_per_step": rk_s * 1e3, "rays_per_s": n / rk_s,
+                     "ray_steps": rk_steps,
+                     "roofline_frac": FLOPS_PER_RAY_STEP * rk_steps / rk_launch / 1e12
+                     / FP64_PEAK_TFLOPS}}
+    for name, dt, ms in [("euler", w["dt"], w["max_steps"]),
+                         ("euler_dt/4", w["dt"] / 4, 4 * w["max_steps"])]:
+        sec, launch, steps, got = run(dt, ms, g.GR_EULER)
+        err = mixed_errors(w["M"], w["a"], w["Q"], w["escape_factor"] * w["r0"], ref, got)
+        achieved = FLOPS_PER_RAY_STEP_EULER * steps / launch / 1e12
+        lines[name] = {"dt": dt, "ms_per_step": sec * 1e3, "rays_per_s": n / sec,
+                       "speedup_vs_rk4": rk_s / sec, "ray_steps": steps,
+                       "angle_err_vs_rk4_rad": err,
+                       "roofline": {"bound": "alu", "achieved": achieved,
+                                    "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                    "frac": achieved / FP64_PEAK_TFLOPS,
+                                    "flops_per_ray_step": FLOPS_PER_RAY_STEP_EULER}}
+    print(json.dumps({"metric": "geodesic rays/s, RK4 vs explicit Euler, 1000^2 Kerr-Newman",
+                      "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "data": "synthetic", "dtype": "f64",
+                      "workload": "kerr-newman 1000x1000 fp64 (the headline frame)",
+                      "results": lines}), flush=True)
+
+
 def bench_batch(args):
     """All 256 seeded instances (uneven sizes, spins, charges, cameras) traced
     in one persistent launch per step, with the autotuned launch shape."""
@@ -550,13 +608,15 @@ def main():
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter scale)")
-    ap.add_argument("--workload", choices=["frame", "batch", "mixed", "surrogate", "mn"],
+    ap.add_argument("--workload", choices=["frame", "batch", "mixed", "surrogate", "mn",
+                                           "euler"],
                     default="frame",
                     help="frame: the 1000x1000 Kerr-Newman frame (default, the headline "
                          "line); batch: the 256-instance uneven batch in one launch; mixed: "
                          "near-extremal Kerr at 1000^2 and 2048^2, binary64 vs mixed; "
                          "surrogate: 4096^2 frames, surrogate + fallback vs binary64; "
-                         "mn: the 1000x1000 Manko-Novikov frame")
+                         "mn: the 1000x1000 Manko-Novikov frame; euler: RK4 vs explicit "
+                         "Euler on the headline frame")
     ap.add_argument("--train-rays", type=int, default=10_000_000,
                     help="surrogate: labelled rays to train on")
     ap.add_argument("--train-epochs", type=int, default=12)
@@ -592,6 +652,9 @@ def main():
         return
     if args.workload == "mn":
         bench_mn(args)
+        return
+    if args.workload == "euler":
+        bench_euler(args)
         return
 
     import numpy as np

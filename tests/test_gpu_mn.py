@@ -140,3 +140,18 @@ def test_mn_megapixel_sampled(g, ctx):
     print(st, np.bincount(ref["flag"], minlength=4))
     assert st["bit_identical"] == st["n"]
     g.gr_trace_set_integrator(ctx, g.make_integrator(dt=0.01, max_steps=20000))
+
+
+def test_mn_euler_frame_is_bit_exact(g, ctx):
+    case = (M, 0.24, 2.0, 8.0, math.pi / 2, 0.0, 75 * DEG, 20, 14)
+    integ = g.make_integrator(dt=0.01, max_steps=20000, method=g.GR_EULER)
+    g.gr_trace_set_integrator(ctx, integ)
+    gpu = gpu_trace_mn(g, ctx, *case)
+    import oracle
+    res = oracle.trace_frame_mn(*case, dt=0.01, max_steps=20000, want_p0=True, method=1)
+    ref = {"t": res.t, "r": res.r, "theta": res.theta, "phi": res.phi, "p_t": res.p0[:, 0],
+           "p_r": res.pr, "p_theta": res.ptheta, "p_phi": res.p0[:, 3], "flag": res.flag,
+           "steps": res.steps}
+    st = compare(gpu, ref)
+    assert st["bit_identical"] == st["n"]
+    g.gr_trace_set_integrator(ctx, g.make_integrator(dt=0.01, max_steps=20000))

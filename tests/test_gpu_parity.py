@@ -183,3 +183,44 @@ def test_kerr_newman_megapixel_sampled(g, ctx):
     st = compare(sub, ref, angle_tol=0.0, f32=True)
     print(st, "escape", int((ref["flag"] == 1).sum()), "horizon", int((ref["flag"] == 2).sum()))
     assert st["bit_identical"] == st["n"]
+
+
+@pytest.mark.parametrize("case", [
+    (0.5, 0.24, 0.3, 20.0, 80 * DEG, 0.0, 75 * DEG, 37, 23),     # Kerr-Newman, ragged
+    (0.5, 0.49, 0.0, 20.0, 60 * DEG, 0.0, 75 * DEG, 24, 16),     # near-extremal
+])
+def test_euler_frames_are_bit_exact(g, ctx, case):
+    """Explicit Euler steps (Sec. 3.1.1), whatever the launch shape."""
+    integ = g.make_integrator(dt=0.01, max_steps=40000, method=g.GR_EULER)
+    g.gr_trace_set_integrator(ctx, integ)
+    for shape in [None, g.gr_launch(256, 0, 1, 2)]:
+        g.gr_trace_set_launch(ctx, shape)
+        gpu = gpu_trace(ctx, *case)
+        import oracle
+        res = oracle.trace_frame(*case, dt=0.01, max_steps=40000, want_p0=True, method=1)
+        ref = {"t": res.t, "r": res.r, "theta": res.theta, "phi": res.phi,
+               "p_t": res.p0[:, 0], "p_r": res.pr, "p_theta": res.ptheta, "p_phi": res.p0[:, 3],
+               "flag": res.flag, "steps": res.steps}
+        st = compare(gpu, ref)
+        assert st["bit_identical"] == st["n"]
+    g.gr_trace_set_launch(ctx, None)
+    g.gr_trace_set_integrator(ctx, g.make_integrator(dt=0.01, max_steps=20000))
+
+
+def test_euler_is_refused_where_it_is_not_built(g):
+    import torch
+    ctx = g.gr_trace_init(0, g.make_integrator(method=g.GR_EULER))
+    try:
+        out = g.alloc_outputs(16, fields=("r",))
+        inst = g.gr_instance(g.gr_metric(0.5, 0.24, 0.0),
+                             g.gr_camera(20.0, math.pi / 2, 0.0, 75 * DEG, 4, 4), out.struct,
+                             None, -1)
+        with pytest.raises(g.GrError) as e:
+            g.gr_trace_batch(ctx, [inst])
+        assert e.value.code == g.GR_EUNSUPPORTED
+        torch.cuda.synchronize()
+    finally:
+        g.gr_trace_destroy(ctx)
+    with pytest.raises(g.GrError) as e:
+        g.gr_trace_init(0, g.make_integrator(method=g.GR_EULER, precision=g.GR_MIXED))
+    assert e.value.code == g.GR_EUNSUPPORTED
