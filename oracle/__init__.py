@@ -75,6 +75,8 @@ def _load():
         lib.oracle_rhs_mn.argtypes = [d, d, d, d, d, d, d, d, d, d, vp, vp]
         lib.oracle_exp.restype = None
         lib.oracle_exp.argtypes = [vp, i64, vp]
+        lib.oracle_shade.restype = None
+        lib.oracle_shade.argtypes = [i, d, d, vp, vp, vp, vp, i64, vp]
         lib.oracle_mn_consts.restype = None
         lib.oracle_mn_consts.argtypes = [d, d, d, vp]
         _lib = lib
@@ -251,4 +253,17 @@ def exp_def(x) -> np.ndarray:
     x = np.ascontiguousarray(x, dtype=np.float64).ravel()
     out = np.empty_like(x)
     _load().oracle_exp(_ptr(x), x.size, _ptr(out))
+    return out
+
+
+def shade(mode, t, theta, phi, flag, t_max=1.0, band=0.0) -> np.ndarray:
+    """Colours (uint32, bytes R, G, B, A) of traced rays: mode 0 the listing's
+    background bands, mode 1 the exit-time map (see oracle.c)."""
+    flag = np.ascontiguousarray(flag, dtype=np.int8)
+    n = flag.size
+    conv = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)  # noqa: E731
+    t, theta, phi = conv(t), conv(theta), conv(phi)
+    out = np.empty(n, np.uint32)
+    _load().oracle_shade(int(mode), float(t_max), float(band), _ptr(t), _ptr(theta), _ptr(phi),
+                         _ptr(flag), n, _ptr(out))
     return out

@@ -810,3 +810,48 @@ void oracle_mn_consts(double M, double S, double q, double *out3)
     out3[1] = K.k;
     out3[2] = K.beta;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Shading of a traced frame (32-bit colours, bytes R, G, B, A in memory).
+ * Mode 0, background bands (the appendix listing's colour kernel): an
+ * escaped ray is red where sin^2(phi) < 0.01, else green where
+ * cos^2(phi) < 0.01, else blue where sin^2(2 theta) < 0.01, else dark blue;
+ * every other ray is black.
+ * Mode 1, exit time (Sec. 4, the exit-time figures): tau = |t| at the end;
+ * escaped rays with tau < t_max go from dark blue (tau = 0) to cyan, with
+ * level = floor(255 tau / t_max) dimmed to 7/8 on every other band of width
+ * `band` (band > 0); rays that did not escape (captured, step limit) and
+ * escaped rays with tau >= t_max are cyan; invalid rays are black. */
+static uint32_t shade_one(int mode, double t_max, double band, double t, double theta,
+                          double phi, int flag)
+{
+    const uint32_t BLACK = 0xff000000u, CYAN = 0xffffff00u;
+    if (mode == 0) {
+        if (flag != FLAG_ESCAPE) return BLACK;
+        double sp, cp, s2t, c2t;
+        trig_sincos(phi, &sp, &cp);
+        trig_sincos(2.0 * theta, &s2t, &c2t);
+        if (sp * sp < 0.01) return 0xff0000ffu;
+        if (cp * cp < 0.01) return 0xff00ff00u;
+        if (s2t * s2t < 0.01) return 0xffff0000u;
+        return 0xff3c0000u;
+    }
+    if (flag == FLAG_INVALID) return BLACK;
+    if (flag != FLAG_ESCAPE) return CYAN;
+    const double tau = fabs(t);
+    const double u = tau / t_max;
+    if (!(u < 1.0)) return CYAN;
+    uint32_t level = (uint32_t)(u * 255.0);
+    if (band > 0.0 && (((int64_t)(tau / band)) & 1)) level = (level * 7u) / 8u;
+    const uint32_t blue = 64u + (level * 191u) / 255u;
+    return 0xff000000u | (blue << 16) | (level << 8);
+}
+
+void oracle_shade(int mode, double t_max, double band, const double *t, const double *theta,
+                  const double *phi, const int8_t *flag, int64_t n, uint32_t *out)
+{
+    pthread_once(&trig_once, trig_init);
+    for (int64_t k = 0; k < n; ++k)
+        out[k] = shade_one(mode, t_max, band, t ? t[k] : 0.0, theta ? theta[k] : 0.0,
+                           phi ? phi[k] : 0.0, flag[k]);
+}
