@@ -538,6 +538,58 @@ def bench_euler(args):
                       "results": lines}), flush=True)
 
 
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+
+
+def bench_shade(args):
+    """Shading kernels (the listing's background bands, the exit-time map) on
+    a traced 4096x4096 Kerr-Newman frame (binary32 end coordinates): time
+    per frame, pixels/s and algorithmic bytes against the HBM peak."""
+    import numpy as np
+    import torch
+
+    import paper_2310_15183_amd as g
+    w = workload()
+    side = 4096
+    n = side * side
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    ctx = g.gr_trace_init(0, g.make_integrator(dt=0.01, max_steps=20000))
+    out = g.alloc_outputs(n, dtype=g.GR_F32, fields=("t", "r", "theta", "phi"), steps=False)
+    g.gr_trace_frame(ctx, g.gr_metric(w["M"], w["a"], w["Q"]),
+                     g.gr_camera(w["r0"], w["theta0"], w["phi0"], w["fov"], side, side),
+                     out.struct, stream)
+    torch.cuda.synchronize()
+    g.gr_trace_destroy(ctx)
+    rgba = torch.empty(n, dtype=torch.int32, device="cuda")
+    reps = max(args.steps, 10)
+    results = {}
+    # bytes per pixel: binary32 inputs the mode reads + int8 flag + 32-bit colour
+    for name, mode, t_max, band, bpp in [("bands", g.GR_SHADE_BANDS, 1.0, 0.0, 4 + 4 + 1 + 4),
+                                         ("exit_time", g.GR_SHADE_TIME, 80.0, 5.0, 4 + 1 + 4)]:
+        sh = g.gr_shade(mode, t_max, band)
+        for _ in range(max(args.warmup, 2)):
+            g.gr_shade_frame(sh, out.struct, n, rgba, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            g.gr_shade_frame(sh, out.struct, n, rgba, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / reps
+        gbs = bpp * n / sec / 1e9
+        colours = np.unique(rgba.cpu().numpy()).size
+        results[name] = {"ms_per_frame": sec * 1e3, "pixels_per_s": n / sec,
+                         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                                      "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                                      "bytes_per_pixel": bpp},
+                         "distinct_colours": int(colours)}
+    print(json.dumps({"metric": "shaded pixels/s, 4096^2 traced Kerr-Newman frame",
+                      "unit": "pixels/s", "n_gpus": 1, "data": "synthetic", "dtype": "f64",
+                      "workload": "kerr-newman 4096x4096 (dt=0.01, 20000 steps), binary32 "
+                                  "end coordinates", "results": results}), flush=True)
+
+
 def bench_batch(args):
     """All 256 seeded instances (uneven sizes, spins, charges, cameras) traced
     in one persistent launch per step, with the autotuned launch shape."""
@@ -609,14 +661,15 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter scale)")
     ap.add_argument("--workload", choices=["frame", "batch", "mixed", "surrogate", "mn",
-                                           "euler"],
+                                           "euler", "shade"],
                     default="frame",
                     help="frame: the 1000x1000 Kerr-Newman frame (default, the headline "
                          "line); batch: the 256-instance uneven batch in one launch; mixed: "
                          "near-extremal Kerr at 1000^2 and 2048^2, binary64 vs mixed; "
                          "surrogate: 4096^2 frames, surrogate + fallback vs binary64; "
                          "mn: the 1000x1000 Manko-Novikov frame; euler: RK4 vs explicit "
-                         "Euler on the headline frame")
+                         "Euler on the headline frame; shade: the shading kernels on a "
+                         "4096^2 frame")
     ap.add_argument("--train-rays", type=int, default=10_000_000,
                     help="surrogate: labelled rays to train on")
     ap.add_argument("--train-epochs", type=int, default=12)
@@ -655,6 +708,9 @@ def main():
         return
     if args.workload == "euler":
         bench_euler(args)
+        return
+    if args.workload == "shade":
+        bench_shade(args)
         return
 
     import numpy as np

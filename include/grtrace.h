@@ -196,6 +196,32 @@ int gr_trace_frame(gr_ctx *ctx, const gr_metric *m, const gr_camera *c,
 int gr_trace_frame_mn(gr_ctx *ctx, const gr_metric_mn *m, const gr_camera *c,
                       const gr_output *out, void *hip_stream);
 
+/* Shading of traced rays into 32-bit colours (bytes R, G, B, A in memory).
+ * GR_SHADE_BANDS (the appendix listing's colour kernel): an escaped ray is
+ *   red where sin^2(phi) < 0.01, else green where cos^2(phi) < 0.01, else
+ *   blue where sin^2(2 theta) < 0.01, else dark blue (lines on the sky
+ *   sphere); other rays black.  Reads theta, phi, flag.
+ * GR_SHADE_TIME (the exit-time figures of Sec. 4): tau = |t| at the end;
+ *   escaped rays with tau < t_max shade from dark blue to cyan with
+ *   level = floor(255 tau / t_max), dimmed to 7/8 on every other band of
+ *   width `band` when band > 0; rays that did not escape, and tau >= t_max,
+ *   are cyan; invalid rays black.  Reads t, flag.
+ * Decisions are taken in binary64 with the tracer's sin/cos. */
+enum { GR_SHADE_BANDS = 0, GR_SHADE_TIME = 1 };
+
+typedef struct {
+    int32_t mode;
+    double t_max;   /* GR_SHADE_TIME: > 0 */
+    double band;    /* GR_SHADE_TIME: >= 0, 0 = no banding */
+} gr_shade;
+
+/* Colour n rays held in `out` (device arrays of a traced frame or batch
+ * instance, binary64 or binary32) into rgba[n] (device), asynchronously on
+ * the stream.  Errors: GR_EINVAL (NULL arguments, n < 0, a needed output
+ * array missing, t_max <= 0 or band < 0 for GR_SHADE_TIME), GR_EDEVICE. */
+int gr_shade_frame(const gr_shade *shade, const gr_output *out, int64_t n, uint32_t *rgba,
+                   void *hip_stream);
+
 /* Trace n >= 1 instances (possibly different black holes, cameras and image
  * sizes) in one persistent launch fed by one work queue (GR_FP64 only:
  * GR_EUNSUPPORTED for GR_MIXED).  The instance table

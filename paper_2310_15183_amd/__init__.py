@@ -21,6 +21,7 @@ GR_OK, GR_EINVAL, GR_ENOMEM, GR_EDEVICE, GR_EUNSUPPORTED = 0, -1, -2, -3, -4
 GR_FLAG_TIMEOUT, GR_FLAG_ESCAPE, GR_FLAG_HORIZON, GR_FLAG_INVALID = 0, 1, 2, 3
 GR_FP64, GR_MIXED = 0, 1
 GR_RK4, GR_EULER = 0, 1
+GR_SHADE_BANDS, GR_SHADE_TIME = 0, 1
 GR_F64, GR_F32 = 0, 1
 
 
@@ -30,6 +31,10 @@ class gr_metric(ctypes.Structure):
 
 class gr_metric_mn(ctypes.Structure):
     _fields_ = [("M", ctypes.c_double), ("S", ctypes.c_double), ("q", ctypes.c_double)]
+
+
+class gr_shade(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("t_max", ctypes.c_double), ("band", ctypes.c_double)]
 
 
 class gr_camera(ctypes.Structure):
@@ -85,6 +90,7 @@ def _load():
         "gr_trace_frame_mn": (ctypes.c_int, [vp, P(gr_metric_mn), P(gr_camera), P(gr_output),
                                              vp]),
         "gr_trace_batch": (ctypes.c_int, [vp, P(gr_instance), ctypes.c_int32, vp]),
+        "gr_shade_frame": (ctypes.c_int, [P(gr_shade), P(gr_output), ctypes.c_int64, vp, vp]),
         "gr_trace_set_integrator": (ctypes.c_int, [vp, P(gr_integrator)]),
         "gr_trace_set_launch": (ctypes.c_int, [vp, P(gr_launch)]),
         "gr_trace_get_launch": (ctypes.c_int, [vp, P(gr_launch)]),
@@ -124,6 +130,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ["gr_trace_init", "gr_trace_frame", "gr_trace_frame_mn", "gr_trace_batch",
+            "gr_shade_frame",
             "gr_trace_set_integrator",
             "gr_trace_set_launch", "gr_trace_get_launch", "gr_trace_autotune", "gr_trace_destroy",
             "gr_trace_strerror", "gr_trace_last_device_error", "gr_horizon_radius",
@@ -175,6 +182,13 @@ def gr_trace_frame_mn(ctx, metric: gr_metric_mn, camera: gr_camera, out: gr_outp
     _check(_lib.gr_trace_frame_mn(ctx, ctypes.byref(metric), ctypes.byref(camera),
                                   ctypes.byref(out), _stream_handle(stream)),
            "gr_trace_frame_mn")
+
+
+def gr_shade_frame(shade: gr_shade, out: gr_output, n: int, rgba, stream=None):
+    """Colour n traced rays into rgba (a device tensor of n int32/uint32)."""
+    _check(_lib.gr_shade_frame(ctypes.byref(shade), ctypes.byref(out), int(n),
+                               ctypes.c_void_p(rgba.data_ptr()), _stream_handle(stream)),
+           "gr_shade_frame")
 
 
 def gr_trace_batch(ctx, instances, stream=None):

@@ -665,6 +665,25 @@ int gr_trace_frame_mn(gr_ctx* ctx, const gr_metric_mn* m, const gr_camera* c,
     return GR_OK;
 }
 
+int gr_shade_frame(const gr_shade* sh, const gr_output* out, int64_t n, uint32_t* rgba,
+                   void* hip_stream) {
+    if (!sh || !rgba || n < 0) return GR_EINVAL;
+    int rc = check_output(out);
+    if (rc) return rc;
+    if (sh->mode == GR_SHADE_BANDS) {
+        if (!out->theta || !out->phi) return GR_EINVAL;
+    } else if (sh->mode == GR_SHADE_TIME) {
+        if (!out->t || !(sh->t_max > 0.0) || !(sh->band >= 0.0) || !std::isfinite(sh->band))
+            return GR_EINVAL;
+    } else {
+        return GR_EINVAL;
+    }
+    const hipError_t e = gr::launch_shade(sh->mode, out_ptrs(out), out->dtype == GR_F32, n,
+                                          sh->t_max, sh->band, rgba, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return device_error(e, "shade launch");
+    return GR_OK;
+}
+
 int gr_trace_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, void* hip_stream) {
     const int rc = validate_batch(ctx, inst, n);
     if (rc) return rc;

@@ -113,6 +113,11 @@ hipError_t launch_trace_mixed(const FrameArgs& A, double r_plus, bool f32_out,
                               hipStream_t s);
 int occupancy_trace_mixed(int block, bool f32_out);
 
+// Colours of n traced rays (mode 0 background bands, 1 exit time) from the
+// output arrays o (binary32 when f32).
+hipError_t launch_shade(int mode, const OutPtrs& o, bool f32, int64_t n, double t_max,
+                        double band, uint32_t* rgba, hipStream_t s);
+
 // A Manko-Novikov frame, one ray per lane over 8x8 pixel tiles (L.refill
 // must be 0); A.hole is not used.
 hipError_t launch_trace_mn(const FrameArgs& A, const MnHole& K, bool f32_out, bool euler,
