@@ -11,6 +11,7 @@ Flags: 0 timeout (step limit reached), 1 escape (r > escape_factor * r0),
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -51,7 +52,7 @@ def _load():
         vp = ctypes.c_void_p
         lib.oracle_trace_frame.restype = i64
         lib.oracle_trace_frame.argtypes = [d, d, d, d, d, d, d, i, i, d, d, d, d, i,
-                                           vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, i, i]
+                                           vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, i, i, vp]
         lib.oracle_trace_rays.restype = i64
         lib.oracle_trace_rays.argtypes = [d, d, d, d, d, d, d, i, vp, i64,
                                           vp, vp, vp, vp, vp, vp, vp, vp, i]
@@ -75,6 +76,12 @@ def _load():
         lib.oracle_rhs_mn.argtypes = [d, d, d, d, d, d, d, d, d, d, vp, vp]
         lib.oracle_exp.restype = None
         lib.oracle_exp.argtypes = [vp, i64, vp]
+        lib.oracle_redshift.restype = None
+        lib.oracle_redshift.argtypes = [d, d, d, d, d, d, vp, vp, vp, vp, vp, i64, vp]
+        lib.oracle_redshift_mn.restype = None
+        lib.oracle_redshift_mn.argtypes = lib.oracle_redshift.argtypes
+        lib.oracle_disk_orbit.restype = i
+        lib.oracle_disk_orbit.argtypes = [i, d, d, d, d, d, d, vp]
         lib.oracle_shade.restype = None
         lib.oracle_shade.argtypes = [i, d, d, vp, vp, vp, vp, i64, vp]
         lib.oracle_mn_consts.restype = None
@@ -107,6 +114,10 @@ class Result:
     p0: np.ndarray | None = None   # (n, 4) initial covector, frame mode only
 
 
+def _disk(disk):
+    return None if disk is None else np.ascontiguousarray(disk, dtype=np.float64)
+
+
 def _alloc(n):
     return [np.empty(n, np.float64) for _ in range(6)] + [np.empty(n, np.int8),
                                                           np.empty(n, np.int32)]
@@ -114,9 +125,10 @@ def _alloc(n):
 
 def trace_frame(M, a, Q, r0, theta0, phi0, fov, width, height, dt=0.01, eps=1e-8,
                 horizon_norm=1e4, escape_factor=1.5, max_steps=20000, pixels=None,
-                threads=None, want_p0=False, method=0) -> Result:
+                threads=None, want_p0=False, method=0, disk=None) -> Result:
     """Trace the camera rays of a width x height frame (or the listed pixels);
-    method 0 is RK4, 1 explicit Euler."""
+    method 0 is RK4, 1 explicit Euler; disk = (r_in, r_out, half_angle) adds
+    the solid equatorial ring (flag 4 on hitting it)."""
     lib = _load()
     if pixels is not None:
         pixels = np.ascontiguousarray(pixels, dtype=np.int64)
@@ -129,7 +141,7 @@ def trace_frame(M, a, Q, r0, theta0, phi0, fov, width, height, dt=0.01, eps=1e-8
                            horizon_norm, escape_factor, int(max_steps), _ptr(pixels), n,
                            _ptr(t), _ptr(r), _ptr(th), _ptr(ph), _ptr(pr), _ptr(pth), _ptr(p0),
                            _ptr(flag), _ptr(steps), int(threads or default_threads()),
-                           int(method))
+                           int(method), _ptr(_disk(disk)))
     return Result(t, r, th, ph, pr, pth, flag, steps, p0)
 
 
@@ -204,7 +216,7 @@ def sincos(x) -> tuple[np.ndarray, np.ndarray]:
 # ---------------------------------------------------------------- Manko-Novikov
 def trace_frame_mn(M, S, q, r0, theta0, phi0, fov, width, height, dt=0.01, eps=1e-8,
                    horizon_norm=1e4, escape_factor=1.5, max_steps=20000, pixels=None,
-                   threads=None, want_p0=False, method=0) -> Result:
+                   threads=None, want_p0=False, method=0, disk=None) -> Result:
     """trace_frame for the Manko-Novikov spacetime (mass M, spin S, quadrupole
     deviation q; paper Sec. 2.2.3)."""
     lib = _load()
@@ -219,7 +231,7 @@ def trace_frame_mn(M, S, q, r0, theta0, phi0, fov, width, height, dt=0.01, eps=1
                               horizon_norm, escape_factor, int(max_steps), _ptr(pixels), n,
                               _ptr(t), _ptr(r), _ptr(th), _ptr(ph), _ptr(pr), _ptr(pth),
                               _ptr(p0), _ptr(flag), _ptr(steps), int(threads or default_threads()),
-                              int(method))
+                              int(method), _ptr(_disk(disk)))
     return Result(t, r, th, ph, pr, pth, flag, steps, p0)
 
 
@@ -267,3 +279,25 @@ def shade(mode, t, theta, phi, flag, t_max=1.0, band=0.0) -> np.ndarray:
     _load().oracle_shade(int(mode), float(t_max), float(band), _ptr(t), _ptr(theta), _ptr(phi),
                          _ptr(flag), n, _ptr(out))
     return out
+
+
+# ------------------------------------------------------------------ ring redshift
+def redshift(M, a, Q, r0, theta0, r, theta, pt, pph, flag, eps=1e-8, mn=False) -> np.ndarray:
+    """z = lambda_O / lambda_S of rays that ended on the ring (flag 4; NaN for
+    the others); (M, a, Q) are (M, S, q) with mn=True.  See oracle.c."""
+    conv = lambda x: np.ascontiguousarray(x, dtype=np.float64)   # noqa: E731
+    r, theta, pt, pph = conv(r), conv(theta), conv(pt), conv(pph)
+    flag = np.ascontiguousarray(flag, dtype=np.int8)
+    z = np.empty(flag.size)
+    fn = _load().oracle_redshift_mn if mn else _load().oracle_redshift
+    fn(M, a, Q, eps, r0, theta0, _ptr(r), _ptr(theta), _ptr(pt), _ptr(pph), _ptr(flag),
+       flag.size, _ptr(z))
+    return z
+
+
+def disk_orbit(M, a, Q, r, theta=math.pi / 2, eps=1e-8, mn=False):
+    """(S^t, S^phi, dphi/dt) of the ring's orbit at (r, theta), or None."""
+    out = np.empty(3)
+    ok = _load().oracle_disk_orbit(1 if mn else 0, M, a, Q, eps, float(r), float(theta),
+                                   _ptr(out))
+    return tuple(out) if ok else None

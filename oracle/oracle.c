@@ -19,7 +19,9 @@
  * integrated with classical RK4 whose step h = dt / |dq^t/dtau| is fixed for
  * the whole step from the first stage, so that coordinate time advances by
  * about dt per step (or, on request, with explicit Euler and the same h,
- * Sec. 3.1.1).  d_r g and d_theta g are one-sided forward differences
+ * Sec. 3.1.1).  Optionally a solid ring around the equator stops the rays
+ * that enter it (Sec. 3.3.2), and the redshift of its light is computed from
+ * the end states (Sec. 3.3.3, see redshift_rays).  d_r g and d_theta g are one-sided forward differences
  * with step eps; the t and phi derivatives vanish (stationary, axisymmetric),
  * so p_t and p_phi never change.  A ray stops when r exceeds escape_factor
  * times its starting radius (escape), else when |dq^t/dtau| exceeds
@@ -41,7 +43,8 @@
  * and deflection integral, Kerr/Kerr-Newman capture by the radial potential,
  * conserved p_t, p_phi, H and Carter constant, mirror symmetries; for
  * Manko-Novikov: the Kerr limit q = 0, vacuum field equations, asymptotic
- * flatness, the far-field quadrupole, equatorial symmetry, H along rays).
+ * flatness, the far-field quadrupole, equatorial symmetry, H along rays;
+ * the ring: Keplerian orbits, closed-form redshifts, flat-space hits).
  */
 #include <math.h>
 #include <pthread.h>
@@ -49,7 +52,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { FLAG_TIMEOUT = 0, FLAG_ESCAPE = 1, FLAG_HORIZON = 2, FLAG_INVALID = 3 };
+enum { FLAG_TIMEOUT = 0, FLAG_ESCAPE = 1, FLAG_HORIZON = 2, FLAG_INVALID = 3, FLAG_DISK = 4 };
 
 /* Constants of a Manko-Novikov spacetime (mass M, spin S, quadrupole
  * deviation q; see mn_inverse_metric). */
@@ -73,6 +76,10 @@ typedef struct {
     int trig_mode;               /* 0: trig_sincos below; 1: C library sin/cos */
     int kind;                    /* METRIC_KN or METRIC_MN */
     int method;                  /* 0: RK4 (Sec. 3.1.2); 1: explicit Euler (Sec. 3.1.1) */
+    /* solid equatorial ring (Sec. 3.3.2, 3.3.3): a ray stops when a step ends
+     * with disk_r_in <= r <= disk_r_out and |theta - pi/2| <= disk_dth;
+     * off when disk_dth <= 0 */
+    double disk_r_in, disk_r_out, disk_dth;
     mn_consts mn;                /* METRIC_MN only */
 } oracle_params;
 
@@ -421,6 +428,12 @@ static void hamilton_rhs(const oracle_params *P, const double eps_sc[2], double 
     qdot[3] = fma(g[1], pt, g[4] * pph);                       /* dphi/dtau */
 }
 
+static int in_disk(const oracle_params *P, const double q[4])
+{
+    return P->disk_dth > 0.0 && q[1] >= P->disk_r_in && q[1] <= P->disk_r_out &&
+           fabs(q[2] - PIO2_HI) <= P->disk_dth;                 /* PIO2_HI = fl(pi/2) */
+}
+
 static int all_finite(const double q[4], double pr, double pth)
 {
     return isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && isfinite(q[3]) &&
@@ -453,6 +466,7 @@ int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nste
             for (int m = 0; m < 4; ++m) q[m] = fma(h, k1q[m], q[m]);
             pr = fma(h, k1p[0], pr);
             pth = fma(h, k1p[1], pth);
+            if (in_disk(P, q)) { flag = FLAG_DISK; break; }
             if (q[1] > r_esc) { flag = FLAG_ESCAPE; break; }
             if (nu > P->horizon_norm) { flag = FLAG_HORIZON; break; }
             if (!all_finite(q, pr, pth)) { flag = FLAG_INVALID; break; }
@@ -477,6 +491,7 @@ int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nste
         pr = fma(h6, ((k1p[0] + 2.0 * k2p[0]) + 2.0 * k3p[0]) + k4p[0], pr);
         pth = fma(h6, ((k1p[1] + 2.0 * k2p[1]) + 2.0 * k3p[1]) + k4p[1], pth);
 
+        if (in_disk(P, q)) { flag = FLAG_DISK; break; }
         if (q[1] > r_esc) { flag = FLAG_ESCAPE; break; }
         if (nu > P->horizon_norm) { flag = FLAG_HORIZON; break; }
         if (!all_finite(q, pr, pth)) { flag = FLAG_INVALID; break; }
@@ -656,6 +671,7 @@ static oracle_params make_params(double M, double a, double Q, double dt, double
     P.max_steps = max_steps; P.trig_mode = g_trig_mode;
     P.kind = METRIC_KN;
     P.method = 0;
+    P.disk_r_in = P.disk_r_out = P.disk_dth = 0.0;
     memset(&P.mn, 0, sizeof P.mn);
     pthread_once(&trig_once, trig_init);
     return P;
@@ -683,10 +699,12 @@ int64_t oracle_trace_frame(double M, double a, double Q,
                            const int64_t *pixels, int64_t n,
                            double *t, double *r, double *th, double *ph,
                            double *pr, double *pth, double *p0,
-                           int8_t *flag, int32_t *steps, int nthreads, int method)
+                           int8_t *flag, int32_t *steps, int nthreads, int method,
+                           const double *disk)
 {
     oracle_params P = make_params(M, a, Q, dt, eps, horizon_norm, escape_factor, max_steps);
     P.method = method;
+    if (disk) { P.disk_r_in = disk[0]; P.disk_r_out = disk[1]; P.disk_dth = disk[2]; }
     camera_consts C;
     camera_setup(&P, r0, th0, fov, W, H, &C);
     job J;
@@ -760,10 +778,12 @@ int64_t oracle_trace_frame_mn(double M, double S, double q,
                               const int64_t *pixels, int64_t n,
                               double *t, double *r, double *th, double *ph,
                               double *pr, double *pth, double *p0,
-                              int8_t *flag, int32_t *steps, int nthreads, int method)
+                              int8_t *flag, int32_t *steps, int nthreads, int method,
+                              const double *disk)
 {
     oracle_params P = make_params_mn(M, S, q, dt, eps, horizon_norm, escape_factor, max_steps);
     P.method = method;
+    if (disk) { P.disk_r_in = disk[0]; P.disk_r_out = disk[1]; P.disk_dth = disk[2]; }
     camera_consts C;
     camera_setup(&P, r0, th0, fov, W, H, &C);
     job J;
@@ -854,4 +874,91 @@ void oracle_shade(int mode, double t_max, double band, const double *t, const do
     for (int64_t k = 0; k < n; ++k)
         out[k] = shade_one(mode, t_max, band, t ? t[k] : 0.0, theta ? theta[k] : 0.0,
                            phi ? phi[k] : 0.0, flag[k]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Redshift of light from the ring (Sec. 3.3.3 "Redshift").  The ring's matter
+ * moves on circular equatorial-type orbits: p_r = p_theta = 0 and dp/dtau = 0,
+ * so with s_t = -1 its s_phi solves
+ *   s_phi^2 d_r g^{phph} - 2 s_phi d_r g^{tph} + d_r g^{tt} = 0
+ * (d_r by the same forward difference of step eps as the integrator); of the
+ * two roots the orbit with the larger dphi/dt is taken (prograde: the ring
+ * turns toward +phi when the hole does).  s is rescaled to g^{mu nu} s_mu
+ * s_nu = -1 and S^mu = g^{mu nu} s_nu.  A ray whose covector p is scaled to
+ * dt/dtau = -1 at the camera (the camera rays of this tracer) reaches the
+ * ring's matter with frequency p_mu S^mu, and the camera's locally
+ * non-rotating observer receives it with frequency sqrt(-1/g^{tt}) at the
+ * camera, so z = lambda_O / lambda_S = (p_t S^t + p_phi S^phi) /
+ * sqrt(-1/g^{tt}(camera)).  NaN where no timelike circular orbit exists. */
+static int disk_orbit(const oracle_params *P, double r, double theta, double out[3])
+{
+    double g[5], gr[5], s, c;
+    trig_sincos(theta, &s, &c);
+    if (P->kind == METRIC_MN) {
+        mn_inverse_metric(&P->mn, r, c, s * s, g);
+        mn_inverse_metric(&P->mn, r + P->eps, c, s * s, gr);
+    } else {
+        inverse_metric(P, r, s * s, c * c, g);
+        inverse_metric(P, r + P->eps, s * s, c * c, gr);
+    }
+    const double dtt = gr[0] - g[0], dtp = gr[1] - g[1], dpp = gr[4] - g[4];
+    const double disc = dtp * dtp - dpp * dtt;                 /* (B^2 - 4AC) / 4 */
+    if (!(disc >= 0.0) || dpp == 0.0) return 0;
+    const double sq = sqrt(disc);
+    const double x1 = (dtp + sq) / dpp, x2 = (dtp - sq) / dpp; /* s_phi with s_t = -1 */
+    /* dphi/dt = (g^tph s_t + g^phph s_phi) / (g^tt s_t + g^tph s_phi) */
+    const double w1 = fma(g[4], x1, -g[1]) / fma(g[1], x1, -g[0]);
+    const double w2 = fma(g[4], x2, -g[1]) / fma(g[1], x2, -g[0]);
+    const double x = (w1 >= w2) ? x1 : x2;
+    const double norm = fma(g[4] * x, x, fma(-2.0 * g[1], x, g[0]));  /* g^{mu nu} s s */
+    if (!(norm < 0.0)) return 0;
+    const double k = 1.0 / sqrt(-norm);
+    const double st = -k, sp = x * k;
+    out[0] = fma(g[0], st, g[1] * sp);                         /* S^t */
+    out[1] = fma(g[1], st, g[4] * sp);                         /* S^phi */
+    out[2] = out[1] / out[0];                                  /* dphi/dt */
+    return 1;
+}
+
+static void redshift_rays(const oracle_params *P, double r0, double th0, const double *r,
+                          const double *theta, const double *pt, const double *pph,
+                          const int8_t *flag, int64_t n, double *z)
+{
+    double g0[5];
+    metric_at_point(P, r0, th0, g0);
+    const double nu_o = sqrt(-1.0 / g0[0]);
+    for (int64_t k = 0; k < n; ++k) {
+        double S[3];
+        if (flag[k] != FLAG_DISK || !disk_orbit(P, r[k], theta[k], S)) {
+            z[k] = NAN;
+            continue;
+        }
+        z[k] = fma(pt[k], S[0], pph[k] * S[1]) / nu_o;
+    }
+}
+
+void oracle_redshift(double M, double a, double Q, double eps, double r0, double th0,
+                     const double *r, const double *theta, const double *pt, const double *pph,
+                     const int8_t *flag, int64_t n, double *z)
+{
+    oracle_params P = make_params(M, a, Q, 0.01, eps, 1e4, 1.5, 1);
+    redshift_rays(&P, r0, th0, r, theta, pt, pph, flag, n, z);
+}
+
+void oracle_redshift_mn(double M, double S, double q, double eps, double r0, double th0,
+                        const double *r, const double *theta, const double *pt,
+                        const double *pph, const int8_t *flag, int64_t n, double *z)
+{
+    oracle_params P = make_params_mn(M, S, q, 0.01, eps, 1e4, 1.5, 1);
+    redshift_rays(&P, r0, th0, r, theta, pt, pph, flag, n, z);
+}
+
+/* The ring's orbit at (r, theta) for tests: (S^t, S^phi, dphi/dt), 0 if none. */
+int oracle_disk_orbit(int kind, double M, double a_or_S, double Q_or_q, double eps, double r,
+                      double theta, double *out3)
+{
+    oracle_params P = kind == METRIC_MN
+                          ? make_params_mn(M, a_or_S, Q_or_q, 0.01, eps, 1e4, 1.5, 1)
+                          : make_params(M, a_or_S, Q_or_q, 0.01, eps, 1e4, 1.5, 1);
+    return disk_orbit(&P, r, theta, out3);
 }
