@@ -590,6 +590,63 @@ def bench_shade(args):
                                   "end coordinates", "results": results}), flush=True)
 
 
+def bench_disk(args):
+    """Kerr (M=0.5, a=0.98 M) with a solid ring (r in [2, 5], |theta - pi/2| <=
+    0.02) seen from r0=20, theta0=80 deg, fov 50 deg, 1000x1000, dt=0.005,
+    50000 steps: the tracer with and without the ring, and the redshift of
+    the ring's light (paper Sec. 3.3.3)."""
+    import numpy as np
+    import torch
+
+    import paper_2310_15183_amd as g
+    n = 1000 * 1000
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    metric = g.gr_metric(0.5, 0.49, 0.0)
+    cam = g.gr_camera(20.0, math.radians(80.0), 0.0, math.radians(50.0), 1000, 1000)
+    fields = ("t", "r", "theta", "phi", "p_t", "p_phi")
+    res = {}
+    for name, disk in [("no_ring", None), ("ring", (2.0, 5.0, 0.02))]:
+        ctx = g.gr_trace_init(0, g.make_integrator(dt=0.005, max_steps=50000, disk=disk))
+        out = g.alloc_outputs(n, dtype=g.GR_F32, fields=fields)
+        wall, launch_s = time_frames(g, ctx, metric, cam, out, args.steps, args.warmup, stream)
+        steps = int(out["steps"].cpu().numpy().astype(np.int64).sum())
+        flags = out["flag"].cpu().numpy()
+        achieved = FLOPS_PER_RAY_STEP * steps / launch_s / 1e12
+        res[name] = {"ms_per_step": wall / args.steps * 1e3, "rays_per_s": n * args.steps / wall,
+                     "ray_steps": steps, "ring_frac": float((flags == 4).mean()),
+                     "roofline": {"bound": "alu", "achieved": achieved,
+                                  "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": achieved / FP64_PEAK_TFLOPS,
+                                  "flops_per_ray_step": FLOPS_PER_RAY_STEP}}
+        if disk:
+            z = torch.empty(n, dtype=torch.float32, device="cuda")
+            for _ in range(2):
+                g.gr_redshift(ctx, metric, cam, out.struct, n, z, stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 10
+            e0.record(stream)
+            for _ in range(reps):
+                g.gr_redshift(ctx, metric, cam, out.struct, n, z, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) / 1e3 / reps
+            zz = z.cpu().numpy()
+            ok = np.isfinite(zz)
+            bpr = 4 * 4 + 1 + 4              # r, theta, p_t, p_phi (binary32), flag, z
+            gbs = bpr * n / sec / 1e9
+            res["redshift"] = {"ms": sec * 1e3, "rays_per_s": n / sec,
+                               "z_min": float(zz[ok].min()), "z_max": float(zz[ok].max()),
+                               "z_median": float(np.median(zz[ok])),
+                               "roofline": {"bound": "hbm", "achieved": gbs,
+                                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                            "frac": gbs / HBM_PEAK_GBS, "bytes_per_ray": bpr}}
+        g.gr_trace_destroy(ctx)
+    print(json.dumps({"metric": "geodesic rays/s with a solid ring, 1000^2 Kerr a=0.98M",
+                      "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "data": "synthetic", "dtype": "f64", "results": res}), flush=True)
+
+
 def bench_batch(args):
     """All 256 seeded instances (uneven sizes, spins, charges, cameras) traced
     in one persistent launch per step, with the autotuned launch shape."""
@@ -661,7 +718,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (HBM counter scale)")
     ap.add_argument("--workload", choices=["frame", "batch", "mixed", "surrogate", "mn",
-                                           "euler", "shade"],
+                                           "euler", "shade", "disk"],
                     default="frame",
                     help="frame: the 1000x1000 Kerr-Newman frame (default, the headline "
                          "line); batch: the 256-instance uneven batch in one launch; mixed: "
@@ -669,7 +726,7 @@ def main():
                          "surrogate: 4096^2 frames, surrogate + fallback vs binary64; "
                          "mn: the 1000x1000 Manko-Novikov frame; euler: RK4 vs explicit "
                          "Euler on the headline frame; shade: the shading kernels on a "
-                         "4096^2 frame")
+                         "4096^2 frame; disk: Kerr with a solid ring and its redshift")
     ap.add_argument("--train-rays", type=int, default=10_000_000,
                     help="surrogate: labelled rays to train on")
     ap.add_argument("--train-epochs", type=int, default=12)
@@ -711,6 +768,9 @@ def main():
         return
     if args.workload == "shade":
         bench_shade(args)
+        return
+    if args.workload == "disk":
+        bench_disk(args)
         return
 
     import numpy as np

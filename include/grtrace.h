@@ -32,8 +32,9 @@
  *     launched and no output is touched.  Device errors reported by the HIP
  *     runtime come back as GR_EDEVICE (see gr_trace_last_device_error).
  *   - Flags written per ray: GR_FLAG_TIMEOUT (0, step limit), GR_FLAG_ESCAPE
- *     (1), GR_FLAG_HORIZON (2), GR_FLAG_INVALID (3, non-finite state).
- *     Escape is tested before horizon, both after the update.
+ *     (1), GR_FLAG_HORIZON (2), GR_FLAG_INVALID (3, non-finite state),
+ *     GR_FLAG_DISK (4, stopped in the ring of gr_integrator).  After each
+ *     update the ring is tested first, then escape, then horizon.
  *   - GR_FP64 results are a deterministic function of the inputs: they do not
  *     depend on the launch configuration, the stream, or which other pixels
  *     are traced in the same call.
@@ -55,7 +56,13 @@ enum {
     GR_EUNSUPPORTED = -4   /* valid request this build does not support */
 };
 
-enum { GR_FLAG_TIMEOUT = 0, GR_FLAG_ESCAPE = 1, GR_FLAG_HORIZON = 2, GR_FLAG_INVALID = 3 };
+enum {
+    GR_FLAG_TIMEOUT = 0,
+    GR_FLAG_ESCAPE = 1,
+    GR_FLAG_HORIZON = 2,
+    GR_FLAG_INVALID = 3,
+    GR_FLAG_DISK = 4
+};
 
 /* Integrator precision.
  * GR_FP64: binary64 throughout; results are reproducible bit for bit.
@@ -119,6 +126,13 @@ typedef struct {
     int32_t max_steps;
     int32_t precision;
     int32_t method;
+    /* Solid ring around the equator (Sec. 3.3.2: objects are volumes a ray
+     * stops in; Fig. KerrDisk): a ray whose step ends with
+     * disk_r_in <= r <= disk_r_out and |theta - pi/2| <= disk_half_angle
+     * stops with GR_FLAG_DISK.  Off when disk_half_angle == 0; otherwise
+     * 0 <= disk_r_in < disk_r_out and 0 < disk_half_angle < pi/2.  Binary64
+     * frames only (batches, the surrogate and GR_MIXED: GR_EUNSUPPORTED). */
+    double disk_r_in, disk_r_out, disk_half_angle;
 } gr_integrator;
 
 /* Per-ray outputs (device pointers).  The eight floating-point arrays hold
@@ -195,6 +209,26 @@ int gr_trace_frame(gr_ctx *ctx, const gr_metric *m, const gr_camera *c,
  * context), GR_EDEVICE. */
 int gr_trace_frame_mn(gr_ctx *ctx, const gr_metric_mn *m, const gr_camera *c,
                       const gr_output *out, void *hip_stream);
+
+/* Redshift z = lambda_O / lambda_S of the light of the ring (Sec. 3.3.3) for
+ * n traced rays: the ring's matter moves on circular orbits (p_r = p_theta =
+ * 0, dp/dtau = 0; with s_t = -1, s_phi solves s_phi^2 d_r g^{phph}
+ * - 2 s_phi d_r g^{tph} + d_r g^{tt} = 0, d_r by the context's forward
+ * difference; the root turning faster toward +phi; normalised to
+ * g^{mu nu} s s = -1), and the camera's locally non-rotating observer
+ * receives the ray: z = (p_t S^t + p_phi S^phi) / sqrt(-1/g^{tt}(camera))
+ * with S^mu = g^{mu nu} s_nu at the ray's end.  Rays without GR_FLAG_DISK,
+ * and rings inside the photon orbit (no timelike circular orbit), get NaN.
+ * Reads r, theta, p_t, p_phi and flag of `out` (traced with camera c; the
+ * dtype of out), writes z[n] (device, the same dtype).  Errors: GR_EINVAL
+ * (NULL arguments, a needed array missing, n < 0, invalid metric/camera),
+ * GR_EDEVICE. */
+int gr_redshift(gr_ctx *ctx, const gr_metric *m, const gr_camera *c, const gr_output *out,
+                int64_t n, void *z, void *hip_stream);
+
+/* gr_redshift for a Manko-Novikov spacetime. */
+int gr_redshift_mn(gr_ctx *ctx, const gr_metric_mn *m, const gr_camera *c,
+                   const gr_output *out, int64_t n, void *z, void *hip_stream);
 
 /* Shading of traced rays into 32-bit colours (bytes R, G, B, A in memory).
  * GR_SHADE_BANDS (the appendix listing's colour kernel): an escaped ray is

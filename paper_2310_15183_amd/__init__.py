@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgrtrace.so")
 
 GR_OK, GR_EINVAL, GR_ENOMEM, GR_EDEVICE, GR_EUNSUPPORTED = 0, -1, -2, -3, -4
-GR_FLAG_TIMEOUT, GR_FLAG_ESCAPE, GR_FLAG_HORIZON, GR_FLAG_INVALID = 0, 1, 2, 3
+GR_FLAG_TIMEOUT, GR_FLAG_ESCAPE, GR_FLAG_HORIZON, GR_FLAG_INVALID, GR_FLAG_DISK = 0, 1, 2, 3, 4
 GR_FP64, GR_MIXED = 0, 1
 GR_RK4, GR_EULER = 0, 1
 GR_SHADE_BANDS, GR_SHADE_TIME = 0, 1
@@ -47,7 +47,8 @@ class gr_integrator(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("fd_eps", ctypes.c_double),
                 ("horizon_norm", ctypes.c_double), ("escape_factor", ctypes.c_double),
                 ("max_steps", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("method", ctypes.c_int32)]
+                ("method", ctypes.c_int32), ("disk_r_in", ctypes.c_double),
+                ("disk_r_out", ctypes.c_double), ("disk_half_angle", ctypes.c_double)]
 
 
 class gr_output(ctypes.Structure):
@@ -91,6 +92,10 @@ def _load():
                                              vp]),
         "gr_trace_batch": (ctypes.c_int, [vp, P(gr_instance), ctypes.c_int32, vp]),
         "gr_shade_frame": (ctypes.c_int, [P(gr_shade), P(gr_output), ctypes.c_int64, vp, vp]),
+        "gr_redshift": (ctypes.c_int, [vp, P(gr_metric), P(gr_camera), P(gr_output),
+                                       ctypes.c_int64, vp, vp]),
+        "gr_redshift_mn": (ctypes.c_int, [vp, P(gr_metric_mn), P(gr_camera), P(gr_output),
+                                          ctypes.c_int64, vp, vp]),
         "gr_trace_set_integrator": (ctypes.c_int, [vp, P(gr_integrator)]),
         "gr_trace_set_launch": (ctypes.c_int, [vp, P(gr_launch)]),
         "gr_trace_get_launch": (ctypes.c_int, [vp, P(gr_launch)]),
@@ -130,7 +135,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ["gr_trace_init", "gr_trace_frame", "gr_trace_frame_mn", "gr_trace_batch",
-            "gr_shade_frame",
+            "gr_shade_frame", "gr_redshift", "gr_redshift_mn",
             "gr_trace_set_integrator",
             "gr_trace_set_launch", "gr_trace_get_launch", "gr_trace_autotune", "gr_trace_destroy",
             "gr_trace_strerror", "gr_trace_last_device_error", "gr_horizon_radius",
@@ -191,6 +196,14 @@ def gr_shade_frame(shade: gr_shade, out: gr_output, n: int, rgba, stream=None):
            "gr_shade_frame")
 
 
+def gr_redshift(ctx, metric, camera: gr_camera, out: gr_output, n: int, z, stream=None):
+    """Ring redshift of n traced rays into z (a device tensor of out's dtype);
+    metric is a gr_metric or a gr_metric_mn."""
+    fn = _lib.gr_redshift_mn if isinstance(metric, gr_metric_mn) else _lib.gr_redshift
+    _check(fn(ctx, ctypes.byref(metric), ctypes.byref(camera), ctypes.byref(out), int(n),
+              ctypes.c_void_p(z.data_ptr()), _stream_handle(stream)), "gr_redshift")
+
+
 def gr_trace_batch(ctx, instances, stream=None):
     arr = (gr_instance * len(instances))(*instances)
     _check(_lib.gr_trace_batch(ctx, arr, len(instances), _stream_handle(stream)),
@@ -249,9 +262,12 @@ def gr_horizon_radius(metric: gr_metric) -> float:
 
 # ---------------------------------------------------------------- marshalling helpers
 def make_integrator(dt=0.01, fd_eps=1e-8, horizon_norm=1e4, escape_factor=1.5,
-                    max_steps=20000, precision=GR_FP64, method=None) -> gr_integrator:
+                    max_steps=20000, precision=GR_FP64, method=None,
+                    disk=None) -> gr_integrator:
+    """disk = (r_in, r_out, half_angle) adds the solid equatorial ring."""
+    d = (0.0, 0.0, 0.0) if disk is None else tuple(float(v) for v in disk)
     return gr_integrator(dt, fd_eps, horizon_norm, escape_factor, int(max_steps),
-                         int(precision), GR_RK4 if method is None else int(method))
+                         int(precision), GR_RK4 if method is None else int(method), *d)
 
 
 FIELDS = ("t", "r", "theta", "phi", "p_t", "p_r", "p_theta", "p_phi")

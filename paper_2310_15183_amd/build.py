@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libgrtrace.so")
 ARCH = os.environ.get("GRTRACE_ARCH", "gfx950")
 
 SOURCES = ["api.hip", "trace_fp64.hip", "trace_mixed.hip", "trace_mn.hip", "shade.hip",
-           "order.hip", "mlp.hip", "mlp_api.hip", "surrogate.hip"]
+           "redshift.hip", "order.hip", "mlp.hip", "mlp_api.hip", "surrogate.hip"]
 HEADERS = ["grmath.h", "internal.h", "step_fp64.h", "mlp_internal.h", "surrogate_internal.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -65,8 +65,17 @@ int check_integrator(const gr_integrator* in) {
     if (in->precision != GR_FP64 && in->precision != GR_MIXED) return GR_EINVAL;
     if (in->method != GR_RK4 && in->method != GR_EULER) return GR_EINVAL;
     if (in->method == GR_EULER && in->precision != GR_FP64) return GR_EUNSUPPORTED;
+    if (in->disk_half_angle != 0.0) {
+        if (!(in->disk_half_angle > 0.0 && in->disk_half_angle < M_PI / 2)) return GR_EINVAL;
+        if (!(finite(in->disk_r_in) && finite(in->disk_r_out) && in->disk_r_in >= 0.0 &&
+              in->disk_r_in < in->disk_r_out))
+            return GR_EINVAL;
+        if (in->precision != GR_FP64) return GR_EUNSUPPORTED;
+    }
     return GR_OK;
 }
+
+bool has_disk(const gr_integrator& in) { return in.disk_half_angle > 0.0; }
 
 // Flat space (M = Q = 0, any a: oblate spheroidal coordinates) has no horizon.
 bool is_flat(const gr_metric* m) { return m->M == 0.0 && m->Q == 0.0; }
@@ -187,6 +196,9 @@ gr::Integrator device_integrator(const gr_integrator& in) {
     I.scale = -0.5 * (1.0 / in.fd_eps);
     I.hnorm = in.horizon_norm;
     I.esc_factor = in.escape_factor;
+    I.disk_r_in = in.disk_r_in;
+    I.disk_r_out = in.disk_r_out;
+    I.disk_dth = in.disk_half_angle;
     I.max_steps = in.max_steps;
     return I;
 }
@@ -226,7 +238,7 @@ int64_t instance_rays(const gr_instance* I) {
 
 int validate_batch(const gr_ctx* ctx, const gr_instance* inst, int32_t n) {
     if (!ctx || !inst || n < 1) return GR_EINVAL;
-    if (ctx->integ.method != GR_RK4) return GR_EUNSUPPORTED;
+    if (ctx->integ.method != GR_RK4 || has_disk(ctx->integ)) return GR_EUNSUPPORTED;
     for (int32_t k = 0; k < n; ++k) {
         const gr_instance* I = &inst[k];
         int rc = check_metric(&I->metric);
@@ -512,6 +524,38 @@ int grow_surrogate_ws(gr_ctx* c, int64_t n) {
     return GR_OK;
 }
 
+// Validation of a Manko-Novikov spacetime and a camera outside its horizon.
+int check_mn(const gr_metric_mn* m, const gr_camera* c, gr::MnHole* K) {
+    if (!m || !c) return GR_EINVAL;
+    if (!(std::isfinite(m->M) && std::isfinite(m->S) && std::isfinite(m->q))) return GR_EINVAL;
+    if (!(m->M > 0.0) || m->S == 0.0 || !(fabs(m->S) < m->M * m->M)) return GR_EINVAL;
+    *K = gr::make_mn_hole(m->M, m->S, m->q);
+    if (!(K->k > 0.0 && std::isfinite(K->beta))) return GR_EINVAL;
+    if (!(std::isfinite(c->r0) && std::isfinite(c->theta0) && std::isfinite(c->phi0) &&
+          std::isfinite(c->fov)))
+        return GR_EINVAL;
+    if (!(c->r0 > m->M + K->k)) return GR_EINVAL;
+    if (!(c->theta0 > 0.0 && c->theta0 < M_PI) || !(c->fov > 0.0 && c->fov < M_PI))
+        return GR_EINVAL;
+    if (c->width < 1 || c->height < 1 ||
+        (int64_t)c->width * (int64_t)c->height > ((int64_t)1 << 40))
+        return GR_EINVAL;
+    return GR_OK;
+}
+
+int redshift_common(gr_ctx* ctx, const gr::Hole& H, const gr::MnHole& K, bool mn, double nu_o,
+                    const gr_output* out, int64_t n, void* z, void* hip_stream) {
+    int rc = check_output(out);
+    if (rc) return rc;
+    if (!z || n < 0 || !out->r || !out->theta || !out->p_t || !out->p_phi) return GR_EINVAL;
+    DeviceGuard guard(ctx->device);
+    const hipError_t e = gr::launch_redshift(H, K, mn, device_integrator(ctx->integ), nu_o,
+                                             out_ptrs(out), out->dtype == GR_F32, n, z,
+                                             (hipStream_t)hip_stream);
+    if (e != hipSuccess) return device_error(e, "redshift launch");
+    return GR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -610,37 +654,27 @@ int gr_trace_frame(gr_ctx* ctx, const gr_metric* m, const gr_camera* c, const gr
         return GR_OK;
     }
     gr::LaunchShape L = frame_shape(ctx, A, f32);
-    const bool euler = ctx->integ.method == GR_EULER;
-    if (euler && L.refill) {
-        // Euler steps exist in the one-ray-per-lane kernel only
+    const bool euler = ctx->integ.method == GR_EULER, disk = has_disk(ctx->integ);
+    if ((euler || disk) && L.refill) {
+        // Euler steps and the ring exist in the one-ray-per-lane kernel only
         const int64_t tiles = ((int64_t)c->width + 7) / 8 * (((int64_t)c->height + 7) / 8);
         if (tiles > INT32_MAX) return GR_EUNSUPPORTED;
         L.block = 64;
         L.refill = 0;
         L.grid = (int)tiles;
     }
-    e = gr::launch_trace_fp64(A, f32, euler, L, ctx->counter, (hipStream_t)hip_stream);
+    e = gr::launch_trace_fp64(A, f32, euler, disk, L, ctx->counter, (hipStream_t)hip_stream);
     if (e != hipSuccess) return device_error(e, "trace_fp64 launch");
     return GR_OK;
 }
 
 int gr_trace_frame_mn(gr_ctx* ctx, const gr_metric_mn* m, const gr_camera* c,
                       const gr_output* out, void* hip_stream) {
-    if (!ctx || !m || !c) return GR_EINVAL;
-    if (!(std::isfinite(m->M) && std::isfinite(m->S) && std::isfinite(m->q))) return GR_EINVAL;
-    if (!(m->M > 0.0) || m->S == 0.0 || !(fabs(m->S) < m->M * m->M)) return GR_EINVAL;
-    const gr::MnHole K = gr::make_mn_hole(m->M, m->S, m->q);
-    if (!(K.k > 0.0 && std::isfinite(K.beta))) return GR_EINVAL;
-    if (!(std::isfinite(c->r0) && std::isfinite(c->theta0) && std::isfinite(c->phi0) &&
-          std::isfinite(c->fov)))
-        return GR_EINVAL;
-    if (!(c->r0 > m->M + K.k)) return GR_EINVAL;
-    if (!(c->theta0 > 0.0 && c->theta0 < M_PI) || !(c->fov > 0.0 && c->fov < M_PI))
-        return GR_EINVAL;
-    if (c->width < 1 || c->height < 1 ||
-        (int64_t)c->width * (int64_t)c->height > ((int64_t)1 << 40))
-        return GR_EINVAL;
-    int rc = check_output(out);
+    if (!ctx) return GR_EINVAL;
+    gr::MnHole K;
+    int rc = check_mn(m, c, &K);
+    if (rc) return rc;
+    rc = check_output(out);
     if (rc) return rc;
     if (ctx->integ.precision != GR_FP64) return GR_EUNSUPPORTED;
     DeviceGuard guard(ctx->device);
@@ -659,10 +693,38 @@ int gr_trace_frame_mn(gr_ctx* ctx, const gr_metric_mn* m, const gr_camera* c,
     if (blocks > INT32_MAX) return GR_EINVAL;
     L.grid = (int)blocks;
     const hipError_t e = gr::launch_trace_mn(A, K, out->dtype == GR_F32,
-                                             ctx->integ.method == GR_EULER, L,
-                                             (hipStream_t)hip_stream);
+                                             ctx->integ.method == GR_EULER,
+                                             has_disk(ctx->integ), L, (hipStream_t)hip_stream);
     if (e != hipSuccess) return device_error(e, "trace_mn launch");
     return GR_OK;
+}
+
+int gr_redshift(gr_ctx* ctx, const gr_metric* m, const gr_camera* c, const gr_output* out,
+                int64_t n, void* z, void* hip_stream) {
+    if (!ctx) return GR_EINVAL;
+    int rc = check_metric(m);
+    if (!rc) rc = check_camera(m, c);
+    if (rc) return rc;
+    const gr::Hole H = gr::make_hole(m->M, m->a, m->Q);
+    const gr::InvMetric g0 =
+        gr::inverse_metric(H, gr::radial_terms(H, c->r0), gr::theta_terms(H, c->theta0));
+    gr::MnHole K;
+    memset(&K, 0, sizeof K);
+    return redshift_common(ctx, H, K, false, sqrt(-1.0 / g0.tt), out, n, z, hip_stream);
+}
+
+int gr_redshift_mn(gr_ctx* ctx, const gr_metric_mn* m, const gr_camera* c, const gr_output* out,
+                   int64_t n, void* z, void* hip_stream) {
+    if (!ctx) return GR_EINVAL;
+    gr::MnHole K;
+    const int rc = check_mn(m, c, &K);
+    if (rc) return rc;
+    double s, co;
+    gr::sincos_def(c->theta0, s, co);
+    const gr::InvMetric g0 = gr::mn_inverse_metric<gr::IeeeDiv>(K, c->r0, co, s * s);
+    gr::Hole H;
+    memset(&H, 0, sizeof H);
+    return redshift_common(ctx, H, K, true, sqrt(-1.0 / g0.tt), out, n, z, hip_stream);
 }
 
 int gr_shade_frame(const gr_shade* sh, const gr_output* out, int64_t n, uint32_t* rgba,
@@ -811,7 +873,8 @@ int gr_surrogate_frame(gr_ctx* ctx, gr_mlp* mlp, const gr_metric* m, const gr_ca
     // a turn of max_gain pixel widths (fov / width) as a chord of unit vectors
     const double turn = std::min((double)max_gain * (c->fov / c->width), M_PI);
     const float chord = max_gain > 0.0f ? (float)(2.0 * sin(0.5 * turn)) : 0.0f;
-    if (ctx->integ.precision != GR_FP64 || ctx->integ.method != GR_RK4) return GR_EUNSUPPORTED;
+    if (ctx->integ.precision != GR_FP64 || ctx->integ.method != GR_RK4 || has_disk(ctx->integ))
+        return GR_EUNSUPPORTED;
     if (gr_mlp_device_of(mlp) != ctx->device) return GR_EINVAL;
     const int64_t npix = (int64_t)c->width * c->height;
     if (npix > ((int64_t)1 << 31) - 1) return GR_EINVAL;

@@ -28,6 +28,7 @@ struct Integrator {
     double dt, eps, inv_eps, hnorm, esc_factor;
     double sin_eps, cos_eps;   // sincos_def(eps): angle addition for theta + eps
     double scale;              // -0.5 * (1/eps): p-dot = scale * sum of differences
+    double disk_r_in, disk_r_out, disk_dth;   // the ring (used by kernels built with it)
     int32_t max_steps;
 };
 
@@ -100,7 +101,7 @@ size_t frame_order_temp(int64_t npix);
 hipError_t launch_reset_counter(unsigned long long* counter, hipStream_t s);
 
 // FP64 frame tracer.  f32_out selects binary32 outputs.
-hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, bool euler,
+hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, bool euler, bool disk,
                              const LaunchShape& L, unsigned long long* counter, hipStream_t s);
 
 // Workgroups of `block` threads that fit on one CU for the FP64 tracer.
@@ -121,7 +122,14 @@ hipError_t launch_shade(int mode, const OutPtrs& o, bool f32, int64_t n, double 
 // A Manko-Novikov frame, one ray per lane over 8x8 pixel tiles (L.refill
 // must be 0); A.hole is not used.
 hipError_t launch_trace_mn(const FrameArgs& A, const MnHole& K, bool f32_out, bool euler,
-                           const LaunchShape& L, hipStream_t s);
+                           bool disk, const LaunchShape& L, hipStream_t s);
+
+// Ring redshift of n rays (flag GR_FLAG_DISK; NaN otherwise) from the output
+// arrays o, with the camera observer's frequency nu_o = sqrt(-1/g^tt(camera)).
+// mn selects the Manko-Novikov metric K, else the Kerr-Newman hole H.
+hipError_t launch_redshift(const Hole& H, const MnHole& K, bool mn, const Integrator& in,
+                           double nu_o, const OutPtrs& o, bool f32, int64_t n, void* z,
+                           hipStream_t s);
 
 // All instances of a batch in one launch: persistent (L.refill), or one ray
 // per lane over the waves of B.wfirsts.

@@ -215,8 +215,14 @@ static __device__ __forceinline__ double mn_step(const MnHole& K, const Integrat
     else return rk4_generic(f, in, y);
 }
 
+// Exit tests after an update: the ring (kernels built with DISK), escape,
+// horizon, a non-finite state, the step limit.
+template <bool DISK = false>
 static __device__ __forceinline__ int exit_flag(const Integrator& in, double r_esc, const Ray& y,
                                          double nu, int s) {
+    if (DISK && y.r >= in.disk_r_in && y.r <= in.disk_r_out &&
+        fabs(y.th - PI2_HI) <= in.disk_dth)
+        return GR_FLAG_DISK;
     if (y.r > r_esc) return GR_FLAG_ESCAPE;
     if (nu > in.hnorm) return GR_FLAG_HORIZON;
     if (!finite6(y)) return GR_FLAG_INVALID;

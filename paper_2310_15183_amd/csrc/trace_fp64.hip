@@ -25,8 +25,8 @@ namespace {
 using namespace detail;
 
 // One lane, one ray (static_ray); the grid covers every ray.  EULER selects
-// explicit Euler steps in place of RK4.
-template <typename T, bool EULER>
+// explicit Euler steps in place of RK4, DISK adds the ring's exit test.
+template <typename T, bool EULER, bool DISK>
 __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
     int64_t k, pix;
     if (!static_ray(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, k, pix)) return;
@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
     while (f == RUNNING) {
         const double nu = kn_step<EULER>(A.hole, A.in, y);
         ++s;
-        f = exit_flag(A.in, A.r_esc, y, nu, s);
+        f = exit_flag<DISK>(A.in, A.r_esc, y, nu, s);
     }
     write_ray<T>(A.out, k, y, f, s);
 }
@@ -197,17 +197,25 @@ hipError_t launch_reset_counter(unsigned long long* counter, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, bool euler,
+template <bool EULER, bool DISK>
+static hipError_t launch_static(const FrameArgs& A, bool f32_out, const LaunchShape& L,
+                                hipStream_t s) {
+    if (f32_out)
+        hipLaunchKernelGGL((trace_fp64_static<float, EULER, DISK>), dim3(L.grid), dim3(L.block),
+                           0, s, A);
+    else
+        hipLaunchKernelGGL((trace_fp64_static<double, EULER, DISK>), dim3(L.grid), dim3(L.block),
+                           0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, bool euler, bool disk,
                              const LaunchShape& L, unsigned long long* counter, hipStream_t s) {
-    if (euler) {                                  // one ray per lane only
+    if (euler || disk) {                          // one ray per lane only
         if (L.refill) return hipErrorInvalidValue;
-        if (f32_out)
-            hipLaunchKernelGGL((trace_fp64_static<float, true>), dim3(L.grid), dim3(L.block), 0,
-                               s, A);
-        else
-            hipLaunchKernelGGL((trace_fp64_static<double, true>), dim3(L.grid), dim3(L.block),
-                               0, s, A);
-        return hipGetLastError();
+        if (euler && disk) return launch_static<true, true>(A, f32_out, L, s);
+        if (euler) return launch_static<true, false>(A, f32_out, L, s);
+        return launch_static<false, true>(A, f32_out, L, s);
     }
     if (L.refill) {
         hipError_t e = launch_reset_counter(counter, s);
@@ -219,12 +227,7 @@ hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, bool euler,
             hipLaunchKernelGGL(trace_fp64_refill<double>, dim3(L.grid), dim3(L.block), 0, s, A,
                                counter);
     } else {
-        if (f32_out)
-            hipLaunchKernelGGL((trace_fp64_static<float, false>), dim3(L.grid), dim3(L.block), 0,
-                               s, A);
-        else
-            hipLaunchKernelGGL((trace_fp64_static<double, false>), dim3(L.grid), dim3(L.block), 0,
-                               s, A);
+        return launch_static<false, false>(A, f32_out, L, s);
     }
     return hipGetLastError();
 }

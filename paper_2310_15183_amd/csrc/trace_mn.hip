@@ -18,7 +18,7 @@ struct MnArgs {
     MnHole mn;
 };
 
-template <typename T, bool EULER>
+template <typename T, bool EULER, bool DISK>
 __global__ void __launch_bounds__(256) trace_mn_static(const MnArgs X) {
     const FrameArgs& A = X.f;
     int64_t k, pix;
@@ -30,28 +30,33 @@ __global__ void __launch_bounds__(256) trace_mn_static(const MnArgs X) {
     while (f == RUNNING) {
         const double nu = mn_step<EULER>(X.mn, A.in, y);
         ++s;
-        f = exit_flag(A.in, A.r_esc, y, nu, s);
+        f = exit_flag<DISK>(A.in, A.r_esc, y, nu, s);
     }
     write_ray<T>(A.out, k, y, f, s);
 }
 
 }  // namespace
 
+template <bool EULER, bool DISK>
+static hipError_t launch_mn(const MnArgs& X, bool f32_out, const LaunchShape& L, hipStream_t s) {
+    if (f32_out)
+        hipLaunchKernelGGL((trace_mn_static<float, EULER, DISK>), dim3(L.grid), dim3(L.block), 0,
+                           s, X);
+    else
+        hipLaunchKernelGGL((trace_mn_static<double, EULER, DISK>), dim3(L.grid), dim3(L.block), 0,
+                           s, X);
+    return hipGetLastError();
+}
+
 hipError_t launch_trace_mn(const FrameArgs& A, const MnHole& K, bool f32_out, bool euler,
-                           const LaunchShape& L, hipStream_t s) {
+                           bool disk, const LaunchShape& L, hipStream_t s) {
     MnArgs X;
     X.f = A;
     X.mn = K;
-    if (f32_out && euler)
-        hipLaunchKernelGGL((trace_mn_static<float, true>), dim3(L.grid), dim3(L.block), 0, s, X);
-    else if (f32_out)
-        hipLaunchKernelGGL((trace_mn_static<float, false>), dim3(L.grid), dim3(L.block), 0, s, X);
-    else if (euler)
-        hipLaunchKernelGGL((trace_mn_static<double, true>), dim3(L.grid), dim3(L.block), 0, s, X);
-    else
-        hipLaunchKernelGGL((trace_mn_static<double, false>), dim3(L.grid), dim3(L.block), 0, s,
-                           X);
-    return hipGetLastError();
+    if (euler && disk) return launch_mn<true, true>(X, f32_out, L, s);
+    if (euler) return launch_mn<true, false>(X, f32_out, L, s);
+    if (disk) return launch_mn<false, true>(X, f32_out, L, s);
+    return launch_mn<false, false>(X, f32_out, L, s);
 }
 
 }  // namespace gr
