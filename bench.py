@@ -115,6 +115,37 @@ def time_frames(g, ctx, metric, cam, out, steps, warmup, stream):
     return wall, sum(s.elapsed_time(e) for s, e in zip(starts, ends)) / 1e3 / steps
 
 
+def frames_in_flight(g, w, n_rays, ray_steps, nstreams=3, nframes=6):
+    """Binary64 frames on several streams at once (one context each): the
+    tail of one frame overlaps the next.  Frame throughput, not the
+    single-frame figure."""
+    import torch
+    streams = [torch.cuda.Stream() for _ in range(nstreams)]
+    ctxs = [g.gr_trace_init(0, g.make_integrator(dt=w["dt"], fd_eps=w["fd_eps"],
+                                                 horizon_norm=w["horizon_norm"],
+                                                 escape_factor=w["escape_factor"],
+                                                 max_steps=w["max_steps"]))
+            for _ in range(nstreams)]
+    outs = [g.alloc_outputs(n_rays, dtype=g.GR_F32, fields=("t", "r", "theta", "phi"))
+            for _ in range(nstreams)]
+    metric = g.gr_metric(w["M"], w["a"], w["Q"])
+    cam = g.gr_camera(w["r0"], w["theta0"], w["phi0"], w["fov"], w["W"], w["H"])
+    for j in range(nstreams):
+        g.gr_trace_frame(ctxs[j], metric, cam, outs[j].struct, streams[j])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(nframes):
+        j = k % nstreams
+        g.gr_trace_frame(ctxs[j], metric, cam, outs[j].struct, streams[j])
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / nframes
+    for c in ctxs:
+        g.gr_trace_destroy(c)
+    return {"streams": nstreams, "frames": nframes, "ms_per_frame": sec * 1e3,
+            "rays_per_s": n_rays / sec,
+            "frac": FLOPS_PER_RAY_STEP * ray_steps / sec / 1e12 / FP64_PEAK_TFLOPS}
+
+
 def traced_frame(g, w, stream, precision):
     """Trace the frame once with every output in binary64 (host arrays)."""
     import torch
@@ -438,6 +469,27 @@ def bench_mn(args):
     ray_steps = int(steps.sum())
     g.gr_trace_destroy(ctx)
     achieved = FLOPS_PER_RAY_STEP_MN * ray_steps / launch_s / 1e12
+    # frames in flight on three streams: one frame's tail of trapped rays
+    # overlaps the next frame's bulk
+    nstreams, nframes = 3, 6
+    streams = [torch.cuda.Stream() for _ in range(nstreams)]
+    ctxs = [g.gr_trace_init(0, g.make_integrator(dt=w["dt"], fd_eps=w["fd_eps"],
+                                                 horizon_norm=w["horizon_norm"],
+                                                 escape_factor=w["escape_factor"],
+                                                 max_steps=w["max_steps"]))
+            for _ in range(nstreams)]
+    outs = [g.alloc_outputs(n, dtype=g.GR_F32, fields=("t", "r", "theta", "phi"))
+            for _ in range(nstreams)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(nframes):
+        j = k % nstreams
+        g.gr_trace_frame_mn(ctxs[j], metric, cam, outs[j].struct, streams[j])
+    torch.cuda.synchronize()
+    pipe_s = (time.perf_counter() - t0) / nframes
+    for c in ctxs:
+        g.gr_trace_destroy(c)
+    del outs
     result = {
         "metric": "geodesic rays/s, Manko-Novikov 1000x1000 (binary64)",
         "value": n * args.steps / wall, "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
@@ -457,6 +509,10 @@ def bench_mn(args):
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
                      "kernel": "trace_mn", "flops_per_ray_step": FLOPS_PER_RAY_STEP_MN,
                      "launch_ms": launch_s * 1e3},
+        "pipelined": {"streams": nstreams, "frames": nframes, "ms_per_frame": pipe_s * 1e3,
+                      "rays_per_s": n / pipe_s,
+                      "frac": FLOPS_PER_RAY_STEP_MN * ray_steps / pipe_s / 1e12
+                      / FP64_PEAK_TFLOPS},
         "cpu_baseline": None,
     }
     if not args.skip_cpu_baseline:
@@ -838,6 +894,7 @@ def main():
     }
     if not args.skip_variants:
         ref = traced_frame(g, w, stream, g.GR_FP64)
+        result["variants"]["fp64_in_flight"] = frames_in_flight(g, w, n, ray_steps)
         result["variants"]["mixed"] = mixed_variant(g, w, args, stream, result["value"], ref)
         net, info = train_surrogate(g, args)
         sur = surrogate_variant(g, net, w, args, stream, result["value"], ref)

@@ -140,7 +140,9 @@ static __device__ __forceinline__ bool finite6(const Ray& y) {
 }
 
 // One RK4 step with the right-hand side rhs_at(r, theta, p_r, p_theta);
-// returns nu = |dt/dtau| of the first stage.
+// returns nu = |dt/dtau| of the first stage.  The weighted sums
+// ((k1 + 2 k2) + 2 k3) + k4 are taken as fma(2, k, s): 2 k is exact, so this
+// is the same single rounding as s + 2 k.
 template <class Rhs>
 static __device__ __forceinline__ double rk4_generic(const Rhs& rhs_at, const Integrator& in,
                                                      Ray& y) {
@@ -151,12 +153,12 @@ static __device__ __forceinline__ double rk4_generic(const Rhs& rhs_at, const In
     double st = k.qt, sr = k.qr, sh = k.qh, sp = k.qp, spr = k.pr, sph = k.ph;
     k = rhs_at(fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), fma(hh, k.pr, y.pr),
                fma(hh, k.ph, y.pth));
-    st = st + 2.0 * k.qt; sr = sr + 2.0 * k.qr; sh = sh + 2.0 * k.qh; sp = sp + 2.0 * k.qp;
-    spr = spr + 2.0 * k.pr; sph = sph + 2.0 * k.ph;
+    st = fma(2.0, k.qt, st); sr = fma(2.0, k.qr, sr); sh = fma(2.0, k.qh, sh);
+    sp = fma(2.0, k.qp, sp); spr = fma(2.0, k.pr, spr); sph = fma(2.0, k.ph, sph);
     k = rhs_at(fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), fma(hh, k.pr, y.pr),
                fma(hh, k.ph, y.pth));
-    st = st + 2.0 * k.qt; sr = sr + 2.0 * k.qr; sh = sh + 2.0 * k.qh; sp = sp + 2.0 * k.qp;
-    spr = spr + 2.0 * k.pr; sph = sph + 2.0 * k.ph;
+    st = fma(2.0, k.qt, st); sr = fma(2.0, k.qr, sr); sh = fma(2.0, k.qh, sh);
+    sp = fma(2.0, k.qp, sp); spr = fma(2.0, k.pr, spr); sph = fma(2.0, k.ph, sph);
     k = rhs_at(fma(h, k.qr, y.r), fma(h, k.qh, y.th), fma(h, k.pr, y.pr), fma(h, k.ph, y.pth));
     st = st + k.qt; sr = sr + k.qr; sh = sh + k.qh; sp = sp + k.qp;
     spr = spr + k.pr; sph = sph + k.ph;
