@@ -22,6 +22,12 @@ SOURCES = ["api.hip", "trace_fp64.hip", "trace_mixed.hip", "trace_mn.hip", "shad
            "redshift.hip", "order.hip", "mlp.hip", "mlp_api.hip", "surrogate.hip"]
 HEADERS = ["grmath.h", "internal.h", "step_fp64.h", "mlp_internal.h", "surrogate_internal.h"]
 
+# Per-source options.  The Manko-Novikov step is a long block of binary64
+# arithmetic whose trapped rays leave at most two long waves per SIMD at the
+# end of a frame; the instruction-level-parallel scheduler (231 VGPRs, two
+# waves per SIMD) makes each of those waves run faster.
+EXTRA = {"trace_mn.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -42,7 +48,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd))
         _run(cmd)
