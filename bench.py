@@ -41,7 +41,8 @@ STRICT_TURN = 0.05                # surrogate_strict: also re-trace where neighb
 MIN_IMPACT = 1.2                  # surrogate_strict: also re-trace escaping rays with b < 1.2 b_c
 KERNEL_SOURCES = ["paper_2310_15183_amd/csrc/trace_fp64.hip",
                   "paper_2310_15183_amd/csrc/step_fp64.h",
-                  "paper_2310_15183_amd/csrc/grmath.h"]
+                  "paper_2310_15183_amd/csrc/grmath.h",
+                  "paper_2310_15183_amd/build.py"]   # build options change the code too
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "trace_fp64_kn1000_traffic.md")
 
 

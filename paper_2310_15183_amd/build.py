@@ -22,11 +22,15 @@ SOURCES = ["api.hip", "trace_fp64.hip", "trace_mixed.hip", "trace_mn.hip", "shad
            "redshift.hip", "order.hip", "mlp.hip", "mlp_api.hip", "surrogate.hip"]
 HEADERS = ["grmath.h", "internal.h", "step_fp64.h", "mlp_internal.h", "surrogate_internal.h"]
 
-# Per-source options.  The Manko-Novikov step is a long block of binary64
-# arithmetic whose trapped rays leave at most two long waves per SIMD at the
-# end of a frame; the instruction-level-parallel scheduler (231 VGPRs, two
-# waves per SIMD) makes each of those waves run faster.
-EXTRA = {"trace_mn.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+# Per-source options.  The binary64 tracers' steps are long blocks of
+# arithmetic whose three metric evaluations per stage are independent; where
+# few waves are left (the trapped Manko-Novikov rays at the end of a frame,
+# the short fallback lists of the surrogate) the frame time is one wave's
+# latency, and LLVM's instruction-level-parallel scheduler, which interleaves
+# the independent chains, shortens it.  Throughput-bound launches are not
+# slower with it; the mixed-precision tracer is, and keeps the default.
+EXTRA = {src: ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
+         for src in ("trace_fp64.hip", "trace_mn.hip")}
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
