@@ -119,3 +119,55 @@ def test_ring_arguments(g):
         assert e.value.code == g.GR_EUNSUPPORTED
     finally:
         g.gr_trace_destroy(ctx)
+
+
+def _sample(flag, side, stride, n_edge, seed):
+    """Every stride-th pixel in both axes plus n_edge seeded pixels where the
+    flag changes between vertical neighbours."""
+    f = flag.reshape(side, side)
+    edge = np.zeros_like(f, bool)
+    edge[1:-1, 1:-1] = (f[1:-1, 1:-1] != f[:-2, 1:-1]) | (f[1:-1, 1:-1] != f[2:, 1:-1])
+    edge_pix = np.nonzero(edge.ravel())[0]
+    edge_pix = np.random.default_rng(seed).choice(edge_pix, size=min(n_edge, edge_pix.size),
+                                                  replace=False)
+    grid = (np.arange(stride // 2, side, stride)[:, None] * side +
+            np.arange(stride // 2, side, stride)[None, :]).ravel()
+    return np.unique(np.concatenate([grid, edge_pix]))
+
+
+def test_ring_megapixel_sampled(g):
+    """The ringed frame in the benchmark's configuration (Kerr M=0.5, a=0.49,
+    Q=0, r0=20, theta0=80 deg, fov 50 deg, 1000x1000, dt=0.005, 50000 steps,
+    ring r in [2, 5], |theta - pi/2| <= 0.02, binary32 outputs): the oracle
+    re-traces every 32nd pixel in both axes plus 256 pixels on flag edges
+    (ring rims, shadow edge); then the redshift of the whole frame against the
+    oracle's on the same sampled rays."""
+    import torch
+
+    import oracle
+    side, r0, th0, fov = 1000, 20.0, 80 * DEG, 50 * DEG
+    params = (M, 0.49, 0.0)
+    ctx = g.gr_trace_init(0, g.make_integrator(dt=0.005, max_steps=50000, disk=DISK))
+    try:
+        metric, cam = g.gr_metric(*params), g.gr_camera(r0, th0, 0.0, fov, side, side)
+        out = g.alloc_outputs(side * side, dtype=g.GR_F32,
+                              fields=("t", "r", "theta", "phi", "p_t", "p_phi"))
+        g.gr_trace_frame(ctx, metric, cam, out.struct)
+        z = torch.empty(side * side, dtype=torch.float32, device="cuda")
+        g.gr_redshift(ctx, metric, cam, out.struct, side * side, z)
+        torch.cuda.synchronize()
+        gpu = {k: v.cpu().numpy() for k, v in out.tensors.items()}
+        z = z.cpu().numpy()
+    finally:
+        g.gr_trace_destroy(ctx)
+    assert 0.05 < (gpu["flag"] == 4).mean() < 0.2
+    pix = _sample(gpu["flag"], side, 32, 256, seed=11)
+    res = oracle.trace_frame(*params, r0, th0, 0.0, fov, side, side, dt=0.005, max_steps=50000,
+                             pixels=pix, want_p0=True, disk=DISK)
+    st = compare({k: v[pix] for k, v in gpu.items()}, _ref(res), angle_tol=0.0, f32=True)
+    assert st["bit_identical"] == st["n"]
+    assert (res.flag == 4).sum() > 100
+    h = {k: gpu[k][pix].astype(np.float64) for k in ("r", "theta", "p_t", "p_phi")}
+    want = oracle.redshift(*params, r0, th0, h["r"], h["theta"], h["p_t"], h["p_phi"],
+                           gpu["flag"][pix]).astype(np.float32)
+    np.testing.assert_array_equal(z[pix], want)

@@ -36,6 +36,8 @@ def _pair(g, case, dt=0.005, max_steps=50000):
     ("near-extremal Kerr", (0.5, 0.49, 0.0, 20.0, 60 * DEG, 0.0, 75 * DEG, 320, 320)),
     ("Kerr-Newman", (0.5, 0.24, 0.3, 20.0, 80 * DEG, 0.0, 75 * DEG, 320, 320)),
     ("wide Kerr-Newman, far camera", (0.5, 0.3, 0.35, 45.0, 30 * DEG, 0.4, 90 * DEG, 200, 150)),
+    ("the benchmark's 1000x1000 Kerr-Newman frame",
+     (0.5, 0.24, 0.3, 20.0, 80 * DEG, 0.0, 75 * DEG, 1000, 1000)),
 ])
 def test_mixed_accuracy_against_fp64(g, name, case):
     ref, mix = _pair(g, case)
