@@ -120,3 +120,15 @@ def test_method_and_ring_accepted():
                   g.make_integrator(disk=(0.0, 5.0, 0.02)),
                   g.make_integrator(method=g.GR_EULER, disk=(2.0, 5.0, 0.3))]:
         assert g.gr_trace_validate(m, c, integ, o) == g.GR_OK
+
+
+@pytest.mark.parametrize("w,h,code", [
+    (1 << 20, 1 << 20, 0),                  # 2^40 rays: the largest frame accepted
+    ((1 << 20) + 1, 1 << 20, -1),           # one column more
+    ((1 << 31) - 1, 1, 0),                  # widest single row
+    (1, (1 << 31) - 1, 0),                  # tallest single column
+    (1, 1, 0)])                             # a single pixel
+def test_frame_size_limits(w, h, code):
+    m, c, i, o = _valid()
+    c.width, c.height = w, h
+    assert g.gr_trace_validate(m, c, i, o) == (g.GR_OK if code == 0 else g.GR_EINVAL)

@@ -286,3 +286,27 @@ def test_euler_is_refused_where_it_is_not_built(g):
     with pytest.raises(g.GrError) as e:
         g.gr_trace_init(0, g.make_integrator(method=g.GR_EULER, precision=g.GR_MIXED))
     assert e.value.code == g.GR_EUNSUPPORTED
+
+
+def test_oversized_frames_are_refused_before_launch(g, ctx):
+    """A 2^20 x 2^20 frame (the largest the ABI accepts) has 2^34 8x8 tiles,
+    more than one launch's grid holds.  Frames that exist only in the
+    one-ray-per-lane form (Euler steps, the ring, the Manko-Novikov metric)
+    refuse it before anything is launched: the (deliberately tiny) output
+    arrays stay untouched."""
+    import torch
+    side = 1 << 20
+    out = g.alloc_outputs(64, fields=("t",))
+    out["flag"].fill_(77)
+    cam = g.gr_camera(20.0, 80 * DEG, 0.0, 75 * DEG, side, side)
+    for integ in (g.make_integrator(method=g.GR_EULER), g.make_integrator(disk=(2.0, 5.0, 0.02))):
+        g.gr_trace_set_integrator(ctx, integ)
+        with pytest.raises(g.GrError) as e:
+            g.gr_trace_frame(ctx, g.gr_metric(0.5, 0.24, 0.3), cam, out.struct)
+        assert e.value.code == g.GR_EUNSUPPORTED
+    g.gr_trace_set_integrator(ctx, g.make_integrator())
+    with pytest.raises(g.GrError) as e:
+        g.gr_trace_frame_mn(ctx, g.gr_metric_mn(0.5, 0.24, 2.0), cam, out.struct)
+    assert e.value.code == g.GR_EINVAL
+    torch.cuda.synchronize()
+    assert np.all(out["flag"].cpu().numpy() == 77)
