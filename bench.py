@@ -79,6 +79,19 @@ def recorded_traffic(units_per_launch):
     return float(m_bytes.group(1))
 
 
+def host_cpu_model():
+    """The host CPU's model name (Linux), else the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(w, stride, threads):
     """Time the CPU oracle on every stride-th pixel in both axes of the same
     frame; returns rays/s and the sample's mean steps."""
@@ -911,11 +924,18 @@ def main():
         import oracle
         threads = min(16, oracle.default_threads())
         rays_s, nsample, mean_steps, secs = cpu_baseline(w, args.cpu_stride, threads)
+        stride1 = 4 * args.cpu_stride
+        rays_s1, nsample1, _, secs1 = cpu_baseline(w, stride1, 1)
         result["cpu_baseline"] = {
             "value": rays_s, "unit": "rays/s", "cores": threads, "kind": "oracle",
             "sample": f"every {args.cpu_stride}th pixel in both axes of the same frame "
                       f"({nsample} rays, mean {mean_steps:.0f} steps/ray vs "
                       f"{ray_steps / n:.0f} for the full frame), {secs:.1f} s",
+            "single_thread": {"value": rays_s1, "unit": "rays/s",
+                              "sample": f"every {stride1}th pixel in both axes "
+                                        f"({nsample1} rays), {secs1:.1f} s"},
+            "host": {"cpu": host_cpu_model(), "nproc": os.cpu_count(),
+                     "compiled": "gcc " + " ".join(oracle.CFLAGS)},
         }
     print(json.dumps(result), flush=True)
 
