@@ -204,9 +204,14 @@ int gr_trace_frame(gr_ctx *ctx, const gr_metric *m, const gr_camera *c,
  * exits, the metric evaluated in full at the three points of every stage
  * (its exponentials from their series definition, so results are
  * reproducible bit for bit).  One ray per lane over 8x8 pixel tiles whatever
- * the context's launch shape.  The camera needs r0 > M + k.  Errors:
- * GR_EINVAL (validation, NULL arguments), GR_EUNSUPPORTED (a GR_MIXED
- * context), GR_EDEVICE. */
+ * the context's launch shape.  With a step limit of 4096 or more, rays still
+ * running after a quarter of it are parked in context workspace (60 bytes per
+ * pixel, at most 2^22 pixels, grown with hipMalloc on first need) and a
+ * second launch on the same stream continues them all together; the results
+ * are those of one uninterrupted integration.  If the workspace cannot be
+ * allocated, one launch does everything.  The camera needs r0 > M + k.
+ * Errors: GR_EINVAL (validation, NULL arguments, a frame of more than
+ * 2^31 - 1 tiles), GR_EUNSUPPORTED (a GR_MIXED context), GR_EDEVICE. */
 int gr_trace_frame_mn(gr_ctx *ctx, const gr_metric_mn *m, const gr_camera *c,
                       const gr_output *out, void *hip_stream);
 

@@ -42,6 +42,12 @@ struct gr_ctx {
     int32_t* ord_vals;                // 2 x cap
     void* ord_temp;
     size_t ord_temp_bytes;
+    // rays parked between the two launches of a Manko-Novikov frame (grown on demand)
+    int64_t pk_cap;                   // rays it holds
+    double* pk_y;                     // 6 x cap: t, r, theta, phi, p_r, p_theta
+    int32_t* pk_steps;
+    int64_t* pk_pix;
+    unsigned long long* pk_count;
 };
 
 namespace {
@@ -507,6 +513,38 @@ int grow_order_ws(gr_ctx* c, int64_t n) {
     return GR_OK;
 }
 
+void free_park_ws(gr_ctx* c) {
+    hipFree(c->pk_y);
+    hipFree(c->pk_steps);
+    hipFree(c->pk_pix);
+    hipFree(c->pk_count);
+    c->pk_y = nullptr;
+    c->pk_steps = nullptr;
+    c->pk_pix = nullptr;
+    c->pk_count = nullptr;
+    c->pk_cap = 0;
+}
+
+// Room for n parked rays (at most PARK_MAX; rays past it finish in the first launch).
+constexpr int64_t PARK_MAX = (int64_t)1 << 22;
+
+int grow_park_ws(gr_ctx* c, int64_t n) {
+    n = std::min(n, PARK_MAX);
+    if (n <= c->pk_cap) return GR_OK;
+    hipDeviceSynchronize();
+    free_park_ws(c);
+    bool ok = hipMalloc(&c->pk_y, 6 * n * sizeof(double)) == hipSuccess &&
+              hipMalloc(&c->pk_steps, n * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&c->pk_pix, n * sizeof(int64_t)) == hipSuccess &&
+              hipMalloc(&c->pk_count, sizeof(unsigned long long)) == hipSuccess;
+    if (!ok) {
+        free_park_ws(c);
+        return GR_ENOMEM;
+    }
+    c->pk_cap = n;
+    return GR_OK;
+}
+
 int grow_surrogate_ws(gr_ctx* c, int64_t n) {
     if (n <= c->sw_cap) return GR_OK;
     hipDeviceSynchronize();
@@ -692,9 +730,28 @@ int gr_trace_frame_mn(gr_ctx* ctx, const gr_metric_mn* m, const gr_camera* c,
     const int64_t blocks = ((int64_t)c->width + 7) / 8 * (((int64_t)c->height + 7) / 8);
     if (blocks > INT32_MAX) return GR_EINVAL;
     L.grid = (int)blocks;
+    // Park the rays still running after a quarter of the step limit and
+    // continue them together in a second launch (without the workspace, one
+    // launch does everything).
+    gr::Parked park;
+    memset(&park, 0, sizeof park);
+    gr::LaunchShape L2 = L;
+    const int32_t cap = ctx->integ.max_steps >= 4096 ? ctx->integ.max_steps / 4 : 0;
+    if (cap > 0 && grow_park_ws(ctx, nray) == GR_OK) {
+        park.y = ctx->pk_y;
+        park.steps = ctx->pk_steps;
+        park.pix = ctx->pk_pix;
+        park.count = ctx->pk_count;
+        park.capacity = std::min(nray, ctx->pk_cap);
+        park.cap = cap;
+        const int64_t resident =
+            (int64_t)std::max(1, gr::occupancy_trace_mn_resume(64)) * ctx->num_cu;
+        L2.grid = (int)std::max<int64_t>(1, std::min(resident, (park.capacity + 63) / 64));
+    }
     const hipError_t e = gr::launch_trace_mn(A, K, out->dtype == GR_F32,
                                              ctx->integ.method == GR_EULER,
-                                             has_disk(ctx->integ), L, (hipStream_t)hip_stream);
+                                             has_disk(ctx->integ), L, park, L2,
+                                             (hipStream_t)hip_stream);
     if (e != hipSuccess) return device_error(e, "trace_mn launch");
     return GR_OK;
 }
@@ -945,6 +1002,7 @@ int gr_trace_destroy(gr_ctx* ctx) {
     DeviceGuard guard(ctx->device);
     free_surrogate_ws(ctx);
     free_order_ws(ctx);
+    free_park_ws(ctx);
     hipFree(ctx->counter);
     hipFree(ctx->table);
     hipFree(ctx->firsts);

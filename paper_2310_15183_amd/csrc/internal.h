@@ -119,10 +119,27 @@ int occupancy_trace_mixed(int block, bool f32_out);
 hipError_t launch_shade(int mode, const OutPtrs& o, bool f32, int64_t n, double t_max,
                         double band, uint32_t* rgba, hipStream_t s);
 
+// Rays a one-ray-per-lane launch parks after `cap` steps (0: none) for a
+// second launch to continue: structure-of-arrays state of up to `capacity`
+// rays (y: t, r, theta, phi, p_r, p_theta, each `capacity` long), their step
+// counts and pixels, and the number parked (zeroed by the launcher).  Rays
+// beyond the capacity are finished by the first launch.
+struct Parked {
+    double* y;
+    int32_t* steps;
+    int64_t* pix;
+    unsigned long long* count;
+    int64_t capacity;
+    int32_t cap;
+};
+
 // A Manko-Novikov frame, one ray per lane over 8x8 pixel tiles (L.refill
-// must be 0); A.hole is not used.
+// must be 0), then (park.cap > 0) the parked rays in a persistent launch of
+// shape L2; A.hole is not used.
 hipError_t launch_trace_mn(const FrameArgs& A, const MnHole& K, bool f32_out, bool euler,
-                           bool disk, const LaunchShape& L, hipStream_t s);
+                           bool disk, const LaunchShape& L, const Parked& park,
+                           const LaunchShape& L2, hipStream_t s);
+int occupancy_trace_mn_resume(int block);
 
 // Ring redshift of n rays (flag GR_FLAG_DISK; NaN otherwise) from the output
 // arrays o, with the camera observer's frequency nu_o = sqrt(-1/g^tt(camera)).

@@ -155,3 +155,46 @@ def test_mn_euler_frame_is_bit_exact(g, ctx):
     st = compare(gpu, ref)
     assert st["bit_identical"] == st["n"]
     g.gr_trace_set_integrator(ctx, g.make_integrator(dt=0.01, max_steps=20000))
+
+
+def test_mn_parked_rays_continue_bit_exact(g, ctx):
+    """With a step limit of 4096 or more the tracer parks the rays still running
+    after a quarter of it and continues them in a second launch.  On the
+    listing's spacetime at dt=0.01 and 20000 steps, many rays pass 5000 steps
+    (some to the limit): every field stays bit-identical to the oracle's
+    single loop."""
+    case = (M, 0.24, 2.0, 8.0, math.pi / 2, 0.0, 75 * DEG, 40, 32)
+    integ = g.make_integrator(dt=0.01, max_steps=20000)
+    gpu = gpu_trace_mn(g, ctx, *case)
+    assert (gpu["steps"] > 5000).sum() > 50          # rays of the second launch
+    assert (gpu["flag"] == g.GR_FLAG_TIMEOUT).sum() > 10
+    st = compare(gpu, oracle_trace_mn(*case, integ))
+    assert st["bit_identical"] == st["n"]
+
+
+def test_mn_more_parked_rays_than_room(g, ctx):
+    """A frame of 2100 x 2048 = 4.3e6 pixels whose rays all outlast a quarter
+    of the 4096-step limit (camera at r0 = 50, escape at 75, dt = 0.01): more
+    rays want parking than the 2^22 the workspace holds, and those past it are
+    finished by the first launch.  Sampled rays from the first and last tiles
+    and across the frame are bit-identical to the oracle."""
+    import torch
+    W, H = 2100, 2048
+    case = (M, 0.24, 2.0, 50.0, 70 * DEG, 0.0, 60 * DEG, W, H)
+    integ = g.make_integrator(dt=0.01, max_steps=4096)
+    g.gr_trace_set_integrator(ctx, integ)
+    out = g.alloc_outputs(W * H, fields=g.FIELDS)
+    g.gr_trace_frame_mn(ctx, g.gr_metric_mn(*case[:3]), g.gr_camera(*case[3:]), out.struct)
+    torch.cuda.synchronize()
+    steps = out["steps"].cpu().numpy()
+    assert np.all(steps > 1024)                      # every ray passed the parking point
+    rng = np.random.default_rng(5)
+    tile_rows = [0, 1, H - 2, H - 1]
+    pix = np.unique(np.concatenate([
+        np.array([j * W + i for j in tile_rows for i in (0, 7, W // 2, W - 9, W - 1)]),
+        rng.choice(W * H, size=300, replace=False)]))
+    gpu = {k: v[torch.as_tensor(pix, device="cuda")].cpu().numpy()
+           for k, v in out.tensors.items()}
+    st = compare(gpu, oracle_trace_mn(*case, integ, pixels=pix))
+    assert st["bit_identical"] == st["n"]
+    g.gr_trace_set_integrator(ctx, g.make_integrator(dt=0.01, max_steps=20000))
