@@ -286,15 +286,21 @@ __device__ __forceinline__ void frame_layer(__bf16* act, const __bf16* __restric
         for (int t = 0; t < FR / 16; ++t) acc[i][t] = f4{0.f, 0.f, 0.f, 0.f};
     const bf8* A = reinterpret_cast<const bf8*>(frag);
     const int rn = lane & 15, kq = (lane >> 4) * 8;
-#pragma unroll 2
+    // the A fragments of the next k-step load while this one's products run
+    bf8 an[4];
+    for (int i = 0; i < 4; ++i) an[i] = A[((4 * wave + i) * KS + 0) * 64 + lane];
+#pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-        bf8 a[4], b[FR / 16];
-        for (int i = 0; i < 4; ++i) a[i] = A[((4 * wave + i) * KS + ks) * 64 + lane];
-        for (int t = 0; t < FR / 16; ++t)
-            b[t] = *reinterpret_cast<const bf8*>(act + (16 * t + rn) * LDA + 32 * ks + kq);
-        for (int i = 0; i < 4; ++i)
-            for (int t = 0; t < FR / 16; ++t)
-                acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[t], acc[i][t], 0, 0, 0);
+        bf8 a[4];
+        for (int i = 0; i < 4; ++i) a[i] = an[i];
+        if (ks + 1 < KS)
+            for (int i = 0; i < 4; ++i) an[i] = A[((4 * wave + i) * KS + ks + 1) * 64 + lane];
+        for (int t = 0; t < FR / 16; ++t) {
+            const bf8 b =
+                *reinterpret_cast<const bf8*>(act + (16 * t + rn) * LDA + 32 * ks + kq);
+            for (int i = 0; i < 4; ++i)
+                acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][t], 0, 0, 0);
+        }
     }
     __syncthreads();                       // every wave has read this layer's inputs
     // lane holds features f .. f + 3 (f = 16 (4 wave + i) + 4 (lane / 16)) of ray 16 t + lane % 16
