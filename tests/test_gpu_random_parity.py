@@ -85,3 +85,68 @@ def test_random_draw_is_bit_exact(g, seed):
            "steps": res.steps}
     st = compare(gpu, ref, angle_tol=0.0, f32=f32)
     assert st["bit_identical"] == st["n"]
+
+
+BATCH_DRAWS = 16
+
+
+@pytest.mark.parametrize("seed", range(BATCH_DRAWS))
+def test_random_batch_is_bit_exact(g, seed):
+    """Random batches: 1-6 Kerr-Newman instances of random spacetimes, cameras
+    and small ragged frames, some as pixel lists (possibly empty or with
+    repeated pixels), traced in one gr_trace_batch call under a random launch
+    shape; every instance bit-identical to the oracle."""
+    import torch
+
+    import oracle
+    rng = np.random.default_rng(7000 + seed)
+    dt = float(rng.choice([0.02, 0.05]))
+    max_steps = int(rng.choice([137, 3000]))
+    f32 = bool(rng.random() < 0.5)
+    ctx = g.gr_trace_init(0, g.make_integrator(dt=dt, max_steps=max_steps))
+    keep, insts, outs, spec = [], [], [], []
+    try:
+        if rng.random() < 0.7:
+            g.gr_trace_set_launch(ctx, g.gr_launch(int(rng.choice([64, 128, 256])),
+                                                   int(rng.integers(0, 5)),
+                                                   int(rng.integers(0, 2)),
+                                                   int(rng.integers(0, 3))))
+        for _ in range(int(rng.integers(1, 7))):
+            M = 0.5
+            a = float(rng.uniform(0.0, 0.98)) * M
+            Q = float(rng.uniform(0.0, 0.95)) * math.sqrt(M * M - a * a)
+            cam = (float(rng.uniform(6.0, 25.0)) * M, float(rng.uniform(5, 175)) * math.pi / 180,
+                   float(rng.uniform(-math.pi, math.pi)), float(rng.uniform(20, 100)) * math.pi / 180,
+                   int(rng.integers(1, 20)), int(rng.integers(1, 14)))
+            pix = None
+            if rng.random() < 0.4:
+                pix = rng.integers(0, cam[4] * cam[5], int(rng.integers(0, 40))).astype(np.int32)
+            n = cam[4] * cam[5] if pix is None else len(pix)
+            o = g.alloc_outputs(n, dtype=g.GR_F32 if f32 else g.GR_F64, fields=g.FIELDS)
+            p_ptr, npix = None, -1
+            if pix is not None:
+                t = torch.as_tensor(pix, device="cuda")
+                keep.append(t)
+                p_ptr, npix = (t.data_ptr() or None), len(pix)
+            insts.append(g.gr_instance(g.gr_metric(M, a, Q), g.gr_camera(*cam), o.struct, p_ptr,
+                                       npix))
+            outs.append(o)
+            spec.append(((M, a, Q), cam, pix))
+        print("batch draw", seed, dt, max_steps, f32, [(s[0], s[1], None if s[2] is None else
+                                                        len(s[2])) for s in spec], flush=True)
+        g.gr_trace_batch(ctx, insts)
+        torch.cuda.synchronize()
+        got = [{k: v.cpu().numpy() for k, v in o.tensors.items()} for o in outs]
+    finally:
+        g.gr_trace_destroy(ctx)
+    for (hole, cam, pix), res in zip(spec, got):
+        if pix is not None and len(pix) == 0:
+            assert res["flag"].size == 0
+            continue
+        r = oracle.trace_frame(*hole, *cam, dt=dt, max_steps=max_steps, pixels=pix,
+                               want_p0=True)
+        ref = {"t": r.t, "r": r.r, "theta": r.theta, "phi": r.phi, "p_t": r.p0[:, 0],
+               "p_r": r.pr, "p_theta": r.ptheta, "p_phi": r.p0[:, 3], "flag": r.flag,
+               "steps": r.steps}
+        st = compare(res, ref, angle_tol=0.0, f32=f32)
+        assert st["bit_identical"] == st["n"]
