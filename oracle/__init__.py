@@ -2,8 +2,23 @@
 
 Only the test suite, ``__graft_entry__.smoke()`` and the benchmark's
 ``cpu_baseline`` leg may import this package.  It shares no code with the HIP
-implementation in ``paper_2310_15183_amd``; see ``oracle.c`` for the
-arithmetic and the passages of the paper each step follows.
+implementation in ``paper_2310_15183_amd``.
+
+Two forms of the same method:
+
+* ``form="listing"`` (the default, ``listing.c``): the paper's method as its
+  plain definitions -- the metric evaluated afresh at every finite-difference
+  point with the C library's sin/cos/exp and its own divisions, differences
+  divided by eps, the full 4x4x4 contraction, textbook RK4 on (q, p), a
+  camera built from the locally non-rotating frame's vectors.  ``probe=n``
+  re-runs each ray from n one-ulp perturbations of its start and reports its
+  end-angle sensitivity, the yardstick for comparing two correct
+  implementations whose roundings differ.
+* ``form="twin"`` (``oracle.c``): the kernel-twin form, one fixed IEEE
+  operation sequence (series sin/cos, shared reciprocals with Newton steps,
+  angle addition for theta + eps, one scaling by -1/(2 eps)) that the HIP
+  kernels evaluate bit for bit.  Its arithmetic is tied to the listing form
+  by a per-ray bound at the measured sensitivity, not assumed.
 
 Flags: 0 timeout (step limit reached), 1 escape (r > escape_factor * r0),
 2 horizon (|dt/dtau| > horizon_norm), 3 invalid (non-finite state).
@@ -19,7 +34,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "listing.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # Flags chosen so that no product is fused behind the source's back and libm is
@@ -30,11 +45,16 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-pt
 FLAG_TIMEOUT, FLAG_ESCAPE, FLAG_HORIZON, FLAG_INVALID = 0, 1, 2, 3
 
 
+def _stale() -> bool:
+    return (not os.path.exists(_LIB)
+            or any(os.path.getmtime(_LIB) < os.path.getmtime(s) for s in _SRCS))
+
+
 def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so next to it (gcc, plain C11)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile oracle.c and listing.c into liboracle.so next to them (gcc, plain C11)."""
+    if force or _stale():
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -45,7 +65,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _stale():
             build(force=True)
         lib = ctypes.CDLL(_LIB)
         d, i, i64 = ctypes.c_double, ctypes.c_int, ctypes.c_int64
@@ -86,6 +106,18 @@ def _load():
         lib.oracle_shade.argtypes = [i, d, d, vp, vp, vp, vp, i64, vp]
         lib.oracle_mn_consts.restype = None
         lib.oracle_mn_consts.argtypes = [d, d, d, vp]
+        lib.listing_trace_frame.restype = i64
+        lib.listing_trace_frame.argtypes = [i, d, d, d, d, d, d, d, i, i, d, d, d, d, i, i, vp,
+                                            vp, i64, i, vp, vp, vp, vp, vp, vp, i]
+        lib.listing_trace_rays.restype = i64
+        lib.listing_trace_rays.argtypes = [i, d, d, d, d, d, d, d, i, i, vp, i64, i, vp, vp,
+                                           vp, vp, vp, i]
+        lib.listing_camera.restype = None
+        lib.listing_camera.argtypes = [i, d, d, d, d, d, d, d, i, i, vp, i64, vp]
+        lib.listing_metric.restype = None
+        lib.listing_metric.argtypes = [i, d, d, d, d, d, vp, vp]
+        lib.listing_rhs.restype = None
+        lib.listing_rhs.argtypes = [i, d, d, d, d, vp, vp]
         _lib = lib
     return _lib
 
@@ -112,6 +144,8 @@ class Result:
     flag: np.ndarray
     steps: np.ndarray
     p0: np.ndarray | None = None   # (n, 4) initial covector, frame mode only
+    sens: np.ndarray | None = None  # listing form with probe > 0: end-angle sensitivity
+    flip: np.ndarray | None = None  # listing form with probe > 0: a probe changed flag/steps
 
 
 def _disk(disk):
@@ -123,12 +157,46 @@ def _alloc(n):
                                                           np.empty(n, np.int32)]
 
 
+def _listing_frame(kind, p1, p2, p3, r0, theta0, phi0, fov, width, height, dt, eps,
+                   horizon_norm, escape_factor, max_steps, pixels, threads, method, disk,
+                   probe) -> Result:
+    lib = _load()
+    if pixels is not None:
+        pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+        n = int(pixels.size)
+    else:
+        n = int(width) * int(height)
+    out8 = np.empty((n, 8), np.float64)
+    p0 = np.empty((n, 4), np.float64)
+    flag = np.empty(n, np.int8)
+    steps = np.empty(n, np.int32)
+    sens = np.zeros(n, np.float64) if probe else None
+    flip = np.zeros(n, np.int8) if probe else None
+    lib.listing_trace_frame(int(kind), p1, p2, p3, r0, theta0, phi0, fov, int(width),
+                            int(height), dt, eps, horizon_norm, escape_factor, int(max_steps),
+                            int(method), _ptr(_disk(disk)), _ptr(pixels), n, int(probe),
+                            _ptr(out8), _ptr(p0), _ptr(flag), _ptr(steps), _ptr(sens),
+                            _ptr(flip), int(threads or default_threads()))
+    return Result(out8[:, 0].copy(), out8[:, 1].copy(), out8[:, 2].copy(), out8[:, 3].copy(),
+                  out8[:, 5].copy(), out8[:, 6].copy(), flag, steps, p0, sens,
+                  None if flip is None else flip.astype(bool))
+
+
 def trace_frame(M, a, Q, r0, theta0, phi0, fov, width, height, dt=0.01, eps=1e-8,
                 horizon_norm=1e4, escape_factor=1.5, max_steps=20000, pixels=None,
-                threads=None, want_p0=False, method=0, disk=None) -> Result:
+                threads=None, want_p0=False, method=0, disk=None, form="listing",
+                probe=0) -> Result:
     """Trace the camera rays of a width x height frame (or the listed pixels);
     method 0 is RK4, 1 explicit Euler; disk = (r_in, r_out, half_angle) adds
-    the solid equatorial ring (flag 4 on hitting it)."""
+    the solid equatorial ring (flag 4 on hitting it).  form "listing" (default)
+    or "twin" (see the module docstring); probe (listing form, 0..4) adds the
+    per-ray sensitivity."""
+    if form == "listing":
+        return _listing_frame(0, M, a, Q, r0, theta0, phi0, fov, width, height, dt, eps,
+                              horizon_norm, escape_factor, max_steps, pixels, threads, method,
+                              disk, probe)
+    if form != "twin":
+        raise ValueError(form)
     lib = _load()
     if pixels is not None:
         pixels = np.ascontiguousarray(pixels, dtype=np.int64)
@@ -146,11 +214,28 @@ def trace_frame(M, a, Q, r0, theta0, phi0, fov, width, height, dt=0.01, eps=1e-8
 
 
 def trace_rays(M, a, Q, init, dt=0.01, eps=1e-8, horizon_norm=1e4, escape_factor=1.5,
-               max_steps=20000, threads=None) -> Result:
-    """Trace rays from explicit initial states, init[k] = (t, r, th, ph, p_t, p_r, p_th, p_ph)."""
+               max_steps=20000, threads=None, form="listing", probe=0, method=0,
+               mn=False) -> Result:
+    """Trace rays from explicit initial states, init[k] = (t, r, th, ph, p_t, p_r, p_th, p_ph);
+    (M, a, Q) are (M, S, q) with mn=True (listing form only)."""
     lib = _load()
     init = np.ascontiguousarray(init, dtype=np.float64).reshape(-1, 8)
     n = init.shape[0]
+    if form == "listing":
+        out8 = np.empty((n, 8), np.float64)
+        flag = np.empty(n, np.int8)
+        steps = np.empty(n, np.int32)
+        sens = np.zeros(n, np.float64) if probe else None
+        flip = np.zeros(n, np.int8) if probe else None
+        lib.listing_trace_rays(1 if mn else 0, M, a, Q, dt, eps, horizon_norm, escape_factor,
+                               int(max_steps), int(method), _ptr(init), n, int(probe),
+                               _ptr(out8), _ptr(flag), _ptr(steps), _ptr(sens), _ptr(flip),
+                               int(threads or default_threads()))
+        return Result(out8[:, 0].copy(), out8[:, 1].copy(), out8[:, 2].copy(),
+                      out8[:, 3].copy(), out8[:, 5].copy(), out8[:, 6].copy(), flag, steps,
+                      None, sens, None if flip is None else flip.astype(bool))
+    if form != "twin" or mn or method:
+        raise ValueError("the twin ray-list form is Kerr-Newman RK4 only")
     t, r, th, ph, pr, pth, flag, steps = _alloc(n)
     lib.oracle_trace_rays(M, a, Q, dt, eps, horizon_norm, escape_factor, int(max_steps),
                           _ptr(init), n, _ptr(t), _ptr(r), _ptr(th), _ptr(ph), _ptr(pr),
@@ -158,8 +243,10 @@ def trace_rays(M, a, Q, init, dt=0.01, eps=1e-8, horizon_norm=1e4, escape_factor
     return Result(t, r, th, ph, pr, pth, flag, steps)
 
 
-def camera(M, a, Q, r0, theta0, phi0, fov, width, height, pixels=None) -> np.ndarray:
-    """Initial states (n, 8) = (q^mu, p_mu) of the camera rays."""
+def camera(M, a, Q, r0, theta0, phi0, fov, width, height, pixels=None, form="listing",
+           mn=False) -> np.ndarray:
+    """Initial states (n, 8) = (q^mu, p_mu) of the camera rays ((M, S, q) with
+    mn=True, listing form only)."""
     lib = _load()
     if pixels is not None:
         pixels = np.ascontiguousarray(pixels, dtype=np.int64)
@@ -167,13 +254,37 @@ def camera(M, a, Q, r0, theta0, phi0, fov, width, height, pixels=None) -> np.nda
     else:
         n = int(width) * int(height)
     out = np.empty((n, 8), np.float64)
+    if form == "listing":
+        lib.listing_camera(1 if mn else 0, M, a, Q, r0, theta0, phi0, fov, int(width),
+                           int(height), _ptr(pixels), n, _ptr(out))
+        return out
+    if form != "twin" or mn:
+        raise ValueError(form)
     lib.oracle_camera(M, a, Q, r0, theta0, phi0, fov, int(width), int(height), _ptr(pixels),
                       n, _ptr(out))
     return out
 
 
+def listing_metric(M, a, Q, r, theta, mn=False):
+    """Listing form: (g^{mu nu}, g_{mu nu}) as 4x4 arrays at (r, theta)
+    ((M, S, q) with mn=True)."""
+    inv = np.empty(16)
+    cov = np.empty(16)
+    _load().listing_metric(1 if mn else 0, M, a, Q, float(r), float(theta), _ptr(inv),
+                           _ptr(cov))
+    return inv.reshape(4, 4), cov.reshape(4, 4)
+
+
+def listing_rhs(M, a, Q, y, eps=1e-8, mn=False) -> np.ndarray:
+    """Listing form: dy/dtau (8 values) at y = (q, p)."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    dy = np.empty(8)
+    _load().listing_rhs(1 if mn else 0, M, a, Q, eps, _ptr(y), _ptr(dy))
+    return dy
+
+
 def inverse_metric(M, a, Q, r, theta) -> np.ndarray:
-    """(g^tt, g^tphi, g^rr, g^thth, g^phph) at (r, theta)."""
+    """Kernel-twin form: (g^tt, g^tphi, g^rr, g^thth, g^phph) at (r, theta)."""
     lib = _load()
     g = np.empty(5, np.float64)
     lib.oracle_inverse_metric(M, a, Q, float(r), float(theta), _ptr(g))
@@ -216,9 +327,16 @@ def sincos(x) -> tuple[np.ndarray, np.ndarray]:
 # ---------------------------------------------------------------- Manko-Novikov
 def trace_frame_mn(M, S, q, r0, theta0, phi0, fov, width, height, dt=0.01, eps=1e-8,
                    horizon_norm=1e4, escape_factor=1.5, max_steps=20000, pixels=None,
-                   threads=None, want_p0=False, method=0, disk=None) -> Result:
+                   threads=None, want_p0=False, method=0, disk=None, form="listing",
+                   probe=0) -> Result:
     """trace_frame for the Manko-Novikov spacetime (mass M, spin S, quadrupole
     deviation q; paper Sec. 2.2.3)."""
+    if form == "listing":
+        return _listing_frame(1, M, S, q, r0, theta0, phi0, fov, width, height, dt, eps,
+                              horizon_norm, escape_factor, max_steps, pixels, threads, method,
+                              disk, probe)
+    if form != "twin":
+        raise ValueError(form)
     lib = _load()
     if pixels is not None:
         pixels = np.ascontiguousarray(pixels, dtype=np.int64)

@@ -277,3 +277,17 @@ def mn_quadrupole_moment(M, S, q):
     """Mass quadrupole of the Manko-Novikov spacetime: the Kerr value -S^2/M
     plus the deviation -q M^3."""
     return -(S * S) / M - q * M ** 3
+
+
+def escape_crossing(M, a, Q, r_esc, r, theta, phi, p):
+    """(theta, phi) where each ray crosses r = r_esc: its end state (r, theta,
+    phi, covector p of shape (n, 4)) moved back along its velocity
+    dq/dtau = g^{mu nu} p_nu, with g^{mu nu} the numerical inverse of the
+    textbook covariant metric (linear over the last part of a step)."""
+    th_out, ph_out = [], []
+    for rk, tk, fk, pk in zip(r, theta, phi, np.asarray(p, float)):
+        v = inverse_metric_numeric(M, a, Q, rk, tk) @ pk
+        lam = (r_esc - rk) / v[1]
+        th_out.append(tk + v[2] * lam)
+        ph_out.append(fk + v[3] * lam)
+    return np.array(th_out), np.array(ph_out)

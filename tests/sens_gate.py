@@ -1,0 +1,56 @@
+"""Comparison of a traced frame with the listing form of the oracle at each
+ray's own rounding sensitivity.
+
+The forward difference of step eps = 1e-8 divides the rounding of the metric
+by eps, so two correct implementations whose roundings differ (the listing
+form with the C library's sin/cos and a division per component, against the
+kernel's fixed sequence) end their rays ~1e-9 rad apart, about as far as the
+same implementation started one ulp away.  The listing form measures that
+per ray (oracle probe: p_theta scaled by 1 + 2^-52, the camera latitude moved
+by one ulp, and the whole covector scaled by 1 + 2^-52 and 1 - 2^-53, which
+leaves the ray unchanged in coordinate time but changes every rounding); s
+is the largest end-angle change of the probes.
+
+Gate: flags and step counts identical on every ray whose probes did not
+change them, and d = max(|d theta|, |d phi|) <= K_MAX * s on each such ray,
+with the median and 99th percentile of d / s at most K_MED and K_P99.  On
+the small Kerr frame the kernel-twin form measures 1.4 / 9 / 25 (median,
+p99, max over 4096 rays); a planted mistake (a dropped factor, a sign, the
+listing's 0.1667 in place of 1/6) gives ratios of 1e3 or more.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+K_MAX, K_MED, K_P99 = 64.0, 3.0, 16.0
+S_FLOOR = 1e-14   # a ray whose probes agree to this is compared at this floor
+
+
+def compare_at_sensitivity(got, ref, k_max=K_MAX, k_med=K_MED, k_p99=K_P99, check=True):
+    """got: mapping with theta, phi, flag, steps (binary64); ref: oracle Result
+    of the listing form traced with probe > 0.  Returns statistics; with
+    check=True asserts the gate."""
+    flip = np.asarray(ref.flip, bool)
+    ok = ~flip
+    st = {"n": int(flip.size), "probe_flipped": int(flip.sum())}
+    flags_same = np.asarray(got["flag"])[ok] == ref.flag[ok]
+    steps_same = np.asarray(got["steps"])[ok] == ref.steps[ok]
+    st["flag_mismatch"] = int((~flags_same).sum())
+    st["steps_mismatch"] = int((~steps_same).sum())
+    th = np.asarray(got["theta"], np.float64)
+    ph = np.asarray(got["phi"], np.float64)
+    d = np.maximum(np.abs(th - ref.theta), np.abs(ph - ref.phi))
+    both_nan = np.isnan(th) & np.isnan(ref.theta)
+    use = ok & ~both_nan
+    ratio = d[use] / np.maximum(ref.sens[use], S_FLOOR)
+    if ratio.size:
+        st.update(ratio_median=float(np.median(ratio)), ratio_p99=float(np.percentile(ratio, 99)),
+                  ratio_max=float(ratio.max()), d_median=float(np.median(d[use])),
+                  d_max=float(d[use].max()), s_median=float(np.median(ref.sens[use])))
+    if check:
+        assert st["flag_mismatch"] == 0, st
+        assert st["steps_mismatch"] == 0, st
+        assert not np.isnan(ratio).any(), st
+        assert ratio.size == 0 or (st["ratio_max"] <= k_max and st["ratio_median"] <= k_med
+                                   and st["ratio_p99"] <= k_p99), st
+    return st

@@ -131,7 +131,7 @@ MUTANTS = [
 
 
 def _mutant_lib(tmp_path, k, old, new):
-    src = open(oracle._SRC).read()
+    src = open(oracle._SRCS[0]).read()   # oracle.c, the kernel-twin form
     assert src.count(old) == 1, old
     path = tmp_path / f"mutant{k}.c"
     path.write_text(src.replace(old, new))

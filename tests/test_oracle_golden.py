@@ -1,22 +1,20 @@
-"""The oracle reproduces its recorded end states bit for bit (regression
-record written by tests/golden/make_oracle_golden.py)."""
-import math
+"""Both forms of the oracle reproduce their recorded end states bit for bit
+(regression records written by tests/golden/make_oracle_golden.py)."""
 import os
+import sys
 
 import numpy as np
+import pytest
 
-import oracle
-
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
-                      "oracle_kerr64_sample.txt")
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import make_oracle_golden as mk  # noqa: E402
 
 
-def test_oracle_matches_its_record():
-    rows = [ln.split() for ln in open(GOLDEN) if not ln.startswith("#")]
+@pytest.mark.parametrize("form", mk.FORMS)
+def test_oracle_matches_its_record(form):
+    rows = [ln.split() for ln in open(mk.record_path(form)) if not ln.startswith("#")]
     pixels = np.array([int(r[0]) for r in rows])
-    res = oracle.trace_frame(0.5, 0.24, 0.0, 20.0, math.pi / 2, 0.0, math.radians(75.0),
-                             64, 64, dt=0.01, eps=1e-8, horizon_norm=1e4, escape_factor=1.5,
-                             max_steps=20000, pixels=pixels)
+    res = mk.trace(form, pixels)
     for k, r in enumerate(rows):
         assert res.flag[k] == int(r[1]) and res.steps[k] == int(r[2])
         got = [res.t[k], res.r[k], res.theta[k], res.phi[k], res.pr[k], res.ptheta[k]]

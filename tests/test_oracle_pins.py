@@ -385,8 +385,9 @@ def test_reissner_nordstrom_sweep_reference():
     st = {"r": res.r, "theta": res.theta, "phi": res.phi, "p_t": res.p0[:, 0], "p_r": res.pr,
           "p_theta": res.ptheta, "p_phi": res.p0[:, 3]}
     esc = res.flag == oracle.FLAG_ESCAPE
-    from paper_2310_15183_amd.evaluate import sky_at_escape
-    th, ph = sky_at_escape(M, 0.0, Q, 1.5 * r0, {k: v[esc] for k, v in st.items()})
+    pcov = np.stack([st["p_t"], st["p_r"], st["p_theta"], st["p_phi"]], axis=1)[esc]
+    th, ph = physics.escape_crossing(M, 0.0, Q, 1.5 * r0, st["r"][esc], st["theta"][esc],
+                                     st["phi"][esc], pcov)
     assert esc.sum() >= 10 and np.allclose(th, math.pi / 2, atol=1e-12)
     want = np.array([physics.rn_sweep(M, Q, bb, r0, 1.5 * r0) for bb in b[esc]])
     assert np.abs(ph - want).max() < 1e-6
