@@ -61,7 +61,7 @@ def test_ring_frames_and_redshift_are_bit_exact(g, mn, method):
             out = _gpu(g, ctx, metric, cam, W * H, g.GR_F64)
             gpu = {k: v.cpu().numpy() for k, v in out.tensors.items()}
             res = trace(*params, r0, th0, 0.0, fov, W, H, dt=0.01, max_steps=20000,
-                        want_p0=True, method=method, disk=DISK)
+                        want_p0=True, form="twin", method=method, disk=DISK)
             st = compare(gpu, _ref(res))
             assert st["bit_identical"] == st["n"]
         assert (res.flag == 4).sum() > 50
@@ -163,7 +163,7 @@ def test_ring_megapixel_sampled(g):
     assert 0.05 < (gpu["flag"] == 4).mean() < 0.2
     pix = _sample(gpu["flag"], side, 32, 256, seed=11)
     res = oracle.trace_frame(*params, r0, th0, 0.0, fov, side, side, dt=0.005, max_steps=50000,
-                             pixels=pix, want_p0=True, disk=DISK)
+                             pixels=pix, want_p0=True, form="twin", disk=DISK)
     st = compare({k: v[pix] for k, v in gpu.items()}, _ref(res), angle_tol=0.0, f32=True)
     assert st["bit_identical"] == st["n"]
     assert (res.flag == 4).sum() > 100

@@ -45,7 +45,7 @@ def oracle_trace_mn(M, S, q, r0, th0, ph0, fov, W, H, integ, pixels=None):
     res = oracle.trace_frame_mn(M, S, q, r0, th0, ph0, fov, W, H, dt=integ.dt,
                                 eps=integ.fd_eps, horizon_norm=integ.horizon_norm,
                                 escape_factor=integ.escape_factor, max_steps=integ.max_steps,
-                                pixels=pixels, want_p0=True)
+                                pixels=pixels, want_p0=True, form="twin")
     return {"t": res.t, "r": res.r, "theta": res.theta, "phi": res.phi,
             "p_t": res.p0[:, 0], "p_r": res.pr, "p_theta": res.ptheta, "p_phi": res.p0[:, 3],
             "flag": res.flag, "steps": res.steps}
@@ -148,7 +148,7 @@ def test_mn_euler_frame_is_bit_exact(g, ctx):
     g.gr_trace_set_integrator(ctx, integ)
     gpu = gpu_trace_mn(g, ctx, *case)
     import oracle
-    res = oracle.trace_frame_mn(*case, dt=0.01, max_steps=20000, want_p0=True, method=1)
+    res = oracle.trace_frame_mn(*case, dt=0.01, max_steps=20000, want_p0=True, form="twin", method=1)
     ref = {"t": res.t, "r": res.r, "theta": res.theta, "phi": res.phi, "p_t": res.p0[:, 0],
            "p_r": res.pr, "p_theta": res.ptheta, "p_phi": res.p0[:, 3], "flag": res.flag,
            "steps": res.steps}

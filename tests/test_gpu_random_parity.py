@@ -79,7 +79,7 @@ def test_random_draw_is_bit_exact(g, seed):
         gpu = {k: v.cpu().numpy() for k, v in out.tensors.items()}
     finally:
         g.gr_trace_destroy(ctx)
-    res = trace(*hole, *cam, dt=dt, max_steps=max_steps, want_p0=True, method=method, disk=disk)
+    res = trace(*hole, *cam, dt=dt, max_steps=max_steps, want_p0=True, form="twin", method=method, disk=disk)
     ref = {"t": res.t, "r": res.r, "theta": res.theta, "phi": res.phi, "p_t": res.p0[:, 0],
            "p_r": res.pr, "p_theta": res.ptheta, "p_phi": res.p0[:, 3], "flag": res.flag,
            "steps": res.steps}
@@ -144,7 +144,7 @@ def test_random_batch_is_bit_exact(g, seed):
             assert res["flag"].size == 0
             continue
         r = oracle.trace_frame(*hole, *cam, dt=dt, max_steps=max_steps, pixels=pix,
-                               want_p0=True)
+                               want_p0=True, form="twin")
         ref = {"t": r.t, "r": r.r, "theta": r.theta, "phi": r.phi, "p_t": r.p0[:, 0],
                "p_r": r.pr, "p_theta": r.ptheta, "p_phi": r.p0[:, 3], "flag": r.flag,
                "steps": r.steps}
