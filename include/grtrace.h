@@ -264,11 +264,29 @@ int gr_shade_frame(const gr_shade *shade, const gr_output *out, int64_t n, uint3
 /* Trace n >= 1 instances (possibly different black holes, cameras and image
  * sizes) in one persistent launch fed by one work queue (GR_FP64 only:
  * GR_EUNSUPPORTED for GR_MIXED).  The instance table
- * (about 330 bytes per instance) is copied to device memory owned by the
+ * (384 bytes per instance) is copied to device memory owned by the
  * context, which grows it with hipMalloc when a larger batch arrives.  Same
  * errors as gr_trace_frame (GR_ENOMEM if the table cannot grow); an error in
  * any instance rejects the whole call. */
 int gr_trace_batch(gr_ctx *ctx, const gr_instance *inst, int32_t n, void *hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * trace as gr_trace_batch, with the same arguments, validation and results
+ * bit for bit, but the instance table, prefix offsets and work counter live
+ * in one fixed array per device (GR_NOALLOC_MAX_INSTANCES instances, about
+ * 200 KB) that the library holds until the process ends, instead of context
+ * memory grown with hipMalloc.  Allocates nothing (no hipMalloc, hipFree or
+ * allocating library call); copies the table from host memory with
+ * hipMemcpyAsync and clears the counter with a kernel, on the stream.  Every
+ * call on one device shares that device's array and overwrites it: two calls
+ * that may overlap on one device (two streams, two host threads, two
+ * contexts) race and must be serialised by the caller.  Errors: those of
+ * gr_trace_batch, except that the table never grows: more than
+ * GR_NOALLOC_MAX_INSTANCES instances with rays give GR_EINVAL (the text of
+ * gr_trace_last_device_error names the limit) and launch nothing. */
+#define GR_NOALLOC_MAX_INSTANCES 512
+int gr_trace_batch_noalloc(gr_ctx *ctx, const gr_instance *inst, int32_t n, void *hip_stream);
 
 /* Replace the integrator settings of a context (same validation as init). */
 int gr_trace_set_integrator(gr_ctx *ctx, const gr_integrator *integ);

@@ -23,6 +23,7 @@ GR_FP64, GR_MIXED = 0, 1
 GR_RK4, GR_EULER = 0, 1
 GR_SHADE_BANDS, GR_SHADE_TIME = 0, 1
 GR_F64, GR_F32 = 0, 1
+GR_NOALLOC_MAX_INSTANCES = 512
 
 
 class gr_metric(ctypes.Structure):
@@ -91,6 +92,7 @@ def _load():
         "gr_trace_frame_mn": (ctypes.c_int, [vp, P(gr_metric_mn), P(gr_camera), P(gr_output),
                                              vp]),
         "gr_trace_batch": (ctypes.c_int, [vp, P(gr_instance), ctypes.c_int32, vp]),
+        "gr_trace_batch_noalloc": (ctypes.c_int, [vp, P(gr_instance), ctypes.c_int32, vp]),
         "gr_shade_frame": (ctypes.c_int, [P(gr_shade), P(gr_output), ctypes.c_int64, vp, vp]),
         "gr_redshift": (ctypes.c_int, [vp, P(gr_metric), P(gr_camera), P(gr_output),
                                        ctypes.c_int64, vp, vp]),
@@ -135,6 +137,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ["gr_trace_init", "gr_trace_frame", "gr_trace_frame_mn", "gr_trace_batch",
+            "gr_trace_batch_noalloc",
             "gr_shade_frame", "gr_redshift", "gr_redshift_mn",
             "gr_trace_set_integrator",
             "gr_trace_set_launch", "gr_trace_get_launch", "gr_trace_autotune", "gr_trace_destroy",
@@ -208,6 +211,12 @@ def gr_trace_batch(ctx, instances, stream=None):
     arr = (gr_instance * len(instances))(*instances)
     _check(_lib.gr_trace_batch(ctx, arr, len(instances), _stream_handle(stream)),
            "gr_trace_batch")
+
+
+def gr_trace_batch_noalloc(ctx, instances, stream=None):
+    arr = (gr_instance * len(instances))(*instances)
+    _check(_lib.gr_trace_batch_noalloc(ctx, arr, len(instances), _stream_handle(stream)),
+           "gr_trace_batch_noalloc")
 
 
 def gr_trace_set_integrator(ctx, integrator: gr_integrator):

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -48,7 +49,48 @@ struct gr_ctx {
     int32_t* pk_steps;
     int64_t* pk_pix;
     unsigned long long* pk_count;
+    unsigned char* scratch;           // this device's copy of `scratch` (device address)
 };
+
+// Device memory of gr_trace_batch_noalloc: the work counter, the prefix
+// offsets and the instance table of at most GR_NOALLOC_MAX_INSTANCES
+// instances, in one fixed array per device (the library holds it until the
+// process ends).  Host code never passes `scratch` itself to the device: its
+// name is a host-side stand-in, and each device's address comes from
+// hipGetSymbolAddress (scratch_address below).
+namespace {
+constexpr size_t kScratchAlign = 256;
+constexpr size_t round_up(size_t x) { return (x + kScratchAlign - 1) / kScratchAlign * kScratchAlign; }
+constexpr size_t kScratchFirsts = kScratchAlign;     // [0, 256): the work counter
+constexpr size_t kScratchTable =
+    kScratchFirsts + round_up(2 * (GR_NOALLOC_MAX_INSTANCES + 1) * sizeof(int64_t));
+constexpr size_t kScratchBytes =
+    kScratchTable + round_up(GR_NOALLOC_MAX_INSTANCES * sizeof(gr::BatchInstance));
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Device address of `scratch` on `device` (which must be current), looked up
+// once per device.
+hipError_t scratch_address(int device, unsigned char** out) {
+    static std::mutex mu;
+    static std::vector<unsigned char*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0) return hipErrorInvalidDevice;
+    if ((size_t)device >= addr.size()) addr.resize(device + 1, nullptr);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = (unsigned char*)p;
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
+
+}  // namespace
 
 namespace {
 
@@ -338,8 +380,25 @@ int reserve_table(gr_ctx* ctx, int64_t m) {
     return GR_OK;
 }
 
+// Device buffers of a batch: instance table, prefix offsets, work counter.
+struct BatchBuffers {
+    gr::BatchInstance* table;
+    int64_t* firsts;
+    unsigned long long* counter;
+};
+
+// Non-empty instances of a batch.
+int64_t nonempty_instances(const gr_instance* inst, int32_t n) {
+    int64_t m = 0;
+    for (int32_t k = 0; k < n; ++k) m += instance_rays(&inst[k]) > 0;
+    return m;
+}
+
+// dst == nullptr: the context's table, grown with hipMalloc as needed.
+// Otherwise dst must hold the batch (the caller checked its size).
 int upload_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, int order,
-                 hipStream_t s, int32_t* ninst, int64_t* total, int64_t* waves = nullptr) {
+                 hipStream_t s, int32_t* ninst, int64_t* total, int64_t* waves = nullptr,
+                 const BatchBuffers* dst = nullptr) {
     std::vector<int32_t> idx;
     for (int32_t k = 0; k < n; ++k)
         if (instance_rays(&inst[k]) > 0) idx.push_back(k);
@@ -368,31 +427,38 @@ int upload_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, int order,
     *total = firsts[m];
     if (waves) *waves = wf[m];
     if (m == 0) return GR_OK;
-    int rc = reserve_table(ctx, m);
-    if (rc) return rc;
+    gr::BatchInstance* table = dst ? dst->table : nullptr;
+    int64_t* dfirsts = dst ? dst->firsts : nullptr;
+    if (!dst) {
+        int rc = reserve_table(ctx, m);
+        if (rc) return rc;
+        table = ctx->table;
+        dfirsts = ctx->firsts;
+    }
     // pageable sources: the copies are staged before hipMemcpyAsync returns
-    hipError_t e = hipMemcpyAsync(ctx->table, tab.data(), m * sizeof(gr::BatchInstance),
+    hipError_t e = hipMemcpyAsync(table, tab.data(), m * sizeof(gr::BatchInstance),
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(ctx->firsts, firsts.data(), 2 * (m + 1) * sizeof(int64_t),
+        e = hipMemcpyAsync(dfirsts, firsts.data(), 2 * (m + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return device_error(e, "batch table upload");
     return GR_OK;
 }
 
 int run_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, const gr_launch& l,
-              hipStream_t s) {
+              hipStream_t s, const BatchBuffers* dst = nullptr) {
     int32_t ninst = 0;
     int64_t total = 0, waves = 0;
-    int rc = upload_batch(ctx, inst, n, l.order, s, &ninst, &total, &waves);
+    int rc = upload_batch(ctx, inst, n, l.order, s, &ninst, &total, &waves, dst);
     if (rc) return rc;
     if (total == 0) return GR_OK;
+    const BatchBuffers buf = dst ? *dst : BatchBuffers{ctx->table, ctx->firsts, ctx->counter};
     gr::BatchArgs B;
     memset(&B, 0, sizeof B);
     B.in = device_integrator(ctx->integ);
-    B.inst = ctx->table;
-    B.firsts = ctx->firsts;
-    B.wfirsts = ctx->firsts + ninst + 1;
+    B.inst = buf.table;
+    B.firsts = buf.firsts;
+    B.wfirsts = buf.firsts + ninst + 1;
     B.ninst = ninst;
     B.total = total;
     gr::LaunchShape L;
@@ -404,7 +470,7 @@ int run_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, const gr_launch& 
     } else {
         L = resident_shape(ctx, l, gr::occupancy_trace_fp64_batch(l.block), total);
     }
-    hipError_t e = gr::launch_trace_fp64_batch(B, L, ctx->counter, s);
+    hipError_t e = gr::launch_trace_fp64_batch(B, L, buf.counter, s);
     if (e != hipSuccess) return device_error(e, "trace_fp64_batch launch");
     return GR_OK;
 }
@@ -623,6 +689,11 @@ int gr_trace_init(gr_ctx** ctx, int device, const gr_integrator* integ) {
     snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
     for (char* p = c->arch; *p; ++p)
         if (*p == ':') *p = '\0';      // drop feature suffixes such as ":sramecc+"
+    e = scratch_address(device, &c->scratch);
+    if (e != hipSuccess) {
+        delete c;
+        return device_error(e, "hipGetSymbolAddress(scratch)");
+    }
     e = hipMalloc(&c->counter, sizeof(unsigned long long));
     if (e != hipSuccess) {
         delete c;
@@ -808,6 +879,23 @@ int gr_trace_batch(gr_ctx* ctx, const gr_instance* inst, int32_t n, void* hip_st
     if (rc) return rc;
     DeviceGuard guard(ctx->device);
     return run_batch(ctx, inst, n, effective_launch(ctx, true), (hipStream_t)hip_stream);
+}
+
+int gr_trace_batch_noalloc(gr_ctx* ctx, const gr_instance* inst, int32_t n, void* hip_stream) {
+    const int rc = validate_batch(ctx, inst, n);
+    if (rc) return rc;
+    const int64_t m = nonempty_instances(inst, n);
+    if (m > GR_NOALLOC_MAX_INSTANCES) {
+        snprintf(g_last_error, sizeof g_last_error,
+                 "gr_trace_batch_noalloc: %lld instances with rays exceed the maximum of %d",
+                 (long long)m, GR_NOALLOC_MAX_INSTANCES);
+        return GR_EINVAL;
+    }
+    DeviceGuard guard(ctx->device);
+    const BatchBuffers dst{(gr::BatchInstance*)(ctx->scratch + kScratchTable),
+                           (int64_t*)(ctx->scratch + kScratchFirsts),
+                           (unsigned long long*)ctx->scratch};
+    return run_batch(ctx, inst, n, effective_launch(ctx, true), (hipStream_t)hip_stream, &dst);
 }
 
 int gr_trace_autotune(gr_ctx* ctx, const gr_instance* inst, int32_t n, int32_t trial_steps,
