@@ -14,9 +14,15 @@ black-hole inputs of this configuration are binary32); state is binary64;
 end coordinates are stored as binary32 with an int8 flag.
 
 The roofline object reports the tracing kernel against the MI355X FP64
-vector peak: achieved = algorithmic flops per launch (697 per ray-step times
-the ray-steps of the launch, read from the kernel's own step counts) divided
-by the launch's duration measured with HIP events on the launch stream.
+vector peak: achieved = algorithmic work per launch (613 operations per
+ray-step times the ray-steps of the launch, read from the kernel's own step
+counts) divided by the launch's duration measured with HIP events on the
+launch stream.  The 613 are the method's own operations, whatever the kernel
+executes: 584 arithmetic flops (an fma counts 2) plus 21 divisions and 8
+sin/cos pairs, each of those counted once.  The fraction that hardware
+counters measure for executed binary64 flops (the kernel's own series sin/cos
+and reciprocal refinements included) is reported beside it, read from the
+committed counter summary when that was taken on the current kernel source.
 """
 from __future__ import annotations
 
@@ -33,7 +39,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "geodesic rays/s @1000² Kerr: FP64 vs mixed vs surrogate, ≤1e-4 rad err"
-FLOPS_PER_RAY_STEP = 697          # binary64 ops of one RK4 step (add/sub/mul/div 1, fma 2)
+# Algorithmic operations of one binary64 step of the method: fma = 2 flops,
+# add/sub/mul 1, and each division, square root, exp and sin/cos pair 1.
+# RK4 on Kerr-Newman: 4 stages of (3 metric evaluations of 23 flops + 1
+# division, 2 sin/cos, 2 reciprocals of sin^2, differences 20, contraction 26,
+# dq/dtau 8) + stage arguments 24 + update 42 + the normaliser's division
+# = 584 flops + 21 divisions + 8 sin/cos.
+FLOPS_PER_RAY_STEP = 613
+OP_COUNTING = ("fma = 2 flops, add/sub/mul 1; each division, square root, exp and sin/cos "
+               "pair counts 1 (the method's operations, not the kernel's instructions)")
 FP64_PEAK_TFLOPS = 78.6           # MI355X FP64 vector (256 CU x 128 flop/clk x 2.4 GHz)
 BF16_PEAK_TFLOPS = 2500.0         # MI355X dense bfloat16 MFMA
 STRICT_TURN = 0.05                # surrogate_strict: also re-trace where neighbours' directions
@@ -42,7 +56,7 @@ MIN_IMPACT = 1.2                  # surrogate_strict: also re-trace escaping ray
 KERNEL_SOURCES = ["paper_2310_15183_amd/csrc/trace_fp64.hip",
                   "paper_2310_15183_amd/csrc/step_fp64.h",
                   "paper_2310_15183_amd/csrc/grmath.h",
-                  "paper_2310_15183_amd/build.py"]   # build options change the code too
+                  "paper_2310_15183_amd/csrc/internal.h"]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "trace_fp64_kn1000_traffic.md")
 
 
@@ -59,10 +73,18 @@ def workload():
 
 
 def kernel_hash() -> str:
+    """Hash of the tracing kernel's sources and of the hipcc options it is
+    built with (the options change the code too)."""
+    import importlib.util
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
+    spec = importlib.util.spec_from_file_location(
+        "_grtrace_build_opts", os.path.join(ROOT, "paper_2310_15183_amd", "build.py"))
+    opts = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(opts)
+    h.update(" ".join(opts.FLAGS + opts.EXTRA.get("trace_fp64.hip", [])).encode())
     return h.hexdigest()[:16]
 
 
@@ -77,6 +99,25 @@ def recorded_traffic(units_per_launch):
     if not (m_hash and m_bytes) or m_hash.group(1) != kernel_hash():
         return None
     return float(m_bytes.group(1))
+
+
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "trace_fp64_kn1000_counters.md")
+
+
+def recorded_executed():
+    """Executed binary64 flops of the tracing kernel as the committed counter
+    summary measured them (64 x SQ_INSTS_VALU_FLOPS_FP64 over the kernel
+    time), if it was taken on the current kernel source (else None)."""
+    if not os.path.exists(COUNTER_PROFILE):
+        return None
+    text = open(COUNTER_PROFILE).read()
+    m_hash = re.search(r"kernel source hash:\s*([0-9a-f]+)", text)
+    m_frac = re.search(r"executed FP64 fraction of peak:\s*([0-9.]+)", text)
+    m_step = re.search(r"executed flop per ray-step:\s*([0-9.]+)", text)
+    if not (m_hash and m_frac and m_step) or m_hash.group(1) != kernel_hash():
+        return None
+    return {"frac": float(m_frac.group(1)), "flop_per_ray_step": float(m_step.group(1)),
+            "source": os.path.relpath(COUNTER_PROFILE, ROOT)}
 
 
 def host_cpu_model():
@@ -433,7 +474,11 @@ def copy_calibration(mib=256, reps=3):
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": reps}))
 
 
-FLOPS_PER_RAY_STEP_MN = 3365     # binary64 ops of one Manko-Novikov RK4 step (same counting)
+# One Manko-Novikov RK4 step, same counting: 4 stages of (3 metric
+# evaluations of 112 operations with 4 exp, 1 square root and 6 divisions, 2
+# sin/cos, 4 squares and displaced points, differences 20, contraction 26,
+# dq/dtau 8) + stage arguments 24 + update 42 + the normaliser's division.
+FLOPS_PER_RAY_STEP_MN = 1651
 
 
 def mn_workload():
@@ -550,7 +595,7 @@ def bench_mn(args):
     print(json.dumps(result), flush=True)
 
 
-FLOPS_PER_RAY_STEP_EULER = 170   # one stage (157), h (1), update (6 fma)
+FLOPS_PER_RAY_STEP_EULER = 149   # one Kerr-Newman stage (136), the normaliser (1), update (6 fma)
 
 
 def bench_euler(args):
@@ -901,7 +946,9 @@ def main():
             "traffic": traffic,
             "kernel": "trace_fp64",
             "flops_per_ray_step": FLOPS_PER_RAY_STEP,
+            "counting": OP_COUNTING,
             "launch_ms": launch_s * 1e3,
+            "executed_by_counters": recorded_executed(),
         },
         "cpu_baseline": None,
         "variants": {},

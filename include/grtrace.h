@@ -66,12 +66,17 @@ enum {
 
 /* Integrator precision.
  * GR_FP64: binary64 throughout; results are reproducible bit for bit.
- * GR_MIXED (gr_trace_frame only): binary32 state, RK4 stages and contraction;
- *   binary64 metric evaluations and forward differences (sin/cos at
- *   theta+eps by angle addition, reciprocals by v_rcp_f64 and two Newton
- *   steps); whole binary64 steps while r < 1.2 r_+ or |p_r| < 1e-3, back to
- *   binary32 once r > 1.25 r_+ and |p_r| > 2e-3.  Accuracy is stated against
- *   GR_FP64, not bit for bit. */
+ * GR_MIXED (gr_trace_frame only): binary32 RK4 stages (stage points,
+ *   right-hand sides, contraction, the RK4 combination); binary64 metric
+ *   evaluations and forward differences (sin/cos at theta+eps by angle
+ *   addition, reciprocals by v_rcp_f64 and two Newton steps); whole binary64
+ *   steps while r < 1.2 r_+ or |p_r| < 1e-3, back to binary32 stages once
+ *   r > 1.25 r_+ and |p_r| > 2e-3.  The state itself stays binary64: each
+ *   step's binary32 increment is added to it in binary64, because rounding
+ *   theta and phi to binary32 at every step alone random-walks the end angles
+ *   by ~5e-6 rad over 1e4 steps, a twentieth of the 1e-4 rad accuracy target
+ *   before any other error.  Accuracy is stated against GR_FP64, not bit for
+ *   bit. */
 enum { GR_FP64 = 0, GR_MIXED = 1 };
 
 /* Element type of the floating-point outputs. */
@@ -320,9 +325,10 @@ int gr_trace_autotune(gr_ctx *ctx, const gr_instance *inst, int32_t n, int32_t t
  * image-plane coordinates, a/M, |Q|/M, theta0, r0/(50 M), fov (M taken as 1
  * for flat space).  Outputs: an escape logit and a correction d of the end
  * sky direction: the ray is predicted to escape when the logit is positive,
- * towards normalise(u_flat + d), where u_flat is the unit vector of the point
- * where the camera ray's straight line (flat space) leaves the escape sphere
- * r = escape_factor * r0.  Parameters are one packed binary32 vector: for each
+ * towards normalise(u_flat + d), where u_flat is the baseline direction of
+ * gr_surrogate_inputs: where the camera ray would leave the escape sphere
+ * r = escape_factor * r0 around the Reissner-Nordstrom hole with the same M
+ * and Q (the straight line of flat space if that hole captures the ray).  Parameters are one packed binary32 vector: for each
  * layer, W (in x out, row-major) then b (out).  Loss of a batch of n rays with
  * targets (escaped, d): mean of softplus(y0) - escaped*y0 +
  * lam*escaped*sum_c huber(y[c] - d[c]), huber(e) = e^2 for |e| <= delta and
@@ -432,6 +438,17 @@ const char *gr_trace_strerror(int code);
 /* Text of the last HIP error seen by this library in the calling thread
  * ("" if none). */
 const char *gr_trace_last_device_error(void);
+
+/* Check of the binary64 step's divisions (not part of tracing): for k < n,
+ * q[k] = a[k] / x[k] and r[k] = 1 / x[k] formed as the Kerr-Newman step forms
+ * them (hardware reciprocal estimate, Newton-Raphson refinements, Markstein's
+ * correction), so that tests can compare them with IEEE division.  Correctly
+ * rounded for finite, normal operands with a normal quotient; other operands
+ * give unspecified values.  Device arrays of n doubles, asynchronous on the
+ * stream.  Errors: GR_EINVAL (n < 0, or a NULL array with n > 0), GR_EDEVICE
+ * (launch failed). */
+int gr_check_division(const double *a, const double *x, double *q, double *r, int64_t n,
+                      void *hip_stream);
 
 /* Run the host-side validation of gr_trace_frame on its arguments without a
  * device or context (integ may be NULL to skip it).  Returns GR_OK or

@@ -107,6 +107,7 @@ def _load():
         "gr_trace_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "gr_trace_last_device_error": (ctypes.c_char_p, []),
         "gr_horizon_radius": (ctypes.c_double, [P(gr_metric)]),
+        "gr_check_division": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_int64, vp]),
         "gr_trace_validate": (ctypes.c_int, [P(gr_metric), P(gr_camera), P(gr_integrator),
                                              P(gr_output)]),
         "gr_mlp_num_params": (ctypes.c_int64, []),
@@ -137,7 +138,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ["gr_trace_init", "gr_trace_frame", "gr_trace_frame_mn", "gr_trace_batch",
-            "gr_trace_batch_noalloc",
+            "gr_trace_batch_noalloc", "gr_check_division",
             "gr_shade_frame", "gr_redshift", "gr_redshift_mn",
             "gr_trace_set_integrator",
             "gr_trace_set_launch", "gr_trace_get_launch", "gr_trace_autotune", "gr_trace_destroy",
@@ -251,6 +252,18 @@ def gr_trace_destroy(ctx):
 
 def gr_trace_strerror(code: int) -> str:
     return _lib.gr_trace_strerror(int(code)).decode()
+
+
+def gr_check_division(a, x, stream=None):
+    """(a / x, 1 / x) of two float64 device tensors of equal length, formed
+    as the binary64 step forms its divisions."""
+    import torch
+    assert a.dtype == x.dtype == torch.float64 and a.numel() == x.numel()
+    a, x = a.contiguous(), x.contiguous()
+    q, r = torch.empty_like(a), torch.empty_like(x)
+    _check(_lib.gr_check_division(_p(a), _p(x), _p(q), _p(r), a.numel(),
+                                  _stream_handle(stream)), "gr_check_division")
+    return q, r
 
 
 def gr_trace_last_device_error() -> str:

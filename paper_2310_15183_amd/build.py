@@ -9,6 +9,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -19,7 +20,7 @@ LIB = os.path.join(HERE, "libgrtrace.so")
 ARCH = os.environ.get("GRTRACE_ARCH", "gfx950")
 
 SOURCES = ["api.hip", "trace_fp64.hip", "trace_mixed.hip", "trace_mn.hip", "shade.hip",
-           "redshift.hip", "order.hip", "mlp.hip", "mlp_api.hip", "surrogate.hip"]
+           "redshift.hip", "order.hip", "mlp.hip", "mlp_api.hip", "surrogate.hip", "diag.hip"]
 HEADERS = ["grmath.h", "internal.h", "step_fp64.h", "mlp_internal.h", "surrogate_internal.h"]
 
 # Per-source options.  The binary64 tracers' steps are long blocks of
@@ -49,14 +50,17 @@ def _run(cmd):
 def build(verbose: bool = False) -> str:
     """Compile every source and link libgrtrace.so (always rebuilds)."""
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd))
-        _run(cmd)
+        cmds.append(cmd)
         objs.append(obj)
+    # one hipcc per source, a few at a time
+    with ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1))) as pool:
+        list(pool.map(_run, cmds))
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)

@@ -43,5 +43,33 @@ def test_traffic_is_read_only_for_the_current_sources(tmp_path, monkeypatch):
     assert bench.recorded_traffic(1) is None
 
 
-def test_kernel_hash_covers_the_build_options():
-    assert "paper_2310_15183_amd/build.py" in bench.KERNEL_SOURCES
+def test_kernel_hash_covers_the_build_options(monkeypatch):
+    """The hash changes with the tracing kernel's hipcc options, not with the
+    rest of the build script."""
+    import importlib.util
+    base = bench.kernel_hash()
+    real = importlib.util.spec_from_file_location
+
+    def patched(name, path, *a, **k):
+        spec = real(name, path, *a, **k)
+        if name == "_grtrace_build_opts":
+            loader = spec.loader
+
+            class L(type(loader)):
+                def exec_module(self, module):
+                    loader.exec_module(module)
+                    module.FLAGS = module.FLAGS + ["-DX"]
+            spec.loader = L(loader.name, loader.path)
+        return spec
+    monkeypatch.setattr(importlib.util, "spec_from_file_location", patched)
+    assert bench.kernel_hash() != base
+
+
+def test_executed_counters_are_read_only_for_the_current_sources(tmp_path, monkeypatch):
+    fresh = tmp_path / "counters.md"
+    fresh.write_text("kernel source hash: " + bench.kernel_hash() +
+                     "\nexecuted FP64 fraction of peak: 0.5\nexecuted flop per ray-step: 800\n")
+    monkeypatch.setattr(bench, "COUNTER_PROFILE", str(fresh))
+    assert bench.recorded_executed()["frac"] == 0.5
+    fresh.write_text(fresh.read_text().replace(bench.kernel_hash(), "0" * 16))
+    assert bench.recorded_executed() is None

@@ -128,6 +128,27 @@ def test_twin_matches_listing_on_other_frames(name):
     print(name, compare_at_sensitivity(_as_dict(twin), lis))
 
 
+def test_twin_matches_listing_on_headline_frame_sample():
+    """The 1000^2 Kerr-Newman frame of the benchmark (binary32-rounded inputs,
+    dt = 0.005, 50000 steps): every 50th pixel in both axes, plus the pixels
+    within two of each capture/escape transition along the middle row."""
+    f = lambda x: float(np.float32(x))                                   # noqa: E731
+    case = (f(0.5), f(0.24), f(0.3), f(20.0), f(80 * DEG), 0.0, f(75 * DEG), 1000, 1000)
+    kw = dict(dt=0.005, max_steps=50000)
+    row = 500 * 1000 + np.arange(1000)
+    flags = oracle.trace_frame(*case, pixels=row, form="twin", **kw).flag
+    cut = np.nonzero(flags[1:] != flags[:-1])[0]
+    assert cut.size >= 2
+    edge = (row[0] + cut[:, None] + np.arange(-1, 3)[None, :]).ravel()
+    grid = (np.arange(25, 1000, 50)[:, None] * 1000 + np.arange(25, 1000, 50)[None, :]).ravel()
+    pix = np.unique(np.concatenate([grid, edge]))
+    lis = oracle.trace_frame(*case, pixels=pix, probe=4, **kw)
+    twin = oracle.trace_frame(*case, pixels=pix, form="twin", **kw)
+    st = compare_at_sensitivity(_as_dict(twin), lis)
+    print(st)
+    assert (lis.flag == 2).sum() >= 8 and (lis.flag == 1).sum() > 300
+
+
 @pytest.mark.parametrize("name", sorted(MN_FRAMES))
 def test_twin_matches_listing_manko_novikov(name):
     case = MN_FRAMES[name]
