@@ -106,6 +106,10 @@ def _load():
         lib.oracle_shade.argtypes = [i, d, d, vp, vp, vp, vp, i64, vp]
         lib.oracle_mn_consts.restype = None
         lib.oracle_mn_consts.argtypes = [d, d, d, vp]
+        lib.oracle_rotate.restype = None
+        lib.oracle_rotate.argtypes = [vp, i64, vp]
+        lib.oracle_halved_rotations.restype = ctypes.c_long
+        lib.oracle_halved_rotations.argtypes = [i]
         lib.listing_trace_frame.restype = i64
         lib.listing_trace_frame.argtypes = [i, d, d, d, d, d, d, d, i, i, d, d, d, d, i, i, vp,
                                             vp, i64, i, vp, vp, vp, vp, vp, vp, i]
@@ -263,6 +267,23 @@ def camera(M, a, Q, r0, theta0, phi0, fov, width, height, pixels=None, form="lis
     lib.oracle_camera(M, a, Q, r0, theta0, phi0, fov, int(width), int(height), _ptr(pixels),
                       n, _ptr(out))
     return out
+
+
+def rotate(s, c, d) -> tuple[np.ndarray, np.ndarray]:
+    """Kernel-twin form: (sin, cos) of x + d from s = sin x, c = cos x and d
+    by the twin's rotation (series of d / 2^m, m doublings)."""
+    s, c, d = np.broadcast_arrays(np.asarray(s, float), np.asarray(c, float),
+                                  np.asarray(d, float))
+    inp = np.ascontiguousarray(np.stack([s.ravel(), c.ravel(), d.ravel()], axis=1))
+    out = np.empty((inp.shape[0], 2))
+    _load().oracle_rotate(_ptr(inp), inp.shape[0], _ptr(out))
+    return out[:, 0].reshape(s.shape), out[:, 1].reshape(s.shape)
+
+
+def halved_rotations(reset=False) -> int:
+    """Kernel-twin form: rotations by more than 1/16 (halved before the
+    series) since the last reset."""
+    return int(_load().oracle_halved_rotations(1 if reset else 0))
 
 
 def listing_metric(M, a, Q, r, theta, mn=False):

@@ -147,6 +147,46 @@ static void sincos_mode(int mode, double x, double *s, double *c)
     }
 }
 
+/* Rotation of the pair (s, c) = (sin x, cos x) by an angle d, giving
+ * (sin(x + d), cos(x + d)) by the angle-addition identity:
+ *   sin(x + d) = s + (c sin d + s (cos d - 1)),
+ *   cos(x + d) = c + (-s sin d + c (cos d - 1)).
+ * sin d and cos d - 1 are formed for u = d / 2^m, with m the smallest number
+ * of halvings that brings |u| to 1/16 or below (at most 64), from the Taylor
+ * series u + u^3 (S1 + u^2 (S2 + u^2 (S3 + u^2 S4))) and
+ * u^2 (C1 + u^2 (C2 + u^2 (C3 + u^2 C4))) (S_n, C_n as above; the next
+ * terms are below 2e-21 and 3e-19 for |u| <= 1/16), and then doubled m
+ * times: sin 2u = 2 sin u (1 + (cos u - 1)), cos 2u - 1 = -2 sin^2 u.
+ * The twin form carries sin/cos of theta along a Kerr-Newman RK4 ray this
+ * way instead of evaluating them at every stage point. */
+static long g_halved_rotations = 0;       /* rotations that needed halving (test statistics) */
+
+static void rotate_pair(double s, double c, double d, double *s_out, double *c_out)
+{
+    double u = d;
+    int m = 0;
+    while (m < 64 && fabs(u) > 0.0625) {
+        u *= 0.5;
+        ++m;
+    }
+    if (m > 0) __atomic_fetch_add(&g_halved_rotations, 1, __ATOMIC_RELAXED);
+    const double z = u * u;
+    double ps = SIN_C[4], pc = COS_C[4];
+    for (int n = 3; n >= 1; --n) {
+        ps = fma(ps, z, SIN_C[n]);
+        pc = fma(pc, z, COS_C[n]);
+    }
+    double sd = fma(u * z, ps, u);
+    double cm1 = z * pc;
+    for (int i = 0; i < m; ++i) {
+        const double s2 = 2.0 * fma(sd, cm1, sd);
+        cm1 = -2.0 * (sd * sd);
+        sd = s2;
+    }
+    *s_out = s + fma(c, sd, s * cm1);
+    *c_out = c + fma(-s, sd, c * cm1);
+}
+
 /* ------------------------------------------------------------------------ */
 /* exp from its definition (the Manko-Novikov metric needs it; as with sin and
  * cos, a library exp would make the forward differences irreproducible).
@@ -368,18 +408,18 @@ static void metric_at_point(const oracle_params *P, double r, double theta, doub
 /* Right-hand side of Hamilton's equations at one RK4 stage point.
  * Paper eq. hamGeodesic with the factor 1/2 of Appendix A; derivatives by
  * forward differences of step eps as in the listing: the metric (Kerr-Newman
- * or Manko-Novikov) at (r,theta), (r+eps,theta) and (r,theta+eps).  sin and cos at theta+eps are the
+ * or Manko-Novikov) at (r,theta), (r+eps,theta) and (r,theta+eps), given s and c,
+ * the sine and cosine of the point's theta.  sin and cos at theta+eps are the
  * angle-addition identity applied to those at theta and at eps (for eps =
  * 1e-8, cos eps rounds to 1 and sin eps to eps), so the theta step is eps
  * itself.  The contraction sums the differences of the five independent
  * components times p_nu p_sigma in the order tt, t-phi (weight 2 p_t p_phi),
  * rr, theta-theta, phi-phi, then scales once by -1/(2 eps). */
-static void hamilton_rhs(const oracle_params *P, const double eps_sc[2], double r,
-                         double theta, double pt, double pr, double pth, double pph,
-                         double qdot[4], double pdot[2])
+static void hamilton_rhs_sc(const oracle_params *P, const double eps_sc[2], double r,
+                            double s, double c, double pt, double pr, double pth, double pph,
+                            double qdot[4], double pdot[2])
 {
-    double s, c, g[5], gr[5], gth[5];
-    sincos_mode(P->trig_mode, theta, &s, &c);
+    double g[5], gr[5], gth[5];
     const double se = fma(c, eps_sc[0], s * eps_sc[1]);      /* sin(theta + eps) */
     const double ce = fma(-s, eps_sc[0], c * eps_sc[1]);     /* cos(theta + eps) */
     const double s2 = s * s, c2 = c * c, se2 = se * se, ce2 = ce * ce;
@@ -428,6 +468,16 @@ static void hamilton_rhs(const oracle_params *P, const double eps_sc[2], double 
     qdot[3] = fma(g[1], pt, g[4] * pph);                       /* dphi/dtau */
 }
 
+/* The same at (r, theta), sin and cos of theta from the stated definition. */
+static void hamilton_rhs(const oracle_params *P, const double eps_sc[2], double r,
+                         double theta, double pt, double pr, double pth, double pph,
+                         double qdot[4], double pdot[2])
+{
+    double s, c;
+    sincos_mode(P->trig_mode, theta, &s, &c);
+    hamilton_rhs_sc(P, eps_sc, r, s, c, pt, pr, pth, pph, qdot, pdot);
+}
+
 static int in_disk(const oracle_params *P, const double q[4])
 {
     return P->disk_dth > 0.0 && q[1] >= P->disk_r_in && q[1] <= P->disk_r_out &&
@@ -452,6 +502,8 @@ int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nste
     const double pt = p[0], pph = p[3];
     double pr = p[1], pth = p[2];
     int flag = FLAG_TIMEOUT, s = 0;
+    double sn, cs;                                             /* sin, cos of theta, carried */
+    sincos_mode(P->trig_mode, q[2], &sn, &cs);
     *nsteps = 0;
     if (!(all_finite(q, pr, pth) && isfinite(pt) && isfinite(pph)))
         return FLAG_INVALID;
@@ -472,24 +524,54 @@ int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nste
             if (!all_finite(q, pr, pth)) { flag = FLAG_INVALID; break; }
             continue;
         }
-        /* K1 at the current point; its dt/dtau fixes the step. */
-        hamilton_rhs(P, eps_sc, q[1], q[2], pt, pr, pth, pph, k1q, k1p);
-        const double nu = fabs(k1q[0]);
-        const double h = P->dt / nu;
-        const double hh = 0.5 * h;
-        /* K2, K3 at half steps, K4 at the full step. */
-        hamilton_rhs(P, eps_sc, fma(hh, k1q[1], q[1]), fma(hh, k1q[2], q[2]), pt,
-                     fma(hh, k1p[0], pr), fma(hh, k1p[1], pth), pph, k2q, k2p);
-        hamilton_rhs(P, eps_sc, fma(hh, k2q[1], q[1]), fma(hh, k2q[2], q[2]), pt,
-                     fma(hh, k2p[0], pr), fma(hh, k2p[1], pth), pph, k3q, k3p);
-        hamilton_rhs(P, eps_sc, fma(h, k3q[1], q[1]), fma(h, k3q[2], q[2]), pt,
-                     fma(h, k3p[0], pr), fma(h, k3p[1], pth), pph, k4q, k4p);
+        double nu, h;
+        if (P->kind == METRIC_MN) {
+            /* K1 at the current point; its dt/dtau fixes the step. */
+            hamilton_rhs(P, eps_sc, q[1], q[2], pt, pr, pth, pph, k1q, k1p);
+            nu = fabs(k1q[0]);
+            h = P->dt / nu;
+            const double hh = 0.5 * h;
+            /* K2, K3 at half steps, K4 at the full step. */
+            hamilton_rhs(P, eps_sc, fma(hh, k1q[1], q[1]), fma(hh, k1q[2], q[2]), pt,
+                         fma(hh, k1p[0], pr), fma(hh, k1p[1], pth), pph, k2q, k2p);
+            hamilton_rhs(P, eps_sc, fma(hh, k2q[1], q[1]), fma(hh, k2q[2], q[2]), pt,
+                         fma(hh, k2p[0], pr), fma(hh, k2p[1], pth), pph, k3q, k3p);
+            hamilton_rhs(P, eps_sc, fma(h, k3q[1], q[1]), fma(h, k3q[2], q[2]), pt,
+                         fma(h, k3p[0], pr), fma(h, k3p[1], pth), pph, k4q, k4p);
+        } else {
+            /* Kerr-Newman: theta enters through its sine and cosine only, and
+             * the ray carries them; each stage point's pair is the carried
+             * pair rotated by that stage's increment of theta. */
+            double s2, c2;
+            hamilton_rhs_sc(P, eps_sc, q[1], sn, cs, pt, pr, pth, pph, k1q, k1p);
+            nu = fabs(k1q[0]);
+            h = P->dt / nu;
+            const double hh = 0.5 * h;
+            rotate_pair(sn, cs, hh * k1q[2], &s2, &c2);
+            hamilton_rhs_sc(P, eps_sc, fma(hh, k1q[1], q[1]), s2, c2, pt,
+                            fma(hh, k1p[0], pr), fma(hh, k1p[1], pth), pph, k2q, k2p);
+            rotate_pair(sn, cs, hh * k2q[2], &s2, &c2);
+            hamilton_rhs_sc(P, eps_sc, fma(hh, k2q[1], q[1]), s2, c2, pt,
+                            fma(hh, k2p[0], pr), fma(hh, k2p[1], pth), pph, k3q, k3p);
+            rotate_pair(sn, cs, h * k3q[2], &s2, &c2);
+            hamilton_rhs_sc(P, eps_sc, fma(h, k3q[1], q[1]), s2, c2, pt,
+                            fma(h, k3p[0], pr), fma(h, k3p[1], pth), pph, k4q, k4p);
+        }
         /* x += h/6 (k1 + 2 k2 + 2 k3 + k4) */
         const double h6 = h * (1.0 / 6.0);
-        for (int m = 0; m < 4; ++m)
-            q[m] = fma(h6, ((k1q[m] + 2.0 * k2q[m]) + 2.0 * k3q[m]) + k4q[m], q[m]);
+        double S[4];
+        for (int m = 0; m < 4; ++m) {
+            S[m] = ((k1q[m] + 2.0 * k2q[m]) + 2.0 * k3q[m]) + k4q[m];
+            q[m] = fma(h6, S[m], q[m]);
+        }
         pr = fma(h6, ((k1p[0] + 2.0 * k2p[0]) + 2.0 * k3p[0]) + k4p[0], pr);
         pth = fma(h6, ((k1p[1] + 2.0 * k2p[1]) + 2.0 * k3p[1]) + k4p[1], pth);
+        if (P->kind != METRIC_MN) {
+            double s2, c2;
+            rotate_pair(sn, cs, h6 * S[2], &s2, &c2);     /* the carried pair follows theta */
+            sn = s2;
+            cs = c2;
+        }
 
         if (in_disk(P, q)) { flag = FLAG_DISK; break; }
         if (q[1] > r_esc) { flag = FLAG_ESCAPE; break; }
@@ -657,6 +739,22 @@ void oracle_sincos(const double *x, int64_t n, double *sc)
 }
 
 /* Accuracy checks of the Newton-refined reciprocal: out[k] = recip_newton(x[k], y0[k]). */
+/* rotate_pair on n triples (x_sin, x_cos, d): out[2k], out[2k+1]. */
+void oracle_rotate(const double *in3, int64_t n, double *out2)
+{
+    pthread_once(&trig_once, trig_init);
+    for (int64_t k = 0; k < n; ++k)
+        rotate_pair(in3[3 * k], in3[3 * k + 1], in3[3 * k + 2], &out2[2 * k], &out2[2 * k + 1]);
+}
+
+/* Number of rotations so far that needed halving (reset = 1 clears it). */
+long oracle_halved_rotations(int reset)
+{
+    const long v = __atomic_load_n(&g_halved_rotations, __ATOMIC_RELAXED);
+    if (reset) __atomic_store_n(&g_halved_rotations, 0, __ATOMIC_RELAXED);
+    return v;
+}
+
 void oracle_recip_newton(const double *x, const double *y0, int64_t n, double *out)
 {
     for (int64_t k = 0; k < n; ++k) out[k] = recip_newton(x[k], y0[k]);

@@ -71,6 +71,59 @@ GR_HD void sincos_def(double x, double& s_out, double& c_out) {
     c_out = c;
 }
 
+// Rotation of a (sin, cos) pair by an angle d: (sin(x + d), cos(x + d)) from
+// s = sin x, c = cos x by the angle-addition identity.  sin and cos - 1 of
+// u = d 2^-m, m the least count of halvings with |u| <= 1/16 (at most 64),
+// come from their Taylor series through u^9 and u^8 (the first omitted terms
+// are below 2e-21 and 3e-19 there), then m double-angle steps
+// sin 2u = 2 sin u (1 + (cos u - 1)), cos 2u - 1 = -2 sin^2 u give those of d;
+// the small corrections are summed first and added to s and c with one
+// rounding each.  rotate_small is the case m = 0 alone (no branch), equal to
+// rotate_sc bit for bit wherever |d| <= 1/16.
+constexpr double ROT_SERIES_MAX = 0.0625;
+
+GR_HD void small_angle(double u, double& sd, double& cm1) {
+    const double z = u * u;
+    double ps = series_coef(9);
+    ps = fma(ps, z, series_coef(7));
+    ps = fma(ps, z, series_coef(5));
+    ps = fma(ps, z, series_coef(3));
+    sd = fma(u * z, ps, u);
+    double pc = series_coef(8);
+    pc = fma(pc, z, series_coef(6));
+    pc = fma(pc, z, series_coef(4));
+    pc = fma(pc, z, series_coef(2));
+    cm1 = z * pc;
+}
+
+GR_HD void rotate_by(double s, double c, double sd, double cm1, double& s_out, double& c_out) {
+    s_out = s + fma(c, sd, s * cm1);
+    c_out = c + fma(-s, sd, c * cm1);
+}
+
+GR_HD void rotate_small(double s, double c, double d, double& s_out, double& c_out) {
+    double sd, cm1;
+    small_angle(d, sd, cm1);
+    rotate_by(s, c, sd, cm1, s_out, c_out);
+}
+
+GR_HD void rotate_sc(double s, double c, double d, double& s_out, double& c_out) {
+    double u = d;
+    int m = 0;
+    while (m < 64 && fabs(u) > ROT_SERIES_MAX) {
+        u *= 0.5;
+        ++m;
+    }
+    double sd, cm1;
+    small_angle(u, sd, cm1);
+    for (int i = 0; i < m; ++i) {
+        const double s2 = 2.0 * fma(sd, cm1, sd);
+        cm1 = -2.0 * (sd * sd);
+        sd = s2;
+    }
+    rotate_by(s, c, sd, cm1, s_out, c_out);
+}
+
 // ------------------------------------------------------------ black hole
 // Uniform per-hole constants.  a2 = a*a, aq = a2 + Q*Q, M2 = 2M, Q2 = Q*Q.
 struct Hole {
@@ -313,6 +366,7 @@ GR_HD InvMetric mn_inverse_metric(const MnHole& K, double r, double y, double s2
 // the inverse metric at the camera.
 struct Camera {
     double r0, th0, ph0;
+    double s0, c0;                 // sincos_def(th0)
     double tan_h, tan_v;
     double er, eth, eph;
     InvMetric g;
@@ -331,7 +385,8 @@ inline Camera make_camera(const Hole& Hh, double r0, double th0, double ph0, dou
     sincos_def(0.5 * fov, sf, cf);
     C.tan_h = sf / cf;
     C.tan_v = (C.tan_h * (double)H) / (double)W;
-    const ThetaTerms T = theta_terms(Hh, th0);
+    sincos_def(th0, C.s0, C.c0);
+    const ThetaTerms T = theta_terms_sc(Hh, C.s0, C.c0);
     const RadialTerms R = radial_terms(Hh, r0);
     const double rho2 = fma(Hh.a2, T.c2, R.r2);
     const double Sigma2 = fma(-T.w, R.Delta, R.rara);
@@ -358,9 +413,8 @@ inline Camera make_camera_mn(const MnHole& K, double r0, double th0, double ph0,
     sincos_def(0.5 * fov, sf, cf);
     C.tan_h = sf / cf;
     C.tan_v = (C.tan_h * (double)H) / (double)W;
-    double s, c;
-    sincos_def(th0, s, c);
-    C.g = mn_inverse_metric<IeeeDiv>(K, r0, c, s * s);
+    sincos_def(th0, C.s0, C.c0);
+    C.g = mn_inverse_metric<IeeeDiv>(K, r0, C.c0, C.s0 * C.s0);
     C.er = sqrt(1.0 / C.g.rr);
     C.eth = sqrt(1.0 / C.g.hh);
     C.eph = sqrt(C.g.tt / ((C.g.tt * C.g.pp) - (C.g.tp * C.g.tp)));

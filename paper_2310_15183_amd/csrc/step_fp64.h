@@ -80,11 +80,11 @@ static __device__ __forceinline__ Deriv deriv_from(const InvMetric& g, const Inv
 // (r, th+eps) 1/(rho2 Delta) is refined from inv and multiplied by a divided
 // 1/sin^2 (near the axis sin^2 changes by a large factor over eps, rho2 Delta
 // never does).
-static __device__ __forceinline__ Deriv rhs(const Hole& H, const Integrator& in, double r,
-                                            double th, double pt, double pr, double pth,
-                                            double pph, double wtt, double wtp, double wpp) {
-    double s, c;
-    sincos_def(th, s, c);
+// s, c: sin and cos of the stage point's theta.
+static __device__ __forceinline__ Deriv rhs_sc(const Hole& H, const Integrator& in, double r,
+                                               double s, double c, double pt, double pr,
+                                               double pth, double pph, double wtt, double wtp,
+                                               double wpp) {
     const ThetaTerms T0 = theta_terms_sc(H, s, c);
     const ThetaTerms T1 = theta_terms_sc(H, fma(c, in.sin_eps, s * in.cos_eps),
                                          fma(-s, in.sin_eps, c * in.cos_eps));
@@ -98,6 +98,15 @@ static __device__ __forceinline__ Deriv rhs(const Hole& H, const Integrator& in,
     const InvMetric gr = metric_from(H, R1, T0, is_r * T0.s2, is_r);
     const InvMetric gh = metric_from(H, R0, T1, inv_t, inv_t * rcp_rn(T1.s2));
     return deriv_from(g, gr, gh, in, pt, pr, pth, pph, wtt, wtp, wpp);
+}
+
+// The right-hand side at (r, th): sin and cos of th by sincos_def.
+static __device__ __forceinline__ Deriv rhs(const Hole& H, const Integrator& in, double r,
+                                            double th, double pt, double pr, double pth,
+                                            double pph, double wtt, double wtp, double wpp) {
+    double s, c;
+    sincos_def(th, s, c);
+    return rhs_sc(H, in, r, s, c, pt, pr, pth, pph, wtt, wtp, wpp);
 }
 
 // The same right-hand side for the Manko-Novikov spacetime: three full
@@ -120,6 +129,7 @@ static __device__ __forceinline__ Deriv rhs_mn(const MnHole& K, const Integrator
 struct Ray {
     double t, r, th, ph, pt, pr, pth, pph;
     double wtt, wtp, wpp;    // p_t^2, 2 p_t p_phi, p_phi^2 (constant along the ray)
+    double sn, cs;           // sin and cos of theta carried along the ray (rk4_step)
 };
 
 static __device__ __forceinline__ void start_ray(const Camera& C, int64_t pix, Ray& y) {
@@ -129,6 +139,8 @@ static __device__ __forceinline__ void start_ray(const Camera& C, int64_t pix, R
     y.r = C.r0;
     y.th = C.th0;
     y.ph = C.ph0;
+    y.sn = C.s0;
+    y.cs = C.c0;
     y.wtt = y.pt * y.pt;
     y.wtp = (2.0 * y.pt) * y.pph;
     y.wpp = y.pph * y.pph;
@@ -189,8 +201,90 @@ static __device__ __forceinline__ double euler_generic(const Rhs& rhs_at, const 
     return nu;
 }
 
-// One Kerr-Newman RK4 step.
-static __device__ __forceinline__ double rk4_step(const Hole& H, const Integrator& in, Ray& y) {
+// One Kerr-Newman RK4 step with theta entering through its sin and cos
+// only (the carried form): the ray carries (sin, cos) of its angle, each
+// stage point's pair is that pair rotated (rotate_sc) by the stage's
+// increment c_k h dtheta/dtau, and the update rotates the carried pair by the
+// step's increment h/6 S_theta while theta itself is summed as before.  Same
+// RK4 as rk4_generic; the metric sees sin and cos of the unrounded stage
+// angles, and the carried pair departs from sin/cos of the summed theta only
+// by the accumulated rounding of the rotations (a random walk of ~1e-16 per
+// step).
+// GENERAL = false rotates by rotate_small (no branch) and returns in dmax the
+// largest |increment|; the step equals the GENERAL one when dmax <= 1/16.
+template <bool GENERAL>
+static __device__ __forceinline__ double rk4_carry(const Hole& H, const Integrator& in, Ray& y,
+                                                   double& dmax) {
+    const auto f = [&](double r, double sn, double cs, double pr, double pth) {
+        return rhs_sc(H, in, r, sn, cs, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
+    };
+    dmax = 0.0;
+    const auto rot = [&](double d, double& sn, double& cs) {
+        if constexpr (GENERAL) {
+            rotate_sc(y.sn, y.cs, d, sn, cs);
+        } else {
+            dmax = fmax(dmax, fabs(d));
+            rotate_small(y.sn, y.cs, d, sn, cs);
+        }
+    };
+    double sn, cs;
+    Deriv k = f(y.r, y.sn, y.cs, y.pr, y.pth);
+    const double nu = fabs(k.qt);
+    const double h = div_rn(in.dt, nu);
+    const double hh = 0.5 * h;
+    double st = k.qt, sr = k.qr, sh = k.qh, sp = k.qp, spr = k.pr, sph = k.ph;
+    rot(hh * k.qh, sn, cs);
+    k = f(fma(hh, k.qr, y.r), sn, cs, fma(hh, k.pr, y.pr), fma(hh, k.ph, y.pth));
+    st = fma(2.0, k.qt, st); sr = fma(2.0, k.qr, sr); sh = fma(2.0, k.qh, sh);
+    sp = fma(2.0, k.qp, sp); spr = fma(2.0, k.pr, spr); sph = fma(2.0, k.ph, sph);
+    rot(hh * k.qh, sn, cs);
+    k = f(fma(hh, k.qr, y.r), sn, cs, fma(hh, k.pr, y.pr), fma(hh, k.ph, y.pth));
+    st = fma(2.0, k.qt, st); sr = fma(2.0, k.qr, sr); sh = fma(2.0, k.qh, sh);
+    sp = fma(2.0, k.qp, sp); spr = fma(2.0, k.pr, spr); sph = fma(2.0, k.ph, sph);
+    rot(h * k.qh, sn, cs);
+    k = f(fma(h, k.qr, y.r), sn, cs, fma(h, k.pr, y.pr), fma(h, k.ph, y.pth));
+    st = st + k.qt; sr = sr + k.qr; sh = sh + k.qh; sp = sp + k.qp;
+    spr = spr + k.pr; sph = sph + k.ph;
+    const double h6 = h * (1.0 / 6.0);
+    rot(h6 * sh, sn, cs);
+    y.t = fma(h6, st, y.t);
+    y.r = fma(h6, sr, y.r);
+    y.th = fma(h6, sh, y.th);
+    y.ph = fma(h6, sp, y.ph);
+    y.pr = fma(h6, spr, y.pr);
+    y.pth = fma(h6, sph, y.pth);
+    y.sn = sn;
+    y.cs = cs;
+    return nu;
+}
+
+// The tracing kernels take the branch-free step; a ray one of whose steps
+// rotates by more than 1/16 (it needs h |dtheta/dtau| > 1/16, which no
+// configured workload reaches) is not finished there: its flag is set to
+// PENDING and a second pass over the outputs traces it again from its start
+// with the general step.  Either way each ray's result is that of the
+// general step.
+enum { PENDING = -2 };
+
+static __device__ __forceinline__ double rk4_step(const Hole& H, const Integrator& in, Ray& y,
+                                                  bool& pending) {
+    double dmax;
+    const double nu = rk4_carry<false>(H, in, y, dmax);
+    pending = dmax > ROT_SERIES_MAX;
+    return nu;
+}
+
+static __device__ __forceinline__ double rk4_step_general(const Hole& H, const Integrator& in,
+                                                          Ray& y) {
+    double dmax;
+    return rk4_carry<true>(H, in, y, dmax);
+}
+
+// One Kerr-Newman RK4 step from theta itself (sincos_def at every stage
+// point): the binary64 steps of the mixed-precision tracer, whose binary32
+// steps do not carry the (sin, cos) pair.
+static __device__ __forceinline__ double rk4_step_direct(const Hole& H, const Integrator& in,
+                                                         Ray& y) {
     return rk4_generic(
         [&](double r, double th, double pr, double pth) {
             return rhs(H, in, r, th, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
@@ -198,14 +292,14 @@ static __device__ __forceinline__ double rk4_step(const Hole& H, const Integrato
         in, y);
 }
 
-// One step of the chosen method (EULER: explicit Euler, else RK4).
-template <bool EULER>
-static __device__ __forceinline__ double kn_step(const Hole& H, const Integrator& in, Ray& y) {
-    const auto f = [&](double r, double th, double pr, double pth) {
-        return rhs(H, in, r, th, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
-    };
-    if constexpr (EULER) return euler_generic(f, in, y);
-    else return rk4_generic(f, in, y);
+// One explicit Euler step on Kerr-Newman (sin/cos of theta by sincos_def).
+static __device__ __forceinline__ double kn_euler_step(const Hole& H, const Integrator& in,
+                                                       Ray& y) {
+    return euler_generic(
+        [&](double r, double th, double pr, double pth) {
+            return rhs(H, in, r, th, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
+        },
+        in, y);
 }
 
 template <bool EULER>

@@ -34,12 +34,43 @@ __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
     start_ray(A.cam, pix, y);
     int s = 0;
     int f = start_flag(A.in, y);
-    while (f == RUNNING) {
-        const double nu = kn_step<EULER>(A.hole, A.in, y);
-        ++s;
-        f = exit_flag<DISK>(A.in, A.r_esc, y, nu, s);
+    if constexpr (EULER) {
+        while (f == RUNNING) {
+            const double nu = kn_euler_step(A.hole, A.in, y);
+            ++s;
+            f = exit_flag<DISK>(A.in, A.r_esc, y, nu, s);
+        }
+    } else {
+        while (f == RUNNING) {
+            bool pending;
+            const double nu = rk4_step(A.hole, A.in, y, pending);
+            ++s;
+            f = pending ? PENDING : exit_flag<DISK>(A.in, A.r_esc, y, nu, s);
+        }
     }
-    write_ray<T>(A.out, k, y, f, s);
+    if (f == PENDING) A.out.flag[k] = (int8_t)PENDING;
+    else write_ray<T>(A.out, k, y, f, s);
+}
+
+// Second pass of a binary64 RK4 frame: the rays left PENDING by the first
+// are traced again from the start with the general step (grid-stride over
+// the output entries; nothing to do on the configured workloads).
+template <typename T, bool DISK>
+__global__ void __launch_bounds__(256) trace_fp64_redo(const FrameArgs A) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < A.nray; k += stride) {
+        if (A.out.flag[k] != PENDING) continue;
+        Ray y;
+        start_ray(A.cam, A.pixels ? (int64_t)A.pixels[k] : k, y);
+        int s = 0;
+        int f = start_flag(A.in, y);
+        while (f == RUNNING) {
+            const double nu = rk4_step_general(A.hole, A.in, y);
+            ++s;
+            f = exit_flag<DISK>(A.in, A.r_esc, y, nu, s);
+        }
+        write_ray<T>(A.out, k, y, f, s);
+    }
 }
 
 // Persistent lanes with ballot refill from the global counter.
@@ -70,11 +101,13 @@ __global__ void __launch_bounds__(256) trace_fp64_refill(const FrameArgs A,
         }
         if (!__any(live || want)) break;
         if (live) {
-            const double nu = rk4_step(A.hole, A.in, y);
+            bool pending;
+            const double nu = rk4_step(A.hole, A.in, y, pending);
             ++s;
-            const int f = exit_flag(A.in, A.r_esc, y, nu, s);
+            const int f = pending ? PENDING : exit_flag(A.in, A.r_esc, y, nu, s);
             if (f != RUNNING) {
-                write_ray<T>(A.out, k, y, f, s);
+                if (f == PENDING) A.out.flag[k] = (int8_t)PENDING;
+                else write_ray<T>(A.out, k, y, f, s);
                 live = false;
                 want = true;
             }
@@ -94,9 +127,11 @@ __device__ __forceinline__ int find_instance(const BatchArgs& B, int64_t id) {
     return lo;
 }
 
+// A PENDING ray writes its flag only (the second pass writes the rest).
 __device__ __forceinline__ void write_batch(const BatchInstance& I, int64_t k, const Ray& y,
                                             int f, int s) {
-    if (I.f32) write_ray<float>(I.out, k, y, f, s);
+    if (f == PENDING) I.out.flag[k] = (int8_t)PENDING;
+    else if (I.f32) write_ray<float>(I.out, k, y, f, s);
     else write_ray<double>(I.out, k, y, f, s);
 }
 
@@ -134,9 +169,10 @@ __global__ void __launch_bounds__(256) trace_fp64_batch(const BatchArgs B,
         }
         if (!__any(live || want)) break;
         if (live) {
-            const double nu = rk4_step(H, B.in, y);
+            bool pending;
+            const double nu = rk4_step(H, B.in, y, pending);
             ++s;
-            const int f = exit_flag(B.in, r_esc, y, nu, s);
+            const int f = pending ? PENDING : exit_flag(B.in, r_esc, y, nu, s);
             if (f != RUNNING) {
                 write_batch(B.inst[inst], k, y, f, s);
                 live = false;
@@ -181,11 +217,35 @@ __global__ void __launch_bounds__(256) trace_fp64_batch_static(const BatchArgs B
     int s = 0;
     int f = start_flag(B.in, y);
     while (f == RUNNING) {
-        const double nu = rk4_step(H, B.in, y);
+        bool pending;
+        const double nu = rk4_step(H, B.in, y, pending);
         ++s;
-        f = exit_flag(B.in, r_esc, y, nu, s);
+        f = pending ? PENDING : exit_flag(B.in, r_esc, y, nu, s);
     }
     write_batch(I, k, y, f, s);
+}
+
+// Second pass of a batch: its PENDING rays traced again with the general
+// step (grid-stride over the global ray ids).
+__global__ void __launch_bounds__(256) trace_fp64_batch_redo(const BatchArgs B) {
+    const int64_t total = B.firsts[B.ninst];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < total; id += stride) {
+        const int inst = find_instance(B, id);
+        const BatchInstance& I = B.inst[inst];
+        const int64_t k = id - B.firsts[inst];
+        if (I.out.flag[k] != PENDING) continue;
+        Ray y;
+        start_ray(I.cam, I.pixels ? (int64_t)I.pixels[k] : k, y);
+        int s = 0;
+        int f = start_flag(B.in, y);
+        while (f == RUNNING) {
+            const double nu = rk4_step_general(I.hole, B.in, y);
+            ++s;
+            f = exit_flag(B.in, I.r_esc, y, nu, s);
+        }
+        write_batch(I, k, y, f, s);
+    }
 }
 
 __global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
@@ -194,6 +254,24 @@ __global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
 
 hipError_t launch_reset_counter(unsigned long long* counter, hipStream_t s) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+    return hipGetLastError();
+}
+
+// Grid of a second pass: grid-stride, at most 4096 workgroups of 256.
+static int redo_grid(int64_t n) {
+    const int64_t b = (n + 255) / 256;
+    return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+template <bool DISK>
+static hipError_t launch_redo(const FrameArgs& A, bool f32_out, hipStream_t s) {
+    if (A.nray <= 0) return hipSuccess;
+    if (f32_out)
+        hipLaunchKernelGGL((trace_fp64_redo<float, DISK>), dim3(redo_grid(A.nray)), dim3(256), 0,
+                           s, A);
+    else
+        hipLaunchKernelGGL((trace_fp64_redo<double, DISK>), dim3(redo_grid(A.nray)), dim3(256),
+                           0, s, A);
     return hipGetLastError();
 }
 
@@ -206,7 +284,9 @@ static hipError_t launch_static(const FrameArgs& A, bool f32_out, const LaunchSh
     else
         hipLaunchKernelGGL((trace_fp64_static<double, EULER, DISK>), dim3(L.grid), dim3(L.block),
                            0, s, A);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || EULER) return e;
+    return launch_redo<DISK>(A, f32_out, s);
 }
 
 hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, bool euler, bool disk,
@@ -226,21 +306,25 @@ hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, bool euler, bool 
         else
             hipLaunchKernelGGL(trace_fp64_refill<double>, dim3(L.grid), dim3(L.block), 0, s, A,
                                counter);
-    } else {
-        return launch_static<false, false>(A, f32_out, L, s);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_redo<false>(A, f32_out, s);
     }
-    return hipGetLastError();
+    return launch_static<false, false>(A, f32_out, L, s);
 }
 
 hipError_t launch_trace_fp64_batch(const BatchArgs& B, const LaunchShape& L,
                                    unsigned long long* counter, hipStream_t s) {
     if (!L.refill) {
         hipLaunchKernelGGL(trace_fp64_batch_static, dim3(L.grid), dim3(L.block), 0, s, B);
-        return hipGetLastError();
+    } else {
+        hipError_t e = launch_reset_counter(counter, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(trace_fp64_batch, dim3(L.grid), dim3(L.block), 0, s, B, counter);
     }
-    hipError_t e = launch_reset_counter(counter, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(trace_fp64_batch, dim3(L.grid), dim3(L.block), 0, s, B, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || B.total <= 0) return e;
+    hipLaunchKernelGGL(trace_fp64_batch_redo, dim3(redo_grid(B.total)), dim3(256), 0, s, B);
     return hipGetLastError();
 }
 

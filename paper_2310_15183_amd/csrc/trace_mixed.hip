@@ -187,7 +187,7 @@ __device__ __forceinline__ double mixed_step(const MixedArgs& X, const ConstF& K
     const double apr = fabs(y.pr);
     if (!in64 && (y.r < X.r_enter || apr < PR_ENTER)) in64 = true;
     else if (in64 && y.r > X.r_leave && apr > PR_LEAVE) in64 = false;
-    return in64 ? rk4_step(A.hole, A.in, y) : rk4_step_mixed(A.hole, A.in, K, dtf, y);
+    return in64 ? rk4_step_direct(A.hole, A.in, y) : rk4_step_mixed(A.hole, A.in, K, dtf, y);
 }
 
 // One lane, one ray (static_ray: 8x8 pixel tiles per wave); the grid covers

@@ -279,3 +279,47 @@ def test_oversized_frames_are_refused_before_launch(g, ctx):
     assert e.value.code == g.GR_EINVAL
     torch.cuda.synchronize()
     assert np.all(out["flag"].cpu().numpy() == 77)
+
+
+LARGE_STEP = (0.5, 0.3, 0.2, 12.0, 70 * DEG, 0.0, 60 * DEG, 24, 24)
+
+
+@pytest.mark.parametrize("launch", [None, (256, 0, 1, 0), (64, 0, 1, 0)])
+def test_large_steps_finish_in_the_second_pass(g, ctx, launch):
+    """dt = 0.5: steps rotate theta's (sin, cos) by more than 1/16, beyond the
+    first pass's series; those rays are traced again by the second pass with
+    the general rotation.  Every ray bit-identical to the twin form, whatever
+    the launch form (tiles, persistent lanes)."""
+    import oracle
+    integ = g.make_integrator(dt=0.5, max_steps=20000)
+    oracle.halved_rotations(reset=True)
+    g.gr_trace_set_integrator(ctx, integ)
+    if launch is not None:
+        g.gr_trace_set_launch(ctx, g.gr_launch(*launch))
+    gpu, ref = gpu_trace(ctx, *LARGE_STEP), oracle_trace(*LARGE_STEP, integ)
+    assert oracle.halved_rotations() > 1000
+    st = compare(gpu, ref, angle_tol=0.0)
+    assert st["bit_identical"] == st["n"]
+
+
+def test_large_steps_in_a_batch(g, ctx):
+    """The same through the batch path (whole frame and a pixel list)."""
+    import torch
+    integ = g.make_integrator(dt=0.5, max_steps=20000)
+    g.gr_trace_set_integrator(ctx, integ)
+    M, a, Q, r0, th0, ph0, fov, W, H = LARGE_STEP
+    pix = np.arange(0, W * H, 7)[::-1].copy()
+    out1 = g.alloc_outputs(W * H, fields=("t", "r", "theta", "phi"))
+    out2 = g.alloc_outputs(pix.size, fields=("t", "r", "theta", "phi"))
+    pt = torch.as_tensor(pix.astype(np.int32), device="cuda")
+    m, c = g.gr_metric(M, a, Q), g.gr_camera(r0, th0, ph0, fov, W, H)
+    for launch in (None, g.gr_launch(64, 0, 0, 0)):
+        g.gr_trace_set_launch(ctx, launch)
+        g.gr_trace_batch(ctx, [g.gr_instance(m, c, out1.struct, None, -1),
+                               g.gr_instance(m, c, out2.struct, pt.data_ptr(), pix.size)])
+        torch.cuda.synchronize()
+        for out, p in ((out1, None), (out2, pix)):
+            got = {k: v.cpu().numpy() for k, v in out.tensors.items()}
+            ref = oracle_trace(*LARGE_STEP, integ, pixels=p)
+            st = compare(got, ref, angle_tol=0.0)
+            assert st["bit_identical"] == st["n"]
