@@ -38,8 +38,13 @@ def _pair(g, case, dt=0.005, max_steps=50000):
     ("wide Kerr-Newman, far camera", (0.5, 0.3, 0.35, 45.0, 30 * DEG, 0.4, 90 * DEG, 200, 150)),
     ("the benchmark's 1000x1000 Kerr-Newman frame",
      (0.5, 0.24, 0.3, 20.0, 80 * DEG, 0.0, 75 * DEG, 1000, 1000)),
+    ("near-extremal Kerr at 1000x1000", (0.5, 0.49, 0.0, 20.0, 60 * DEG, 0.0, 75 * DEG, 1000, 1000)),
+    ("near-extremal Kerr at 2048x2048", (0.5, 0.49, 0.0, 20.0, 60 * DEG, 0.0, 75 * DEG, 2048, 2048)),
 ])
 def test_mixed_accuracy_against_fp64(g, name, case):
+    """Whole frames, every pixel; the last two are the near-extremal Kerr frames
+    of the precision workload (a = 0.98 M, theta0 = 60 deg, dt = 0.005,
+    50000 steps) at both of its sizes."""
     ref, mix = _pair(g, case)
     e = mixed_errors(case[0], case[1], case[2], 1.5 * case[3], ref, mix)
     print(name, e)

@@ -51,6 +51,19 @@ def test_param_count(g):
     assert g.gr_mlp_num_params() == ref.num_params() == 200452
 
 
+BF16_ULP = 2.0 ** -8        # spacing of bfloat16 just above 1 (8 significand bits)
+
+
+def _elementwise(got, want, c):
+    """max |got - want| in units of one bfloat16 ulp of the reference's
+    magnitude (the largest |want| of the tensor): a differently rounded
+    activation or weight moves a result by about that much."""
+    scale = BF16_ULP * np.abs(want).max()
+    r = float(np.abs(got - want).max() / scale)
+    assert r <= c, r
+    return r
+
+
 def test_forward_matches_reference(g, net):
     import torch
     p = g.gr_mlp_get_params(net).astype(np.float64)
@@ -61,6 +74,8 @@ def test_forward_matches_reference(g, net):
     got = y.cpu().numpy().astype(np.float64)
     want = ref.forward(p, x.astype(np.float64), bf16_mode=True)
     assert _rel(got, want) < 1e-2 and _cos(got, want) > 0.9999
+    print("forward, per output column, in bf16 ulps:",
+          [round(_elementwise(got[:, j], want[:, j], 1.0), 3) for j in range(4)])
 
 
 def test_gradient_matches_reference(g, net):
@@ -85,6 +100,7 @@ def test_gradient_matches_reference(g, net):
             got, want = gg[o:o + size], gref[o:o + size]
             o += size
             assert _rel(got, want) < 1e-2 and _cos(got, want) > 0.9999, (a, b, size)
+            print("gradient", (a, b, size), "in bf16 ulps:", round(_elementwise(got, want, 1.0), 3))
 
 
 def test_row_gather_equals_permuted_batch(g, net):
@@ -247,6 +263,7 @@ def test_fused_frame_network_matches_forward(g, net):
     nn = (v32[:, 0] * v32[:, 0] + v32[:, 1] * v32[:, 1]) + v32[:, 2] * v32[:, 2]
     exact = np.all(got_dir[both] == v32[both] * (np.float32(1) / np.sqrt(nn[both]))[:, None], axis=1)
     print(f"escaped {esc.mean():.3f}; directions bit-identical to the unfused path: {exact.mean():.4f}")
+    assert exact.all()
 
 
 def test_asynchronous_frames_on_two_streams_equal_the_synchronous_frame(g):
@@ -416,3 +433,74 @@ def test_min_impact_rule_marks_escaping_rays_near_the_critical_impact(g, net):
     sure = np.abs(b_rel - 1.6) > 1e-5
     assert want[sure].sum() > 50 and (~want[sure]).sum() > 50
     np.testing.assert_array_equal(got[sure], want[sure])
+
+
+def test_fallback_selection_follows_the_rule_element_by_element(g, net):
+    """The fallback rule, |logit| < L or a pixel within Chebyshev distance D
+    of a pixel of the other predicted class, evaluated on the host from the
+    network's own logits (gr_mlp_forward on the frame's inputs, bit-identical
+    to the fused frame kernel) and compared with the frame's fallback mask
+    pixel by pixel: the spec rule (L = 3, D = 2) and a wider one
+    (L = 25, D = 1); over the two, each trigger marks many pixels the other
+    does not."""
+    import torch
+    p = g.gr_mlp_get_params(net)
+    p = (p + np.random.default_rng(11).normal(scale=0.02, size=p.size)).astype(np.float32)
+    g.gr_mlp_set_params(net, p)
+    ctx = g.gr_trace_init(0, g.make_integrator(dt=0.01, max_steps=20000))
+    try:
+        W, H = 160, 120
+        metric = g.gr_metric(0.5, 0.3, 0.2)
+        cam = g.gr_camera(20.0, 75 * DEG, 0.0, 60 * DEG, W, H)
+        inst = g.gr_instance(metric, cam, g.gr_output(), None, -1)
+        x = torch.empty(W * H, 7, device="cuda")
+        u = torch.empty(W * H, 3, device="cuda")
+        g.gr_surrogate_inputs(ctx, [inst], x, u)
+        y = torch.empty(W * H, 4, device="cuda")
+        g.gr_mlp_forward(net, x, y)
+        # spread the logits (every 4th weight of the last layer is the logit
+        # column's) and centre them, so that both classes, confident pixels
+        # and small logits all occur
+        y0 = y[:, 0].cpu().numpy()
+        k = np.float32(200.0 / max(float(y0.std()), 1e-6))
+        w_end = p.size - 4                                  # last layer: W (256 x 4), then b (4)
+        p[w_end - 1024:w_end:4] *= k
+        p[-4] = np.float32(p[-4] * k)
+        g.gr_mlp_set_params(net, p)
+        g.gr_mlp_forward(net, x, y)
+        p[-4] -= np.float32(np.median(y[:, 0].cpu().numpy()))
+        g.gr_mlp_set_params(net, p)
+        g.gr_mlp_forward(net, x, y)
+        flag = torch.empty(W * H, dtype=torch.int8, device="cuda")
+        direc = torch.empty(W * H, 3, device="cuda")
+        fb = torch.empty(W * H, dtype=torch.int8, device="cuda")
+        assert g.gr_surrogate_frame(ctx, net, metric, cam, 0.0, 0, flag, direc, fb) == 0
+        cls = flag.cpu().numpy().reshape(H, W)              # the network's classes, no fallback
+        masks = {}
+        for L, D in ((3.0, 2), (25.0, 1)):
+            nfb = g.gr_surrogate_frame(ctx, net, metric, cam, L, D, flag, direc, fb)
+            torch.cuda.synchronize()
+            masks[(L, D)] = (nfb, fb.cpu().numpy().reshape(H, W).astype(bool))
+        logit = y[:, 0].cpu().numpy().reshape(H, W)
+    finally:
+        g.gr_trace_destroy(ctx)
+    np.testing.assert_array_equal(cls, np.where(logit > 0, g.GR_FLAG_ESCAPE, g.GR_FLAG_HORIZON))
+    only = [0, 0]                                     # pixels marked by the logit / edge trigger alone
+    for (L, D), (nfb, got) in masks.items():
+        low = np.abs(logit) < np.float32(L)
+        edge = np.zeros((H, W), bool)
+        for dj in range(-D, D + 1):
+            for di in range(-D, D + 1):
+                sh = np.full((H, W), -1, np.int64)
+                sh[max(0, -dj):H - max(0, dj), max(0, -di):W - max(0, di)] = \
+                    cls[max(0, dj):H - max(0, -dj), max(0, di):W - max(0, -di)]
+                edge |= (sh >= 0) & (sh != cls)
+        want = low | edge
+        print((L, D), "fallback", int(want.sum()), "of", want.size, "; logit only:",
+              int((low & ~edge).sum()), "; class edge only:", int((edge & ~low).sum()),
+              "; both:", int((low & edge).sum()))
+        np.testing.assert_array_equal(got, want)
+        assert nfb == int(want.sum())
+        only[0] += int((low & ~edge).sum())
+        only[1] += int((edge & ~low).sum())
+    assert only[0] >= 100 and only[1] >= 100          # each trigger alone marks pixels
