@@ -240,29 +240,47 @@ int gr_redshift(gr_ctx *ctx, const gr_metric *m, const gr_camera *c, const gr_ou
 int gr_redshift_mn(gr_ctx *ctx, const gr_metric_mn *m, const gr_camera *c,
                    const gr_output *out, int64_t n, void *z, void *hip_stream);
 
-/* Shading of traced rays into 32-bit colours (bytes R, G, B, A in memory).
- * GR_SHADE_BANDS (the appendix listing's colour kernel): an escaped ray is
- *   red where sin^2(phi) < 0.01, else green where cos^2(phi) < 0.01, else
- *   blue where sin^2(2 theta) < 0.01, else dark blue (lines on the sky
- *   sphere); other rays black.  Reads theta, phi, flag.
- * GR_SHADE_TIME (the exit-time figures of Sec. 4): tau = |t| at the end;
- *   escaped rays with tau < t_max shade from dark blue to cyan with
+/* Shading of traced rays into 32-bit colours (bytes R, G, B, A in memory),
+ * the figures of arXiv 2310.15183, Sec. 4.
+ * GR_SHADE_BANDS (the exit-position figures, "perspective" and "flat
+ *   space"): an escaped ray shows a dark-blue sky with three lines on it,
+ *   each a narrow interval of one Boyer-Lindquist angle of its end position,
+ *   drawn where the squared sine of the offset from the line is < 0.01, in
+ *   this precedence: red, the meridian through the camera (phi = 0, pi: a
+ *   vertical line through the hole); green, the meridian across the view
+ *   (phi = +-pi/2: a circle around the hole); light blue, the equator (the
+ *   interval in 2 theta also covers the poles).  Other rays black.  Reads
+ *   theta, phi, flag.
+ * GR_SHADE_TIME (the exit-time figures): tau = |t| at the end; escaped rays
+ *   with tau < t_max shade from dark blue to cyan with
  *   level = floor(255 tau / t_max), dimmed to 7/8 on every other band of
  *   width `band` when band > 0; rays that did not escape, and tau >= t_max,
  *   are cyan; invalid rays black.  Reads t, flag.
+ * GR_SHADE_TEXTURE (the textured figures, bilinear texture filtering): an
+ *   escaped ray shows an equirectangular sky texture (tex_width x
+ *   tex_height device words, row-major, row 0 at theta = 0, column 0 at
+ *   phi = 0) at its end direction, filtered bilinearly: theta brought into
+ *   [0, pi] (mod 2 pi; above pi reflected with phi turned by pi), texel
+ *   (i, j) centred at phi = 2 pi (i + 1/2)/tex_width, theta = pi (j + 1/2)
+ *   /tex_height, columns wrapping around in phi, rows clamped at the poles;
+ *   each byte is the bilinear interpolation of the four nearest texels'
+ *   bytes, rounded half up.  Other rays black.  Reads theta, phi, flag.
  * Decisions are taken in binary64 with the tracer's sin/cos. */
-enum { GR_SHADE_BANDS = 0, GR_SHADE_TIME = 1 };
+enum { GR_SHADE_BANDS = 0, GR_SHADE_TIME = 1, GR_SHADE_TEXTURE = 2 };
 
 typedef struct {
     int32_t mode;
-    double t_max;   /* GR_SHADE_TIME: > 0 */
-    double band;    /* GR_SHADE_TIME: >= 0, 0 = no banding */
+    double t_max;               /* GR_SHADE_TIME: > 0 */
+    double band;                /* GR_SHADE_TIME: >= 0, 0 = no banding */
+    const uint32_t *texture;    /* GR_SHADE_TEXTURE: device texels, caller-owned */
+    int32_t tex_width, tex_height;  /* GR_SHADE_TEXTURE: >= 1 */
 } gr_shade;
 
 /* Colour n rays held in `out` (device arrays of a traced frame or batch
  * instance, binary64 or binary32) into rgba[n] (device), asynchronously on
  * the stream.  Errors: GR_EINVAL (NULL arguments, n < 0, a needed output
- * array missing, t_max <= 0 or band < 0 for GR_SHADE_TIME), GR_EDEVICE. */
+ * array missing, t_max <= 0 or band < 0 for GR_SHADE_TIME, no texture or a
+ * texture side < 1 for GR_SHADE_TEXTURE), GR_EDEVICE. */
 int gr_shade_frame(const gr_shade *shade, const gr_output *out, int64_t n, uint32_t *rgba,
                    void *hip_stream);
 

@@ -103,7 +103,7 @@ def _load():
         lib.oracle_disk_orbit.restype = i
         lib.oracle_disk_orbit.argtypes = [i, d, d, d, d, d, d, vp]
         lib.oracle_shade.restype = None
-        lib.oracle_shade.argtypes = [i, d, d, vp, vp, vp, vp, i64, vp]
+        lib.oracle_shade.argtypes = [i, d, d, vp, i, i, vp, vp, vp, vp, i64, vp]
         lib.oracle_mn_consts.restype = None
         lib.oracle_mn_consts.argtypes = [d, d, d, vp]
         lib.oracle_rotate.restype = None
@@ -407,16 +407,20 @@ def exp_def(x) -> np.ndarray:
     return out
 
 
-def shade(mode, t, theta, phi, flag, t_max=1.0, band=0.0) -> np.ndarray:
-    """Colours (uint32, bytes R, G, B, A) of traced rays: mode 0 the listing's
-    background bands, mode 1 the exit-time map (see oracle.c)."""
+def shade(mode, t, theta, phi, flag, t_max=1.0, band=0.0, texture=None) -> np.ndarray:
+    """Colours (uint32, bytes R, G, B, A) of traced rays: mode 0 the sky's
+    three lines, mode 1 the exit-time map, mode 2 the bilinearly filtered
+    equirectangular texture (uint32 array of shape (height, width)); see
+    oracle.c."""
     flag = np.ascontiguousarray(flag, dtype=np.int8)
     n = flag.size
     conv = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)  # noqa: E731
     t, theta, phi = conv(t), conv(theta), conv(phi)
+    tex = None if texture is None else np.ascontiguousarray(texture, dtype=np.uint32)
+    th_, tw_ = (0, 0) if tex is None else tex.shape
     out = np.empty(n, np.uint32)
-    _load().oracle_shade(int(mode), float(t_max), float(band), _ptr(t), _ptr(theta), _ptr(phi),
-                         _ptr(flag), n, _ptr(out))
+    _load().oracle_shade(int(mode), float(t_max), float(band), _ptr(tex), int(tw_), int(th_),
+                         _ptr(t), _ptr(theta), _ptr(phi), _ptr(flag), n, _ptr(out))
     return out
 
 

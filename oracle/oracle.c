@@ -931,29 +931,110 @@ void oracle_mn_consts(double M, double S, double q, double *out3)
 
 /* ------------------------------------------------------------------------ */
 /* Shading of a traced frame (32-bit colours, bytes R, G, B, A in memory).
- * Mode 0, background bands (the appendix listing's colour kernel): an
- * escaped ray is red where sin^2(phi) < 0.01, else green where
- * cos^2(phi) < 0.01, else blue where sin^2(2 theta) < 0.01, else dark blue;
- * every other ray is black.
+ *
+ * Mode 0, background lines (Sec. 4, the "perspective" and "flat space"
+ * figures): the sky an escaping ray reaches is dark blue, with three lines
+ * drawn on it, each a narrow interval in one Boyer-Lindquist angle of the
+ * ray's end position:
+ *   - red, the great circle through the poles in the camera's meridian plane
+ *     (phi = 0 or pi): a vertical line through the hole in the image;
+ *   - green, the great circle through the poles across the line of sight
+ *     (phi = +-pi/2): seen from the camera, a circle around the hole;
+ *   - light blue, the equator theta = pi/2 (the interval in 2 theta also
+ *     covers the poles, theta = 0 and pi).
+ * A line is drawn where the squared sine of the angle's offset from its
+ * centre is below 0.01 (a band about 11.5 degrees wide); where lines cross,
+ * the one listed first is drawn.  Rays that did not escape are black.
+ *
  * Mode 1, exit time (Sec. 4, the exit-time figures): tau = |t| at the end;
  * escaped rays with tau < t_max go from dark blue (tau = 0) to cyan, with
  * level = floor(255 tau / t_max) dimmed to 7/8 on every other band of width
  * `band` (band > 0); rays that did not escape (captured, step limit) and
- * escaped rays with tau >= t_max are cyan; invalid rays are black. */
-static uint32_t shade_one(int mode, double t_max, double band, double t, double theta,
-                          double phi, int flag)
+ * escaped rays with tau >= t_max are cyan; invalid rays are black.
+ *
+ * Mode 2, texture (Sec. 4, the textured figures): an escaping ray shows the
+ * colour of an equirectangular sky texture (tw x th texels, row 0 at theta =
+ * 0, column 0 at phi = 0, phi increasing with the column) at its end
+ * direction, with bilinear filtering; other rays are black.  theta is first
+ * brought into [0, pi] (theta mod 2 pi; above pi it is reflected, 2 pi -
+ * theta, and phi turned by pi, the same direction), u = frac(phi / 2 pi),
+ * v = theta / pi; texel (i, j) is centred at ((i + 1/2)/tw, (j + 1/2)/th), so
+ * x = u tw - 1/2, y = v th - 1/2, (i0, j0) = floor(x, y), (fx, fy) their
+ * fractions; columns wrap around (i0 and i0 + 1 modulo tw), rows clamp to
+ * [0, th - 1].  Each channel is the linear interpolation of the four texels,
+ * first along the row and then between the rows:
+ *   a = c00 + fx (c10 - c00),  b = c01 + fx (c11 - c01),  c = a + fy (b - a)
+ * (each a single fma in binary64) and the byte is floor(c + 1/2). */
+enum { BAND_PHI = 0, BAND_TWO_THETA = 1 };
+enum { BAND_SIN = 0, BAND_COS = 1 };
+typedef struct {
+    int angle, part;
+    uint32_t rgba;
+} sky_line;
+
+static const sky_line SKY_LINES[3] = {
+    {BAND_PHI, BAND_SIN, 0xff0000ffu},        /* red: phi = 0, pi */
+    {BAND_PHI, BAND_COS, 0xff00ff00u},        /* green: phi = +-pi/2 */
+    {BAND_TWO_THETA, BAND_SIN, 0xffff0000u},  /* light blue: equator (and poles) */
+};
+static const double SKY_LINE_SIN2 = 0.01;
+static const uint32_t SKY = 0xff3c0000u;      /* dark blue */
+
+static uint32_t sky_lines(double theta, double phi)
+{
+    double sc[2][2];                          /* [angle][sin, cos] */
+    trig_sincos(phi, &sc[BAND_PHI][0], &sc[BAND_PHI][1]);
+    trig_sincos(2.0 * theta, &sc[BAND_TWO_THETA][0], &sc[BAND_TWO_THETA][1]);
+    for (int k = 0; k < 3; ++k) {
+        const double v = sc[SKY_LINES[k].angle][SKY_LINES[k].part];
+        if (v * v < SKY_LINE_SIN2) return SKY_LINES[k].rgba;
+    }
+    return SKY;
+}
+
+static uint32_t texture_lookup(const uint32_t *tex, int tw, int th, double theta, double phi)
+{
+    const double two_pi = 2.0 * PIO2_HI * 2.0;                 /* fl(2 pi) */
+    const double pi = 2.0 * PIO2_HI;                           /* fl(pi) */
+    double t = theta - two_pi * floor(theta / two_pi);
+    double p = phi;
+    if (t > pi) {
+        t = two_pi - t;
+        p = p + pi;
+    }
+    double u = p / two_pi;
+    u = u - floor(u);
+    const double v = t / pi;
+    const double x = u * (double)tw - 0.5, y = v * (double)th - 0.5;
+    const double xf = floor(x), yf = floor(y);
+    const double fx = x - xf, fy = y - yf;
+    int64_t i0 = (int64_t)xf % tw;
+    if (i0 < 0) i0 += tw;
+    const int64_t i1 = (i0 + 1) % tw;
+    int64_t j0 = (int64_t)yf, j1 = j0 + 1;
+    j0 = j0 < 0 ? 0 : (j0 > th - 1 ? th - 1 : j0);
+    j1 = j1 < 0 ? 0 : (j1 > th - 1 ? th - 1 : j1);
+    const uint32_t q00 = tex[j0 * tw + i0], q10 = tex[j0 * tw + i1];
+    const uint32_t q01 = tex[j1 * tw + i0], q11 = tex[j1 * tw + i1];
+    uint32_t out = 0;
+    for (int ch = 0; ch < 4; ++ch) {
+        const int sh = 8 * ch;
+        const double c00 = (double)((q00 >> sh) & 255u), c10 = (double)((q10 >> sh) & 255u);
+        const double c01 = (double)((q01 >> sh) & 255u), c11 = (double)((q11 >> sh) & 255u);
+        const double a = fma(fx, c10 - c00, c00);
+        const double b = fma(fx, c11 - c01, c01);
+        const double c = fma(fy, b - a, a);
+        out |= ((uint32_t)floor(c + 0.5)) << sh;
+    }
+    return out;
+}
+
+static uint32_t shade_one(int mode, double t_max, double band, const uint32_t *tex, int tw,
+                          int th, double t, double theta, double phi, int flag)
 {
     const uint32_t BLACK = 0xff000000u, CYAN = 0xffffff00u;
-    if (mode == 0) {
-        if (flag != FLAG_ESCAPE) return BLACK;
-        double sp, cp, s2t, c2t;
-        trig_sincos(phi, &sp, &cp);
-        trig_sincos(2.0 * theta, &s2t, &c2t);
-        if (sp * sp < 0.01) return 0xff0000ffu;
-        if (cp * cp < 0.01) return 0xff00ff00u;
-        if (s2t * s2t < 0.01) return 0xffff0000u;
-        return 0xff3c0000u;
-    }
+    if (mode == 0) return flag == FLAG_ESCAPE ? sky_lines(theta, phi) : BLACK;
+    if (mode == 2) return flag == FLAG_ESCAPE ? texture_lookup(tex, tw, th, theta, phi) : BLACK;
     if (flag == FLAG_INVALID) return BLACK;
     if (flag != FLAG_ESCAPE) return CYAN;
     const double tau = fabs(t);
@@ -965,13 +1046,14 @@ static uint32_t shade_one(int mode, double t_max, double band, double t, double 
     return 0xff000000u | (blue << 16) | (level << 8);
 }
 
-void oracle_shade(int mode, double t_max, double band, const double *t, const double *theta,
-                  const double *phi, const int8_t *flag, int64_t n, uint32_t *out)
+void oracle_shade(int mode, double t_max, double band, const uint32_t *tex, int tw, int th,
+                  const double *t, const double *theta, const double *phi, const int8_t *flag,
+                  int64_t n, uint32_t *out)
 {
     pthread_once(&trig_once, trig_init);
     for (int64_t k = 0; k < n; ++k)
-        out[k] = shade_one(mode, t_max, band, t ? t[k] : 0.0, theta ? theta[k] : 0.0,
-                           phi ? phi[k] : 0.0, flag[k]);
+        out[k] = shade_one(mode, t_max, band, tex, tw, th, t ? t[k] : 0.0,
+                           theta ? theta[k] : 0.0, phi ? phi[k] : 0.0, flag[k]);
 }
 
 /* ------------------------------------------------------------------------ */

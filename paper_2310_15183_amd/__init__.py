@@ -21,7 +21,7 @@ GR_OK, GR_EINVAL, GR_ENOMEM, GR_EDEVICE, GR_EUNSUPPORTED = 0, -1, -2, -3, -4
 GR_FLAG_TIMEOUT, GR_FLAG_ESCAPE, GR_FLAG_HORIZON, GR_FLAG_INVALID, GR_FLAG_DISK = 0, 1, 2, 3, 4
 GR_FP64, GR_MIXED = 0, 1
 GR_RK4, GR_EULER = 0, 1
-GR_SHADE_BANDS, GR_SHADE_TIME = 0, 1
+GR_SHADE_BANDS, GR_SHADE_TIME, GR_SHADE_TEXTURE = 0, 1, 2
 GR_F64, GR_F32 = 0, 1
 GR_NOALLOC_MAX_INSTANCES = 512
 
@@ -35,7 +35,9 @@ class gr_metric_mn(ctypes.Structure):
 
 
 class gr_shade(ctypes.Structure):
-    _fields_ = [("mode", ctypes.c_int32), ("t_max", ctypes.c_double), ("band", ctypes.c_double)]
+    _fields_ = [("mode", ctypes.c_int32), ("t_max", ctypes.c_double), ("band", ctypes.c_double),
+                ("texture", ctypes.c_void_p), ("tex_width", ctypes.c_int32),
+                ("tex_height", ctypes.c_int32)]
 
 
 class gr_camera(ctypes.Structure):
@@ -191,6 +193,14 @@ def gr_trace_frame_mn(ctx, metric: gr_metric_mn, camera: gr_camera, out: gr_outp
     _check(_lib.gr_trace_frame_mn(ctx, ctypes.byref(metric), ctypes.byref(camera),
                                   ctypes.byref(out), _stream_handle(stream)),
            "gr_trace_frame_mn")
+
+
+def shade_texture(texture) -> gr_shade:
+    """GR_SHADE_TEXTURE settings for a (height, width) device tensor of
+    32-bit texels (bytes R, G, B, A); the tensor must outlive the call."""
+    assert texture.dim() == 2 and texture.element_size() == 4 and texture.is_contiguous()
+    return gr_shade(GR_SHADE_TEXTURE, 0.0, 0.0, texture.data_ptr(), texture.shape[1],
+                    texture.shape[0])
 
 
 def gr_shade_frame(shade: gr_shade, out: gr_output, n: int, rgba, stream=None):

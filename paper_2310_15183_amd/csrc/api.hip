@@ -865,11 +865,15 @@ int gr_shade_frame(const gr_shade* sh, const gr_output* out, int64_t n, uint32_t
     } else if (sh->mode == GR_SHADE_TIME) {
         if (!out->t || !(sh->t_max > 0.0) || !(sh->band >= 0.0) || !std::isfinite(sh->band))
             return GR_EINVAL;
+    } else if (sh->mode == GR_SHADE_TEXTURE) {
+        if (!out->theta || !out->phi || !sh->texture || sh->tex_width < 1 || sh->tex_height < 1)
+            return GR_EINVAL;
     } else {
         return GR_EINVAL;
     }
     const hipError_t e = gr::launch_shade(sh->mode, out_ptrs(out), out->dtype == GR_F32, n,
-                                          sh->t_max, sh->band, rgba, (hipStream_t)hip_stream);
+                                          sh->t_max, sh->band, sh->texture, sh->tex_width,
+                                          sh->tex_height, rgba, (hipStream_t)hip_stream);
     if (e != hipSuccess) return device_error(e, "shade launch");
     return GR_OK;
 }

@@ -114,10 +114,12 @@ hipError_t launch_trace_mixed(const FrameArgs& A, double r_plus, bool f32_out,
                               hipStream_t s);
 int occupancy_trace_mixed(int block, bool f32_out);
 
-// Colours of n traced rays (mode 0 background bands, 1 exit time) from the
-// output arrays o (binary32 when f32).
+// Colours of n traced rays (mode 0 the sky's lines, 1 exit time, 2 the sky
+// texture, tex_w x tex_h device words) from the output arrays o (binary32
+// when f32).
 hipError_t launch_shade(int mode, const OutPtrs& o, bool f32, int64_t n, double t_max,
-                        double band, uint32_t* rgba, hipStream_t s);
+                        double band, const uint32_t* texture, int tex_w, int tex_h,
+                        uint32_t* rgba, hipStream_t s);
 
 // Rays a one-ray-per-lane launch parks after `cap` steps (0: none) for a
 // second launch to continue: structure-of-arrays state of up to `capacity`

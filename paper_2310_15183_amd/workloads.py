@@ -55,3 +55,18 @@ def kerr_newman_frame(f32_params: bool = True, width: int = 1000, height: int = 
     if f32_params:
         vals = {k: float(np.float32(v)) for k, v in vals.items()}
     return Instance(width=width, height=height, **vals)
+
+
+def sky_texture(width: int, height: int, seed: int = 7) -> np.ndarray:
+    """A seeded synthetic equirectangular sky (height x width 32-bit texels,
+    bytes R, G, B, A): smooth colour gradients across the sphere with seeded
+    random stars, standing in for the paper's panorama (not available)."""
+    rng = np.random.default_rng(seed)
+    j, i = np.meshgrid(np.arange(height), np.arange(width), indexing="ij")
+    r = (40 + 80 * (i / max(width - 1, 1))).astype(np.int64)
+    gch = (30 + 120 * (j / max(height - 1, 1))).astype(np.int64)
+    b = (60 + 60 * ((i + 2 * j) % 64) / 63).astype(np.int64)
+    stars = rng.random((height, width)) < 0.02
+    bright = rng.integers(150, 256, (height, width))
+    r, gch, b = (np.where(stars, bright, c) for c in (r, gch, b))
+    return (r | (gch << 8) | (b << 16) | (255 << 24)).astype(np.uint32)

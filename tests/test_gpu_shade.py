@@ -1,4 +1,4 @@
-"""Shading kernels (the listing's background bands, the exit-time map)
+"""Shading kernels (the sky's three lines, the exit-time map, the sky texture)
 against the oracle's shading on the same arrays: every colour identical."""
 import math
 
@@ -119,3 +119,86 @@ def test_binary32_paths(g, n, offset, mode):
     want = oracle.shade(mode, host(t), host(th), host(ph), fl.cpu().numpy()[offset:],
                         t_max=100.0, band=7.5)
     np.testing.assert_array_equal(got, want)
+
+
+def _texture(g, w, h, seed):
+    import torch
+
+    from paper_2310_15183_amd.workloads import sky_texture
+    tex = sky_texture(w, h, seed)
+    return tex, torch.from_numpy(tex.view(np.int32)).cuda()
+
+
+@pytest.mark.parametrize("dtype_name", ["GR_F64", "GR_F32"])
+def test_texture_shading_of_a_traced_frame(g, dtype_name):
+    """A traced Kerr-Newman frame shaded with a seeded 256 x 128 sky texture
+    (bilinear filtering): every colour identical to the oracle's."""
+    import torch
+
+    import oracle
+    W, H = 64, 48
+    tex, tex_dev = _texture(g, 256, 128, 3)
+    ctx = g.gr_trace_init(0, g.make_integrator(dt=0.01, max_steps=20000))
+    try:
+        out = g.alloc_outputs(W * H, dtype=getattr(g, dtype_name),
+                              fields=("t", "r", "theta", "phi"))
+        g.gr_trace_frame(ctx, g.gr_metric(0.5, 0.24, 0.3),
+                         g.gr_camera(20.0, 80 * DEG, 0.0, 75 * DEG, W, H), out.struct)
+        rgba = torch.empty(W * H, dtype=torch.int32, device="cuda")
+        g.gr_shade_frame(g.shade_texture(tex_dev), out.struct, W * H, rgba)
+        torch.cuda.synchronize()
+        host = {k: v.cpu().numpy() for k, v in out.tensors.items()}
+    finally:
+        g.gr_trace_destroy(ctx)
+    got = rgba.cpu().numpy().view(np.uint32)
+    want = oracle.shade(2, None, host["theta"].astype(np.float64),
+                        host["phi"].astype(np.float64), host["flag"], texture=tex)
+    np.testing.assert_array_equal(got, want)
+    assert len(set(got.tolist())) > 100
+
+
+@pytest.mark.parametrize("n,offset,f32", [((1 << 22) + 1001, 0, True), (4099, 1, True),
+                                          ((1 << 22) + 7, 0, False)])
+def test_texture_shading_of_seeded_rays(g, n, offset, f32):
+    """Seeded synthetic end directions, theta over [-2 pi, 3 pi] (reflections
+    over the poles) and phi over [-30, 30] (wraps), on a 97 x 31 texture (odd
+    sides); binary32 through the four-pixel kernel with a ragged tail and
+    through the one-pixel kernel (arrays one element off a 16-byte
+    boundary), and binary64."""
+    import torch
+
+    import oracle
+    rng = np.random.default_rng(n + offset)
+    m = n + offset
+    dt = np.float32 if f32 else np.float64
+    th = torch.from_numpy(rng.uniform(-2 * math.pi, 3 * math.pi, m).astype(dt)).cuda()
+    ph = torch.from_numpy(rng.uniform(-30.0, 30.0, m).astype(dt)).cuda()
+    fl = torch.from_numpy(rng.choice(np.array([0, 1, 1, 1, 2, 3], np.int8), m)).cuda()
+    tex, tex_dev = _texture(g, 97, 31, 4)
+    ptr = lambda x: x[offset:].data_ptr()      # noqa: E731
+    out = g.gr_output(None, None, ptr(th), ptr(ph), None, None, None, None, ptr(fl), None,
+                      g.GR_F32 if f32 else g.GR_F64)
+    rgba = torch.empty(n, dtype=torch.int32, device="cuda")
+    g.gr_shade_frame(g.shade_texture(tex_dev), out, n, rgba)
+    torch.cuda.synchronize()
+    got = rgba.cpu().numpy().view(np.uint32)
+    host = lambda x: x.cpu().numpy()[offset:].astype(np.float64)     # noqa: E731
+    want = oracle.shade(2, None, host(th), host(ph), fl.cpu().numpy()[offset:], texture=tex)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_texture_shading_invalid_arguments(g):
+    import torch
+    out = g.alloc_outputs(16, fields=("theta", "phi"))
+    rgba = torch.empty(16, dtype=torch.int32, device="cuda")
+    tex = torch.zeros(4, 8, dtype=torch.int32, device="cuda")
+    bad = [g.gr_shade(g.GR_SHADE_TEXTURE, 0.0, 0.0, None, 8, 4),
+           g.gr_shade(g.GR_SHADE_TEXTURE, 0.0, 0.0, tex.data_ptr(), 0, 4),
+           g.gr_shade(g.GR_SHADE_TEXTURE, 0.0, 0.0, tex.data_ptr(), 8, 0)]
+    for sh in bad:
+        with pytest.raises(g.GrError) as e:
+            g.gr_shade_frame(sh, out.struct, 16, rgba)
+        assert e.value.code == g.GR_EINVAL
+    out2 = g.alloc_outputs(16, fields=("t",))
+    with pytest.raises(g.GrError):
+        g.gr_shade_frame(g.shade_texture(tex), out2.struct, 16, rgba)
