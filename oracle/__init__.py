@@ -191,7 +191,8 @@ def trace_frame(M, a, Q, r0, theta0, phi0, fov, width, height, dt=0.01, eps=1e-8
                 threads=None, want_p0=False, method=0, disk=None, form="listing",
                 probe=0) -> Result:
     """Trace the camera rays of a width x height frame (or the listed pixels);
-    method 0 is RK4, 1 explicit Euler; disk = (r_in, r_out, half_angle) adds
+    method 0 is RK4, 1 explicit Euler, 2 RK4 in coordinate time (each stage
+    reparametrised); disk = (r_in, r_out, half_angle) adds
     the solid equatorial ring (flag 4 on hitting it).  form "listing" (default)
     or "twin" (see the module docstring); probe (listing form, 0..4) adds the
     per-ray sensitivity."""

@@ -70,7 +70,7 @@ typedef struct {
     double M, a, Q;                  /* Kerr-Newman mass, spin length, charge */
     double alpha, k, beta;           /* Manko-Novikov constants from (M, S, q) */
     double dt, eps, hnorm, esc;
-    int max_steps, euler;
+    int max_steps, method;           /* 0 RK4, 1 explicit Euler, 2 RK4 in coordinate time */
     double ring_in, ring_out, ring_dth;   /* ring off when ring_dth <= 0 */
 } lspec;
 
@@ -248,8 +248,24 @@ static int integrate(const lspec *L, double y[8], int *nsteps)
         hamilton(L, y, k1);
         const double nu = fabs(k1[0]);
         const double h = L->dt / nu;
-        if (L->euler) {
+        if (L->method == 1) {
             for (int m = 0; m < 8; ++m) y[m] = y[m] + h * k1[m];
+        } else if (L->method == 2) {
+            /* RK4 with coordinate time as the parameter: every stage's
+             * derivative is divided by its own |dt/dtau|, and the step is dt */
+            const double n1 = nu;
+            for (int m = 0; m < 8; ++m) z[m] = y[m] + 0.5 * L->dt * (k1[m] / n1);
+            hamilton(L, z, k2);
+            const double n2 = fabs(k2[0]);
+            for (int m = 0; m < 8; ++m) z[m] = y[m] + 0.5 * L->dt * (k2[m] / n2);
+            hamilton(L, z, k3);
+            const double n3 = fabs(k3[0]);
+            for (int m = 0; m < 8; ++m) z[m] = y[m] + L->dt * (k3[m] / n3);
+            hamilton(L, z, k4);
+            const double n4 = fabs(k4[0]);
+            for (int m = 0; m < 8; ++m)
+                y[m] = y[m] + L->dt / 6.0 * (k1[m] / n1 + 2.0 * (k2[m] / n2) +
+                                             2.0 * (k3[m] / n3) + k4[m] / n4);
         } else {
             for (int m = 0; m < 8; ++m) z[m] = y[m] + 0.5 * h * k1[m];
             hamilton(L, z, k2);
@@ -423,7 +439,7 @@ static void mn_setup(lspec *L, double M, double S, double q)
 
 /* Trace pixels of a frame in the listing form.  kind 0: (p1, p2, p3) =
  * (M, a, Q) Kerr-Newman; kind 1: (M, S, q) Manko-Novikov.  method 0 RK4,
- * 1 Euler; ring = (r_in, r_out, half angle) or NULL.  out8 receives the end
+ * 1 Euler, 2 RK4 in coordinate time; ring = (r_in, r_out, half angle) or NULL.  out8 receives the end
  * (t, r, theta, phi, p_t, p_r, p_theta, p_phi) of every ray; with nprobe > 0
  * (at most 4) each ray is re-run from that many perturbed starts and sens/flip
  * receive the largest end-angle change and whether flag or steps changed. */
@@ -442,7 +458,7 @@ int64_t listing_trace_frame(int kind, double p1, double p2, double p3, double r0
         L.M = p1; L.a = p2; L.Q = p3;
     }
     L.dt = dt; L.eps = eps; L.hnorm = horizon_norm; L.esc = escape_factor;
-    L.max_steps = max_steps; L.euler = method == 1;
+    L.max_steps = max_steps; L.method = method;
     if (ring) { L.ring_in = ring[0]; L.ring_out = ring[1]; L.ring_dth = ring[2]; }
     ljob J;
     memset(&J, 0, sizeof J);
@@ -471,7 +487,7 @@ int64_t listing_trace_rays(int kind, double p1, double p2, double p3, double dt,
         L.M = p1; L.a = p2; L.Q = p3;
     }
     L.dt = dt; L.eps = eps; L.hnorm = horizon_norm; L.esc = escape_factor;
-    L.max_steps = max_steps; L.euler = method == 1;
+    L.max_steps = max_steps; L.method = method;
     ljob J;
     memset(&J, 0, sizeof J);
     J.L = &L; J.init = init; J.n = n; J.nprobe = nprobe;

@@ -75,7 +75,8 @@ typedef struct {
     int max_steps;
     int trig_mode;               /* 0: trig_sincos below; 1: C library sin/cos */
     int kind;                    /* METRIC_KN or METRIC_MN */
-    int method;                  /* 0: RK4 (Sec. 3.1.2); 1: explicit Euler (Sec. 3.1.1) */
+    int method;                  /* 0: RK4 (Sec. 3.1.2); 1: explicit Euler (Sec. 3.1.1);
+                                    2: RK4 with coordinate time as the parameter */
     /* solid equatorial ring (Sec. 3.3.2, 3.3.3): a ray stops when a step ends
      * with disk_r_in <= r <= disk_r_out and |theta - pi/2| <= disk_dth;
      * off when disk_dth <= 0 */
@@ -518,6 +519,48 @@ int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nste
             for (int m = 0; m < 4; ++m) q[m] = fma(h, k1q[m], q[m]);
             pr = fma(h, k1p[0], pr);
             pth = fma(h, k1p[1], pth);
+            if (in_disk(P, q)) { flag = FLAG_DISK; break; }
+            if (q[1] > r_esc) { flag = FLAG_ESCAPE; break; }
+            if (nu > P->horizon_norm) { flag = FLAG_HORIZON; break; }
+            if (!all_finite(q, pr, pth)) { flag = FLAG_INVALID; break; }
+            continue;
+        }
+        if (P->method == 2) {
+            /* RK4 with coordinate time as the parameter (each stage
+             * reparametrised): a stage's derivative is multiplied by
+             * w = 1/|dt/dtau| at that stage, so every stage moves t at the
+             * same rate, and the step is dt itself. */
+            const double hh = 0.5 * P->dt;
+            double w;
+            hamilton_rhs(P, eps_sc, q[1], q[2], pt, pr, pth, pph, k1q, k1p);
+            const double nu = fabs(k1q[0]);
+            w = 1.0 / nu;
+            for (int m = 0; m < 4; ++m) k1q[m] = k1q[m] * w;
+            k1p[0] = k1p[0] * w;
+            k1p[1] = k1p[1] * w;
+            hamilton_rhs(P, eps_sc, fma(hh, k1q[1], q[1]), fma(hh, k1q[2], q[2]), pt,
+                         fma(hh, k1p[0], pr), fma(hh, k1p[1], pth), pph, k2q, k2p);
+            w = 1.0 / fabs(k2q[0]);
+            for (int m = 0; m < 4; ++m) k2q[m] = k2q[m] * w;
+            k2p[0] = k2p[0] * w;
+            k2p[1] = k2p[1] * w;
+            hamilton_rhs(P, eps_sc, fma(hh, k2q[1], q[1]), fma(hh, k2q[2], q[2]), pt,
+                         fma(hh, k2p[0], pr), fma(hh, k2p[1], pth), pph, k3q, k3p);
+            w = 1.0 / fabs(k3q[0]);
+            for (int m = 0; m < 4; ++m) k3q[m] = k3q[m] * w;
+            k3p[0] = k3p[0] * w;
+            k3p[1] = k3p[1] * w;
+            hamilton_rhs(P, eps_sc, fma(P->dt, k3q[1], q[1]), fma(P->dt, k3q[2], q[2]), pt,
+                         fma(P->dt, k3p[0], pr), fma(P->dt, k3p[1], pth), pph, k4q, k4p);
+            w = 1.0 / fabs(k4q[0]);
+            for (int m = 0; m < 4; ++m) k4q[m] = k4q[m] * w;
+            k4p[0] = k4p[0] * w;
+            k4p[1] = k4p[1] * w;
+            const double h6 = P->dt * (1.0 / 6.0);
+            for (int m = 0; m < 4; ++m)
+                q[m] = fma(h6, ((k1q[m] + 2.0 * k2q[m]) + 2.0 * k3q[m]) + k4q[m], q[m]);
+            pr = fma(h6, ((k1p[0] + 2.0 * k2p[0]) + 2.0 * k3p[0]) + k4p[0], pr);
+            pth = fma(h6, ((k1p[1] + 2.0 * k2p[1]) + 2.0 * k3p[1]) + k4p[1], pth);
             if (in_disk(P, q)) { flag = FLAG_DISK; break; }
             if (q[1] > r_esc) { flag = FLAG_ESCAPE; break; }
             if (nu > P->horizon_norm) { flag = FLAG_HORIZON; break; }
