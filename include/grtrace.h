@@ -113,18 +113,24 @@ typedef struct {
 
 /* Integration method (arXiv 2310.15183, Sec. 3.1).
  * GR_RK4: classical Runge-Kutta with the step h = dt / |dt/dtau| fixed from
- *   the first stage (Sec. 3.1.2).
+ *   the first stage (Sec. 3.1.2, as in the appendix listing).
  * GR_EULER: explicit Euler, x += h f(x) with the same h (Sec. 3.1.1); first
- *   order, for the accuracy/cost comparison of Sec. 3.2.  Binary64 frames
- *   only (gr_trace_frame, gr_trace_frame_mn): batches, the surrogate and
- *   GR_MIXED return GR_EUNSUPPORTED. */
-enum { GR_RK4 = 0, GR_EULER = 1 };
+ *   order, for the accuracy/cost comparison of Sec. "Resolution and
+ *   Calculation Speed".
+ * GR_RK4_TIME: classical Runge-Kutta with coordinate time as the parameter,
+ *   each stage reparametrised: every stage's derivative is divided by that
+ *   stage's own |dt/dtau|, the stage points are x + dt/2 k1, x + dt/2 k2,
+ *   x + dt k3, so each step advances t by exactly dt (fourth order in dt).
+ * GR_EULER and GR_RK4_TIME: binary64 frames only (gr_trace_frame,
+ *   gr_trace_frame_mn): batches, the surrogate and GR_MIXED return
+ *   GR_EUNSUPPORTED. */
+enum { GR_RK4 = 0, GR_EULER = 1, GR_RK4_TIME = 2 };
 
 /* Integrator settings.  dt > 0 is the coordinate-time step, fd_eps > 0 the
  * forward-difference step, horizon_norm > 0 the |dt/dtau| at which a ray is
  * declared captured, escape_factor > 1 the escape radius in units of r0,
  * max_steps >= 0 the step limit (0 returns the initial state), precision
- * GR_FP64 or GR_MIXED, method GR_RK4 or GR_EULER.
+ * GR_FP64 or GR_MIXED, method GR_RK4, GR_EULER or GR_RK4_TIME.
  * Suggested: 0.01, 1e-8, 1e4, 1.5, 20000, GR_FP64, GR_RK4. */
 typedef struct {
     double dt, fd_eps, horizon_norm, escape_factor;

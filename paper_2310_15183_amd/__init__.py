@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libgrtrace.so")
 GR_OK, GR_EINVAL, GR_ENOMEM, GR_EDEVICE, GR_EUNSUPPORTED = 0, -1, -2, -3, -4
 GR_FLAG_TIMEOUT, GR_FLAG_ESCAPE, GR_FLAG_HORIZON, GR_FLAG_INVALID, GR_FLAG_DISK = 0, 1, 2, 3, 4
 GR_FP64, GR_MIXED = 0, 1
-GR_RK4, GR_EULER = 0, 1
+GR_RK4, GR_EULER, GR_RK4_TIME = 0, 1, 2
 GR_SHADE_BANDS, GR_SHADE_TIME, GR_SHADE_TEXTURE = 0, 1, 2
 GR_F64, GR_F32 = 0, 1
 GR_NOALLOC_MAX_INSTANCES = 512

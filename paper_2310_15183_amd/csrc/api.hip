@@ -111,8 +111,9 @@ int check_integrator(const gr_integrator* in) {
     if (!(finite(in->escape_factor) && in->escape_factor > 1.0)) return GR_EINVAL;
     if (in->max_steps < 0) return GR_EINVAL;
     if (in->precision != GR_FP64 && in->precision != GR_MIXED) return GR_EINVAL;
-    if (in->method != GR_RK4 && in->method != GR_EULER) return GR_EINVAL;
-    if (in->method == GR_EULER && in->precision != GR_FP64) return GR_EUNSUPPORTED;
+    if (in->method != GR_RK4 && in->method != GR_EULER && in->method != GR_RK4_TIME)
+        return GR_EINVAL;
+    if (in->method != GR_RK4 && in->precision != GR_FP64) return GR_EUNSUPPORTED;
     if (in->disk_half_angle != 0.0) {
         if (!(in->disk_half_angle > 0.0 && in->disk_half_angle < M_PI / 2)) return GR_EINVAL;
         if (!(finite(in->disk_r_in) && finite(in->disk_r_out) && in->disk_r_in >= 0.0 &&
@@ -763,16 +764,17 @@ int gr_trace_frame(gr_ctx* ctx, const gr_metric* m, const gr_camera* c, const gr
         return GR_OK;
     }
     gr::LaunchShape L = frame_shape(ctx, A, f32);
-    const bool euler = ctx->integ.method == GR_EULER, disk = has_disk(ctx->integ);
-    if ((euler || disk) && L.refill) {
-        // Euler steps and the ring exist in the one-ray-per-lane kernel only
+    const int method = ctx->integ.method;
+    const bool disk = has_disk(ctx->integ);
+    if ((method != GR_RK4 || disk) && L.refill) {
+        // the other methods and the ring exist in the one-ray-per-lane kernel only
         const int64_t tiles = ((int64_t)c->width + 7) / 8 * (((int64_t)c->height + 7) / 8);
         if (tiles > INT32_MAX) return GR_EUNSUPPORTED;
         L.block = 64;
         L.refill = 0;
         L.grid = (int)tiles;
     }
-    e = gr::launch_trace_fp64(A, f32, euler, disk, L, ctx->counter, (hipStream_t)hip_stream);
+    e = gr::launch_trace_fp64(A, f32, method, disk, L, ctx->counter, (hipStream_t)hip_stream);
     if (e != hipSuccess) return device_error(e, "trace_fp64 launch");
     return GR_OK;
 }
@@ -820,8 +822,8 @@ int gr_trace_frame_mn(gr_ctx* ctx, const gr_metric_mn* m, const gr_camera* c,
         L2.grid = (int)std::max<int64_t>(1, std::min(resident, (park.capacity + 63) / 64));
     }
     const hipError_t e = gr::launch_trace_mn(A, K, out->dtype == GR_F32,
-                                             ctx->integ.method == GR_EULER,
-                                             has_disk(ctx->integ), L, park, L2,
+                                             ctx->integ.method, has_disk(ctx->integ), L, park,
+                                             L2,
                                              (hipStream_t)hip_stream);
     if (e != hipSuccess) return device_error(e, "trace_mn launch");
     return GR_OK;

@@ -101,7 +101,7 @@ size_t frame_order_temp(int64_t npix);
 hipError_t launch_reset_counter(unsigned long long* counter, hipStream_t s);
 
 // FP64 frame tracer.  f32_out selects binary32 outputs.
-hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, bool euler, bool disk,
+hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, int method, bool disk,
                              const LaunchShape& L, unsigned long long* counter, hipStream_t s);
 
 // Workgroups of `block` threads that fit on one CU for the FP64 tracer.
@@ -138,7 +138,7 @@ struct Parked {
 // A Manko-Novikov frame, one ray per lane over 8x8 pixel tiles (L.refill
 // must be 0), then (park.cap > 0) the parked rays in a persistent launch of
 // shape L2; A.hole is not used.
-hipError_t launch_trace_mn(const FrameArgs& A, const MnHole& K, bool f32_out, bool euler,
+hipError_t launch_trace_mn(const FrameArgs& A, const MnHole& K, bool f32_out, int method,
                            bool disk, const LaunchShape& L, const Parked& park,
                            const LaunchShape& L2, hipStream_t s);
 int occupancy_trace_mn_resume(int block);

@@ -184,6 +184,50 @@ static __device__ __forceinline__ double rk4_generic(const Rhs& rhs_at, const In
     return nu;
 }
 
+// One RK4 step with coordinate time as the parameter (RK4 of Sec. 3.1.2
+// applied to dx/dt = f(x)/|dt/dtau|): each stage's derivative is multiplied
+// by w = 1/|dt/dtau| of that stage, the stage points are x + (dt/2) k1,
+// x + (dt/2) k2, x + dt k3, and the update is x += dt/6 (k1 + 2 k2 + 2 k3 +
+// k4), so t advances by dt every step; returns nu of the first stage.
+// Divisions IEEE (1/inf = 0 near the Manko-Novikov ring).
+template <class Rhs>
+static __device__ __forceinline__ double rk4t_generic(const Rhs& rhs_at, const Integrator& in,
+                                                      Ray& y) {
+    const auto per_t = [](Deriv& k) {
+        const double w = 1.0 / fabs(k.qt);
+        k.qt = k.qt * w; k.qr = k.qr * w; k.qh = k.qh * w; k.qp = k.qp * w;
+        k.pr = k.pr * w; k.ph = k.ph * w;
+    };
+    const double hh = 0.5 * in.dt;
+    Deriv k = rhs_at(y.r, y.th, y.pr, y.pth);
+    const double nu = fabs(k.qt);
+    per_t(k);
+    double st = k.qt, sr = k.qr, sh = k.qh, sp = k.qp, spr = k.pr, sph = k.ph;
+    k = rhs_at(fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), fma(hh, k.pr, y.pr),
+               fma(hh, k.ph, y.pth));
+    per_t(k);
+    st = fma(2.0, k.qt, st); sr = fma(2.0, k.qr, sr); sh = fma(2.0, k.qh, sh);
+    sp = fma(2.0, k.qp, sp); spr = fma(2.0, k.pr, spr); sph = fma(2.0, k.ph, sph);
+    k = rhs_at(fma(hh, k.qr, y.r), fma(hh, k.qh, y.th), fma(hh, k.pr, y.pr),
+               fma(hh, k.ph, y.pth));
+    per_t(k);
+    st = fma(2.0, k.qt, st); sr = fma(2.0, k.qr, sr); sh = fma(2.0, k.qh, sh);
+    sp = fma(2.0, k.qp, sp); spr = fma(2.0, k.pr, spr); sph = fma(2.0, k.ph, sph);
+    k = rhs_at(fma(in.dt, k.qr, y.r), fma(in.dt, k.qh, y.th), fma(in.dt, k.pr, y.pr),
+               fma(in.dt, k.ph, y.pth));
+    per_t(k);
+    st = st + k.qt; sr = sr + k.qr; sh = sh + k.qh; sp = sp + k.qp;
+    spr = spr + k.pr; sph = sph + k.ph;
+    const double h6 = in.dt * (1.0 / 6.0);
+    y.t = fma(h6, st, y.t);
+    y.r = fma(h6, sr, y.r);
+    y.th = fma(h6, sh, y.th);
+    y.ph = fma(h6, sp, y.ph);
+    y.pr = fma(h6, spr, y.pr);
+    y.pth = fma(h6, sph, y.pth);
+    return nu;
+}
+
 // One explicit Euler step x += h f(x) with the same h = dt/|dt/dtau| (paper
 // Sec. 3.1.1); returns nu.
 template <class Rhs>
@@ -292,22 +336,28 @@ static __device__ __forceinline__ double rk4_step_direct(const Hole& H, const In
         in, y);
 }
 
-// One explicit Euler step on Kerr-Newman (sin/cos of theta by sincos_def).
-static __device__ __forceinline__ double kn_euler_step(const Hole& H, const Integrator& in,
-                                                       Ray& y) {
-    return euler_generic(
-        [&](double r, double th, double pr, double pth) {
-            return rhs(H, in, r, th, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
-        },
-        in, y);
+// Methods of the one-ray-per-lane kernels (the values of gr_integrator.method).
+enum { M_RK4 = 0, M_EULER = 1, M_RK4_TIME = 2 };
+
+// One explicit Euler or coordinate-time RK4 step on Kerr-Newman (sin/cos of
+// theta by sincos_def at every point).
+template <int METHOD>
+static __device__ __forceinline__ double kn_direct_step(const Hole& H, const Integrator& in,
+                                                        Ray& y) {
+    const auto f = [&](double r, double th, double pr, double pth) {
+        return rhs(H, in, r, th, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
+    };
+    if constexpr (METHOD == M_EULER) return euler_generic(f, in, y);
+    else return rk4t_generic(f, in, y);
 }
 
-template <bool EULER>
+template <int METHOD>
 static __device__ __forceinline__ double mn_step(const MnHole& K, const Integrator& in, Ray& y) {
     const auto f = [&](double r, double th, double pr, double pth) {
         return rhs_mn(K, in, r, th, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
     };
-    if constexpr (EULER) return euler_generic(f, in, y);
+    if constexpr (METHOD == M_EULER) return euler_generic(f, in, y);
+    else if constexpr (METHOD == M_RK4_TIME) return rk4t_generic(f, in, y);
     else return rk4_generic(f, in, y);
 }
 

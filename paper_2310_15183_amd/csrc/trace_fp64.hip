@@ -24,9 +24,10 @@ namespace {
 
 using namespace detail;
 
-// One lane, one ray (static_ray); the grid covers every ray.  EULER selects
-// explicit Euler steps in place of RK4, DISK adds the ring's exit test.
-template <typename T, bool EULER, bool DISK>
+// One lane, one ray (static_ray); the grid covers every ray.  METHOD selects
+// RK4 (the carried form), explicit Euler or RK4 in coordinate time; DISK adds
+// the ring's exit test.
+template <typename T, int METHOD, bool DISK>
 __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
     int64_t k, pix;
     if (!static_ray(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, k, pix)) return;
@@ -34,9 +35,9 @@ __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
     start_ray(A.cam, pix, y);
     int s = 0;
     int f = start_flag(A.in, y);
-    if constexpr (EULER) {
+    if constexpr (METHOD != M_RK4) {
         while (f == RUNNING) {
-            const double nu = kn_euler_step(A.hole, A.in, y);
+            const double nu = kn_direct_step<METHOD>(A.hole, A.in, y);
             ++s;
             f = exit_flag<DISK>(A.in, A.r_esc, y, nu, s);
         }
@@ -275,27 +276,34 @@ static hipError_t launch_redo(const FrameArgs& A, bool f32_out, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <bool EULER, bool DISK>
+template <int METHOD, bool DISK>
 static hipError_t launch_static(const FrameArgs& A, bool f32_out, const LaunchShape& L,
                                 hipStream_t s) {
     if (f32_out)
-        hipLaunchKernelGGL((trace_fp64_static<float, EULER, DISK>), dim3(L.grid), dim3(L.block),
+        hipLaunchKernelGGL((trace_fp64_static<float, METHOD, DISK>), dim3(L.grid), dim3(L.block),
                            0, s, A);
     else
-        hipLaunchKernelGGL((trace_fp64_static<double, EULER, DISK>), dim3(L.grid), dim3(L.block),
-                           0, s, A);
+        hipLaunchKernelGGL((trace_fp64_static<double, METHOD, DISK>), dim3(L.grid),
+                           dim3(L.block), 0, s, A);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || EULER) return e;
+    if (e != hipSuccess || METHOD != M_RK4) return e;
     return launch_redo<DISK>(A, f32_out, s);
 }
 
-hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, bool euler, bool disk,
+template <int METHOD>
+static hipError_t launch_static_disk(const FrameArgs& A, bool f32_out, bool disk,
+                                     const LaunchShape& L, hipStream_t s) {
+    return disk ? launch_static<METHOD, true>(A, f32_out, L, s)
+                : launch_static<METHOD, false>(A, f32_out, L, s);
+}
+
+hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, int method, bool disk,
                              const LaunchShape& L, unsigned long long* counter, hipStream_t s) {
-    if (euler || disk) {                          // one ray per lane only
+    if (method != M_RK4 || disk) {               // one ray per lane only
         if (L.refill) return hipErrorInvalidValue;
-        if (euler && disk) return launch_static<true, true>(A, f32_out, L, s);
-        if (euler) return launch_static<true, false>(A, f32_out, L, s);
-        return launch_static<false, true>(A, f32_out, L, s);
+        if (method == M_EULER) return launch_static_disk<M_EULER>(A, f32_out, disk, L, s);
+        if (method == M_RK4_TIME) return launch_static_disk<M_RK4_TIME>(A, f32_out, disk, L, s);
+        return launch_static<M_RK4, true>(A, f32_out, L, s);
     }
     if (L.refill) {
         hipError_t e = launch_reset_counter(counter, s);
@@ -310,7 +318,7 @@ hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, bool euler, bool 
         if (e != hipSuccess) return e;
         return launch_redo<false>(A, f32_out, s);
     }
-    return launch_static<false, false>(A, f32_out, L, s);
+    return launch_static<M_RK4, false>(A, f32_out, L, s);
 }
 
 hipError_t launch_trace_fp64_batch(const BatchArgs& B, const LaunchShape& L,

@@ -28,17 +28,17 @@ struct MnArgs {
     Parked park;
 };
 
-template <bool EULER, bool DISK>
+template <int METHOD, bool DISK>
 __device__ __forceinline__ int run(const MnArgs& X, Ray& y, int& s, int f, int cap) {
     while (f == RUNNING && s < cap) {
-        const double nu = mn_step<EULER>(X.mn, X.f.in, y);
+        const double nu = mn_step<METHOD>(X.mn, X.f.in, y);
         ++s;
         f = exit_flag<DISK>(X.f.in, X.f.r_esc, y, nu, s);
     }
     return f;
 }
 
-template <typename T, bool EULER, bool DISK>
+template <typename T, int METHOD, bool DISK>
 __global__ void __launch_bounds__(256) trace_mn_static(const MnArgs X) {
     const FrameArgs& A = X.f;
     const Parked& P = X.park;
@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(256) trace_mn_static(const MnArgs X) {
     Ray y;
     start_ray(A.cam, pix, y);
     int s = 0;
-    int f = run<EULER, DISK>(X, y, s, start_flag(A.in, y), P.cap > 0 ? P.cap : INT_MAX);
+    int f = run<METHOD, DISK>(X, y, s, start_flag(A.in, y), P.cap > 0 ? P.cap : INT_MAX);
     // park the rays still running (every active lane takes part in the ballot)
     const int64_t slot = take_ids(f == RUNNING, P.count);
     if (slot >= 0 && slot < P.capacity) {
@@ -61,13 +61,13 @@ __global__ void __launch_bounds__(256) trace_mn_static(const MnArgs X) {
         P.pix[slot] = pix;
         return;
     }
-    f = run<EULER, DISK>(X, y, s, f, INT_MAX);    // no room left: finish here
+    f = run<METHOD, DISK>(X, y, s, f, INT_MAX);    // no room left: finish here
     write_ray<T>(A.out, k, y, f, s);
 }
 
 // Second launch: the parked rays (their number is read from the device),
 // resident waves striding over the list.
-template <typename T, bool EULER, bool DISK>
+template <typename T, int METHOD, bool DISK>
 __global__ void __launch_bounds__(256) trace_mn_resume(const MnArgs X) {
     const FrameArgs& A = X.f;
     const Parked& P = X.park;
@@ -85,14 +85,14 @@ __global__ void __launch_bounds__(256) trace_mn_resume(const MnArgs X) {
         y.pr = P.y[4 * P.capacity + q];
         y.pth = P.y[5 * P.capacity + q];
         int s = P.steps[q];
-        const int f = run<EULER, DISK>(X, y, s, RUNNING, INT_MAX);
+        const int f = run<METHOD, DISK>(X, y, s, RUNNING, INT_MAX);
         write_ray<T>(A.out, pix, y, f, s);
     }
 }
 
 }  // namespace
 
-template <bool EULER, bool DISK>
+template <int METHOD, bool DISK>
 static hipError_t launch_mn(const MnArgs& X, bool f32_out, const LaunchShape& L,
                             const LaunchShape& L2, hipStream_t s) {
     if (X.park.cap > 0) {
@@ -100,39 +100,45 @@ static hipError_t launch_mn(const MnArgs& X, bool f32_out, const LaunchShape& L,
         if (e != hipSuccess) return e;
     }
     if (f32_out)
-        hipLaunchKernelGGL((trace_mn_static<float, EULER, DISK>), dim3(L.grid), dim3(L.block), 0,
+        hipLaunchKernelGGL((trace_mn_static<float, METHOD, DISK>), dim3(L.grid), dim3(L.block), 0,
                            s, X);
     else
-        hipLaunchKernelGGL((trace_mn_static<double, EULER, DISK>), dim3(L.grid), dim3(L.block), 0,
+        hipLaunchKernelGGL((trace_mn_static<double, METHOD, DISK>), dim3(L.grid), dim3(L.block), 0,
                            s, X);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || X.park.cap <= 0) return e;
     if (f32_out)
-        hipLaunchKernelGGL((trace_mn_resume<float, EULER, DISK>), dim3(L2.grid), dim3(L2.block),
+        hipLaunchKernelGGL((trace_mn_resume<float, METHOD, DISK>), dim3(L2.grid), dim3(L2.block),
                            0, s, X);
     else
-        hipLaunchKernelGGL((trace_mn_resume<double, EULER, DISK>), dim3(L2.grid), dim3(L2.block),
+        hipLaunchKernelGGL((trace_mn_resume<double, METHOD, DISK>), dim3(L2.grid), dim3(L2.block),
                            0, s, X);
     return hipGetLastError();
 }
 
-hipError_t launch_trace_mn(const FrameArgs& A, const MnHole& K, bool f32_out, bool euler,
+template <int METHOD>
+static hipError_t launch_mn_disk(const MnArgs& X, bool f32_out, bool disk, const LaunchShape& L,
+                                 const LaunchShape& L2, hipStream_t s) {
+    return disk ? launch_mn<METHOD, true>(X, f32_out, L, L2, s)
+                : launch_mn<METHOD, false>(X, f32_out, L, L2, s);
+}
+
+hipError_t launch_trace_mn(const FrameArgs& A, const MnHole& K, bool f32_out, int method,
                            bool disk, const LaunchShape& L, const Parked& park,
                            const LaunchShape& L2, hipStream_t s) {
     MnArgs X;
     X.f = A;
     X.mn = K;
     X.park = park;
-    if (euler && disk) return launch_mn<true, true>(X, f32_out, L, L2, s);
-    if (euler) return launch_mn<true, false>(X, f32_out, L, L2, s);
-    if (disk) return launch_mn<false, true>(X, f32_out, L, L2, s);
-    return launch_mn<false, false>(X, f32_out, L, L2, s);
+    if (method == M_EULER) return launch_mn_disk<M_EULER>(X, f32_out, disk, L, L2, s);
+    if (method == M_RK4_TIME) return launch_mn_disk<M_RK4_TIME>(X, f32_out, disk, L, L2, s);
+    return launch_mn_disk<M_RK4>(X, f32_out, disk, L, L2, s);
 }
 
 int occupancy_trace_mn_resume(int block) {
     int n = 0;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-               &n, trace_mn_resume<float, false, false>, block, 0) == hipSuccess
+               &n, trace_mn_resume<float, M_RK4, false>, block, 0) == hipSuccess
                ? n
                : 0;
 }

@@ -96,9 +96,10 @@ def test_extremal_and_flat_metrics_are_valid():
 
 
 @pytest.mark.parametrize("fields,code", [
-    ({"method": 2}, "GR_EINVAL"),
+    ({"method": 3}, "GR_EINVAL"),
     ({"method": -1}, "GR_EINVAL"),
     ({"method": 1, "precision": 1}, "GR_EUNSUPPORTED"),
+    ({"method": 2, "precision": 1}, "GR_EUNSUPPORTED"),
     ({"disk_r_in": 2.0, "disk_r_out": 5.0, "disk_half_angle": math.pi / 2}, "GR_EINVAL"),
     ({"disk_r_in": 5.0, "disk_r_out": 2.0, "disk_half_angle": 0.02}, "GR_EINVAL"),
     ({"disk_r_in": -1.0, "disk_r_out": 2.0, "disk_half_angle": 0.02}, "GR_EINVAL"),
@@ -117,6 +118,8 @@ def test_validation_of_method_and_ring(fields, code):
 def test_method_and_ring_accepted():
     m, c, _, o = _valid()
     for integ in [g.make_integrator(method=g.GR_EULER),
+                  g.make_integrator(method=g.GR_RK4_TIME),
+                  g.make_integrator(method=g.GR_RK4_TIME, disk=(2.0, 5.0, 0.3)),
                   g.make_integrator(disk=(0.0, 5.0, 0.02)),
                   g.make_integrator(method=g.GR_EULER, disk=(2.0, 5.0, 0.3))]:
         assert g.gr_trace_validate(m, c, integ, o) == g.GR_OK

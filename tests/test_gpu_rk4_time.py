@@ -1,0 +1,124 @@
+"""RK4 with coordinate time as the parameter (GR_RK4_TIME, each stage
+divided by its own |dt/dtau|) on the GPU: every field bit-identical to the
+oracle's kernel-twin form on Kerr-Newman frames (binary64 and binary32
+outputs, with the ring, whatever launch shape is asked for), Manko-Novikov
+frames (with rays parked and continued), a sampled 1000^2 frame; within the
+per-ray sensitivity bound of the listing form; refused where it is not
+built."""
+import math
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import DEG, compare, fp32_round, gpu_trace
+from tests.sens_gate import compare_at_sensitivity
+
+pytestmark = pytest.mark.gpu
+
+RING = (2.0, 5.0, 0.02)
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2310_15183_amd as g
+    return g
+
+
+def _twin(case, integ, mn=False, pixels=None, disk=None):
+    import oracle
+    trace = oracle.trace_frame_mn if mn else oracle.trace_frame
+    res = trace(*case, dt=integ.dt, eps=integ.fd_eps, horizon_norm=integ.horizon_norm,
+                escape_factor=integ.escape_factor, max_steps=integ.max_steps, pixels=pixels,
+                want_p0=True, form="twin", method=2, disk=disk)
+    return {"t": res.t, "r": res.r, "theta": res.theta, "phi": res.phi, "p_t": res.p0[:, 0],
+            "p_r": res.pr, "p_theta": res.ptheta, "p_phi": res.p0[:, 3], "flag": res.flag,
+            "steps": res.steps}
+
+
+@pytest.mark.parametrize("case,dtype,launch,disk", [
+    ((0.5, 0.24, 0.3, 20.0, 80 * DEG, 0.0, 75 * DEG, 37, 23), "GR_F64", None, None),
+    ((0.5, 0.49, 0.0, 20.0, 60 * DEG, 0.0, 75 * DEG, 30, 30), "GR_F32", (256, 0, 1, 0), None),
+    ((0.5, 0.49, 0.0, 20.0, 80 * DEG, 0.0, 50 * DEG, 32, 24), "GR_F64", None, RING),
+    ((0.0, 0.3, 0.0, 20.0, 70 * DEG, 0.3, 75 * DEG, 13, 7), "GR_F64", None, None),   # flat
+])
+def test_kerr_newman_frames_are_bit_exact(g, case, dtype, launch, disk):
+    integ = g.make_integrator(dt=0.01, max_steps=20000, method=g.GR_RK4_TIME, disk=disk)
+    ctx = g.gr_trace_init(0, integ)
+    try:
+        if launch is not None:
+            g.gr_trace_set_launch(ctx, g.gr_launch(*launch))     # ignored: one ray per lane
+        gpu = gpu_trace(ctx, *case, dtype=getattr(g, dtype))
+    finally:
+        g.gr_trace_destroy(ctx)
+    ref = _twin(case, integ, disk=disk)
+    st = compare(gpu, ref, angle_tol=0.0, f32=dtype == "GR_F32")
+    assert st["bit_identical"] == st["n"]
+    ok = ref["flag"] != 3
+    np.testing.assert_allclose(ref["t"][ok], -0.01 * ref["steps"][ok], rtol=0, atol=1e-9)
+    if disk is not None:
+        assert (ref["flag"] == 4).sum() > 20
+
+
+@pytest.mark.parametrize("max_steps", [20000, 50000])
+def test_manko_novikov_frames_are_bit_exact(g, max_steps):
+    """The listing's spacetime (M = 0.5, S = 0.24, q = 2); with 50000 steps the
+    rays still running at a quarter of the limit are parked and continued."""
+    import torch
+    case = (0.5, 0.24, 2.0, 8.0, math.pi / 2, 0.0, 75 * DEG, 24, 24)
+    integ = g.make_integrator(dt=0.01, max_steps=max_steps, method=g.GR_RK4_TIME)
+    ctx = g.gr_trace_init(0, integ)
+    try:
+        out = g.alloc_outputs(24 * 24, fields=g.FIELDS)
+        g.gr_trace_frame_mn(ctx, g.gr_metric_mn(*case[:3]), g.gr_camera(*case[3:]), out.struct)
+        torch.cuda.synchronize()
+        gpu = {k: v.cpu().numpy() for k, v in out.tensors.items()}
+    finally:
+        g.gr_trace_destroy(ctx)
+    st = compare(gpu, _twin(case, integ, mn=True), angle_tol=0.0)
+    assert st["bit_identical"] == st["n"]
+
+
+def test_megapixel_sampled_and_listing_gate(g):
+    """The 1000^2 Kerr-Newman frame (binary32 inputs, dt = 0.005, 50000
+    steps): every 64th pixel in both axes plus pixels on the shadow edge,
+    bit-exact against the twin form and within the listing form's per-ray
+    sensitivity bound."""
+    import oracle
+    f = fp32_round
+    case = (f(0.5), f(0.24), f(0.3), f(20.0), f(80 * DEG), 0.0, f(75 * DEG), 1000, 1000)
+    integ = g.make_integrator(dt=0.005, max_steps=50000, method=g.GR_RK4_TIME)
+    ctx = g.gr_trace_init(0, integ)
+    try:
+        gpu = gpu_trace(ctx, *case, fields=("t", "r", "theta", "phi"))
+    finally:
+        g.gr_trace_destroy(ctx)
+    flag = gpu["flag"].reshape(1000, 1000)
+    edge = np.zeros_like(flag, bool)
+    edge[1:-1] = (flag[1:-1] != flag[:-2]) | (flag[1:-1] != flag[2:])
+    edge_pix = np.random.default_rng(3).choice(np.nonzero(edge.ravel())[0], 96, replace=False)
+    grid = (np.arange(32, 1000, 64)[:, None] * 1000 + np.arange(32, 1000, 64)[None, :]).ravel()
+    pix = np.unique(np.concatenate([grid, edge_pix]))
+    sub = {k: v[pix] for k, v in gpu.items()}
+    st = compare(sub, _twin(case, integ, pixels=pix), angle_tol=0.0)
+    assert st["bit_identical"] == st["n"]
+    lis = oracle.trace_frame(*case, dt=0.005, max_steps=50000, pixels=pix, method=2, probe=4)
+    print(compare_at_sensitivity(sub, lis))
+
+
+def test_refused_where_not_built(g):
+    with pytest.raises(g.GrError) as e:
+        g.gr_trace_init(0, g.make_integrator(method=g.GR_RK4_TIME, precision=g.GR_MIXED))
+    assert e.value.code == g.GR_EUNSUPPORTED
+    ctx = g.gr_trace_init(0, g.make_integrator(method=g.GR_RK4_TIME))
+    try:
+        out = g.alloc_outputs(4, fields=("r",))
+        inst = g.gr_instance(g.gr_metric(0.5, 0.2, 0.0), g.gr_camera(20.0, 1.0, 0.0, 1.0, 2, 2),
+                             out.struct, None, -1)
+        with pytest.raises(g.GrError) as e:
+            g.gr_trace_batch(ctx, [inst])
+        assert e.value.code == g.GR_EUNSUPPORTED
+    finally:
+        g.gr_trace_destroy(ctx)
+    with pytest.raises(g.GrError) as e:
+        g.gr_trace_init(0, g.make_integrator(method=3))
+    assert e.value.code == g.GR_EINVAL
