@@ -598,59 +598,123 @@ def bench_mn(args):
 FLOPS_PER_RAY_STEP_EULER = 149   # one Kerr-Newman stage (136), the normaliser (1), update (6 fma)
 
 
+FLOPS_PER_RAY_STEP_RK4_TIME = 641   # RK4's 613 + per stage one division and 6 multiplies
+# The same three methods on the Manko-Novikov metric: RK4 1651 (above), the
+# coordinate-time RK4 1651 + 28, Euler one stage (396) + the normaliser + 12.
+MN_OPS = {"rk4": 1651, "rk4_time": 1679, "euler": 409, "euler_dt/4": 409,
+          "reference_rk4_dt/4": 1651}
+
+
 def bench_euler(args):
-    """RK4 against explicit Euler (paper Sec. 3.1.1, the comparison of Sec.
-    3.2) on the 1000x1000 Kerr-Newman frame: rays/s and the end-direction
-    difference from the RK4 frame at the same dt, for Euler at dt and dt/4."""
+    """The integrators of Sec. 3.1 (the comparison of "Resolution and
+    Calculation Speed"): RK4 with h fixed from the first stage, RK4 with
+    coordinate time as the parameter (each stage reparametrised) and
+    explicit Euler at dt and dt/4, on two frames, each against a reference
+    frame traced by RK4 at dt/4:
+      - the 1000x1000 Kerr-Newman frame (dt = 0.005): rays/s and the
+        end-direction error (escape-sphere crossing) of every frame;
+      - the 1000x1000 Manko-Novikov frame of the listing's spacetime
+        (M = 0.5, S = 0.24, q = 2, r0 = 8; dt = 0.005), whose shadow has a
+        chaotic region: the fraction of pixels whose flag or whose sky-line
+        colour (the figures' shading) differs from the reference, over the
+        frame and over the chaotic region (escaped reference pixels whose end
+        direction differs from an 8-neighbour's by more than 0.5 rad, and
+        their neighbours)."""
     import numpy as np
     import torch
 
     import paper_2310_15183_amd as g
     from paper_2310_15183_amd.evaluate import mixed_errors
-    w = workload()
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    n = w["W"] * w["H"]
-    metric = g.gr_metric(w["M"], w["a"], w["Q"])
-    cam = g.gr_camera(w["r0"], w["theta0"], w["phi0"], w["fov"], w["W"], w["H"])
+    methods = [("rk4", g.GR_RK4, 1, FLOPS_PER_RAY_STEP),
+               ("rk4_time", g.GR_RK4_TIME, 1, FLOPS_PER_RAY_STEP_RK4_TIME),
+               ("euler", g.GR_EULER, 1, FLOPS_PER_RAY_STEP_EULER),
+               ("euler_dt/4", g.GR_EULER, 4, FLOPS_PER_RAY_STEP_EULER),
+               ("reference_rk4_dt/4", g.GR_RK4, 4, FLOPS_PER_RAY_STEP)]
 
-    def run(dt, max_steps, method):
-        ctx = g.gr_trace_init(0, g.make_integrator(dt=dt, fd_eps=w["fd_eps"],
+    def run(w, mn, method, div, reps):
+        n = w["W"] * w["H"]
+        ctx = g.gr_trace_init(0, g.make_integrator(dt=w["dt"] / div, fd_eps=w["fd_eps"],
                                                    horizon_norm=w["horizon_norm"],
                                                    escape_factor=w["escape_factor"],
-                                                   max_steps=max_steps, method=method))
-        out = g.alloc_outputs(n, dtype=g.GR_F32, fields=("t", "r", "theta", "phi"))
-        wall, launch_s = time_frames(g, ctx, metric, cam, out, args.steps, args.warmup, stream)
-        ray_steps = int(out["steps"].cpu().numpy().astype(np.int64).sum())
-        full = g.alloc_outputs(n, dtype=g.GR_F64, fields=g.FIELDS)
-        g.gr_trace_frame(ctx, metric, cam, full.struct, stream)
+                                                   max_steps=w["max_steps"] * div,
+                                                   method=method))
+        cam = g.gr_camera(w["r0"], w["theta0"], w["phi0"], w["fov"], w["W"], w["H"])
+        metric = g.gr_metric_mn(w["M"], w["S"], w["q"]) if mn else g.gr_metric(w["M"], w["a"],
+                                                                                w["Q"])
+        trace = g.gr_trace_frame_mn if mn else g.gr_trace_frame
+        out = g.alloc_outputs(n, dtype=g.GR_F64, fields=g.FIELDS)
+        trace(ctx, metric, cam, out.struct, stream)                     # warm-up
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            trace(ctx, metric, cam, out.struct, stream)
+        e1.record(stream)
         torch.cuda.synchronize()
-        res = {k: v.cpu().numpy() for k, v in full.tensors.items()}
+        sec = e0.elapsed_time(e1) / 1e3 / reps
+        rgba = torch.empty(n, dtype=torch.int32, device="cuda")
+        g.gr_shade_frame(g.gr_shade(g.GR_SHADE_BANDS, 1.0, 0.0), out.struct, n, rgba, stream)
+        torch.cuda.synchronize()
+        res = {k: v.cpu().numpy() for k, v in out.tensors.items()}
+        res["rgba"] = rgba.cpu().numpy()
         g.gr_trace_destroy(ctx)
-        return wall / args.steps, launch_s, ray_steps, res
+        return sec, res
 
-    rk_s, rk_launch, rk_steps, ref = run(w["dt"], w["max_steps"], g.GR_RK4)
-    lines = {"rk4": {"dt": w["dt"], "ms_per_step": rk_s * 1e3, "rays_per_s": n / rk_s,
-                     "ray_steps": rk_steps,
-                     "roofline_frac": FLOPS_PER_RAY_STEP * rk_steps / rk_launch / 1e12
-                     / FP64_PEAK_TFLOPS}}
-    for name, dt, ms in [("euler", w["dt"], w["max_steps"]),
-                         ("euler_dt/4", w["dt"] / 4, 4 * w["max_steps"])]:
-        sec, launch, steps, got = run(dt, ms, g.GR_EULER)
-        err = mixed_errors(w["M"], w["a"], w["Q"], w["escape_factor"] * w["r0"], ref, got)
-        achieved = FLOPS_PER_RAY_STEP_EULER * steps / launch / 1e12
-        lines[name] = {"dt": dt, "ms_per_step": sec * 1e3, "rays_per_s": n / sec,
-                       "speedup_vs_rk4": rk_s / sec, "ray_steps": steps,
-                       "angle_err_vs_rk4_rad": err,
-                       "roofline": {"bound": "alu", "achieved": achieved,
-                                    "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                                    "frac": achieved / FP64_PEAK_TFLOPS,
-                                    "flops_per_ray_step": FLOPS_PER_RAY_STEP_EULER}}
-    print(json.dumps({"metric": "geodesic rays/s, RK4 vs explicit Euler, 1000^2 Kerr-Newman",
-                      "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
-                      "warmup": args.warmup, "data": "synthetic", "dtype": "f64",
-                      "workload": "kerr-newman 1000x1000 fp64 (the headline frame)",
-                      "results": lines}), flush=True)
+    report = {}
+    for label, w, mn in [("kerr_newman_1000", workload(), False),
+                         ("manko_novikov_1000", mn_workload(), True)]:
+        n = w["W"] * w["H"]
+        frames = {}
+        for name, method, div, ops in methods:
+            sec, res = run(w, mn, method, div, 1 if mn or div > 1 else max(args.steps, 1))
+            frames[name] = (sec, res, div, ops)
+        ref = frames["reference_rk4_dt/4"][1]
+        lines = {}
+        if mn:
+            # the chaotic region: escaped reference pixels whose end direction
+            # jumps by more than 0.5 rad to an 8-neighbour, grown by one pixel
+            th = ref["theta"].reshape(w["H"], w["W"])
+            ph = ref["phi"].reshape(w["H"], w["W"])
+            v = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], -1)
+            esc = (ref["flag"] == g.GR_FLAG_ESCAPE).reshape(w["H"], w["W"])
+            jump = np.zeros_like(esc)
+            for dj in (-1, 0, 1):
+                for di in (-1, 0, 1):
+                    if dj == 0 and di == 0:
+                        continue
+                    sv = np.roll(np.roll(v, dj, 0), di, 1)
+                    se = np.roll(np.roll(esc, dj, 0), di, 1)
+                    jump |= esc & se & (np.linalg.norm(v - sv, axis=-1) > 0.5)
+            region = jump.copy()
+            for dj in (-1, 0, 1):
+                for di in (-1, 0, 1):
+                    region |= np.roll(np.roll(jump, dj, 0), di, 1)
+            region = region.ravel()
+        for name, (sec, res, div, ops) in frames.items():
+            ops = MN_OPS[name] if mn else ops
+            steps = int(res["steps"].astype(np.int64).sum())
+            line = {"dt": w["dt"] / div, "ms_per_frame": sec * 1e3, "rays_per_s": n / sec,
+                    "ray_steps": steps,
+                    "roofline_frac": ops * steps / sec / 1e12 / FP64_PEAK_TFLOPS,
+                    "ops_per_ray_step": ops}
+            if name != "reference_rk4_dt/4":
+                line["flag_changed_frac"] = float((res["flag"] != ref["flag"]).mean())
+                line["colour_changed_frac"] = float((res["rgba"] != ref["rgba"]).mean())
+                if mn:
+                    line["chaotic_region_pixels"] = int(region.sum())
+                    line["chaotic_region_colour_changed_frac"] = float(
+                        (res["rgba"][region] != ref["rgba"][region]).mean())
+                else:
+                    line["angle_err_vs_reference_rad"] = mixed_errors(
+                        w["M"], w["a"], w["Q"], w["escape_factor"] * w["r0"], ref, res)
+            lines[name] = line
+        report[label] = lines
+    print(json.dumps({"metric": "integrators of Sec. 3.1: rays/s and agreement with RK4 at dt/4",
+                      "unit": "rays/s", "n_gpus": 1, "data": "synthetic", "dtype": "f64",
+                      "workload": "1000x1000 Kerr-Newman (dt=0.005) and Manko-Novikov "
+                                  "(listing spacetime, dt=0.005) frames",
+                      "results": report}), flush=True)
 
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
