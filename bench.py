@@ -415,7 +415,7 @@ def _surrogate_result(n, wall, net_s, nfb, fp64_rays_per_s, pipe_s, err, online,
 
 def bench_surrogate(args):
     """Surrogate + fallback on 4096x4096 frames (the network trained first):
-    the Kerr-Newman point of the headline frame, near-extremal Kerr, and two
+    the Kerr-Newman point of the headline frame, near-extremal Kerr, and four
     seeded draws from the batch parameter ranges; dt=0.01, 20000 steps."""
     import torch
 
@@ -430,7 +430,7 @@ def bench_surrogate(args):
     frames = [("kerr-newman a=0.24 Q=0.3 theta0=80deg", dict(base)),
               ("near-extremal kerr a=0.49 theta0=60deg",
                dict(base, a=0.49, Q=0.0, theta0=math.radians(60.0)))]
-    for k, I in enumerate(batch_instances(2, seed=777)):
+    for k, I in enumerate(batch_instances(4, seed=777)):
         frames.append((f"draw {k}: a={I.a:.3f} Q={I.Q:.3f} r0={I.r0:.1f} "
                        f"theta0={math.degrees(I.theta0):.1f}deg fov={math.degrees(I.fov):.1f}deg",
                        dict(base, M=I.M, a=I.a, Q=I.Q, r0=I.r0, theta0=I.theta0, fov=I.fov)))
@@ -923,7 +923,7 @@ def main():
                     help="surrogate: also re-trace pixels whose predicted direction differs "
                          "from an escaping neighbour's by more than this many pixel widths "
                          "(0: off)")
-    ap.add_argument("--surrogate-frames", type=int, default=4,
+    ap.add_argument("--surrogate-frames", type=int, default=6,
                     help="surrogate: how many of its frames to run (in order)")
     ap.add_argument("--skip-variants", action="store_true",
                     help="frame workload: time only the binary64 path")
