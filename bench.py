@@ -74,7 +74,8 @@ def workload():
 
 def kernel_hash() -> str:
     """Hash of the tracing kernel's sources and of the hipcc options it is
-    built with (the options change the code too)."""
+    built with (the options change the code too), the same wherever the
+    repository is checked out."""
     import importlib.util
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
@@ -84,7 +85,9 @@ def kernel_hash() -> str:
         "_grtrace_build_opts", os.path.join(ROOT, "paper_2310_15183_amd", "build.py"))
     opts = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(opts)
-    h.update(" ".join(opts.FLAGS + opts.EXTRA.get("trace_fp64.hip", [])).encode())
+    # include directories name this checkout's location, not an option of the code
+    flags = [f for f in opts.FLAGS + opts.EXTRA.get("trace_fp64.hip", []) if not f.startswith("-I")]
+    h.update(" ".join(flags).encode())
     return h.hexdigest()[:16]
 
 

@@ -73,3 +73,26 @@ def test_executed_counters_are_read_only_for_the_current_sources(tmp_path, monke
     assert bench.recorded_executed()["frac"] == 0.5
     fresh.write_text(fresh.read_text().replace(bench.kernel_hash(), "0" * 16))
     assert bench.recorded_executed() is None
+
+
+def test_kernel_hash_does_not_depend_on_the_checkout_location(monkeypatch):
+    """Include directories are absolute paths of the checkout; moving the
+    repository must not change the hash (the profiles stay valid)."""
+    import importlib.util
+    base = bench.kernel_hash()
+    real = importlib.util.spec_from_file_location
+
+    def patched(name, path, *a, **k):
+        spec = real(name, path, *a, **k)
+        if name == "_grtrace_build_opts":
+            loader = spec.loader
+
+            class L(type(loader)):
+                def exec_module(self, module):
+                    loader.exec_module(module)
+                    module.FLAGS = [("-I/elsewhere" + f[2:]) if f.startswith("-I") else f
+                                    for f in module.FLAGS]
+            spec.loader = L(loader.name, loader.path)
+        return spec
+    monkeypatch.setattr(importlib.util, "spec_from_file_location", patched)
+    assert bench.kernel_hash() == base
