@@ -81,13 +81,18 @@ static __device__ __forceinline__ Deriv deriv_from(const InvMetric& g, const Inv
 // 1/sin^2 (near the axis sin^2 changes by a large factor over eps, rho2 Delta
 // never does).
 // s, c: sin and cos of the stage point's theta.
+// UNIT_COS: cos eps is 1.0 (it rounds to 1 for eps below 1.05e-8, the
+// paper's 1e-8 included), so the products with it are exact and are left
+// out; chosen per launch, it gives the same bits as the general form.
+template <bool UNIT_COS = false>
 static __device__ __forceinline__ Deriv rhs_sc(const Hole& H, const Integrator& in, double r,
                                                double s, double c, double pt, double pr,
                                                double pth, double pph, double wtt, double wtp,
                                                double wpp) {
     const ThetaTerms T0 = theta_terms_sc(H, s, c);
-    const ThetaTerms T1 = theta_terms_sc(H, fma(c, in.sin_eps, s * in.cos_eps),
-                                         fma(-s, in.sin_eps, c * in.cos_eps));
+    const double sc = UNIT_COS ? s : s * in.cos_eps;
+    const double cc = UNIT_COS ? c : c * in.cos_eps;
+    const ThetaTerms T1 = theta_terms_sc(H, fma(c, in.sin_eps, sc), fma(-s, in.sin_eps, cc));
     const RadialTerms R0 = radial_terms(H, r);
     const RadialTerms R1 = radial_terms(H, r + in.eps);
     const double is = rcp_rn(rho2_delta(H, R0, T0) * T0.s2);
@@ -256,11 +261,11 @@ static __device__ __forceinline__ double euler_generic(const Rhs& rhs_at, const 
 // step).
 // GENERAL = false rotates by rotate_small (no branch) and returns in dmax the
 // largest |increment|; the step equals the GENERAL one when dmax <= 1/16.
-template <bool GENERAL>
+template <bool GENERAL, bool UNIT_COS = false>
 static __device__ __forceinline__ double rk4_carry(const Hole& H, const Integrator& in, Ray& y,
                                                    double& dmax) {
     const auto f = [&](double r, double sn, double cs, double pr, double pth) {
-        return rhs_sc(H, in, r, sn, cs, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
+        return rhs_sc<UNIT_COS>(H, in, r, sn, cs, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
     };
     dmax = 0.0;
     const auto rot = [&](double d, double& sn, double& cs) {
@@ -303,17 +308,18 @@ static __device__ __forceinline__ double rk4_carry(const Hole& H, const Integrat
 }
 
 // The tracing kernels take the branch-free step; a ray one of whose steps
-// rotates by more than 1/16 (it needs h |dtheta/dtau| > 1/16, which no
-// configured workload reaches) is not finished there: its flag is set to
-// PENDING and a second pass over the outputs traces it again from its start
-// with the general step.  Either way each ray's result is that of the
-// general step.
+// rotates by more than 1/16 (it needs h |dtheta/dtau| > 1/16: on the
+// configured workloads only rays that graze the polar axis, where dp_theta/dtau
+// swings within a step) is not finished there: its flag is set to PENDING and
+// a second pass over the outputs traces it again from its start with the
+// general step.  Either way each ray's result is that of the general step.
 enum { PENDING = -2 };
 
+template <bool UNIT_COS = false>
 static __device__ __forceinline__ double rk4_step(const Hole& H, const Integrator& in, Ray& y,
                                                   bool& pending) {
     double dmax;
-    const double nu = rk4_carry<false>(H, in, y, dmax);
+    const double nu = rk4_carry<false, UNIT_COS>(H, in, y, dmax);
     pending = dmax > ROT_SERIES_MAX;
     return nu;
 }

@@ -26,8 +26,8 @@ using namespace detail;
 
 // One lane, one ray (static_ray); the grid covers every ray.  METHOD selects
 // RK4 (the carried form), explicit Euler or RK4 in coordinate time; DISK adds
-// the ring's exit test.
-template <typename T, int METHOD, bool DISK>
+// the ring's exit test; UC: the RK4 step's cos eps is 1.0 (rhs_sc).
+template <typename T, int METHOD, bool DISK, bool UC>
 __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
     int64_t k, pix;
     if (!static_ray(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, k, pix)) return;
@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
     } else {
         while (f == RUNNING) {
             bool pending;
-            const double nu = rk4_step(A.hole, A.in, y, pending);
+            const double nu = rk4_step<UC>(A.hole, A.in, y, pending);
             ++s;
             f = pending ? PENDING : exit_flag<DISK>(A.in, A.r_esc, y, nu, s);
         }
@@ -55,7 +55,8 @@ __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
 
 // Second pass of a binary64 RK4 frame: the rays left PENDING by the first
 // are traced again from the start with the general step (grid-stride over
-// the output entries; nothing to do on the configured workloads).
+// the output entries; on the configured workloads a few rays that graze the
+// polar axis at the larger steps, none on the 1000x1000 frame).
 template <typename T, bool DISK>
 __global__ void __launch_bounds__(256) trace_fp64_redo(const FrameArgs A) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -136,6 +137,7 @@ __device__ __forceinline__ void write_batch(const BatchInstance& I, int64_t k, c
     else write_ray<double>(I.out, k, y, f, s);
 }
 
+template <bool UC>
 __global__ void __launch_bounds__(256) trace_fp64_batch(const BatchArgs B,
                                                          unsigned long long* counter) {
     const int64_t total = B.firsts[B.ninst];     // may be written on the device by an earlier kernel
@@ -171,7 +173,7 @@ __global__ void __launch_bounds__(256) trace_fp64_batch(const BatchArgs B,
         if (!__any(live || want)) break;
         if (live) {
             bool pending;
-            const double nu = rk4_step(H, B.in, y, pending);
+            const double nu = rk4_step<UC>(H, B.in, y, pending);
             ++s;
             const int f = pending ? PENDING : exit_flag(B.in, r_esc, y, nu, s);
             if (f != RUNNING) {
@@ -186,6 +188,7 @@ __global__ void __launch_bounds__(256) trace_fp64_batch(const BatchArgs B,
 // Many instances in one launch, one ray per lane: wave w finds its instance
 // by binary search of the wave offsets and takes the instance's 8x8 tile (or
 // 64 pixel-list entries) w - wfirsts[instance].
+template <bool UC>
 __global__ void __launch_bounds__(256) trace_fp64_batch_static(const BatchArgs B) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t wave = g >> 6;
@@ -219,7 +222,7 @@ __global__ void __launch_bounds__(256) trace_fp64_batch_static(const BatchArgs B
     int f = start_flag(B.in, y);
     while (f == RUNNING) {
         bool pending;
-        const double nu = rk4_step(H, B.in, y, pending);
+        const double nu = rk4_step<UC>(H, B.in, y, pending);
         ++s;
         f = pending ? PENDING : exit_flag(B.in, r_esc, y, nu, s);
     }
@@ -276,15 +279,28 @@ static hipError_t launch_redo(const FrameArgs& A, bool f32_out, hipStream_t s) {
     return hipGetLastError();
 }
 
+// The RK4 kernels come in two forms, for cos eps = 1.0 (eps <= 1.05e-8, the
+// paper's 1e-8 among them) and for any eps; both give the same bits.
+static bool unit_cos(const Integrator& in) { return in.cos_eps == 1.0; }
+
+template <int METHOD, bool DISK, bool UC>
+static void launch_static_kernel(const FrameArgs& A, bool f32_out, const LaunchShape& L,
+                                 hipStream_t s) {
+    if (f32_out)
+        hipLaunchKernelGGL((trace_fp64_static<float, METHOD, DISK, UC>), dim3(L.grid),
+                           dim3(L.block), 0, s, A);
+    else
+        hipLaunchKernelGGL((trace_fp64_static<double, METHOD, DISK, UC>), dim3(L.grid),
+                           dim3(L.block), 0, s, A);
+}
+
 template <int METHOD, bool DISK>
 static hipError_t launch_static(const FrameArgs& A, bool f32_out, const LaunchShape& L,
                                 hipStream_t s) {
-    if (f32_out)
-        hipLaunchKernelGGL((trace_fp64_static<float, METHOD, DISK>), dim3(L.grid), dim3(L.block),
-                           0, s, A);
+    if (METHOD == M_RK4 && unit_cos(A.in))
+        launch_static_kernel<METHOD, DISK, true>(A, f32_out, L, s);
     else
-        hipLaunchKernelGGL((trace_fp64_static<double, METHOD, DISK>), dim3(L.grid),
-                           dim3(L.block), 0, s, A);
+        launch_static_kernel<METHOD, DISK, false>(A, f32_out, L, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || METHOD != M_RK4) return e;
     return launch_redo<DISK>(A, f32_out, s);
@@ -323,12 +339,22 @@ hipError_t launch_trace_fp64(const FrameArgs& A, bool f32_out, int method, bool 
 
 hipError_t launch_trace_fp64_batch(const BatchArgs& B, const LaunchShape& L,
                                    unsigned long long* counter, hipStream_t s) {
+    const bool uc = unit_cos(B.in);
     if (!L.refill) {
-        hipLaunchKernelGGL(trace_fp64_batch_static, dim3(L.grid), dim3(L.block), 0, s, B);
+        if (uc)
+            hipLaunchKernelGGL(trace_fp64_batch_static<true>, dim3(L.grid), dim3(L.block), 0, s, B);
+        else
+            hipLaunchKernelGGL(trace_fp64_batch_static<false>, dim3(L.grid), dim3(L.block), 0, s,
+                               B);
     } else {
         hipError_t e = launch_reset_counter(counter, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(trace_fp64_batch, dim3(L.grid), dim3(L.block), 0, s, B, counter);
+        if (uc)
+            hipLaunchKernelGGL(trace_fp64_batch<true>, dim3(L.grid), dim3(L.block), 0, s, B,
+                               counter);
+        else
+            hipLaunchKernelGGL(trace_fp64_batch<false>, dim3(L.grid), dim3(L.block), 0, s, B,
+                               counter);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || B.total <= 0) return e;
@@ -336,12 +362,16 @@ hipError_t launch_trace_fp64_batch(const BatchArgs& B, const LaunchShape& L,
     return hipGetLastError();
 }
 
+// Resident workgroups per CU of the persistent batch kernel: the smaller of
+// its two forms, so that either fits the grid.
 int occupancy_trace_fp64_batch(int block) {
-    int n = 0;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, trace_fp64_batch, block, 0) ==
-                   hipSuccess
-               ? n
-               : 0;
+    int n1 = 0, n2 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n1, trace_fp64_batch<true>, block, 0) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n2, trace_fp64_batch<false>, block, 0) !=
+            hipSuccess)
+        return 0;
+    return n1 < n2 ? n1 : n2;
 }
 
 int occupancy_trace_fp64(int block, bool f32_out) {
