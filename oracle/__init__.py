@@ -282,7 +282,7 @@ def rotate(s, c, d) -> tuple[np.ndarray, np.ndarray]:
 
 
 def halved_rotations(reset=False) -> int:
-    """Kernel-twin form: rotations by more than 1/16 (halved before the
+    """Kernel-twin form: rotations by more than 1/32 (halved before the
     series) since the last reset."""
     return int(_load().oracle_halved_rotations(1 if reset else 0))
 

@@ -153,11 +153,12 @@ static void sincos_mode(int mode, double x, double *s, double *c)
  *   sin(x + d) = s + (c sin d + s (cos d - 1)),
  *   cos(x + d) = c + (-s sin d + c (cos d - 1)).
  * sin d and cos d - 1 are formed for u = d / 2^m, with m the smallest number
- * of halvings that brings |u| to 1/16 or below (at most 64), from the Taylor
- * series u + u^3 (S1 + u^2 (S2 + u^2 (S3 + u^2 S4))) and
- * u^2 (C1 + u^2 (C2 + u^2 (C3 + u^2 C4))) (S_n, C_n as above; the next
- * terms are below 2e-21 and 3e-19 for |u| <= 1/16), and then doubled m
- * times: sin 2u = 2 sin u (1 + (cos u - 1)), cos 2u - 1 = -2 sin^2 u.
+ * of halvings that brings |u| to 1/32 or below (at most 64), from the Taylor
+ * series u + u^3 (S1 + u^2 (S2 + u^2 S3)) and u^2 (C1 + u^2 (C2 + u^2 C3))
+ * (S_n, C_n as above; the next terms are below 8e-20 and 2.3e-17 for
+ * |u| <= 1/32, the latter entering the result multiplied by s or c: at most
+ * a fifth of its ulp), and then doubled m times:
+ * sin 2u = 2 sin u (1 + (cos u - 1)), cos 2u - 1 = -2 sin^2 u.
  * The twin form carries sin/cos of theta along a Kerr-Newman RK4 ray this
  * way instead of evaluating them at every stage point. */
 static long g_halved_rotations = 0;       /* rotations that needed halving (test statistics) */
@@ -166,14 +167,14 @@ static void rotate_pair(double s, double c, double d, double *s_out, double *c_o
 {
     double u = d;
     int m = 0;
-    while (m < 64 && fabs(u) > 0.0625) {
+    while (m < 64 && fabs(u) > 0.03125) {
         u *= 0.5;
         ++m;
     }
     if (m > 0) __atomic_fetch_add(&g_halved_rotations, 1, __ATOMIC_RELAXED);
     const double z = u * u;
-    double ps = SIN_C[4], pc = COS_C[4];
-    for (int n = 3; n >= 1; --n) {
+    double ps = SIN_C[3], pc = COS_C[3];
+    for (int n = 2; n >= 1; --n) {
         ps = fma(ps, z, SIN_C[n]);
         pc = fma(pc, z, COS_C[n]);
     }

@@ -73,24 +73,24 @@ GR_HD void sincos_def(double x, double& s_out, double& c_out) {
 
 // Rotation of a (sin, cos) pair by an angle d: (sin(x + d), cos(x + d)) from
 // s = sin x, c = cos x by the angle-addition identity.  sin and cos - 1 of
-// u = d 2^-m, m the least count of halvings with |u| <= 1/16 (at most 64),
-// come from their Taylor series through u^9 and u^8 (the first omitted terms
-// are below 2e-21 and 3e-19 there), then m double-angle steps
+// u = d 2^-m, m the least count of halvings with |u| <= 1/32 (at most 64),
+// come from their Taylor series through u^7 and u^6 (the first omitted terms
+// are below 8e-20 and 2.3e-17 there, the latter multiplied by s or c in the
+// rotation: at most a fifth of an ulp of the result, and far less at the
+// increments of ordinary steps), then m double-angle steps
 // sin 2u = 2 sin u (1 + (cos u - 1)), cos 2u - 1 = -2 sin^2 u give those of d;
 // the small corrections are summed first and added to s and c with one
 // rounding each.  rotate_small is the case m = 0 alone (no branch), equal to
-// rotate_sc bit for bit wherever |d| <= 1/16.
-constexpr double ROT_SERIES_MAX = 0.0625;
+// rotate_sc bit for bit wherever |d| <= 1/32.
+constexpr double ROT_SERIES_MAX = 0.03125;
 
 GR_HD void small_angle(double u, double& sd, double& cm1) {
     const double z = u * u;
-    double ps = series_coef(9);
-    ps = fma(ps, z, series_coef(7));
+    double ps = series_coef(7);
     ps = fma(ps, z, series_coef(5));
     ps = fma(ps, z, series_coef(3));
     sd = fma(u * z, ps, u);
-    double pc = series_coef(8);
-    pc = fma(pc, z, series_coef(6));
+    double pc = series_coef(6);
     pc = fma(pc, z, series_coef(4));
     pc = fma(pc, z, series_coef(2));
     cm1 = z * pc;

@@ -260,7 +260,7 @@ static __device__ __forceinline__ double euler_generic(const Rhs& rhs_at, const 
 // by the accumulated rounding of the rotations (a random walk of ~1e-16 per
 // step).
 // GENERAL = false rotates by rotate_small (no branch) and returns in dmax the
-// largest |increment|; the step equals the GENERAL one when dmax <= 1/16.
+// largest |increment|; the step equals the GENERAL one when dmax <= 1/32.
 template <bool GENERAL, bool UNIT_COS = false>
 static __device__ __forceinline__ double rk4_carry(const Hole& H, const Integrator& in, Ray& y,
                                                    double& dmax) {
@@ -308,7 +308,7 @@ static __device__ __forceinline__ double rk4_carry(const Hole& H, const Integrat
 }
 
 // The tracing kernels take the branch-free step; a ray one of whose steps
-// rotates by more than 1/16 (it needs h |dtheta/dtau| > 1/16: on the
+// rotates by more than 1/32 (it needs h |dtheta/dtau| > 1/32: on the
 // configured workloads only rays that graze the polar axis, where dp_theta/dtau
 // swings within a step) is not finished there: its flag is set to PENDING and
 // a second pass over the outputs traces it again from its start with the

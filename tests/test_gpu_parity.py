@@ -286,7 +286,7 @@ LARGE_STEP = (0.5, 0.3, 0.2, 12.0, 70 * DEG, 0.0, 60 * DEG, 24, 24)
 
 @pytest.mark.parametrize("launch", [None, (256, 0, 1, 0), (64, 0, 1, 0)])
 def test_large_steps_finish_in_the_second_pass(g, ctx, launch):
-    """dt = 0.5: steps rotate theta's (sin, cos) by more than 1/16, beyond the
+    """dt = 0.5: steps rotate theta's (sin, cos) by more than 1/32, beyond the
     first pass's series; those rays are traced again by the second pass with
     the general rotation.  Every ray bit-identical to the twin form, whatever
     the launch form (tiles, persistent lanes)."""
