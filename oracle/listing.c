@@ -47,8 +47,12 @@
  * to rounding; since the forward difference divides rounding by eps, their
  * end angles differ by about what a one-ulp change of a ray's start does.
  * That sensitivity is measured per ray by re-running it from perturbed
- * starts (the conditioning probe): p_theta and p_r scaled by 1 + 2^-52, and
- * the camera latitude moved by one ulp.
+ * starts (the conditioning probe): p_theta scaled by 1 + 2^-52, the camera
+ * latitude moved by one ulp, and the whole covector scaled by 1 + 2^-52 and
+ * by 1 - 2^-53.  A ray's flag and step count count as ill-conditioned when a
+ * probe changes them, or when the exit was a tie: the escape or horizon test
+ * was decided by a margin within TIE_K times the probes' spread of the tested
+ * quantity.
  *
  * Parity status: pinned (the pins of the kernel-twin form apply to this form
  * too: flat space, Schwarzschild critical impact parameter and deflection
@@ -237,11 +241,22 @@ static int finite8(const double y[8])
     return 1;
 }
 
-/* Integrate one ray in place; returns the flag and the updates taken. */
-static int integrate(const lspec *L, double y[8], int *nsteps)
+/* What decided a ray's escape or horizon exit: the tested quantity (r for
+ * escape, |dt/dtau| for the horizon) after the final step and after the step
+ * before, and its threshold (has = 0 for the other exits). */
+typedef struct {
+    int has;
+    double now, before, thr;
+} ldecision;
+
+/* Integrate one ray in place; returns the flag and the updates taken (and,
+ * if dec is given, what decided the exit). */
+static int integrate(const lspec *L, double y[8], int *nsteps, ldecision *dec)
 {
     const double r_esc = L->esc * y[1];
+    double r_before = y[1], nu_before = 0.0;
     *nsteps = 0;
+    if (dec) dec->has = 0;
     if (!finite8(y)) return LF_INVALID;
     for (int s = 1; s <= L->max_steps; ++s) {
         double k1[8], k2[8], k3[8], k4[8], z[8];
@@ -280,9 +295,17 @@ static int integrate(const lspec *L, double y[8], int *nsteps)
         if (L->ring_dth > 0.0 && y[1] >= L->ring_in && y[1] <= L->ring_out &&
             fabs(y[2] - HALF_PI) <= L->ring_dth)
             return LF_DISK;
-        if (y[1] > r_esc) return LF_ESCAPE;
-        if (nu > L->hnorm) return LF_HORIZON;
+        if (y[1] > r_esc) {
+            if (dec) *dec = (ldecision){1, y[1], r_before, r_esc};
+            return LF_ESCAPE;
+        }
+        if (nu > L->hnorm) {
+            if (dec) *dec = (ldecision){1, nu, nu_before, L->hnorm};
+            return LF_HORIZON;
+        }
         if (!finite8(y)) return LF_INVALID;
+        r_before = y[1];
+        nu_before = nu;
     }
     return LF_TIMEOUT;
 }
@@ -322,6 +345,12 @@ static void camera_start(const lspec *L, double r0, double th0, double ph0, doub
 /* ------------------------------------------------------------------ drivers */
 
 enum { NPROBE_MAX = 4 };
+
+/* An exit is a tie when its margin from the threshold (on the side of the
+ * final step or of the step before) is within TIE_K times the probes' spread
+ * of the deciding quantity: an evaluation that rounds differently could then
+ * exit one step earlier or later (the factor is the angle gate's). */
+static const double TIE_K = 64.0;
 
 typedef struct {
     const lspec *L;
@@ -363,12 +392,13 @@ static void run_ray(ljob *J, int64_t k)
     if (J->p0) memcpy(J->p0 + 4 * k, y0 + 4, 4 * sizeof(double));
     memcpy(y, y0, sizeof y);
     int ns = 0;
-    const int f = integrate(J->L, y, &ns);
+    ldecision dec;
+    const int f = integrate(J->L, y, &ns, &dec);
     memcpy(J->out8 + 8 * k, y, sizeof y);
     J->flag[k] = (int8_t)f;
     if (J->steps) J->steps[k] = ns;
     if (J->nprobe <= 0) return;
-    double sens = 0.0;
+    double sens = 0.0, spread = 0.0;
     int flip = 0;
     const double up = 1.0 + 0x1p-52;
     for (int pb = 0; pb < J->nprobe && pb < NPROBE_MAX; ++pb) {
@@ -389,10 +419,17 @@ static void run_ray(ljob *J, int64_t k)
             }
         }
         int nz = 0;
-        const int fz = integrate(J->L, z, &nz);
+        ldecision dz;
+        const int fz = integrate(J->L, z, &nz, &dz);
         if (fz != f || nz != ns) flip = 1;
+        else if (dec.has) spread = fmax(spread, fmax(fabs(dz.now - dec.now),
+                                                     fabs(dz.before - dec.before)));
         const double d = angdiff(y, z);
         if (d > sens || d != d) sens = d;
+    }
+    if (dec.has && !flip) {
+        const double margin = fmin(dec.now - dec.thr, dec.thr - dec.before);
+        if (margin <= TIE_K * spread) flip = 1;             /* a tie: see TIE_K */
     }
     if (J->sens) J->sens[k] = sens;
     if (J->flip) J->flip[k] = (int8_t)flip;

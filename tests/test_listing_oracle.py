@@ -116,7 +116,9 @@ def test_twin_matches_listing_on_small_kerr_frame(kerr64_listing):
     twin = oracle.trace_frame(*KERR64, dt=0.01, max_steps=20000, form="twin")
     st = compare_at_sensitivity(_as_dict(twin), kerr64_listing)
     print(st)
-    assert st["probe_flipped"] == 0
+    # rays set apart as ill-conditioned (a probe changed flag or steps, or
+    # the exit was a tie within the probes' spread) stay a small minority
+    assert st["probe_flipped"] <= 0.005 * st["n"]
     assert (kerr64_listing.flag == 2).sum() > 50
 
 
