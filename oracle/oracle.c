@@ -365,6 +365,28 @@ static void metric_from(const oracle_params *P, double r, double s2, double inv,
     g[4] = (Delta - w) * is;
 }
 
+/* The differences d[k] = g^{k}(displaced point) - g0[k] of the five
+ * components between a displaced point (r, sin^2 = s2, the reciprocals inv
+ * and is formed there) and the base point's g0: each displaced component's
+ * last product is fused with its subtraction of g0[k] (one fma), so the
+ * difference is rounded once and the displaced component itself never is;
+ * the other terms are rounded as in metric_from. */
+static void metric_diff(const oracle_params *P, double r, double s2, double inv, double is,
+                        const double g0[5], double d[5])
+{
+    const double a2 = P->a * P->a;
+    const double r2 = r * r;
+    const double ra = r2 + a2;
+    const double Delta = fma(r, r - 2.0 * P->M, a2 + P->Q * P->Q);
+    const double w = a2 * s2;
+    const double Sigma2 = fma(-w, Delta, ra * ra);
+    d[0] = fma(-Sigma2, inv, -g0[0]);
+    d[1] = fma(-(P->a * fma(2.0 * P->M, r, -(P->Q * P->Q))), inv, -g0[1]);
+    d[2] = fma(Delta * Delta, inv, -g0[2]);
+    d[3] = fma(Delta, inv, -g0[3]);
+    d[4] = fma(Delta - w, is, -g0[4]);
+}
+
 /* rho^2 Delta at (r, theta). */
 static double rho2_delta(const oracle_params *P, double r, double c2)
 {
@@ -414,14 +436,17 @@ static void metric_at_point(const oracle_params *P, double r, double theta, doub
  * the sine and cosine of the point's theta.  sin and cos at theta+eps are the
  * angle-addition identity applied to those at theta and at eps (for eps =
  * 1e-8, cos eps rounds to 1 and sin eps to eps), so the theta step is eps
- * itself.  The contraction sums the differences of the five independent
- * components times p_nu p_sigma in the order tt, t-phi (weight 2 p_t p_phi),
- * rr, theta-theta, phi-phi, then scales once by -1/(2 eps). */
+ * itself.  For Kerr-Newman each displaced component is formed together with
+ * its difference from the base point's (metric_diff, one rounding for the
+ * difference); the Manko-Novikov metric is evaluated in full at the three
+ * points and subtracted.  The contraction sums the differences of the five
+ * independent components times p_nu p_sigma in the order tt, t-phi (weight
+ * 2 p_t p_phi), rr, theta-theta, phi-phi, then scales once by -1/(2 eps). */
 static void hamilton_rhs_sc(const oracle_params *P, const double eps_sc[2], double r,
                             double s, double c, double pt, double pr, double pth, double pph,
                             double qdot[4], double pdot[2])
 {
-    double g[5], gr[5], gth[5];
+    double g[5], dr[5], dth[5];        /* base metric; differences to the displaced points */
     const double se = fma(c, eps_sc[0], s * eps_sc[1]);      /* sin(theta + eps) */
     const double ce = fma(-s, eps_sc[0], c * eps_sc[1]);     /* cos(theta + eps) */
     const double s2 = s * s, c2 = c * c, se2 = se * se, ce2 = ce * ce;
@@ -431,18 +456,23 @@ static void hamilton_rhs_sc(const oracle_params *P, const double eps_sc[2], doub
      * by a divided 1/sin^2 (near the axis sin^2 changes by a large factor
      * over eps, rho^2 Delta never does) */
     if (P->kind == METRIC_MN) {
-        /* full evaluations at the three points */
+        /* full evaluations at the three points, then the differences */
+        double gr[5], gth[5];
         mn_inverse_metric(&P->mn, r, c, s2, g);
         mn_inverse_metric(&P->mn, r + P->eps, c, s2, gr);
         mn_inverse_metric(&P->mn, r, ce, se2, gth);
+        for (int k = 0; k < 5; ++k) {
+            dr[k] = gr[k] - g[k];
+            dth[k] = gth[k] - g[k];
+        }
     } else {
         const double is = 1.0 / (rho2_delta(P, r, c2) * s2);
         const double inv = is * s2;
         const double is_r = recip_newton(rho2_delta(P, r + P->eps, c2) * s2, is);
         const double inv_t = recip_newton(rho2_delta(P, r, ce2), inv);
         metric_from(P, r, s2, inv, is, g);
-        metric_from(P, r + P->eps, s2, is_r * s2, is_r, gr);
-        metric_from(P, r, se2, inv_t, inv_t * (1.0 / se2), gth);
+        metric_diff(P, r + P->eps, s2, is_r * s2, is_r, g, dr);
+        metric_diff(P, r, se2, inv_t, inv_t * (1.0 / se2), g, dth);
     }
 
     /* weights p_nu p_sigma of the five independent components */
@@ -450,18 +480,18 @@ static void hamilton_rhs_sc(const oracle_params *P, const double eps_sc[2], doub
     const double wrr = pr * pr, wth = pth * pth;
     const double scale = -0.5 * (1.0 / P->eps);                /* -1/(2 eps) */
 
-    double acc = (gr[0] - g[0]) * wtt;
-    acc = fma(gr[1] - g[1], wtp, acc);
-    acc = fma(gr[2] - g[2], wrr, acc);
-    acc = fma(gr[3] - g[3], wth, acc);
-    acc = fma(gr[4] - g[4], wpp, acc);
+    double acc = dr[0] * wtt;
+    acc = fma(dr[1], wtp, acc);
+    acc = fma(dr[2], wrr, acc);
+    acc = fma(dr[3], wth, acc);
+    acc = fma(dr[4], wpp, acc);
     pdot[0] = acc * scale;                                     /* dp_r/dtau */
 
-    acc = (gth[0] - g[0]) * wtt;
-    acc = fma(gth[1] - g[1], wtp, acc);
-    acc = fma(gth[2] - g[2], wrr, acc);
-    acc = fma(gth[3] - g[3], wth, acc);
-    acc = fma(gth[4] - g[4], wpp, acc);
+    acc = dth[0] * wtt;
+    acc = fma(dth[1], wtp, acc);
+    acc = fma(dth[2], wrr, acc);
+    acc = fma(dth[3], wth, acc);
+    acc = fma(dth[4], wpp, acc);
     pdot[1] = acc * scale;                                     /* dp_theta/dtau */
 
     qdot[0] = fma(g[0], pt, g[1] * pph);                       /* dt/dtau */

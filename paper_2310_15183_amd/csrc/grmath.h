@@ -203,6 +203,22 @@ GR_HD InvMetric metric_from(const Hole& H, const RadialTerms& R, const ThetaTerm
     return g;
 }
 
+// The forward difference of the five components between a displaced point
+// (R, T, inv, is) and the base point's g0: each displaced component's last
+// product and its difference from g0 in one fma, so the difference is
+// rounded once (the displaced component itself is never rounded).
+GR_HD InvMetric metric_diff(const Hole& H, const RadialTerms& R, const ThetaTerms& T,
+                            double inv, double is, const InvMetric& g0) {
+    const double Sigma2 = fma(-T.w, R.Delta, R.rara);
+    InvMetric d;
+    d.tt = fma(-Sigma2, inv, -g0.tt);
+    d.tp = fma(-R.aF, inv, -g0.tp);
+    d.rr = fma(R.DD, inv, -g0.rr);
+    d.hh = fma(R.Delta, inv, -g0.hh);
+    d.pp = fma(R.Delta - T.w, is, -g0.pp);
+    return d;
+}
+
 // Full inverse metric at one point: is divided, inv = is sin^2.
 GR_HD InvMetric inverse_metric(const Hole& H, const RadialTerms& R, const ThetaTerms& T) {
     const double is = 1.0 / (rho2_delta(H, R, T) * T.s2);

@@ -42,27 +42,39 @@ struct Deriv {
     double pr, ph;           // dp_r/dtau, dp_theta/dtau
 };
 
-// Hamilton's equations from the inverse metric g at the stage point and gr,
-// gh at (r + eps, theta) and (r, theta + eps): p-dot = -1/(2 eps) times the
-// sum of the five component differences times p_nu p_sigma, in the order
-// tt, tphi (weight 2 p_t p_phi), rr, thth, phph.
-static __device__ __forceinline__ Deriv deriv_from(const InvMetric& g, const InvMetric& gr,
-                                                   const InvMetric& gh, const Integrator& in,
+// Componentwise a - b (each difference rounded once).
+static __device__ __forceinline__ InvMetric minus(const InvMetric& a, const InvMetric& b) {
+    InvMetric d;
+    d.tt = a.tt - b.tt;
+    d.tp = a.tp - b.tp;
+    d.rr = a.rr - b.rr;
+    d.hh = a.hh - b.hh;
+    d.pp = a.pp - b.pp;
+    return d;
+}
+
+// Hamilton's equations from the inverse metric g at the stage point and the
+// component differences dr, dh from there to (r + eps, theta) and
+// (r, theta + eps): p-dot = -1/(2 eps) times the sum of the five component
+// differences times p_nu p_sigma, in the order tt, tphi (weight 2 p_t p_phi),
+// rr, thth, phph.
+static __device__ __forceinline__ Deriv deriv_from(const InvMetric& g, const InvMetric& dr,
+                                                   const InvMetric& dh, const Integrator& in,
                                                    double pt, double pr, double pth, double pph,
                                                    double wtt, double wtp, double wpp) {
     const double wrr = pr * pr, wth = pth * pth;
-    double acc = (gr.tt - g.tt) * wtt;
-    acc = fma(gr.tp - g.tp, wtp, acc);
-    acc = fma(gr.rr - g.rr, wrr, acc);
-    acc = fma(gr.hh - g.hh, wth, acc);
-    acc = fma(gr.pp - g.pp, wpp, acc);
+    double acc = dr.tt * wtt;
+    acc = fma(dr.tp, wtp, acc);
+    acc = fma(dr.rr, wrr, acc);
+    acc = fma(dr.hh, wth, acc);
+    acc = fma(dr.pp, wpp, acc);
     Deriv d;
     d.pr = acc * in.scale;
-    acc = (gh.tt - g.tt) * wtt;
-    acc = fma(gh.tp - g.tp, wtp, acc);
-    acc = fma(gh.rr - g.rr, wrr, acc);
-    acc = fma(gh.hh - g.hh, wth, acc);
-    acc = fma(gh.pp - g.pp, wpp, acc);
+    acc = dh.tt * wtt;
+    acc = fma(dh.tp, wtp, acc);
+    acc = fma(dh.rr, wrr, acc);
+    acc = fma(dh.hh, wth, acc);
+    acc = fma(dh.pp, wpp, acc);
     d.ph = acc * in.scale;
     d.qt = fma(g.tt, pt, g.tp * pph);
     d.qr = g.rr * pr;
@@ -73,6 +85,8 @@ static __device__ __forceinline__ Deriv deriv_from(const InvMetric& g, const Inv
 
 // Right-hand side at one stage point: metric at (r, th), (r+eps, th) and
 // (r, th+eps), sin/cos at th+eps by angle addition from those at th and eps;
+// each displaced component is formed together with its difference from the
+// base point's (metric_diff: one rounding for the difference);
 // p-dot = -1/(2 eps) times the sum of the five component differences times
 // p_nu p_sigma, in the order tt, tphi (weight 2 p_t p_phi), rr, thth, phph.
 // Two divisions per stage: is = 1/(rho2 Delta sin^2) at (r, th), inv = is
@@ -100,9 +114,9 @@ static __device__ __forceinline__ Deriv rhs_sc(const Hole& H, const Integrator& 
     const double is_r = recip_newton(rho2_delta(H, R1, T0) * T0.s2, is);
     const double inv_t = recip_newton(rho2_delta(H, R0, T1), inv);
     const InvMetric g = metric_from(H, R0, T0, inv, is);
-    const InvMetric gr = metric_from(H, R1, T0, is_r * T0.s2, is_r);
-    const InvMetric gh = metric_from(H, R0, T1, inv_t, inv_t * rcp_rn(T1.s2));
-    return deriv_from(g, gr, gh, in, pt, pr, pth, pph, wtt, wtp, wpp);
+    const InvMetric dr = metric_diff(H, R1, T0, is_r * T0.s2, is_r, g);
+    const InvMetric dh = metric_diff(H, R0, T1, inv_t, inv_t * rcp_rn(T1.s2), g);
+    return deriv_from(g, dr, dh, in, pt, pr, pth, pph, wtt, wtp, wpp);
 }
 
 // The right-hand side at (r, th): sin and cos of th by sincos_def.
@@ -128,7 +142,7 @@ static __device__ __forceinline__ Deriv rhs_mn(const MnHole& K, const Integrator
     const InvMetric g = mn_inverse_metric<IeeeDiv>(K, r, c, s2);
     const InvMetric gr = mn_inverse_metric<IeeeDiv>(K, r + in.eps, c, s2);
     const InvMetric gh = mn_inverse_metric<IeeeDiv>(K, r, ce, se * se);
-    return deriv_from(g, gr, gh, in, pt, pr, pth, pph, wtt, wtp, wpp);
+    return deriv_from(g, minus(gr, g), minus(gh, g), in, pt, pr, pth, pph, wtt, wtp, wpp);
 }
 
 struct Ray {

@@ -88,8 +88,6 @@ __device__ __forceinline__ void sincos_f32(float x, float& s_out, float& c_out) 
     c_out = (q == 1 || q == 2) ? -c : c;
 }
 
-__device__ __forceinline__ float dq(double hi, double lo) { return (float)(hi - lo); }
-
 __device__ __forceinline__ DerivF rhs_mixed(const Hole& H, double eps, float r, float th,
                                             float pr, float pth, const ConstF& K) {
     float sf, cf;
@@ -106,22 +104,22 @@ __device__ __forceinline__ DerivF rhs_mixed(const Hole& H, double eps, float r, 
     const double is_r = recip_newton(rho2_delta(H, R1, T0) * T0.s2, is);
     const double inv_t = recip_newton(rho2_delta(H, R0, T1), inv);
     const InvMetric g = metric_from(H, R0, T0, inv, is);
-    const InvMetric gr = metric_from(H, R1, T0, is_r * T0.s2, is_r);
-    const InvMetric gh = metric_from(H, R0, T1, inv_t, inv_t * rcp_nr(T1.s2));
+    const InvMetric dr = metric_diff(H, R1, T0, is_r * T0.s2, is_r, g);
+    const InvMetric dh = metric_diff(H, R0, T1, inv_t, inv_t * rcp_nr(T1.s2), g);
 
     const float wrr = (pr * pr) * K.ie, wth = (pth * pth) * K.ie;
-    float acc = dq(gr.tt, g.tt) * K.wtt;
-    acc = fmaf(dq(gr.tp, g.tp), K.wtp, acc);
-    acc = fmaf(dq(gr.rr, g.rr), wrr, acc);
-    acc = fmaf(dq(gr.hh, g.hh), wth, acc);
-    acc = fmaf(dq(gr.pp, g.pp), K.wpp, acc);
+    float acc = (float)dr.tt * K.wtt;
+    acc = fmaf((float)dr.tp, K.wtp, acc);
+    acc = fmaf((float)dr.rr, wrr, acc);
+    acc = fmaf((float)dr.hh, wth, acc);
+    acc = fmaf((float)dr.pp, K.wpp, acc);
     DerivF d;
     d.pr = -0.5f * acc;
-    acc = dq(gh.tt, g.tt) * K.wtt;
-    acc = fmaf(dq(gh.tp, g.tp), K.wtp, acc);
-    acc = fmaf(dq(gh.rr, g.rr), wrr, acc);
-    acc = fmaf(dq(gh.hh, g.hh), wth, acc);
-    acc = fmaf(dq(gh.pp, g.pp), K.wpp, acc);
+    acc = (float)dh.tt * K.wtt;
+    acc = fmaf((float)dh.tp, K.wtp, acc);
+    acc = fmaf((float)dh.rr, wrr, acc);
+    acc = fmaf((float)dh.hh, wth, acc);
+    acc = fmaf((float)dh.pp, K.wpp, acc);
     d.ph = -0.5f * acc;
 
     const float gtt = (float)g.tt, gtp = (float)g.tp, grr = (float)g.rr, ghh = (float)g.hh,
