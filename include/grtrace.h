@@ -293,7 +293,7 @@ int gr_shade_frame(const gr_shade *shade, const gr_output *out, int64_t n, uint3
 /* Trace n >= 1 instances (possibly different black holes, cameras and image
  * sizes) in one persistent launch fed by one work queue (GR_FP64 only:
  * GR_EUNSUPPORTED for GR_MIXED).  The instance table
- * (384 bytes per instance) is copied to device memory owned by the
+ * (416 bytes per instance) is copied to device memory owned by the
  * context, which grows it with hipMalloc when a larger batch arrives.  Same
  * errors as gr_trace_frame (GR_ENOMEM if the table cannot grow); an error in
  * any instance rejects the whole call. */

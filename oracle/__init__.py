@@ -194,7 +194,7 @@ def trace_frame(M, a, Q, r0, theta0, phi0, fov, width, height, dt=0.01, eps=1e-8
     method 0 is RK4, 1 explicit Euler, 2 RK4 in coordinate time (each stage
     reparametrised); disk = (r_in, r_out, half_angle) adds
     the solid equatorial ring (flag 4 on hitting it).  form "listing" (default)
-    or "twin" (see the module docstring); probe (listing form, 0..4) adds the
+    or "twin" (see the module docstring); probe (listing form, 0..8) adds the
     per-ray sensitivity."""
     if form == "listing":
         return _listing_frame(0, M, a, Q, r0, theta0, phi0, fov, width, height, dt, eps,

@@ -48,8 +48,10 @@
  * end angles differ by about what a one-ulp change of a ray's start does.
  * That sensitivity is measured per ray by re-running it from perturbed
  * starts (the conditioning probe): p_theta scaled by 1 + 2^-52, the camera
- * latitude moved by one ulp, and the whole covector scaled by 1 + 2^-52 and
- * by 1 - 2^-53.  A ray's flag and step count count as ill-conditioned when a
+ * latitude moved up by one ulp, and the whole covector scaled by 1 + 2^-52
+ * and by 1 - 2^-53 (probes 1-4); then p_theta scaled by 1 - 2^-53, the
+ * latitude moved down by one ulp, and p_r scaled by 1 + 2^-52 and by
+ * 1 - 2^-53 (probes 5-8).  A ray's flag and step count count as ill-conditioned when a
  * probe changes them, or when the exit was a tie: the escape or horizon test
  * was decided by a margin within TIE_K times the probes' spread of the tested
  * quantity.
@@ -344,7 +346,7 @@ static void camera_start(const lspec *L, double r0, double th0, double ph0, doub
 
 /* ------------------------------------------------------------------ drivers */
 
-enum { NPROBE_MAX = 4 };
+enum { NPROBE_MAX = 8 };
 
 /* An exit is a tie when its margin from the threshold (on the side of the
  * final step or of the step before) is within TIE_K times the probes' spread
@@ -401,20 +403,23 @@ static void run_ray(ljob *J, int64_t k)
     double sens = 0.0, spread = 0.0;
     int flip = 0;
     const double up = 1.0 + 0x1p-52;
+    const double down = 1.0 - 0x1p-53;
     for (int pb = 0; pb < J->nprobe && pb < NPROBE_MAX; ++pb) {
         double z[8];
-        if (pb == 1 && !J->init) {
-            start_of(J, k, nextafter(J->th0, INFINITY), z);
+        if ((pb == 1 || pb == 5) && !J->init) {
+            start_of(J, k, nextafter(J->th0, pb == 1 ? INFINITY : -INFINITY), z);
         } else {
             memcpy(z, y0, sizeof z);
-            if (pb == 0) {
-                z[6] = z[6] * up;                     /* p_theta */
-            } else if (pb == 1) {
-                z[2] = nextafter(z[2], INFINITY);     /* theta (ray lists) */
+            if (pb == 0 || pb == 4) {
+                z[6] = z[6] * (pb == 0 ? up : down);                /* p_theta */
+            } else if (pb == 1 || pb == 5) {
+                z[2] = nextafter(z[2], pb == 1 ? INFINITY : -INFINITY);   /* theta (ray lists) */
+            } else if (pb == 6 || pb == 7) {
+                z[5] = z[5] * (pb == 6 ? up : down);                /* p_r */
             } else {
                 /* the whole covector scaled: the same ray in coordinate time,
                  * every rounding different */
-                const double lam = pb == 2 ? up : 1.0 - 0x1p-53;
+                const double lam = pb == 2 ? up : down;
                 for (int m = 4; m < 8; ++m) z[m] = z[m] * lam;
             }
         }
@@ -478,7 +483,7 @@ static void mn_setup(lspec *L, double M, double S, double q)
  * (M, a, Q) Kerr-Newman; kind 1: (M, S, q) Manko-Novikov.  method 0 RK4,
  * 1 Euler, 2 RK4 in coordinate time; ring = (r_in, r_out, half angle) or NULL.  out8 receives the end
  * (t, r, theta, phi, p_t, p_r, p_theta, p_phi) of every ray; with nprobe > 0
- * (at most 4) each ray is re-run from that many perturbed starts and sens/flip
+ * (at most 8) each ray is re-run from that many perturbed starts and sens/flip
  * receive the largest end-angle change and whether flag or steps changed. */
 int64_t listing_trace_frame(int kind, double p1, double p2, double p3, double r0, double th0,
                             double ph0, double fov, int W, int H, double dt, double eps,

@@ -159,8 +159,10 @@ static void sincos_mode(int mode, double x, double *s, double *c)
  * |u| <= 1/32, the latter entering the result multiplied by s or c: at most
  * a fifth of its ulp), and then doubled m times:
  * sin 2u = 2 sin u (1 + (cos u - 1)), cos 2u - 1 = -2 sin^2 u.
- * The twin form carries sin/cos of theta along a Kerr-Newman RK4 ray this
- * way instead of evaluating them at every stage point. */
+ * The results are formed by two fma each, s (1 + (cos d - 1)) first and then
+ * the sin d term.  The twin form carries sin/cos of theta along a
+ * Kerr-Newman RK4 ray this way instead of evaluating them at every stage
+ * point. */
 static long g_halved_rotations = 0;       /* rotations that needed halving (test statistics) */
 
 static void rotate_pair(double s, double c, double d, double *s_out, double *c_out)
@@ -185,8 +187,8 @@ static void rotate_pair(double s, double c, double d, double *s_out, double *c_o
         cm1 = -2.0 * (sd * sd);
         sd = s2;
     }
-    *s_out = s + fma(c, sd, s * cm1);
-    *c_out = c + fma(-s, sd, c * cm1);
+    *s_out = fma(c, sd, fma(s, cm1, s));      /* s cos d, then + c sin d */
+    *c_out = fma(-s, sd, fma(c, cm1, c));     /* c cos d, then - s sin d */
 }
 
 /* ------------------------------------------------------------------------ */
@@ -349,6 +351,12 @@ static void mn_inverse_metric(const mn_consts *K, double r, double y, double s2,
  * same rounded values serve every evaluation at one theta.  The components
  * share the reciprocals inv = 1/(rho^2 Delta) and is = inv / sin^2 (see
  * metric_recips for how they are formed). */
+/* a (2 M r - Q^2), with a 2M and a Q^2 rounded once each. */
+static double a_term(const oracle_params *P, double r)
+{
+    return fma(P->a * (2.0 * P->M), r, -(P->a * (P->Q * P->Q)));
+}
+
 static void metric_from(const oracle_params *P, double r, double s2, double inv, double is,
                         double g[5])
 {
@@ -359,7 +367,7 @@ static void metric_from(const oracle_params *P, double r, double s2, double inv,
     const double w = a2 * s2;                                  /* a^2 sin^2 */
     const double Sigma2 = fma(-w, Delta, ra * ra);
     g[0] = -(Sigma2 * inv);
-    g[1] = -((P->a * fma(2.0 * P->M, r, -(P->Q * P->Q))) * inv);
+    g[1] = -(a_term(P, r) * inv);
     g[2] = (Delta * Delta) * inv;
     g[3] = Delta * inv;
     g[4] = (Delta - w) * is;
@@ -381,7 +389,7 @@ static void metric_diff(const oracle_params *P, double r, double s2, double inv,
     const double w = a2 * s2;
     const double Sigma2 = fma(-w, Delta, ra * ra);
     d[0] = fma(-Sigma2, inv, -g0[0]);
-    d[1] = fma(-(P->a * fma(2.0 * P->M, r, -(P->Q * P->Q))), inv, -g0[1]);
+    d[1] = fma(-a_term(P, r), inv, -g0[1]);
     d[2] = fma(Delta * Delta, inv, -g0[2]);
     d[3] = fma(Delta, inv, -g0[3]);
     d[4] = fma(Delta - w, is, -g0[4]);

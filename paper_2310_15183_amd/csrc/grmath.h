@@ -79,8 +79,7 @@ GR_HD void sincos_def(double x, double& s_out, double& c_out) {
 // rotation: at most a fifth of an ulp of the result, and far less at the
 // increments of ordinary steps), then m double-angle steps
 // sin 2u = 2 sin u (1 + (cos u - 1)), cos 2u - 1 = -2 sin^2 u give those of d;
-// the small corrections are summed first and added to s and c with one
-// rounding each.  rotate_small is the case m = 0 alone (no branch), equal to
+// each result takes two fma, s (1 + (cos d - 1)) first, then the sin d term.  rotate_small is the case m = 0 alone (no branch), equal to
 // rotate_sc bit for bit wherever |d| <= 1/32.
 constexpr double ROT_SERIES_MAX = 0.03125;
 
@@ -97,8 +96,8 @@ GR_HD void small_angle(double u, double& sd, double& cm1) {
 }
 
 GR_HD void rotate_by(double s, double c, double sd, double cm1, double& s_out, double& c_out) {
-    s_out = s + fma(c, sd, s * cm1);
-    c_out = c + fma(-s, sd, c * cm1);
+    s_out = fma(c, sd, fma(s, cm1, s));      // s cos d, then + c sin d
+    c_out = fma(-s, sd, fma(c, cm1, c));     // c cos d, then - s sin d
 }
 
 GR_HD void rotate_small(double s, double c, double d, double& s_out, double& c_out) {
@@ -125,9 +124,11 @@ GR_HD void rotate_sc(double s, double c, double d, double& s_out, double& c_out)
 }
 
 // ------------------------------------------------------------ black hole
-// Uniform per-hole constants.  a2 = a*a, aq = a2 + Q*Q, M2 = 2M, Q2 = Q*Q.
+// Uniform per-hole constants.  a2 = a*a, aq = a2 + Q*Q, M2 = 2M, Q2 = Q*Q,
+// aM2 = a M2, aQ2 = a Q2.
 struct Hole {
     double a, a2, aq, M2, Q2;
+    double aM2, aQ2;           // a (2M) and a Q^2: a(2Mr - Q^2) = fma(aM2, r, -aQ2)
 };
 
 GR_HD Hole make_hole(double M, double a, double Q) {
@@ -137,6 +138,8 @@ GR_HD Hole make_hole(double M, double a, double Q) {
     h.Q2 = Q * Q;
     h.aq = h.a2 + h.Q2;
     h.M2 = 2.0 * M;
+    h.aM2 = a * h.M2;
+    h.aQ2 = a * h.Q2;
     return h;
 }
 
@@ -170,7 +173,7 @@ GR_HD RadialTerms radial_terms(const Hole& H, double r) {
     const double ra = R.r2 + H.a2;
     R.rara = ra * ra;
     R.Delta = fma(r, r - H.M2, H.aq);
-    R.aF = H.a * fma(H.M2, r, -H.Q2);
+    R.aF = fma(H.aM2, r, -H.aQ2);
     R.DD = R.Delta * R.Delta;
     return R;
 }

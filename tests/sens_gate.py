@@ -6,20 +6,22 @@ by eps, so two correct implementations whose roundings differ (the listing
 form with the C library's sin/cos and a division per component, against the
 kernel's fixed sequence) end their rays ~1e-9 rad apart, about as far as the
 same implementation started one ulp away.  The listing form measures that
-per ray (oracle probe: p_theta scaled by 1 + 2^-52, the camera latitude moved
-by one ulp, and the whole covector scaled by 1 + 2^-52 and 1 - 2^-53, which
+per ray (oracle probe=8: p_theta scaled by 1 + 2^-52 and by 1 - 2^-53, the
+camera latitude moved one ulp up and down, p_r scaled by 1 + 2^-52 and by
+1 - 2^-53, and the whole covector scaled by 1 + 2^-52 and 1 - 2^-53, which
 leaves the ray unchanged in coordinate time but changes every rounding); s
-is the largest end-angle change of the probes.  A ray's flag and step count
+is the largest end-angle change of the probes.  (With the first four probes
+alone s was underestimated on some rays: on the 1000^2 frame's far-field
+grid rays the largest d / s fell from 25 to 7 with all eight.)  A ray's flag and step count
 are ill-conditioned (ref.flip) when a probe changes them or when its exit was
 a tie: the escape or horizon test decided by a margin within 64 times the
 probes' spread of the tested quantity (r, or |dt/dtau|), so that rounding
 differently could end it one step earlier or later.
 
 Gate: flags and step counts identical on every ray not so marked, and d = max(|d theta|, |d phi|) <= K_MAX * s on each such ray,
-with the median and 99th percentile of d / s at most K_MED and K_P99.  On
-the small Kerr frame the kernel-twin form measures 1.4 / 9 / 25 (median,
-p99, max over 4096 rays); a planted mistake (a dropped factor, a sign, the
-listing's 0.1667 in place of 1/6) gives ratios of 1e3 or more.
+with the median and 99th percentile of d / s at most K_MED and K_P99; a
+planted mistake (a dropped factor, a sign, the listing's 0.1667 in place of
+1/6) gives ratios of 1e3 or more.
 """
 from __future__ import annotations
 

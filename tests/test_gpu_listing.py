@@ -38,7 +38,7 @@ def _listing(case, integ, pixels=None, mn=False):
     trace = oracle.trace_frame_mn if mn else oracle.trace_frame
     return trace(*case, dt=integ.dt, eps=integ.fd_eps, horizon_norm=integ.horizon_norm,
                  escape_factor=integ.escape_factor, max_steps=integ.max_steps, pixels=pixels,
-                 probe=4)
+                 probe=8)
 
 
 def _gate(gpu, ref):

@@ -101,7 +101,7 @@ def test_megapixel_sampled_and_listing_gate(g):
     sub = {k: v[pix] for k, v in gpu.items()}
     st = compare(sub, _twin(case, integ, pixels=pix), angle_tol=0.0)
     assert st["bit_identical"] == st["n"]
-    lis = oracle.trace_frame(*case, dt=0.005, max_steps=50000, pixels=pix, method=2, probe=4)
+    lis = oracle.trace_frame(*case, dt=0.005, max_steps=50000, pixels=pix, method=2, probe=8)
     print(compare_at_sensitivity(sub, lis))
 
 

@@ -70,7 +70,7 @@ def test_twin_matches_listing_with_coordinate_time_rk4(mn):
     else:
         case = (0.5, 0.3, 0.2, 20.0, math.radians(75.0), 0.0, math.radians(60.0), 24, 18)
         trace = oracle.trace_frame
-    lis = trace(*case, dt=0.01, max_steps=20000, method=2, probe=4)
+    lis = trace(*case, dt=0.01, max_steps=20000, method=2, probe=8)
     twin = trace(*case, dt=0.01, max_steps=20000, method=2, form="twin")
     st = compare_at_sensitivity({"theta": twin.theta, "phi": twin.phi, "flag": twin.flag,
                                  "steps": twin.steps}, lis)

@@ -70,7 +70,7 @@ def test_large_steps_use_halved_rotations_and_meet_the_gate():
     oracle.halved_rotations(reset=True)
     twin = oracle.trace_frame(*case, dt=0.5, max_steps=20000, form="twin")
     assert oracle.halved_rotations() > 1000
-    lis = oracle.trace_frame(*case, dt=0.5, max_steps=20000, probe=4)
+    lis = oracle.trace_frame(*case, dt=0.5, max_steps=20000, probe=8)
     st = compare_at_sensitivity({"theta": twin.theta, "phi": twin.phi, "flag": twin.flag,
                                  "steps": twin.steps}, lis)
     print(st)
