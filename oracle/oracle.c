@@ -450,9 +450,15 @@ static void metric_at_point(const oracle_params *P, double r, double theta, doub
  * points and subtracted.  The contraction sums the differences of the five
  * independent components times p_nu p_sigma in the order tt, t-phi (weight
  * 2 p_t p_phi), rr, theta-theta, phi-phi, then scales once by -1/(2 eps). */
-static void hamilton_rhs_sc(const oracle_params *P, const double eps_sc[2], double r,
-                            double s, double c, double pt, double pr, double pth, double pph,
-                            double qdot[4], double pdot[2])
+/* -1/(2 eps): the scaling of the contracted differences into p-dot. */
+static double fd_scale(const oracle_params *P)
+{
+    return -0.5 * (1.0 / P->eps);
+}
+
+static void rhs_core(const oracle_params *P, const double eps_sc[2], double r, double s,
+                     double c, double pt, double pr, double pth, double pph, double qdot[4],
+                     double pdot[2], int raw)
 {
     double g[5], dr[5], dth[5];        /* base metric; differences to the displaced points */
     const double se = fma(c, eps_sc[0], s * eps_sc[1]);      /* sin(theta + eps) */
@@ -486,26 +492,42 @@ static void hamilton_rhs_sc(const oracle_params *P, const double eps_sc[2], doub
     /* weights p_nu p_sigma of the five independent components */
     const double wtt = pt * pt, wtp = (2.0 * pt) * pph, wpp = pph * pph;
     const double wrr = pr * pr, wth = pth * pth;
-    const double scale = -0.5 * (1.0 / P->eps);                /* -1/(2 eps) */
+    const double scale = fd_scale(P);
 
     double acc = dr[0] * wtt;
     acc = fma(dr[1], wtp, acc);
     acc = fma(dr[2], wrr, acc);
     acc = fma(dr[3], wth, acc);
     acc = fma(dr[4], wpp, acc);
-    pdot[0] = acc * scale;                                     /* dp_r/dtau */
+    pdot[0] = raw ? acc : acc * scale;                         /* dp_r/dtau */
 
     acc = dth[0] * wtt;
     acc = fma(dth[1], wtp, acc);
     acc = fma(dth[2], wrr, acc);
     acc = fma(dth[3], wth, acc);
     acc = fma(dth[4], wpp, acc);
-    pdot[1] = acc * scale;                                     /* dp_theta/dtau */
+    pdot[1] = raw ? acc : acc * scale;                         /* dp_theta/dtau */
 
     qdot[0] = fma(g[0], pt, g[1] * pph);                       /* dt/dtau */
     qdot[1] = g[2] * pr;                                       /* dr/dtau */
     qdot[2] = g[3] * pth;                                      /* dtheta/dtau */
     qdot[3] = fma(g[1], pt, g[4] * pph);                       /* dphi/dtau */
+}
+
+/* The right-hand side with p-dot scaled, and unscaled (the contracted sums
+ * alone: the carried Kerr-Newman RK4 folds -1/(2 eps) into its step sizes). */
+static void hamilton_rhs_sc(const oracle_params *P, const double eps_sc[2], double r,
+                            double s, double c, double pt, double pr, double pth, double pph,
+                            double qdot[4], double pdot[2])
+{
+    rhs_core(P, eps_sc, r, s, c, pt, pr, pth, pph, qdot, pdot, 0);
+}
+
+static void hamilton_rhs_sc_raw(const oracle_params *P, const double eps_sc[2], double r,
+                                double s, double c, double pt, double pr, double pth,
+                                double pph, double qdot[4], double pdot[2])
+{
+    rhs_core(P, eps_sc, r, s, c, pt, pr, pth, pph, qdot, pdot, 1);
 }
 
 /* The same at (r, theta), sin and cos of theta from the stated definition. */
@@ -607,6 +629,7 @@ int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nste
             continue;
         }
         double nu, h;
+        const double pscale = fd_scale(P);
         if (P->kind == METRIC_MN) {
             /* K1 at the current point; its dt/dtau fixes the step. */
             hamilton_rhs(P, eps_sc, q[1], q[2], pt, pr, pth, pph, k1q, k1p);
@@ -623,21 +646,23 @@ int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nste
         } else {
             /* Kerr-Newman: theta enters through its sine and cosine only, and
              * the ray carries them; each stage point's pair is the carried
-             * pair rotated by that stage's increment of theta. */
+             * pair rotated by that stage's increment of theta.  p-dot comes
+             * unscaled and -1/(2 eps) multiplies the momenta's step sizes. */
             double s2, c2;
-            hamilton_rhs_sc(P, eps_sc, q[1], sn, cs, pt, pr, pth, pph, k1q, k1p);
+            hamilton_rhs_sc_raw(P, eps_sc, q[1], sn, cs, pt, pr, pth, pph, k1q, k1p);
             nu = fabs(k1q[0]);
             h = P->dt / nu;
             const double hh = 0.5 * h;
+            const double hhs = hh * pscale, hs = h * pscale;
             rotate_pair(sn, cs, hh * k1q[2], &s2, &c2);
-            hamilton_rhs_sc(P, eps_sc, fma(hh, k1q[1], q[1]), s2, c2, pt,
-                            fma(hh, k1p[0], pr), fma(hh, k1p[1], pth), pph, k2q, k2p);
+            hamilton_rhs_sc_raw(P, eps_sc, fma(hh, k1q[1], q[1]), s2, c2, pt,
+                                fma(hhs, k1p[0], pr), fma(hhs, k1p[1], pth), pph, k2q, k2p);
             rotate_pair(sn, cs, hh * k2q[2], &s2, &c2);
-            hamilton_rhs_sc(P, eps_sc, fma(hh, k2q[1], q[1]), s2, c2, pt,
-                            fma(hh, k2p[0], pr), fma(hh, k2p[1], pth), pph, k3q, k3p);
+            hamilton_rhs_sc_raw(P, eps_sc, fma(hh, k2q[1], q[1]), s2, c2, pt,
+                                fma(hhs, k2p[0], pr), fma(hhs, k2p[1], pth), pph, k3q, k3p);
             rotate_pair(sn, cs, h * k3q[2], &s2, &c2);
-            hamilton_rhs_sc(P, eps_sc, fma(h, k3q[1], q[1]), s2, c2, pt,
-                            fma(h, k3p[0], pr), fma(h, k3p[1], pth), pph, k4q, k4p);
+            hamilton_rhs_sc_raw(P, eps_sc, fma(h, k3q[1], q[1]), s2, c2, pt,
+                                fma(hs, k3p[0], pr), fma(hs, k3p[1], pth), pph, k4q, k4p);
         }
         /* x += h/6 (k1 + 2 k2 + 2 k3 + k4) */
         const double h6 = h * (1.0 / 6.0);
@@ -646,8 +671,9 @@ int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nste
             S[m] = ((k1q[m] + 2.0 * k2q[m]) + 2.0 * k3q[m]) + k4q[m];
             q[m] = fma(h6, S[m], q[m]);
         }
-        pr = fma(h6, ((k1p[0] + 2.0 * k2p[0]) + 2.0 * k3p[0]) + k4p[0], pr);
-        pth = fma(h6, ((k1p[1] + 2.0 * k2p[1]) + 2.0 * k3p[1]) + k4p[1], pth);
+        const double h6p = P->kind == METRIC_MN ? h6 : h6 * pscale;   /* see above */
+        pr = fma(h6p, ((k1p[0] + 2.0 * k2p[0]) + 2.0 * k3p[0]) + k4p[0], pr);
+        pth = fma(h6p, ((k1p[1] + 2.0 * k2p[1]) + 2.0 * k3p[1]) + k4p[1], pth);
         if (P->kind != METRIC_MN) {
             double s2, c2;
             rotate_pair(sn, cs, h6 * S[2], &s2, &c2);     /* the carried pair follows theta */

@@ -57,7 +57,9 @@ static __device__ __forceinline__ InvMetric minus(const InvMetric& a, const InvM
 // component differences dr, dh from there to (r + eps, theta) and
 // (r, theta + eps): p-dot = -1/(2 eps) times the sum of the five component
 // differences times p_nu p_sigma, in the order tt, tphi (weight 2 p_t p_phi),
-// rr, thth, phph.
+// rr, thth, phph.  RAW leaves the sums unscaled (the caller folds -1/(2 eps)
+// into its step sizes).
+template <bool RAW = false>
 static __device__ __forceinline__ Deriv deriv_from(const InvMetric& g, const InvMetric& dr,
                                                    const InvMetric& dh, const Integrator& in,
                                                    double pt, double pr, double pth, double pph,
@@ -69,13 +71,13 @@ static __device__ __forceinline__ Deriv deriv_from(const InvMetric& g, const Inv
     acc = fma(dr.hh, wth, acc);
     acc = fma(dr.pp, wpp, acc);
     Deriv d;
-    d.pr = acc * in.scale;
+    d.pr = RAW ? acc : acc * in.scale;
     acc = dh.tt * wtt;
     acc = fma(dh.tp, wtp, acc);
     acc = fma(dh.rr, wrr, acc);
     acc = fma(dh.hh, wth, acc);
     acc = fma(dh.pp, wpp, acc);
-    d.ph = acc * in.scale;
+    d.ph = RAW ? acc : acc * in.scale;
     d.qt = fma(g.tt, pt, g.tp * pph);
     d.qr = g.rr * pr;
     d.qh = g.hh * pth;
@@ -98,7 +100,7 @@ static __device__ __forceinline__ Deriv deriv_from(const InvMetric& g, const Inv
 // UNIT_COS: cos eps is 1.0 (it rounds to 1 for eps below 1.05e-8, the
 // paper's 1e-8 included), so the products with it are exact and are left
 // out; chosen per launch, it gives the same bits as the general form.
-template <bool UNIT_COS = false>
+template <bool UNIT_COS = false, bool RAW = false>
 static __device__ __forceinline__ Deriv rhs_sc(const Hole& H, const Integrator& in, double r,
                                                double s, double c, double pt, double pr,
                                                double pth, double pph, double wtt, double wtp,
@@ -116,7 +118,7 @@ static __device__ __forceinline__ Deriv rhs_sc(const Hole& H, const Integrator& 
     const InvMetric g = metric_from(H, R0, T0, inv, is);
     const InvMetric dr = metric_diff(H, R1, T0, is_r * T0.s2, is_r, g);
     const InvMetric dh = metric_diff(H, R0, T1, inv_t, inv_t * rcp_rn(T1.s2), g);
-    return deriv_from(g, dr, dh, in, pt, pr, pth, pph, wtt, wtp, wpp);
+    return deriv_from<RAW>(g, dr, dh, in, pt, pr, pth, pph, wtt, wtp, wpp);
 }
 
 // The right-hand side at (r, th): sin and cos of th by sincos_def.
@@ -278,8 +280,11 @@ static __device__ __forceinline__ double euler_generic(const Rhs& rhs_at, const 
 template <bool GENERAL, bool UNIT_COS = false>
 static __device__ __forceinline__ double rk4_carry(const Hole& H, const Integrator& in, Ray& y,
                                                    double& dmax) {
+    // p-dot comes unscaled (RAW): -1/(2 eps) is folded into the step sizes
+    // of the momentum components, hh in.scale, h in.scale and h/6 in.scale
     const auto f = [&](double r, double sn, double cs, double pr, double pth) {
-        return rhs_sc<UNIT_COS>(H, in, r, sn, cs, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
+        return rhs_sc<UNIT_COS, true>(H, in, r, sn, cs, y.pt, pr, pth, y.pph, y.wtt, y.wtp,
+                                      y.wpp);
     };
     dmax = 0.0;
     const auto rot = [&](double d, double& sn, double& cs) {
@@ -295,27 +300,30 @@ static __device__ __forceinline__ double rk4_carry(const Hole& H, const Integrat
     const double nu = fabs(k.qt);
     const double h = div_rn(in.dt, nu);
     const double hh = 0.5 * h;
+    const double hhs = hh * in.scale;
     double st = k.qt, sr = k.qr, sh = k.qh, sp = k.qp, spr = k.pr, sph = k.ph;
     rot(hh * k.qh, sn, cs);
-    k = f(fma(hh, k.qr, y.r), sn, cs, fma(hh, k.pr, y.pr), fma(hh, k.ph, y.pth));
+    k = f(fma(hh, k.qr, y.r), sn, cs, fma(hhs, k.pr, y.pr), fma(hhs, k.ph, y.pth));
     st = fma(2.0, k.qt, st); sr = fma(2.0, k.qr, sr); sh = fma(2.0, k.qh, sh);
     sp = fma(2.0, k.qp, sp); spr = fma(2.0, k.pr, spr); sph = fma(2.0, k.ph, sph);
     rot(hh * k.qh, sn, cs);
-    k = f(fma(hh, k.qr, y.r), sn, cs, fma(hh, k.pr, y.pr), fma(hh, k.ph, y.pth));
+    k = f(fma(hh, k.qr, y.r), sn, cs, fma(hhs, k.pr, y.pr), fma(hhs, k.ph, y.pth));
     st = fma(2.0, k.qt, st); sr = fma(2.0, k.qr, sr); sh = fma(2.0, k.qh, sh);
     sp = fma(2.0, k.qp, sp); spr = fma(2.0, k.pr, spr); sph = fma(2.0, k.ph, sph);
     rot(h * k.qh, sn, cs);
-    k = f(fma(h, k.qr, y.r), sn, cs, fma(h, k.pr, y.pr), fma(h, k.ph, y.pth));
+    const double hs = h * in.scale;
+    k = f(fma(h, k.qr, y.r), sn, cs, fma(hs, k.pr, y.pr), fma(hs, k.ph, y.pth));
     st = st + k.qt; sr = sr + k.qr; sh = sh + k.qh; sp = sp + k.qp;
     spr = spr + k.pr; sph = sph + k.ph;
     const double h6 = h * (1.0 / 6.0);
+    const double h6s = h6 * in.scale;
     rot(h6 * sh, sn, cs);
     y.t = fma(h6, st, y.t);
     y.r = fma(h6, sr, y.r);
     y.th = fma(h6, sh, y.th);
     y.ph = fma(h6, sp, y.ph);
-    y.pr = fma(h6, spr, y.pr);
-    y.pth = fma(h6, sph, y.pth);
+    y.pr = fma(h6s, spr, y.pr);
+    y.pth = fma(h6s, sph, y.pth);
     y.sn = sn;
     y.cs = cs;
     return nu;

@@ -179,7 +179,7 @@ MUTANTS = [
     ("const double h6 = h * (1.0 / 6.0);", "const double h6 = h * 0.1667;"),   # listing's 0.1667
     ("return fma(P->a * (2.0 * P->M), r, -(P->a * (P->Q * P->Q)));",
      "return -fma(P->a * (2.0 * P->M), r, -(P->a * (P->Q * P->Q)));"),      # sign of g^{t phi}
-    ("const double scale = -0.5 * (1.0 / P->eps);", "const double scale = -0.5 * (1.0 / 1.01e-8);"),
+    ("return -0.5 * (1.0 / P->eps);", "return -0.5 * (1.0 / 1.01e-8);"),          # eps off by 1%
 ]
 
 
