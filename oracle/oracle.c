@@ -417,6 +417,15 @@ static double recip_newton(double x, double y0)
     return fma(y, e, y);
 }
 
+/* One Newton step y0 + y0 (1 - x y0): relative error e0^2 plus one rounding.
+ * Enough for the theta displacement, whose e0 is eps times the logarithmic
+ * derivative of rho^2 in theta, at most eps a^2/rho^2 <= eps (1e-8): the
+ * result is then within an ulp and mostly correctly rounded. */
+static double recip_newton1(double x, double y0)
+{
+    return fma(y0, fma(-x, y0, 1.0), y0);
+}
+
 /* Full inverse metric at one point: is = 1/(rho^2 Delta sin^2) divided,
  * inv = is sin^2. */
 static void inverse_metric(const oracle_params *P, double r, double s2, double c2,
@@ -466,8 +475,9 @@ static void rhs_core(const oracle_params *P, const double eps_sc[2], double r, d
     const double s2 = s * s, c2 = c * c, se2 = se * se, ce2 = ce * ce;
     /* reciprocals (two divisions): at (r, theta) is = 1/(rho^2 Delta sin^2)
      * and inv = is sin^2; at (r + eps, theta) is refined from the base point's;
-     * at (r, theta + eps) 1/(rho^2 Delta) is refined from inv and multiplied
-     * by a divided 1/sin^2 (near the axis sin^2 changes by a large factor
+     * at (r, theta + eps) 1/(rho^2 Delta) is refined from inv (one Newton
+     * step: rho^2 moves by at most eps relative there) and multiplied by a
+     * divided 1/sin^2 (near the axis sin^2 changes by a large factor
      * over eps, rho^2 Delta never does) */
     if (P->kind == METRIC_MN) {
         /* full evaluations at the three points, then the differences */
@@ -483,7 +493,7 @@ static void rhs_core(const oracle_params *P, const double eps_sc[2], double r, d
         const double is = 1.0 / (rho2_delta(P, r, c2) * s2);
         const double inv = is * s2;
         const double is_r = recip_newton(rho2_delta(P, r + P->eps, c2) * s2, is);
-        const double inv_t = recip_newton(rho2_delta(P, r, ce2), inv);
+        const double inv_t = recip_newton1(rho2_delta(P, r, ce2), inv);
         metric_from(P, r, s2, inv, is, g);
         metric_diff(P, r + P->eps, s2, is_r * s2, is_r, g, dr);
         metric_diff(P, r, se2, inv_t, inv_t * (1.0 / se2), g, dth);
@@ -846,7 +856,6 @@ void oracle_sincos(const double *x, int64_t n, double *sc)
     for (int64_t k = 0; k < n; ++k) trig_sincos(x[k], sc + 2 * k, sc + 2 * k + 1);
 }
 
-/* Accuracy checks of the Newton-refined reciprocal: out[k] = recip_newton(x[k], y0[k]). */
 /* rotate_pair on n triples (x_sin, x_cos, d): out[2k], out[2k+1]. */
 void oracle_rotate(const double *in3, int64_t n, double *out2)
 {
@@ -863,9 +872,16 @@ long oracle_halved_rotations(int reset)
     return v;
 }
 
+/* Accuracy checks of the Newton-refined reciprocals: out[k] = recip_newton(x[k], y0[k])
+ * (two steps) or recip_newton1 (one step). */
 void oracle_recip_newton(const double *x, const double *y0, int64_t n, double *out)
 {
     for (int64_t k = 0; k < n; ++k) out[k] = recip_newton(x[k], y0[k]);
+}
+
+void oracle_recip_newton1(const double *x, const double *y0, int64_t n, double *out)
+{
+    for (int64_t k = 0; k < n; ++k) out[k] = recip_newton1(x[k], y0[k]);
 }
 
 static oracle_params make_params(double M, double a, double Q, double dt, double eps,

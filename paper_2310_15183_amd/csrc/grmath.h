@@ -240,6 +240,13 @@ GR_HD double recip_newton(double x, double y0) {
     return fma(y, e, y);
 }
 
+// One Newton step y0 + y0 (1 - x y0): relative error e0^2 plus one rounding,
+// within an ulp for |e0| <= 1e-8; the theta displacement's e0 is eps times
+// the logarithmic derivative of rho^2 in theta, at most eps a^2/rho^2 <= eps.
+GR_HD double recip_newton1(double x, double y0) {
+    return fma(y0, fma(-x, y0, 1.0), y0);
+}
+
 // -------------------------------------------------------------------- exp
 // x = k ln2 + r, k = rint(x * fl(1/ln2)), r = (x - k LN2_HI) - k LN2_LO via
 // two fma (|r| <= ln2/2); exp r = sum_{n=0}^{13} r^n/n! by Horner in fma
