@@ -347,8 +347,10 @@ static void mn_inverse_metric(const mn_consts *K, double r, double y, double s2,
  *   g^{phph} = (Delta - a^2 sin^2 theta) / (rho^2 Delta sin^2 theta)
  *
  * The sequence of roundings is fixed (it matters: the forward difference
- * divides rounding noise by eps).  sin^2 and cos^2 are passed in so that the
- * same rounded values serve every evaluation at one theta.  The components
+ * divides rounding noise by eps).  sin^2 is passed in so that the same
+ * rounded value serves every evaluation at one theta; rho^2 is formed from it
+ * as (r^2 + a^2) - a^2 sin^2 (cos^2 = 1 - sin^2), which outside a horizon
+ * (r >= a) keeps it to a few ulp.  The components
  * share the reciprocals inv = 1/(rho^2 Delta) and is = inv / sin^2 (see
  * metric_recips for how they are formed). */
 /* a (2 M r - Q^2), with a 2M and a Q^2 rounded once each. */
@@ -395,11 +397,11 @@ static void metric_diff(const oracle_params *P, double r, double s2, double inv,
     d[4] = fma(Delta - w, is, -g0[4]);
 }
 
-/* rho^2 Delta at (r, theta). */
-static double rho2_delta(const oracle_params *P, double r, double c2)
+/* rho^2 Delta at (r, theta), sin^2 theta = s2. */
+static double rho2_delta(const oracle_params *P, double r, double s2)
 {
     const double a2 = P->a * P->a;
-    const double rho2 = fma(a2, c2, r * r);                    /* r^2 + a^2 cos^2 */
+    const double rho2 = (r * r + a2) - a2 * s2;                /* r^2 + a^2 cos^2 */
     const double Delta = fma(r, r - 2.0 * P->M, a2 + P->Q * P->Q);
     return rho2 * Delta;
 }
@@ -417,21 +419,11 @@ static double recip_newton(double x, double y0)
     return fma(y, e, y);
 }
 
-/* One Newton step y0 + y0 (1 - x y0): relative error e0^2 plus one rounding.
- * Enough for the theta displacement, whose e0 is eps times the logarithmic
- * derivative of rho^2 in theta, at most eps a^2/rho^2 <= eps (1e-8): the
- * result is then within an ulp and mostly correctly rounded. */
-static double recip_newton1(double x, double y0)
-{
-    return fma(y0, fma(-x, y0, 1.0), y0);
-}
-
 /* Full inverse metric at one point: is = 1/(rho^2 Delta sin^2) divided,
  * inv = is sin^2. */
-static void inverse_metric(const oracle_params *P, double r, double s2, double c2,
-                           double g[5])
+static void inverse_metric(const oracle_params *P, double r, double s2, double g[5])
 {
-    const double is = 1.0 / (rho2_delta(P, r, c2) * s2);
+    const double is = 1.0 / (rho2_delta(P, r, s2) * s2);
     metric_from(P, r, s2, is * s2, is, g);
 }
 
@@ -443,7 +435,7 @@ static void metric_at_point(const oracle_params *P, double r, double theta, doub
     if (P->kind == METRIC_MN)
         mn_inverse_metric(&P->mn, r, c, s * s, g);
     else
-        inverse_metric(P, r, s * s, c * c, g);
+        inverse_metric(P, r, s * s, g);
 }
 
 /* Right-hand side of Hamilton's equations at one RK4 stage point.
@@ -472,13 +464,12 @@ static void rhs_core(const oracle_params *P, const double eps_sc[2], double r, d
     double g[5], dr[5], dth[5];        /* base metric; differences to the displaced points */
     const double se = fma(c, eps_sc[0], s * eps_sc[1]);      /* sin(theta + eps) */
     const double ce = fma(-s, eps_sc[0], c * eps_sc[1]);     /* cos(theta + eps) */
-    const double s2 = s * s, c2 = c * c, se2 = se * se, ce2 = ce * ce;
-    /* reciprocals (two divisions): at (r, theta) is = 1/(rho^2 Delta sin^2)
-     * and inv = is sin^2; at (r + eps, theta) is refined from the base point's;
-     * at (r, theta + eps) 1/(rho^2 Delta) is refined from inv (one Newton
-     * step: rho^2 moves by at most eps relative there) and multiplied by a
-     * divided 1/sin^2 (near the axis sin^2 changes by a large factor
-     * over eps, rho^2 Delta never does) */
+    const double s2 = s * s, se2 = se * se;
+    /* reciprocals (two divisions): is = 1/(rho^2 Delta sin^2) divided at
+     * (r, theta) and at (r, theta + eps) (near the axis sin^2 changes by a
+     * large factor over eps), inv = is sin^2 at each; at (r + eps, theta),
+     * where only rho^2 Delta moves, by a factor 1 + O(eps), is is refined
+     * from the base point's */
     if (P->kind == METRIC_MN) {
         /* full evaluations at the three points, then the differences */
         double gr[5], gth[5];
@@ -490,13 +481,13 @@ static void rhs_core(const oracle_params *P, const double eps_sc[2], double r, d
             dth[k] = gth[k] - g[k];
         }
     } else {
-        const double is = 1.0 / (rho2_delta(P, r, c2) * s2);
+        const double is = 1.0 / (rho2_delta(P, r, s2) * s2);
         const double inv = is * s2;
-        const double is_r = recip_newton(rho2_delta(P, r + P->eps, c2) * s2, is);
-        const double inv_t = recip_newton1(rho2_delta(P, r, ce2), inv);
+        const double is_r = recip_newton(rho2_delta(P, r + P->eps, s2) * s2, is);
+        const double is_t = 1.0 / (rho2_delta(P, r, se2) * se2);
         metric_from(P, r, s2, inv, is, g);
         metric_diff(P, r + P->eps, s2, is_r * s2, is_r, g, dr);
-        metric_diff(P, r, se2, inv_t, inv_t * (1.0 / se2), g, dth);
+        metric_diff(P, r, se2, is_t * se2, is_t, g, dth);
     }
 
     /* weights p_nu p_sigma of the five independent components */
@@ -749,7 +740,7 @@ static void camera_setup(const oracle_params *P, double r0, double th0, double f
     C->er = sqrt(rho2 / Delta);
     C->eth = sqrt(rho2);
     C->eph = sqrt((Sigma2 * s2) / rho2);
-    inverse_metric(P, r0, s2, c2, C->g);
+    inverse_metric(P, r0, s2, C->g);
 }
 
 static void camera_ray(const camera_consts *C, int W, int H, int64_t pix,
@@ -872,16 +863,10 @@ long oracle_halved_rotations(int reset)
     return v;
 }
 
-/* Accuracy checks of the Newton-refined reciprocals: out[k] = recip_newton(x[k], y0[k])
- * (two steps) or recip_newton1 (one step). */
+/* Accuracy checks of the Newton-refined reciprocal: out[k] = recip_newton(x[k], y0[k]). */
 void oracle_recip_newton(const double *x, const double *y0, int64_t n, double *out)
 {
     for (int64_t k = 0; k < n; ++k) out[k] = recip_newton(x[k], y0[k]);
-}
-
-void oracle_recip_newton1(const double *x, const double *y0, int64_t n, double *out)
-{
-    for (int64_t k = 0; k < n; ++k) out[k] = recip_newton1(x[k], y0[k]);
 }
 
 static oracle_params make_params(double M, double a, double Q, double dt, double eps,
@@ -1202,8 +1187,8 @@ static int disk_orbit(const oracle_params *P, double r, double theta, double out
         mn_inverse_metric(&P->mn, r, c, s * s, g);
         mn_inverse_metric(&P->mn, r + P->eps, c, s * s, gr);
     } else {
-        inverse_metric(P, r, s * s, c * c, g);
-        inverse_metric(P, r + P->eps, s * s, c * c, gr);
+        inverse_metric(P, r, s * s, g);
+        inverse_metric(P, r + P->eps, s * s, gr);
     }
     const double dtt = gr[0] - g[0], dtp = gr[1] - g[1], dpp = gr[4] - g[4];
     const double disc = dtp * dtp - dpp * dtt;                 /* (B^2 - 4AC) / 4 */

@@ -145,13 +145,12 @@ GR_HD Hole make_hole(double M, double a, double Q) {
 
 // Terms of the metric that depend on theta only.
 struct ThetaTerms {
-    double s2, c2, w;          // sin^2, cos^2, a^2 sin^2
+    double s2, w;              // sin^2, a^2 sin^2
 };
 
-GR_HD ThetaTerms theta_terms_sc(const Hole& H, double s, double c) {
+GR_HD ThetaTerms theta_terms_s(const Hole& H, double s) {
     ThetaTerms T;
     T.s2 = s * s;
-    T.c2 = c * c;
     T.w = H.a2 * T.s2;
     return T;
 }
@@ -159,19 +158,19 @@ GR_HD ThetaTerms theta_terms_sc(const Hole& H, double s, double c) {
 GR_HD ThetaTerms theta_terms(const Hole& H, double theta) {
     double s, c;
     sincos_def(theta, s, c);
-    return theta_terms_sc(H, s, c);
+    return theta_terms_s(H, s);
 }
 
 // Terms that depend on r only.
 struct RadialTerms {
-    double r2, rara, Delta, aF, DD;   // r^2, (r^2+a^2)^2, Delta, a(2Mr - Q^2), Delta^2
+    double r2, ra, rara, Delta, aF, DD;   // r^2, r^2+a^2, (r^2+a^2)^2, Delta, a(2Mr - Q^2), Delta^2
 };
 
 GR_HD RadialTerms radial_terms(const Hole& H, double r) {
     RadialTerms R;
     R.r2 = r * r;
-    const double ra = R.r2 + H.a2;
-    R.rara = ra * ra;
+    R.ra = R.r2 + H.a2;
+    R.rara = R.ra * R.ra;
     R.Delta = fma(r, r - H.M2, H.aq);
     R.aF = fma(H.aM2, r, -H.aQ2);
     R.DD = R.Delta * R.Delta;
@@ -187,9 +186,11 @@ struct InvMetric {
     double tt, tp, rr, hh, pp;
 };
 
-// rho2 Delta at (r-terms, theta-terms).
+// rho2 Delta at (r-terms, theta-terms), with rho2 = r^2 + a^2 cos^2 formed
+// as (r^2 + a^2) - a^2 sin^2 from the terms the other components use: outside
+// a horizon r >= a, so the subtraction keeps rho2 to a few ulp.
 GR_HD double rho2_delta(const Hole& H, const RadialTerms& R, const ThetaTerms& T) {
-    return fma(H.a2, T.c2, R.r2) * R.Delta;
+    return (R.ra - T.w) * R.Delta;
 }
 
 // The five components from the shared reciprocals inv = 1/(rho2 Delta) and
@@ -238,13 +239,6 @@ GR_HD double recip_newton(double x, double y0) {
     const double y = fma(y0, e, y0);
     e = fma(-x, y, 1.0);
     return fma(y, e, y);
-}
-
-// One Newton step y0 + y0 (1 - x y0): relative error e0^2 plus one rounding,
-// within an ulp for |e0| <= 1e-8; the theta displacement's e0 is eps times
-// the logarithmic derivative of rho^2 in theta, at most eps a^2/rho^2 <= eps.
-GR_HD double recip_newton1(double x, double y0) {
-    return fma(y0, fma(-x, y0, 1.0), y0);
 }
 
 // -------------------------------------------------------------------- exp
@@ -412,9 +406,9 @@ inline Camera make_camera(const Hole& Hh, double r0, double th0, double ph0, dou
     C.tan_h = sf / cf;
     C.tan_v = (C.tan_h * (double)H) / (double)W;
     sincos_def(th0, C.s0, C.c0);
-    const ThetaTerms T = theta_terms_sc(Hh, C.s0, C.c0);
+    const ThetaTerms T = theta_terms_s(Hh, C.s0);
     const RadialTerms R = radial_terms(Hh, r0);
-    const double rho2 = fma(Hh.a2, T.c2, R.r2);
+    const double rho2 = fma(Hh.a2, C.c0 * C.c0, R.r2);
     const double Sigma2 = fma(-T.w, R.Delta, R.rara);
     C.er = sqrt(rho2 / R.Delta);                 // sqrt(g_rr)
     C.eth = sqrt(rho2);                          // sqrt(g_thth)

@@ -20,7 +20,7 @@ __device__ __forceinline__ InvMetric metric_at(const Hole& H, const MnHole& K, d
     if constexpr (MN) {
         return mn_inverse_metric<IeeeDiv>(K, r, c, s * s);
     } else {
-        return inverse_metric(H, radial_terms(H, r), theta_terms_sc(H, s, c));
+        return inverse_metric(H, radial_terms(H, r), theta_terms_s(H, s));
     }
 }
 

@@ -91,11 +91,10 @@ static __device__ __forceinline__ Deriv deriv_from(const InvMetric& g, const Inv
 // base point's (metric_diff: one rounding for the difference);
 // p-dot = -1/(2 eps) times the sum of the five component differences times
 // p_nu p_sigma, in the order tt, tphi (weight 2 p_t p_phi), rr, thth, phph.
-// Two divisions per stage: is = 1/(rho2 Delta sin^2) at (r, th), inv = is
-// sin^2; at (r+eps, th) is refined from the base point's by two Newton steps;
-// at (r, th+eps) 1/(rho2 Delta) is refined from inv by one (rho2 moves by at
-// most eps relative there) and multiplied by a divided 1/sin^2 (near the axis
-// sin^2 changes by a large factor over eps, rho2 Delta never does).
+// Two divisions per stage: is = 1/(rho2 Delta sin^2) at (r, th) and at
+// (r, th+eps), inv = is sin^2 at each (near the axis sin^2 changes by a large
+// factor over eps); at (r+eps, th), where only rho2 Delta moves, by a factor
+// 1 + O(eps), is is refined from the base point's by two Newton steps.
 // s, c: sin and cos of the stage point's theta.
 // UNIT_COS: cos eps is 1.0 (it rounds to 1 for eps below 1.05e-8, the
 // paper's 1e-8 included), so the products with it are exact and are left
@@ -105,19 +104,17 @@ static __device__ __forceinline__ Deriv rhs_sc(const Hole& H, const Integrator& 
                                                double s, double c, double pt, double pr,
                                                double pth, double pph, double wtt, double wtp,
                                                double wpp) {
-    const ThetaTerms T0 = theta_terms_sc(H, s, c);
-    const double sc = UNIT_COS ? s : s * in.cos_eps;
-    const double cc = UNIT_COS ? c : c * in.cos_eps;
-    const ThetaTerms T1 = theta_terms_sc(H, fma(c, in.sin_eps, sc), fma(-s, in.sin_eps, cc));
+    const ThetaTerms T0 = theta_terms_s(H, s);
+    const ThetaTerms T1 = theta_terms_s(H, fma(c, in.sin_eps, UNIT_COS ? s : s * in.cos_eps));
     const RadialTerms R0 = radial_terms(H, r);
     const RadialTerms R1 = radial_terms(H, r + in.eps);
     const double is = rcp_rn(rho2_delta(H, R0, T0) * T0.s2);
     const double inv = is * T0.s2;
     const double is_r = recip_newton(rho2_delta(H, R1, T0) * T0.s2, is);
-    const double inv_t = recip_newton1(rho2_delta(H, R0, T1), inv);
+    const double is_t = rcp_rn(rho2_delta(H, R0, T1) * T1.s2);
     const InvMetric g = metric_from(H, R0, T0, inv, is);
     const InvMetric dr = metric_diff(H, R1, T0, is_r * T0.s2, is_r, g);
-    const InvMetric dh = metric_diff(H, R0, T1, inv_t, inv_t * rcp_rn(T1.s2), g);
+    const InvMetric dh = metric_diff(H, R0, T1, is_t * T1.s2, is_t, g);
     return deriv_from<RAW>(g, dr, dh, in, pt, pr, pth, pph, wtt, wtp, wpp);
 }
 

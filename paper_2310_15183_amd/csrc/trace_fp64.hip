@@ -297,10 +297,14 @@ static void launch_static_kernel(const FrameArgs& A, bool f32_out, const LaunchS
 template <int METHOD, bool DISK>
 static hipError_t launch_static(const FrameArgs& A, bool f32_out, const LaunchShape& L,
                                 hipStream_t s) {
-    if (METHOD == M_RK4 && unit_cos(A.in))
-        launch_static_kernel<METHOD, DISK, true>(A, f32_out, L, s);
-    else
+    if constexpr (METHOD == M_RK4) {
+        if (unit_cos(A.in))
+            launch_static_kernel<METHOD, DISK, true>(A, f32_out, L, s);
+        else
+            launch_static_kernel<METHOD, DISK, false>(A, f32_out, L, s);
+    } else {
         launch_static_kernel<METHOD, DISK, false>(A, f32_out, L, s);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || METHOD != M_RK4) return e;
     return launch_redo<DISK>(A, f32_out, s);

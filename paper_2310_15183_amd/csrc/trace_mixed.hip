@@ -45,14 +45,6 @@ __device__ __forceinline__ double rcp_nr(double x) {
     return fma(y, e, y);
 }
 
-__device__ __forceinline__ ThetaTerms theta_from(const Hole& H, double s, double c) {
-    ThetaTerms T;
-    T.s2 = s * s;
-    T.c2 = c * c;
-    T.w = H.a2 * T.s2;
-    return T;
-}
-
 struct DerivF {
     float qt, qr, qh, qp, pr, ph;
 };
@@ -93,8 +85,8 @@ __device__ __forceinline__ DerivF rhs_mixed(const Hole& H, double eps, float r, 
     float sf, cf;
     sincos_f32(th, sf, cf);
     const double s = (double)sf, c = (double)cf;
-    const ThetaTerms T0 = theta_from(H, s, c);
-    const ThetaTerms T1 = theta_from(H, fma(eps, c, s), fma(-eps, s, c));
+    const ThetaTerms T0 = theta_terms_s(H, s);
+    const ThetaTerms T1 = theta_terms_s(H, fma(eps, c, s));
     const RadialTerms R0 = radial_terms(H, (double)r);
     const RadialTerms R1 = radial_terms(H, (double)r + eps);
     // the binary64 tracer's reciprocal scheme, with v_rcp_f64 and two Newton
@@ -102,10 +94,10 @@ __device__ __forceinline__ DerivF rhs_mixed(const Hole& H, double eps, float r, 
     const double is = rcp_nr(rho2_delta(H, R0, T0) * T0.s2);
     const double inv = is * T0.s2;
     const double is_r = recip_newton(rho2_delta(H, R1, T0) * T0.s2, is);
-    const double inv_t = recip_newton(rho2_delta(H, R0, T1), inv);
+    const double is_t = rcp_nr(rho2_delta(H, R0, T1) * T1.s2);
     const InvMetric g = metric_from(H, R0, T0, inv, is);
     const InvMetric dr = metric_diff(H, R1, T0, is_r * T0.s2, is_r, g);
-    const InvMetric dh = metric_diff(H, R0, T1, inv_t, inv_t * rcp_nr(T1.s2), g);
+    const InvMetric dh = metric_diff(H, R0, T1, is_t * T1.s2, is_t, g);
 
     const float wrr = (pr * pr) * K.ie, wth = (pth * pth) * K.ie;
     float acc = (float)dr.tt * K.wtt;

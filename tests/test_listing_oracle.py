@@ -180,6 +180,8 @@ MUTANTS = [
     ("return fma(P->a * (2.0 * P->M), r, -(P->a * (P->Q * P->Q)));",
      "return -fma(P->a * (2.0 * P->M), r, -(P->a * (P->Q * P->Q)));"),      # sign of g^{t phi}
     ("return -0.5 * (1.0 / P->eps);", "return -0.5 * (1.0 / 1.01e-8);"),          # eps off by 1%
+    ("const double rho2 = (r * r + a2) - a2 * s2;",
+     "const double rho2 = (r * r + a2) + a2 * s2;"),                         # rho^2 from sin^2: sign
 ]
 
 
