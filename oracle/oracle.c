@@ -459,7 +459,7 @@ static double fd_scale(const oracle_params *P)
 
 static void rhs_core(const oracle_params *P, const double eps_sc[2], double r, double s,
                      double c, double pt, double pr, double pth, double pph, double qdot[4],
-                     double pdot[2], int raw)
+                     double pdot[2], int raw, double gtp[3])
 {
     double g[5], dr[5], dth[5];        /* base metric; differences to the displaced points */
     const double se = fma(c, eps_sc[0], s * eps_sc[1]);      /* sin(theta + eps) */
@@ -513,22 +513,29 @@ static void rhs_core(const oracle_params *P, const double eps_sc[2], double r, d
     qdot[1] = g[2] * pr;                                       /* dr/dtau */
     qdot[2] = g[3] * pth;                                      /* dtheta/dtau */
     qdot[3] = fma(g[1], pt, g[4] * pph);                       /* dphi/dtau */
+    if (gtp) {                                                 /* g^tt, g^tphi, g^phph */
+        gtp[0] = g[0];
+        gtp[1] = g[1];
+        gtp[2] = g[4];
+    }
 }
 
 /* The right-hand side with p-dot scaled, and unscaled (the contracted sums
- * alone: the carried Kerr-Newman RK4 folds -1/(2 eps) into its step sizes). */
+ * alone: the carried Kerr-Newman RK4 folds -1/(2 eps) into its step sizes;
+ * it also takes g^tt, g^tphi, g^phph, of which dt/dtau and dphi/dtau are
+ * linear combinations with the ray's constant p_t, p_phi). */
 static void hamilton_rhs_sc(const oracle_params *P, const double eps_sc[2], double r,
                             double s, double c, double pt, double pr, double pth, double pph,
                             double qdot[4], double pdot[2])
 {
-    rhs_core(P, eps_sc, r, s, c, pt, pr, pth, pph, qdot, pdot, 0);
+    rhs_core(P, eps_sc, r, s, c, pt, pr, pth, pph, qdot, pdot, 0, NULL);
 }
 
 static void hamilton_rhs_sc_raw(const oracle_params *P, const double eps_sc[2], double r,
                                 double s, double c, double pt, double pr, double pth,
-                                double pph, double qdot[4], double pdot[2])
+                                double pph, double qdot[4], double pdot[2], double gtp[3])
 {
-    rhs_core(P, eps_sc, r, s, c, pt, pr, pth, pph, qdot, pdot, 1);
+    rhs_core(P, eps_sc, r, s, c, pt, pr, pth, pph, qdot, pdot, 1, gtp);
 }
 
 /* The same at (r, theta), sin and cos of theta from the stated definition. */
@@ -630,6 +637,7 @@ int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nste
             continue;
         }
         double nu, h;
+        double g1[3], g2[3], g3[3], g4[3];     /* Kerr-Newman: g^tt, g^tphi, g^phph per stage */
         const double pscale = fd_scale(P);
         if (P->kind == METRIC_MN) {
             /* K1 at the current point; its dt/dtau fixes the step. */
@@ -650,28 +658,40 @@ int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nste
              * pair rotated by that stage's increment of theta.  p-dot comes
              * unscaled and -1/(2 eps) multiplies the momenta's step sizes. */
             double s2, c2;
-            hamilton_rhs_sc_raw(P, eps_sc, q[1], sn, cs, pt, pr, pth, pph, k1q, k1p);
+            hamilton_rhs_sc_raw(P, eps_sc, q[1], sn, cs, pt, pr, pth, pph, k1q, k1p, g1);
             nu = fabs(k1q[0]);
             h = P->dt / nu;
             const double hh = 0.5 * h;
             const double hhs = hh * pscale, hs = h * pscale;
             rotate_pair(sn, cs, hh * k1q[2], &s2, &c2);
             hamilton_rhs_sc_raw(P, eps_sc, fma(hh, k1q[1], q[1]), s2, c2, pt,
-                                fma(hhs, k1p[0], pr), fma(hhs, k1p[1], pth), pph, k2q, k2p);
+                                fma(hhs, k1p[0], pr), fma(hhs, k1p[1], pth), pph, k2q, k2p,
+                                g2);
             rotate_pair(sn, cs, hh * k2q[2], &s2, &c2);
             hamilton_rhs_sc_raw(P, eps_sc, fma(hh, k2q[1], q[1]), s2, c2, pt,
-                                fma(hhs, k2p[0], pr), fma(hhs, k2p[1], pth), pph, k3q, k3p);
+                                fma(hhs, k2p[0], pr), fma(hhs, k2p[1], pth), pph, k3q, k3p,
+                                g3);
             rotate_pair(sn, cs, h * k3q[2], &s2, &c2);
             hamilton_rhs_sc_raw(P, eps_sc, fma(h, k3q[1], q[1]), s2, c2, pt,
-                                fma(hs, k3p[0], pr), fma(hs, k3p[1], pth), pph, k4q, k4p);
+                                fma(hs, k3p[0], pr), fma(hs, k3p[1], pth), pph, k4q, k4p,
+                                g4);
         }
         /* x += h/6 (k1 + 2 k2 + 2 k3 + k4) */
         const double h6 = h * (1.0 / 6.0);
         double S[4];
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < 4; ++m)
             S[m] = ((k1q[m] + 2.0 * k2q[m]) + 2.0 * k3q[m]) + k4q[m];
-            q[m] = fma(h6, S[m], q[m]);
+        if (P->kind != METRIC_MN) {
+            /* Kerr-Newman: the sums of dt/dtau and dphi/dtau through those of
+             * g^tt, g^tphi and g^phph, contracted once with p_t and p_phi */
+            double G[3];
+            for (int m = 0; m < 3; ++m)
+                G[m] = ((g1[m] + 2.0 * g2[m]) + 2.0 * g3[m]) + g4[m];
+            S[0] = fma(G[0], pt, G[1] * pph);
+            S[3] = fma(G[1], pt, G[2] * pph);
         }
+        for (int m = 0; m < 4; ++m)
+            q[m] = fma(h6, S[m], q[m]);
         const double h6p = P->kind == METRIC_MN ? h6 : h6 * pscale;   /* see above */
         pr = fma(h6p, ((k1p[0] + 2.0 * k2p[0]) + 2.0 * k3p[0]) + k4p[0], pr);
         pth = fma(h6p, ((k1p[1] + 2.0 * k2p[1]) + 2.0 * k3p[1]) + k4p[1], pth);

@@ -40,6 +40,8 @@ static __device__ __forceinline__ double div_rn(double a, double x) {
 struct Deriv {
     double qt, qr, qh, qp;   // dq^mu/dtau
     double pr, ph;           // dp_r/dtau, dp_theta/dtau
+    double gtt, gtp, gpp;    // g^tt, g^tphi, g^phph at the point (dt/dtau and dphi/dtau are
+                             // linear in them with the ray's constant p_t, p_phi)
 };
 
 // Componentwise a - b (each difference rounded once).
@@ -82,6 +84,9 @@ static __device__ __forceinline__ Deriv deriv_from(const InvMetric& g, const Inv
     d.qr = g.rr * pr;
     d.qh = g.hh * pth;
     d.qp = fma(g.tp, pt, g.pp * pph);
+    d.gtt = g.tt;
+    d.gtp = g.tp;
+    d.gpp = g.pp;
     return d;
 }
 
@@ -272,6 +277,9 @@ static __device__ __forceinline__ double euler_generic(const Rhs& rhs_at, const 
 // angles, and the carried pair departs from sin/cos of the summed theta only
 // by the accumulated rounding of the rotations (a random walk of ~1e-16 per
 // step).
+// dt/dtau = g^tt p_t + g^tphi p_phi and dphi/dtau = g^tphi p_t + g^phph p_phi
+// with p_t, p_phi constant along the ray, so the weighted sums of t and phi
+// are taken over the three components and contracted once per step.
 // GENERAL = false rotates by rotate_small (no branch) and returns in dmax the
 // largest |increment|; the step equals the GENERAL one when dmax <= 1/32.
 template <bool GENERAL, bool UNIT_COS = false>
@@ -298,20 +306,25 @@ static __device__ __forceinline__ double rk4_carry(const Hole& H, const Integrat
     const double h = div_rn(in.dt, nu);
     const double hh = 0.5 * h;
     const double hhs = hh * in.scale;
-    double st = k.qt, sr = k.qr, sh = k.qh, sp = k.qp, spr = k.pr, sph = k.ph;
+    double stt = k.gtt, stp = k.gtp, spp = k.gpp, sr = k.qr, sh = k.qh, spr = k.pr, sph = k.ph;
     rot(hh * k.qh, sn, cs);
     k = f(fma(hh, k.qr, y.r), sn, cs, fma(hhs, k.pr, y.pr), fma(hhs, k.ph, y.pth));
-    st = fma(2.0, k.qt, st); sr = fma(2.0, k.qr, sr); sh = fma(2.0, k.qh, sh);
-    sp = fma(2.0, k.qp, sp); spr = fma(2.0, k.pr, spr); sph = fma(2.0, k.ph, sph);
+    stt = fma(2.0, k.gtt, stt); stp = fma(2.0, k.gtp, stp); spp = fma(2.0, k.gpp, spp);
+    sr = fma(2.0, k.qr, sr); sh = fma(2.0, k.qh, sh);
+    spr = fma(2.0, k.pr, spr); sph = fma(2.0, k.ph, sph);
     rot(hh * k.qh, sn, cs);
     k = f(fma(hh, k.qr, y.r), sn, cs, fma(hhs, k.pr, y.pr), fma(hhs, k.ph, y.pth));
-    st = fma(2.0, k.qt, st); sr = fma(2.0, k.qr, sr); sh = fma(2.0, k.qh, sh);
-    sp = fma(2.0, k.qp, sp); spr = fma(2.0, k.pr, spr); sph = fma(2.0, k.ph, sph);
+    stt = fma(2.0, k.gtt, stt); stp = fma(2.0, k.gtp, stp); spp = fma(2.0, k.gpp, spp);
+    sr = fma(2.0, k.qr, sr); sh = fma(2.0, k.qh, sh);
+    spr = fma(2.0, k.pr, spr); sph = fma(2.0, k.ph, sph);
     rot(h * k.qh, sn, cs);
     const double hs = h * in.scale;
     k = f(fma(h, k.qr, y.r), sn, cs, fma(hs, k.pr, y.pr), fma(hs, k.ph, y.pth));
-    st = st + k.qt; sr = sr + k.qr; sh = sh + k.qh; sp = sp + k.qp;
+    stt = stt + k.gtt; stp = stp + k.gtp; spp = spp + k.gpp;
+    sr = sr + k.qr; sh = sh + k.qh;
     spr = spr + k.pr; sph = sph + k.ph;
+    const double st = fma(stt, y.pt, stp * y.pph);
+    const double sp = fma(stp, y.pt, spp * y.pph);
     const double h6 = h * (1.0 / 6.0);
     const double h6s = h6 * in.scale;
     rot(h6 * sh, sn, cs);

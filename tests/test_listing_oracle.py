@@ -182,6 +182,8 @@ MUTANTS = [
     ("return -0.5 * (1.0 / P->eps);", "return -0.5 * (1.0 / 1.01e-8);"),          # eps off by 1%
     ("const double rho2 = (r * r + a2) - a2 * s2;",
      "const double rho2 = (r * r + a2) + a2 * s2;"),                         # rho^2 from sin^2: sign
+    ("G[m] = ((g1[m] + 2.0 * g2[m]) + 2.0 * g3[m]) + g4[m];",
+     "G[m] = ((g1[m] + g2[m]) + 2.0 * g3[m]) + g4[m];"),                    # RK4 weight of phi's sum
 ]
 
 

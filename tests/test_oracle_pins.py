@@ -116,10 +116,11 @@ def test_camera_rays_are_null_and_past_directed(M, a, Q, th0):
 
 
 # --------------------------------------------------------------------------- flat space
-def _flat_deviation(a, eps):
+def _flat_deviation(a, eps, form="listing"):
     th0, ph0 = math.radians(70), 0.3
     W, H = 16, 12
-    res = oracle.trace_frame(0.0, a, 0.0, 20.0, th0, ph0, FOV75, W, H, dt=0.01, eps=eps)
+    res = oracle.trace_frame(0.0, a, 0.0, 20.0, th0, ph0, FOV75, W, H, dt=0.01, eps=eps,
+                             form=form)
     init = oracle.camera(0.0, a, 0.0, 20.0, th0, ph0, FOV75, W, H)
     gi = physics.inverse_metric_numeric(0.0, a, 0.0, 20.0, th0)
     v = init[:, 4:] @ gi.T
@@ -133,13 +134,15 @@ def _flat_deviation(a, eps):
     return res, speed, along, angle
 
 
+@pytest.mark.parametrize("form", ["listing", "twin"])
 @pytest.mark.parametrize("a", [0.0, 0.3])
-def test_flat_space_rays_are_straight_lines(a):
+def test_flat_space_rays_are_straight_lines(a, form):
     """M = 0: Boyer-Lindquist coordinates are flat (oblate spheroidal for a != 0),
     so every ray is a straight line travelled at unit speed in coordinate time.
     The forward difference's O(eps) truncation (about 3e-7 rad here) sets the
-    1e-6 rad gate."""
-    res, speed, along, angle = _flat_deviation(a, 1e-8)
+    1e-6 rad gate.  Both forms: the twin's t and phi come from its own RK4
+    sums of g^tt, g^tphi and g^phph."""
+    res, speed, along, angle = _flat_deviation(a, 1e-8, form)
     assert np.all(res.flag == oracle.FLAG_ESCAPE)
     np.testing.assert_allclose(speed, 1.0, atol=1e-14)
     assert angle.max() < 1e-6
@@ -183,15 +186,16 @@ def test_reissner_nordstrom_critical_impact_parameter():
     assert abs(b - bc) / bc < 1e-6
 
 
+@pytest.mark.parametrize("form", ["listing", "twin"])
 @pytest.mark.parametrize("b", [3.0, 4.0, 6.0, 10.0])
-def test_schwarzschild_deflection_and_travel_time(b):
+def test_schwarzschild_deflection_and_travel_time(b, form):
     """End phi and t of an equatorial ray equal the deflection and time
     integrals taken to the oracle's own end radius.  Gate 4e-7 rad / 2e-6 in t:
     the forward-difference step fl(r+eps)-r exceeds eps by 8.3e-8 (relative)
     for 8 <= r < 64, which biases the centrifugal term at that level."""
     M = 0.5
     init = physics.equatorial_state(M, 0.0, 20.0, b)[None]
-    res = oracle.trace_rays(M, 0.0, 0.0, init, dt=0.01, max_steps=200000)
+    res = oracle.trace_rays(M, 0.0, 0.0, init, dt=0.01, max_steps=200000, form=form)
     assert res.flag[0] == oracle.FLAG_ESCAPE
     phi, t = physics.schwarzschild_deflection(M, b, 20.0, res.r[0])
     assert abs(res.phi[0] - phi) < 4e-7
