@@ -67,7 +67,8 @@ enum {
 /* Integrator precision.
  * GR_FP64: binary64 throughout; results are reproducible bit for bit.
  * GR_MIXED (gr_trace_frame only): binary32 RK4 stages (stage points,
- *   right-hand sides, contraction, the RK4 combination); binary64 metric
+ *   right-hand sides, contraction, the RK4 combination; t and phi from
+ *   binary64 sums of g^tt, g^tphi, g^phph); binary64 metric
  *   evaluations and forward differences (sin at theta+eps by angle
  *   addition, reciprocals by v_rcp_f64 and two Newton steps); whole binary64
  *   steps while r < 1.2 r_+ or |p_r| < 1e-3, back to binary32 stages once

@@ -12,16 +12,21 @@
 //    is added to the state in binary64 (one add per component), because
 //    binary32 rounding of theta and phi alone random-walks ~5e-6 rad over
 //    1e4 steps;
-//  - sin and cos of the binary32 stage angle are evaluated in binary32 and
-//    widened; sin and cos at theta+eps follow from them by the angle-addition
-//    identity in binary64 (cos eps rounds to 1, sin eps to eps), so both
-//    evaluations of the theta difference see one consistent angle and the
-//    step is exactly eps;
+//  - sin and cos of the step's binary32 angle are evaluated in binary32; the
+//    later stages rotate that pair by their binary32 increment (short series,
+//    below the binary32 rounding for |increment| <= 1/4; a larger increment
+//    evaluates sin and cos of the stage angle afresh); the pair is widened,
+//    and sin at theta+eps follows by the angle-addition identity in binary64
+//    (cos eps rounds to 1, sin eps to eps), so both evaluations of the theta
+//    difference see one consistent angle and the step is exactly eps;
 //  - the metric's reciprocals follow the binary64 tracer's scheme with
 //    v_rcp_f64 refined by two Newton steps (about 1 ulp) in place of its two
 //    divisions per stage;
 //    the binary32 step divides by |dt/dtau| with v_rcp_f32;
-//  - 1/eps is folded into the binary32 contraction weights.
+//  - -1/(2 eps) is folded into the binary32 contraction weights;
+//  - dt/dtau and dphi/dtau are linear in the ray's constant p_t, p_phi, so
+//    the step sums g^tt, g^tphi, g^phph over the stages in binary64 and
+//    contracts them once.
 // A ray switches to whole binary64 steps (the binary64 tracer's own step)
 // when r < 1.2 r_+ or |p_r| < 1e-3, and back when r > 1.25 r_+ and
 // |p_r| > 2e-3.
@@ -46,13 +51,14 @@ __device__ __forceinline__ double rcp_nr(double x) {
 }
 
 struct DerivF {
-    float qt, qr, qh, qp, pr, ph;
+    float qt, qr, qh, pr, ph;
+    double gtt, gtp, gpp;       // g^tt, g^tphi, g^phph at the stage point
 };
 
 struct ConstF {
     float pt, pph;              // binary32 copies of the ray constants
-    float wtt, wtp, wpp;        // p_t^2/eps, 2 p_t p_phi/eps, p_phi^2/eps
-    float ie;                   // 1/eps
+    float wtt, wtp, wpp;        // -p_t^2/(2 eps), -p_t p_phi/eps, -p_phi^2/(2 eps)
+    float ie;                   // -1/(2 eps)
 };
 
 // sin and cos in binary32: x = k pi/2 + r, |r| <= pi/4 (two-part pi/2), then
@@ -80,10 +86,29 @@ __device__ __forceinline__ void sincos_f32(float x, float& s_out, float& c_out) 
     c_out = (q == 1 || q == 2) ? -c : c;
 }
 
-__device__ __forceinline__ DerivF rhs_mixed(const Hole& H, double eps, float r, float th,
-                                            float pr, float pth, const ConstF& K) {
-    float sf, cf;
-    sincos_f32(th, sf, cf);
+// Largest stage increment of theta that the binary32 rotation takes.
+constexpr float ROT_F32_MAX = 0.25f;
+
+// (sf, cf) rotated by d: sin d = d - d^3/6 + d^5/120 and cos d - 1 =
+// -d^2/2 + d^4/24, omitted terms below 2^-25 for |d| <= 1/4.
+__device__ __forceinline__ void rotate_f32(float sf, float cf, float d, float& s_out,
+                                           float& c_out) {
+    const float z = d * d;
+    const float sd = fmaf(d * z, fmaf(z, 1.0f / 120.0f, -1.0f / 6.0f), d);
+    const float cm1 = z * fmaf(z, 1.0f / 24.0f, -0.5f);
+    s_out = fmaf(cf, sd, fmaf(sf, cm1, sf));
+    c_out = fmaf(-sf, sd, fmaf(cf, cm1, cf));
+}
+
+// sin and cos at the stage angle th + d from those at th.
+__device__ __forceinline__ void stage_sc(float th, float s1, float c1, float d, float& sf,
+                                         float& cf) {
+    if (fabsf(d) <= ROT_F32_MAX) rotate_f32(s1, c1, d, sf, cf);
+    else sincos_f32(fmaf(1.0f, d, th), sf, cf);
+}
+
+__device__ __forceinline__ DerivF rhs_mixed(const Hole& H, double eps, float r, float sf,
+                                            float cf, float pr, float pth, const ConstF& K) {
     const double s = (double)sf, c = (double)cf;
     const ThetaTerms T0 = theta_terms_s(H, s);
     const ThetaTerms T1 = theta_terms_s(H, fma(eps, c, s));
@@ -106,20 +131,20 @@ __device__ __forceinline__ DerivF rhs_mixed(const Hole& H, double eps, float r, 
     acc = fmaf((float)dr.hh, wth, acc);
     acc = fmaf((float)dr.pp, K.wpp, acc);
     DerivF d;
-    d.pr = -0.5f * acc;
+    d.pr = acc;
     acc = (float)dh.tt * K.wtt;
     acc = fmaf((float)dh.tp, K.wtp, acc);
     acc = fmaf((float)dh.rr, wrr, acc);
     acc = fmaf((float)dh.hh, wth, acc);
     acc = fmaf((float)dh.pp, K.wpp, acc);
-    d.ph = -0.5f * acc;
+    d.ph = acc;
 
-    const float gtt = (float)g.tt, gtp = (float)g.tp, grr = (float)g.rr, ghh = (float)g.hh,
-                gpp = (float)g.pp;
-    d.qt = fmaf(gtt, K.pt, gtp * K.pph);
-    d.qr = grr * pr;
-    d.qh = ghh * pth;
-    d.qp = fmaf(gtp, K.pt, gpp * K.pph);
+    d.qt = fmaf((float)g.tt, K.pt, (float)g.tp * K.pph);
+    d.qr = (float)g.rr * pr;
+    d.qh = (float)g.hh * pth;
+    d.gtt = g.tt;
+    d.gtp = g.tp;
+    d.gpp = g.pp;
     return d;
 }
 
@@ -129,27 +154,34 @@ __device__ __forceinline__ double rk4_step_mixed(const Hole& H, const Integrator
     const float r = (float)y.r, th = (float)y.th;
     const float pr = (float)y.pr, pth = (float)y.pth;
     const double eps = in.eps;
-    DerivF k = rhs_mixed(H, eps, r, th, pr, pth, K);
+    float s1, c1, sf, cf;
+    sincos_f32(th, s1, c1);
+    DerivF k = rhs_mixed(H, eps, r, s1, c1, pr, pth, K);
     const float nu = fabsf(k.qt);
     const float h = dt * __builtin_amdgcn_rcpf(nu);
     const float hh = 0.5f * h;
-    float st = k.qt, sr = k.qr, sh = k.qh, sp = k.qp, spr = k.pr, sph = k.ph;
-    k = rhs_mixed(H, eps, fmaf(hh, k.qr, r), fmaf(hh, k.qh, th), fmaf(hh, k.pr, pr),
-                  fmaf(hh, k.ph, pth), K);
-    st = fmaf(2.0f, k.qt, st); sr = fmaf(2.0f, k.qr, sr); sh = fmaf(2.0f, k.qh, sh);
-    sp = fmaf(2.0f, k.qp, sp); spr = fmaf(2.0f, k.pr, spr); sph = fmaf(2.0f, k.ph, sph);
-    k = rhs_mixed(H, eps, fmaf(hh, k.qr, r), fmaf(hh, k.qh, th), fmaf(hh, k.pr, pr),
-                  fmaf(hh, k.ph, pth), K);
-    st = fmaf(2.0f, k.qt, st); sr = fmaf(2.0f, k.qr, sr); sh = fmaf(2.0f, k.qh, sh);
-    sp = fmaf(2.0f, k.qp, sp); spr = fmaf(2.0f, k.pr, spr); sph = fmaf(2.0f, k.ph, sph);
-    k = rhs_mixed(H, eps, fmaf(h, k.qr, r), fmaf(h, k.qh, th), fmaf(h, k.pr, pr),
-                  fmaf(h, k.ph, pth), K);
-    st += k.qt; sr += k.qr; sh += k.qh; sp += k.qp; spr += k.pr; sph += k.ph;
+    double stt = k.gtt, stp = k.gtp, spp = k.gpp;
+    float sr = k.qr, sh = k.qh, spr = k.pr, sph = k.ph;
+    stage_sc(th, s1, c1, hh * k.qh, sf, cf);
+    k = rhs_mixed(H, eps, fmaf(hh, k.qr, r), sf, cf, fmaf(hh, k.pr, pr), fmaf(hh, k.ph, pth), K);
+    stt = fma(2.0, k.gtt, stt); stp = fma(2.0, k.gtp, stp); spp = fma(2.0, k.gpp, spp);
+    sr = fmaf(2.0f, k.qr, sr); sh = fmaf(2.0f, k.qh, sh);
+    spr = fmaf(2.0f, k.pr, spr); sph = fmaf(2.0f, k.ph, sph);
+    stage_sc(th, s1, c1, hh * k.qh, sf, cf);
+    k = rhs_mixed(H, eps, fmaf(hh, k.qr, r), sf, cf, fmaf(hh, k.pr, pr), fmaf(hh, k.ph, pth), K);
+    stt = fma(2.0, k.gtt, stt); stp = fma(2.0, k.gtp, stp); spp = fma(2.0, k.gpp, spp);
+    sr = fmaf(2.0f, k.qr, sr); sh = fmaf(2.0f, k.qh, sh);
+    spr = fmaf(2.0f, k.pr, spr); sph = fmaf(2.0f, k.ph, sph);
+    stage_sc(th, s1, c1, h * k.qh, sf, cf);
+    k = rhs_mixed(H, eps, fmaf(h, k.qr, r), sf, cf, fmaf(h, k.pr, pr), fmaf(h, k.ph, pth), K);
+    stt += k.gtt; stp += k.gtp; spp += k.gpp;
+    sr += k.qr; sh += k.qh; spr += k.pr; sph += k.ph;
     const float h6 = h * (1.0f / 6.0f);
-    y.t += (double)(h6 * st);
+    const double h6d = (double)h6;
+    y.t = fma(h6d, fma(stt, y.pt, stp * y.pph), y.t);
     y.r += (double)(h6 * sr);
     y.th += (double)(h6 * sh);
-    y.ph += (double)(h6 * sp);
+    y.ph = fma(h6d, fma(stp, y.pt, spp * y.pph), y.ph);
     y.pr += (double)(h6 * spr);
     y.pth += (double)(h6 * sph);
     return (double)nu;
@@ -164,7 +196,7 @@ struct MixedArgs {
 __device__ __forceinline__ void mixed_constants(const FrameArgs& A, const Ray& y, ConstF& K) {
     K.pt = (float)y.pt;
     K.pph = (float)y.pph;
-    K.ie = (float)A.in.inv_eps;
+    K.ie = -0.5f * (float)A.in.inv_eps;
     K.wtt = (K.pt * K.pt) * K.ie;
     K.wtp = ((2.0f * K.pt) * K.pph) * K.ie;
     K.wpp = (K.pph * K.pph) * K.ie;
