@@ -560,6 +560,32 @@ static int all_finite(const double q[4], double pr, double pth)
            isfinite(pr) && isfinite(pth);
 }
 
+/* One stage of the coordinate-time RK4 at r and the stage angle theta0 +
+ * coef k_theta, into (kq, kp) multiplied by w = 1/|dt/dtau| there; returns
+ * |dt/dtau|.  Manko-Novikov takes the angle fma(coef, k_theta, theta0);
+ * Kerr-Newman the carried pair (sn, cs) of theta0 rotated by coef k_theta
+ * (the stage at theta0 itself takes the pair as it is). */
+static double rk4t_stage(const oracle_params *P, const double eps_sc[2], double r, double th0,
+                         double sn, double cs, double coef, double kth, double pt, double pr,
+                         double pth, double pph, double kq[4], double kp[2])
+{
+    if (P->kind == METRIC_MN) {
+        hamilton_rhs(P, eps_sc, r, fma(coef, kth, th0), pt, pr, pth, pph, kq, kp);
+    } else if (coef == 0.0) {
+        hamilton_rhs_sc(P, eps_sc, r, sn, cs, pt, pr, pth, pph, kq, kp);
+    } else {
+        double s2, c2;
+        rotate_pair(sn, cs, coef * kth, &s2, &c2);
+        hamilton_rhs_sc(P, eps_sc, r, s2, c2, pt, pr, pth, pph, kq, kp);
+    }
+    const double nu = fabs(kq[0]);
+    const double w = 1.0 / nu;
+    for (int m = 0; m < 4; ++m) kq[m] = kq[m] * w;
+    kp[0] = kp[0] * w;
+    kp[1] = kp[1] * w;
+    return nu;
+}
+
 /* Integrate one ray.  q = (t, r, theta, phi), p = (p_t, p_r, p_theta, p_phi)
  * are updated in place; returns the flag, *nsteps = updates taken.
  * Paper: listing loop body (stages K1..K4, update, exit tests), Sec. 3.1.2
@@ -581,10 +607,23 @@ int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nste
     for (s = 1; s <= P->max_steps; ++s) {
         double k1q[4], k1p[2], k2q[4], k2p[2], k3q[4], k3p[2], k4q[4], k4p[2];
         if (P->method == 1) {
-            /* explicit Euler: x += h f(x), h = dt / |dt/dtau| from f(x) */
-            hamilton_rhs(P, eps_sc, q[1], q[2], pt, pr, pth, pph, k1q, k1p);
-            const double nu = fabs(k1q[0]);
-            const double h = P->dt / nu;
+            /* explicit Euler: x += h f(x), h = dt / |dt/dtau| from f(x); on
+             * Kerr-Newman f from the carried pair, which then turns by the
+             * step's increment of theta */
+            double nu, h;
+            if (P->kind == METRIC_MN) {
+                hamilton_rhs(P, eps_sc, q[1], q[2], pt, pr, pth, pph, k1q, k1p);
+                nu = fabs(k1q[0]);
+                h = P->dt / nu;
+            } else {
+                double s2, c2;
+                hamilton_rhs_sc(P, eps_sc, q[1], sn, cs, pt, pr, pth, pph, k1q, k1p);
+                nu = fabs(k1q[0]);
+                h = P->dt / nu;
+                rotate_pair(sn, cs, h * k1q[2], &s2, &c2);
+                sn = s2;
+                cs = c2;
+            }
             for (int m = 0; m < 4; ++m) q[m] = fma(h, k1q[m], q[m]);
             pr = fma(h, k1p[0], pr);
             pth = fma(h, k1p[1], pth);
@@ -600,36 +639,28 @@ int oracle_integrate(const oracle_params *P, double q[4], double p[4], int *nste
              * w = 1/|dt/dtau| at that stage, so every stage moves t at the
              * same rate, and the step is dt itself. */
             const double hh = 0.5 * P->dt;
-            double w;
-            hamilton_rhs(P, eps_sc, q[1], q[2], pt, pr, pth, pph, k1q, k1p);
-            const double nu = fabs(k1q[0]);
-            w = 1.0 / nu;
-            for (int m = 0; m < 4; ++m) k1q[m] = k1q[m] * w;
-            k1p[0] = k1p[0] * w;
-            k1p[1] = k1p[1] * w;
-            hamilton_rhs(P, eps_sc, fma(hh, k1q[1], q[1]), fma(hh, k1q[2], q[2]), pt,
-                         fma(hh, k1p[0], pr), fma(hh, k1p[1], pth), pph, k2q, k2p);
-            w = 1.0 / fabs(k2q[0]);
-            for (int m = 0; m < 4; ++m) k2q[m] = k2q[m] * w;
-            k2p[0] = k2p[0] * w;
-            k2p[1] = k2p[1] * w;
-            hamilton_rhs(P, eps_sc, fma(hh, k2q[1], q[1]), fma(hh, k2q[2], q[2]), pt,
-                         fma(hh, k2p[0], pr), fma(hh, k2p[1], pth), pph, k3q, k3p);
-            w = 1.0 / fabs(k3q[0]);
-            for (int m = 0; m < 4; ++m) k3q[m] = k3q[m] * w;
-            k3p[0] = k3p[0] * w;
-            k3p[1] = k3p[1] * w;
-            hamilton_rhs(P, eps_sc, fma(P->dt, k3q[1], q[1]), fma(P->dt, k3q[2], q[2]), pt,
-                         fma(P->dt, k3p[0], pr), fma(P->dt, k3p[1], pth), pph, k4q, k4p);
-            w = 1.0 / fabs(k4q[0]);
-            for (int m = 0; m < 4; ++m) k4q[m] = k4q[m] * w;
-            k4p[0] = k4p[0] * w;
-            k4p[1] = k4p[1] * w;
+            const double nu = rk4t_stage(P, eps_sc, q[1], q[2], sn, cs, 0.0, 0.0, pt, pr, pth,
+                                         pph, k1q, k1p);
+            rk4t_stage(P, eps_sc, fma(hh, k1q[1], q[1]), q[2], sn, cs, hh, k1q[2], pt,
+                       fma(hh, k1p[0], pr), fma(hh, k1p[1], pth), pph, k2q, k2p);
+            rk4t_stage(P, eps_sc, fma(hh, k2q[1], q[1]), q[2], sn, cs, hh, k2q[2], pt,
+                       fma(hh, k2p[0], pr), fma(hh, k2p[1], pth), pph, k3q, k3p);
+            rk4t_stage(P, eps_sc, fma(P->dt, k3q[1], q[1]), q[2], sn, cs, P->dt, k3q[2], pt,
+                       fma(P->dt, k3p[0], pr), fma(P->dt, k3p[1], pth), pph, k4q, k4p);
             const double h6 = P->dt * (1.0 / 6.0);
-            for (int m = 0; m < 4; ++m)
-                q[m] = fma(h6, ((k1q[m] + 2.0 * k2q[m]) + 2.0 * k3q[m]) + k4q[m], q[m]);
+            double S[4];
+            for (int m = 0; m < 4; ++m) {
+                S[m] = ((k1q[m] + 2.0 * k2q[m]) + 2.0 * k3q[m]) + k4q[m];
+                q[m] = fma(h6, S[m], q[m]);
+            }
             pr = fma(h6, ((k1p[0] + 2.0 * k2p[0]) + 2.0 * k3p[0]) + k4p[0], pr);
             pth = fma(h6, ((k1p[1] + 2.0 * k2p[1]) + 2.0 * k3p[1]) + k4p[1], pth);
+            if (P->kind != METRIC_MN) {
+                double s2, c2;
+                rotate_pair(sn, cs, h6 * S[2], &s2, &c2);  /* the carried pair follows theta */
+                sn = s2;
+                cs = c2;
+            }
             if (in_disk(P, q)) { flag = FLAG_DISK; break; }
             if (q[1] > r_esc) { flag = FLAG_ESCAPE; break; }
             if (nu > P->horizon_norm) { flag = FLAG_HORIZON; break; }

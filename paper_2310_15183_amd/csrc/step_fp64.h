@@ -377,16 +377,80 @@ static __device__ __forceinline__ double rk4_step_direct(const Hole& H, const In
 // Methods of the one-ray-per-lane kernels (the values of gr_integrator.method).
 enum { M_RK4 = 0, M_EULER = 1, M_RK4_TIME = 2 };
 
-// One explicit Euler or coordinate-time RK4 step on Kerr-Newman (sin/cos of
-// theta by sincos_def at every point).
-template <int METHOD>
-static __device__ __forceinline__ double kn_direct_step(const Hole& H, const Integrator& in,
-                                                        Ray& y) {
-    const auto f = [&](double r, double th, double pr, double pth) {
-        return rhs(H, in, r, th, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
+// One explicit Euler or coordinate-time RK4 step on Kerr-Newman in the
+// carried form of rk4_carry: the ray's (sin, cos) pair, rotated by each stage
+// point's increment of theta and, after the update, by the step's; the same
+// Euler and coordinate-time RK4 as euler_generic and rk4t_generic otherwise
+// (p-dot scaled in the right-hand side, IEEE 1/|dt/dtau| per stage).
+// GENERAL and dmax as for rk4_carry.
+template <int METHOD, bool GENERAL, bool UNIT_COS = false>
+static __device__ __forceinline__ double kn_carry_step(const Hole& H, const Integrator& in,
+                                                       Ray& y, double& dmax) {
+    const auto f = [&](double r, double sn, double cs, double pr, double pth) {
+        return rhs_sc<UNIT_COS>(H, in, r, sn, cs, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
     };
-    if constexpr (METHOD == M_EULER) return euler_generic(f, in, y);
-    else return rk4t_generic(f, in, y);
+    dmax = 0.0;
+    const auto rot = [&](double d, double& sn, double& cs) {
+        if constexpr (GENERAL) {
+            rotate_sc(y.sn, y.cs, d, sn, cs);
+        } else {
+            dmax = fmax(dmax, fabs(d));
+            rotate_small(y.sn, y.cs, d, sn, cs);
+        }
+    };
+    double sn, cs;
+    if constexpr (METHOD == M_EULER) {
+        const Deriv k = f(y.r, y.sn, y.cs, y.pr, y.pth);
+        const double nu = fabs(k.qt);
+        const double h = div_rn(in.dt, nu);
+        rot(h * k.qh, sn, cs);
+        y.t = fma(h, k.qt, y.t);
+        y.r = fma(h, k.qr, y.r);
+        y.th = fma(h, k.qh, y.th);
+        y.ph = fma(h, k.qp, y.ph);
+        y.pr = fma(h, k.pr, y.pr);
+        y.pth = fma(h, k.ph, y.pth);
+        y.sn = sn;
+        y.cs = cs;
+        return nu;
+    } else {
+        const auto per_t = [](Deriv& k) {
+            const double w = 1.0 / fabs(k.qt);
+            k.qt = k.qt * w; k.qr = k.qr * w; k.qh = k.qh * w; k.qp = k.qp * w;
+            k.pr = k.pr * w; k.ph = k.ph * w;
+        };
+        const double hh = 0.5 * in.dt;
+        Deriv k = f(y.r, y.sn, y.cs, y.pr, y.pth);
+        const double nu = fabs(k.qt);
+        per_t(k);
+        double st = k.qt, sr = k.qr, sh = k.qh, sp = k.qp, spr = k.pr, sph = k.ph;
+        rot(hh * k.qh, sn, cs);
+        k = f(fma(hh, k.qr, y.r), sn, cs, fma(hh, k.pr, y.pr), fma(hh, k.ph, y.pth));
+        per_t(k);
+        st = fma(2.0, k.qt, st); sr = fma(2.0, k.qr, sr); sh = fma(2.0, k.qh, sh);
+        sp = fma(2.0, k.qp, sp); spr = fma(2.0, k.pr, spr); sph = fma(2.0, k.ph, sph);
+        rot(hh * k.qh, sn, cs);
+        k = f(fma(hh, k.qr, y.r), sn, cs, fma(hh, k.pr, y.pr), fma(hh, k.ph, y.pth));
+        per_t(k);
+        st = fma(2.0, k.qt, st); sr = fma(2.0, k.qr, sr); sh = fma(2.0, k.qh, sh);
+        sp = fma(2.0, k.qp, sp); spr = fma(2.0, k.pr, spr); sph = fma(2.0, k.ph, sph);
+        rot(in.dt * k.qh, sn, cs);
+        k = f(fma(in.dt, k.qr, y.r), sn, cs, fma(in.dt, k.pr, y.pr), fma(in.dt, k.ph, y.pth));
+        per_t(k);
+        st = st + k.qt; sr = sr + k.qr; sh = sh + k.qh; sp = sp + k.qp;
+        spr = spr + k.pr; sph = sph + k.ph;
+        const double h6 = in.dt * (1.0 / 6.0);
+        rot(h6 * sh, sn, cs);
+        y.t = fma(h6, st, y.t);
+        y.r = fma(h6, sr, y.r);
+        y.th = fma(h6, sh, y.th);
+        y.ph = fma(h6, sp, y.ph);
+        y.pr = fma(h6, spr, y.pr);
+        y.pth = fma(h6, sph, y.pth);
+        y.sn = sn;
+        y.cs = cs;
+        return nu;
+    }
 }
 
 template <int METHOD>

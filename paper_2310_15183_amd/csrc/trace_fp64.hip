@@ -25,8 +25,9 @@ namespace {
 using namespace detail;
 
 // One lane, one ray (static_ray); the grid covers every ray.  METHOD selects
-// RK4 (the carried form), explicit Euler or RK4 in coordinate time; DISK adds
-// the ring's exit test; UC: the RK4 step's cos eps is 1.0 (rhs_sc).
+// RK4, explicit Euler or RK4 in coordinate time, each in the carried form;
+// DISK adds the ring's exit test; UC: cos eps is 1.0 (rhs_sc).  A ray whose
+// rotation leaves the series' range is left PENDING for the second pass.
 template <typename T, int METHOD, bool DISK, bool UC>
 __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
     int64_t k, pix;
@@ -37,9 +38,10 @@ __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
     int f = start_flag(A.in, y);
     if constexpr (METHOD != M_RK4) {
         while (f == RUNNING) {
-            const double nu = kn_direct_step<METHOD>(A.hole, A.in, y);
+            double dmax;
+            const double nu = kn_carry_step<METHOD, false, UC>(A.hole, A.in, y, dmax);
             ++s;
-            f = exit_flag<DISK>(A.in, A.r_esc, y, nu, s);
+            f = dmax > ROT_SERIES_MAX ? PENDING : exit_flag<DISK>(A.in, A.r_esc, y, nu, s);
         }
     } else {
         while (f == RUNNING) {
@@ -53,11 +55,12 @@ __global__ void __launch_bounds__(256) trace_fp64_static(const FrameArgs A) {
     else write_ray<T>(A.out, k, y, f, s);
 }
 
-// Second pass of a binary64 RK4 frame: the rays left PENDING by the first
-// are traced again from the start with the general step (grid-stride over
-// the output entries; on the configured workloads a few rays that graze the
-// polar axis at the larger steps, none on the 1000x1000 frame).
-template <typename T, bool DISK>
+// Second pass of a binary64 Kerr-Newman frame: the rays left PENDING by the
+// first are traced again from the start with the general step of the same
+// method (grid-stride over the output entries; on the configured workloads a
+// few rays that graze the polar axis at the larger steps, none on the
+// 1000x1000 frame).
+template <typename T, bool DISK, int METHOD = M_RK4>
 __global__ void __launch_bounds__(256) trace_fp64_redo(const FrameArgs A) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < A.nray; k += stride) {
@@ -67,7 +70,10 @@ __global__ void __launch_bounds__(256) trace_fp64_redo(const FrameArgs A) {
         int s = 0;
         int f = start_flag(A.in, y);
         while (f == RUNNING) {
-            const double nu = rk4_step_general(A.hole, A.in, y);
+            double dmax;
+            const double nu = METHOD == M_RK4
+                                  ? rk4_step_general(A.hole, A.in, y)
+                                  : kn_carry_step<METHOD, true>(A.hole, A.in, y, dmax);
             ++s;
             f = exit_flag<DISK>(A.in, A.r_esc, y, nu, s);
         }
@@ -267,19 +273,19 @@ static int redo_grid(int64_t n) {
     return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
-template <bool DISK>
+template <bool DISK, int METHOD = M_RK4>
 static hipError_t launch_redo(const FrameArgs& A, bool f32_out, hipStream_t s) {
     if (A.nray <= 0) return hipSuccess;
     if (f32_out)
-        hipLaunchKernelGGL((trace_fp64_redo<float, DISK>), dim3(redo_grid(A.nray)), dim3(256), 0,
-                           s, A);
+        hipLaunchKernelGGL((trace_fp64_redo<float, DISK, METHOD>), dim3(redo_grid(A.nray)),
+                           dim3(256), 0, s, A);
     else
-        hipLaunchKernelGGL((trace_fp64_redo<double, DISK>), dim3(redo_grid(A.nray)), dim3(256),
-                           0, s, A);
+        hipLaunchKernelGGL((trace_fp64_redo<double, DISK, METHOD>), dim3(redo_grid(A.nray)),
+                           dim3(256), 0, s, A);
     return hipGetLastError();
 }
 
-// The RK4 kernels come in two forms, for cos eps = 1.0 (eps <= 1.05e-8, the
+// The frame kernels come in two forms, for cos eps = 1.0 (eps <= 1.05e-8, the
 // paper's 1e-8 among them) and for any eps; both give the same bits.
 static bool unit_cos(const Integrator& in) { return in.cos_eps == 1.0; }
 
@@ -297,17 +303,13 @@ static void launch_static_kernel(const FrameArgs& A, bool f32_out, const LaunchS
 template <int METHOD, bool DISK>
 static hipError_t launch_static(const FrameArgs& A, bool f32_out, const LaunchShape& L,
                                 hipStream_t s) {
-    if constexpr (METHOD == M_RK4) {
-        if (unit_cos(A.in))
-            launch_static_kernel<METHOD, DISK, true>(A, f32_out, L, s);
-        else
-            launch_static_kernel<METHOD, DISK, false>(A, f32_out, L, s);
-    } else {
+    if (unit_cos(A.in))
+        launch_static_kernel<METHOD, DISK, true>(A, f32_out, L, s);
+    else
         launch_static_kernel<METHOD, DISK, false>(A, f32_out, L, s);
-    }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || METHOD != M_RK4) return e;
-    return launch_redo<DISK>(A, f32_out, s);
+    if (e != hipSuccess) return e;
+    return launch_redo<DISK, METHOD>(A, f32_out, s);
 }
 
 template <int METHOD>
