@@ -53,7 +53,7 @@ def _stale() -> bool:
 def build(force: bool = True) -> str:
     """Compile oracle.c and listing.c into liboracle.so next to them (gcc, plain C11)."""
     if force or _stale():
-        tmp = _LIB + ".tmp"
+        tmp = f"{_LIB}.{os.getpid()}.tmp"      # one per process: test workers may build at once
         subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
