@@ -24,12 +24,12 @@ def g():
     return g
 
 
-def _twin(case, integ, mn=False, pixels=None, disk=None):
+def _twin(case, integ, mn=False, pixels=None, disk=None, method=2):
     import oracle
     trace = oracle.trace_frame_mn if mn else oracle.trace_frame
     res = trace(*case, dt=integ.dt, eps=integ.fd_eps, horizon_norm=integ.horizon_norm,
                 escape_factor=integ.escape_factor, max_steps=integ.max_steps, pixels=pixels,
-                want_p0=True, form="twin", method=2, disk=disk)
+                want_p0=True, form="twin", method=method, disk=disk)
     return {"t": res.t, "r": res.r, "theta": res.theta, "phi": res.phi, "p_t": res.p0[:, 0],
             "p_r": res.pr, "p_theta": res.ptheta, "p_phi": res.p0[:, 3], "flag": res.flag,
             "steps": res.steps}
@@ -103,6 +103,28 @@ def test_megapixel_sampled_and_listing_gate(g):
     assert st["bit_identical"] == st["n"]
     lis = oracle.trace_frame(*case, dt=0.005, max_steps=50000, pixels=pix, method=2, probe=8)
     print(compare_at_sensitivity(sub, lis))
+
+
+@pytest.mark.parametrize("method", [2, 1])
+def test_large_steps_take_the_second_pass_bit_exact(g, method):
+    """dt = 0.5 on a 24 x 24 Kerr-Newman frame, coordinate-time RK4 and
+    Euler: stage rotations by more than 1/32 (the twin halves thousands of
+    them) leave rays to the frame's second pass, which traces them again
+    with the general rotation; every field is bit-identical to the twin."""
+    import oracle
+    case = (0.5, 0.3, 0.2, 12.0, 70 * DEG, 0.0, 60 * DEG, 24, 24)
+    integ = g.make_integrator(dt=0.5, max_steps=20000,
+                              method=g.GR_RK4_TIME if method == 2 else g.GR_EULER)
+    ctx = g.gr_trace_init(0, integ)
+    try:
+        gpu = gpu_trace(ctx, *case)
+    finally:
+        g.gr_trace_destroy(ctx)
+    oracle.halved_rotations(reset=True)
+    ref = _twin(case, integ, method=method)
+    assert oracle.halved_rotations() > 1000
+    st = compare(gpu, ref, angle_tol=0.0)
+    assert st["bit_identical"] == st["n"]
 
 
 def test_refused_where_not_built(g):

@@ -14,6 +14,7 @@ import math
 
 import mpmath
 import numpy as np
+import pytest
 
 import oracle
 from tests.sens_gate import compare_at_sensitivity
@@ -63,14 +64,16 @@ def test_rotations_compose():
     assert np.abs(s2 - s3).max() < 8 * ULP1 and np.abs(c2 - c3).max() < 8 * ULP1
 
 
-def test_large_steps_use_halved_rotations_and_meet_the_gate():
+@pytest.mark.parametrize("method", [0, 1, 2])
+def test_large_steps_use_halved_rotations_and_meet_the_gate(method):
     """dt = 0.5 on a 24 x 24 Kerr-Newman frame: thousands of rotations by
-    more than 1/32; the twin still meets the listing-form gate."""
+    more than 1/32 with each integrator (RK4, Euler, coordinate-time RK4);
+    the twin still meets the listing-form gate."""
     case = (0.5, 0.3, 0.2, 12.0, math.radians(70.0), 0.0, math.radians(60.0), 24, 24)
     oracle.halved_rotations(reset=True)
-    twin = oracle.trace_frame(*case, dt=0.5, max_steps=20000, form="twin")
+    twin = oracle.trace_frame(*case, dt=0.5, max_steps=20000, form="twin", method=method)
     assert oracle.halved_rotations() > 1000
-    lis = oracle.trace_frame(*case, dt=0.5, max_steps=20000, probe=8)
+    lis = oracle.trace_frame(*case, dt=0.5, max_steps=20000, probe=8, method=method)
     st = compare_at_sensitivity({"theta": twin.theta, "phi": twin.phi, "flag": twin.flag,
                                  "steps": twin.steps}, lis)
     print(st)
