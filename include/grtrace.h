@@ -180,8 +180,9 @@ typedef struct gr_ctx gr_ctx;
  * block: threads per workgroup (64, 128 or 256); waves_per_simd: target
  * residency used to size the persistent grid (1..8, 0 = as many as fit);
  * refill: 1 = lanes that finish take the next ray from the work queue,
- * 0 = each lane traces one ray and the grid covers every ray (frames only;
- * batches always refill); order: 0 = rays are queued in the order given;
+ * 0 = each lane traces one ray and the grid covers every ray (one 8x8 pixel
+ * tile of a frame, or 64 entries of a pixel list, per wave); order: 0 = rays
+ * are queued in the order given;
  * 1 = batches queue the instances with the longest expected rays (largest
  * escape radius) first, which shortens the tail; 2 = as 1, and frames of at
  * least 4096 pixels traced with refill queue their pixels sorted by how close
