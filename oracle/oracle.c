@@ -442,10 +442,10 @@ static void metric_at_point(const oracle_params *P, double r, double theta, doub
  * Paper eq. hamGeodesic with the factor 1/2 of Appendix A; derivatives by
  * forward differences of step eps as in the listing: the metric (Kerr-Newman
  * or Manko-Novikov) at (r,theta), (r+eps,theta) and (r,theta+eps), given s and c,
- * the sine and cosine of the point's theta.  sin and cos at theta+eps are the
- * angle-addition identity applied to those at theta and at eps (for eps =
- * 1e-8, cos eps rounds to 1 and sin eps to eps), so the theta step is eps
- * itself.  For Kerr-Newman each displaced component is formed together with
+ * the sine and cosine of the point's theta.  sin (and, for Manko-Novikov,
+ * cos) at theta+eps are the angle-addition identity applied to those at theta
+ * and at eps (for eps = 1e-8, cos eps rounds to 1 and sin eps to eps), so the
+ * theta step is eps itself; the Kerr-Newman terms need sin^2 only.  For Kerr-Newman each displaced component is formed together with
  * its difference from the base point's (metric_diff, one rounding for the
  * difference); the Manko-Novikov metric is evaluated in full at the three
  * points and subtracted.  The contraction sums the differences of the five

@@ -91,7 +91,8 @@ static __device__ __forceinline__ Deriv deriv_from(const InvMetric& g, const Inv
 }
 
 // Right-hand side at one stage point: metric at (r, th), (r+eps, th) and
-// (r, th+eps), sin/cos at th+eps by angle addition from those at th and eps;
+// (r, th+eps), sin at th+eps by angle addition from sin/cos at th and eps
+// (the Kerr-Newman terms need sin^2 only: rho2 comes from it);
 // each displaced component is formed together with its difference from the
 // base point's (metric_diff: one rounding for the difference);
 // p-dot = -1/(2 eps) times the sum of the five component differences times
