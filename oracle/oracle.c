@@ -419,6 +419,13 @@ static double recip_newton(double x, double y0)
     return fma(y, e, y);
 }
 
+/* Largest |1 - x y0| from which the theta-displaced point's reciprocal is
+ * refined (two Newton steps, which are correctly rounded there) rather than
+ * divided: 2^-15.  Over the theta displacement rho^2 Delta sin^2 moves by the
+ * factor 1 - 2 eps cot(theta) + O(eps), so only points within about
+ * 1500 eps of the polar axis divide. */
+#define NEWTON_SEED_MAX 0x1p-15
+
 /* Full inverse metric at one point: is = 1/(rho^2 Delta sin^2) divided,
  * inv = is sin^2. */
 static void inverse_metric(const oracle_params *P, double r, double s2, double g[5])
@@ -465,11 +472,12 @@ static void rhs_core(const oracle_params *P, const double eps_sc[2], double r, d
     const double se = fma(c, eps_sc[0], s * eps_sc[1]);      /* sin(theta + eps) */
     const double ce = fma(-s, eps_sc[0], c * eps_sc[1]);     /* cos(theta + eps) */
     const double s2 = s * s, se2 = se * se;
-    /* reciprocals (two divisions): is = 1/(rho^2 Delta sin^2) divided at
-     * (r, theta) and at (r, theta + eps) (near the axis sin^2 changes by a
-     * large factor over eps), inv = is sin^2 at each; at (r + eps, theta),
-     * where only rho^2 Delta moves, by a factor 1 + O(eps), is is refined
-     * from the base point's */
+    /* reciprocals: is = 1/(rho^2 Delta sin^2) divided at (r, theta),
+     * inv = is sin^2; at (r + eps, theta), where only rho^2 Delta moves, by a
+     * factor 1 + O(eps), is is refined from the base point's; at
+     * (r, theta + eps) likewise where the refinement starts within
+     * NEWTON_SEED_MAX, divided where it does not (within about 1500 eps of
+     * the axis, where sin^2 changes by a large factor over eps) */
     if (P->kind == METRIC_MN) {
         /* full evaluations at the three points, then the differences */
         double gr[5], gth[5];
@@ -484,7 +492,9 @@ static void rhs_core(const oracle_params *P, const double eps_sc[2], double r, d
         const double is = 1.0 / (rho2_delta(P, r, s2) * s2);
         const double inv = is * s2;
         const double is_r = recip_newton(rho2_delta(P, r + P->eps, s2) * s2, is);
-        const double is_t = 1.0 / (rho2_delta(P, r, se2) * se2);
+        const double xt = rho2_delta(P, r, se2) * se2;
+        const double is_t = fabs(fma(-xt, is, 1.0)) <= NEWTON_SEED_MAX ? recip_newton(xt, is)
+                                                                       : 1.0 / xt;
         metric_from(P, r, s2, inv, is, g);
         metric_diff(P, r + P->eps, s2, is_r * s2, is_r, g, dr);
         metric_diff(P, r, se2, is_t * se2, is_t, g, dth);

@@ -37,6 +37,13 @@ static __device__ __forceinline__ double div_rn(double a, double x) {
     return fma(fma(-x, q, a), y, q);
 }
 
+// Largest |1 - x y0| from which the theta-displaced point's reciprocal is
+// refined from the base point's (two Newton steps, correctly rounded there)
+// instead of divided: 2^-15.  rho2 Delta sin^2 moves by the factor
+// 1 - 2 eps cot(theta) + O(eps) over the displacement, so only points within
+// about 1500 eps of the polar axis divide.
+constexpr double NEWTON_SEED_MAX = 0x1p-15;
+
 struct Deriv {
     double qt, qr, qh, qp;   // dq^mu/dtau
     double pr, ph;           // dp_r/dtau, dp_theta/dtau
@@ -97,19 +104,24 @@ static __device__ __forceinline__ Deriv deriv_from(const InvMetric& g, const Inv
 // base point's (metric_diff: one rounding for the difference);
 // p-dot = -1/(2 eps) times the sum of the five component differences times
 // p_nu p_sigma, in the order tt, tphi (weight 2 p_t p_phi), rr, thth, phph.
-// Two divisions per stage: is = 1/(rho2 Delta sin^2) at (r, th) and at
-// (r, th+eps), inv = is sin^2 at each (near the axis sin^2 changes by a large
-// factor over eps); at (r+eps, th), where only rho2 Delta moves, by a factor
-// 1 + O(eps), is is refined from the base point's by two Newton steps.
+// Reciprocals: is = 1/(rho2 Delta sin^2) divided at (r, th), inv = is
+// sin^2; at (r+eps, th), where only rho2 Delta moves, by a factor 1 + O(eps),
+// is is refined from the base point's by two Newton steps; at (r, th+eps)
+// likewise where the refinement starts within NEWTON_SEED_MAX and divided
+// where it does not (near the axis sin^2 changes by a large factor over eps),
+// inv = is sin^2 there too.
 // s, c: sin and cos of the stage point's theta.
 // UNIT_COS: cos eps is 1.0 (it rounds to 1 for eps below 1.05e-8, the
 // paper's 1e-8 included), so the products with it are exact and are left
 // out; chosen per launch, it gives the same bits as the general form.
-template <bool UNIT_COS = false, bool RAW = false>
+// SEEDED: the theta-displaced reciprocal is refined whatever its starting
+// residual, whose largest magnitude is kept in emax (a step whose emax exceeds
+// NEWTON_SEED_MAX is not the canonical one and is redone by the caller).
+template <bool UNIT_COS = false, bool RAW = false, bool SEEDED = false>
 static __device__ __forceinline__ Deriv rhs_sc(const Hole& H, const Integrator& in, double r,
                                                double s, double c, double pt, double pr,
                                                double pth, double pph, double wtt, double wtp,
-                                               double wpp) {
+                                               double wpp, double* emax = nullptr) {
     const ThetaTerms T0 = theta_terms_s(H, s);
     const ThetaTerms T1 = theta_terms_s(H, fma(c, in.sin_eps, UNIT_COS ? s : s * in.cos_eps));
     const RadialTerms R0 = radial_terms(H, r);
@@ -117,7 +129,18 @@ static __device__ __forceinline__ Deriv rhs_sc(const Hole& H, const Integrator& 
     const double is = rcp_rn(rho2_delta(H, R0, T0) * T0.s2);
     const double inv = is * T0.s2;
     const double is_r = recip_newton(rho2_delta(H, R1, T0) * T0.s2, is);
-    const double is_t = rcp_rn(rho2_delta(H, R0, T1) * T1.s2);
+    // at (r, th+eps): refined from the base point's where that starts within
+    // NEWTON_SEED_MAX, divided elsewhere (near the axis); SEEDED refines
+    // always and returns the largest starting residual in emax instead
+    const double xt = rho2_delta(H, R0, T1) * T1.s2;
+    const double et = fma(-xt, is, 1.0);
+    double is_t;
+    if constexpr (SEEDED) {
+        *emax = fmax(*emax, fabs(et));
+        is_t = recip_newton(xt, is);
+    } else {
+        is_t = fabs(et) <= NEWTON_SEED_MAX ? recip_newton(xt, is) : rcp_rn(xt);
+    }
     const InvMetric g = metric_from(H, R0, T0, inv, is);
     const InvMetric dr = metric_diff(H, R1, T0, is_r * T0.s2, is_r, g);
     const InvMetric dh = metric_diff(H, R0, T1, is_t * T1.s2, is_t, g);
@@ -281,16 +304,20 @@ static __device__ __forceinline__ double euler_generic(const Rhs& rhs_at, const 
 // dt/dtau = g^tt p_t + g^tphi p_phi and dphi/dtau = g^tphi p_t + g^phph p_phi
 // with p_t, p_phi constant along the ray, so the weighted sums of t and phi
 // are taken over the three components and contracted once per step.
-// GENERAL = false rotates by rotate_small (no branch) and returns in dmax the
-// largest |increment|; the step equals the GENERAL one when dmax <= 1/32.
+// GENERAL = false takes no branch: it rotates by rotate_small and refines
+// every theta-displaced reciprocal from the base point's (rhs_sc SEEDED), and
+// returns in dmax the largest |increment| or the largest starting residual of
+// those refinements times ROT_SERIES_MAX / NEWTON_SEED_MAX, whichever is
+// larger; the step equals the GENERAL one when dmax <= ROT_SERIES_MAX.
 template <bool GENERAL, bool UNIT_COS = false>
 static __device__ __forceinline__ double rk4_carry(const Hole& H, const Integrator& in, Ray& y,
                                                    double& dmax) {
     // p-dot comes unscaled (RAW): -1/(2 eps) is folded into the step sizes
     // of the momentum components, hh in.scale, h in.scale and h/6 in.scale
+    double emax = 0.0;
     const auto f = [&](double r, double sn, double cs, double pr, double pth) {
-        return rhs_sc<UNIT_COS, true>(H, in, r, sn, cs, y.pt, pr, pth, y.pph, y.wtt, y.wtp,
-                                      y.wpp);
+        return rhs_sc<UNIT_COS, true, !GENERAL>(H, in, r, sn, cs, y.pt, pr, pth, y.pph, y.wtt,
+                                                y.wtp, y.wpp, &emax);
     };
     dmax = 0.0;
     const auto rot = [&](double d, double& sn, double& cs) {
@@ -337,6 +364,7 @@ static __device__ __forceinline__ double rk4_carry(const Hole& H, const Integrat
     y.pth = fma(h6s, sph, y.pth);
     y.sn = sn;
     y.cs = cs;
+    if constexpr (!GENERAL) dmax = fmax(dmax, emax * (ROT_SERIES_MAX / NEWTON_SEED_MAX));
     return nu;
 }
 
@@ -387,8 +415,13 @@ enum { M_RK4 = 0, M_EULER = 1, M_RK4_TIME = 2 };
 template <int METHOD, bool GENERAL, bool UNIT_COS = false>
 static __device__ __forceinline__ double kn_carry_step(const Hole& H, const Integrator& in,
                                                        Ray& y, double& dmax) {
+    double emax = 0.0;
     const auto f = [&](double r, double sn, double cs, double pr, double pth) {
-        return rhs_sc<UNIT_COS>(H, in, r, sn, cs, y.pt, pr, pth, y.pph, y.wtt, y.wtp, y.wpp);
+        return rhs_sc<UNIT_COS, false, !GENERAL>(H, in, r, sn, cs, y.pt, pr, pth, y.pph, y.wtt,
+                                                 y.wtp, y.wpp, &emax);
+    };
+    const auto seeded = [&]() {
+        if constexpr (!GENERAL) dmax = fmax(dmax, emax * (ROT_SERIES_MAX / NEWTON_SEED_MAX));
     };
     dmax = 0.0;
     const auto rot = [&](double d, double& sn, double& cs) {
@@ -413,6 +446,7 @@ static __device__ __forceinline__ double kn_carry_step(const Hole& H, const Inte
         y.pth = fma(h, k.ph, y.pth);
         y.sn = sn;
         y.cs = cs;
+        seeded();
         return nu;
     } else {
         const auto per_t = [](Deriv& k) {
@@ -450,6 +484,7 @@ static __device__ __forceinline__ double kn_carry_step(const Hole& H, const Inte
         y.pth = fma(h6, sph, y.pth);
         y.sn = sn;
         y.cs = cs;
+        seeded();
         return nu;
     }
 }

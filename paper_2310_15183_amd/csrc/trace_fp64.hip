@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(256) trace_fp64_batch(const BatchArgs B,
 // by binary search of the wave offsets and takes the instance's 8x8 tile (or
 // 64 pixel-list entries) w - wfirsts[instance].
 template <bool UC>
-__global__ void __launch_bounds__(256) trace_fp64_batch_static(const BatchArgs B) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) trace_fp64_batch_static(const BatchArgs B) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t wave = g >> 6;
     if (wave >= B.wfirsts[B.ninst]) return;
