@@ -35,7 +35,7 @@ def oracle_trace(M, a, Q, r0, th0, ph0, fov, W, H, integ, pixels=None):
     res = oracle.trace_frame(M, a, Q, r0, th0, ph0, fov, W, H, dt=integ.dt,
                              eps=integ.fd_eps, horizon_norm=integ.horizon_norm,
                              escape_factor=integ.escape_factor, max_steps=integ.max_steps,
-                             pixels=pixels, want_p0=True, form="twin")
+                             pixels=pixels, want_p0=True, form="twin", method=integ.method)
     return {"t": res.t, "r": res.r, "theta": res.theta, "phi": res.phi,
             "p_t": res.p0[:, 0], "p_r": res.pr, "p_theta": res.ptheta, "p_phi": res.p0[:, 3],
             "flag": res.flag, "steps": res.steps}
