@@ -86,6 +86,8 @@ def _load():
         lib.oracle_sincos.argtypes = [vp, i64, vp]
         lib.oracle_recip_newton.restype = None
         lib.oracle_recip_newton.argtypes = [vp, vp, i64, vp]
+        lib.oracle_recip_newton3.restype = None
+        lib.oracle_recip_newton3.argtypes = [vp, vp, i64, vp]
         lib.oracle_rhs.restype = None
         lib.oracle_rhs.argtypes = [d, d, d, d, d, d, d, d, d, d, vp, vp]
         lib.oracle_trace_frame_mn.restype = i64
@@ -328,13 +330,15 @@ def set_trig_mode(mode: int) -> None:
     _load().oracle_set_trig_mode(int(mode))
 
 
-def recip_newton(x, y0) -> np.ndarray:
+def recip_newton(x, y0, steps=2) -> np.ndarray:
     """The oracle's Newton-refined reciprocal of x from y0 (an exact 1/x0 of a
-    nearby x0), elementwise."""
+    nearby x0), elementwise, with two steps (the r displacement) or three (the
+    theta displacement)."""
     x = np.ascontiguousarray(x, dtype=np.float64).ravel()
     y0 = np.ascontiguousarray(y0, dtype=np.float64).ravel()
     out = np.empty_like(x)
-    _load().oracle_recip_newton(_ptr(x), _ptr(y0), x.size, _ptr(out))
+    fn = _load().oracle_recip_newton if steps == 2 else _load().oracle_recip_newton3
+    fn(_ptr(x), _ptr(y0), x.size, _ptr(out))
     return out
 
 

@@ -419,12 +419,23 @@ static double recip_newton(double x, double y0)
     return fma(y, e, y);
 }
 
+/* Three Newton steps: relative error e0^8 plus rounding. */
+static double recip_newton3(double x, double y0)
+{
+    double e = fma(-x, y0, 1.0);
+    double y = fma(y0, e, y0);
+    e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
 /* Largest |1 - x y0| from which the theta-displaced point's reciprocal is
- * refined (two Newton steps, which are correctly rounded there) rather than
- * divided: 2^-15.  Over the theta displacement rho^2 Delta sin^2 moves by the
- * factor 1 - 2 eps cot(theta) + O(eps), so only points within about
- * 1500 eps of the polar axis divide. */
-#define NEWTON_SEED_MAX 0x1p-15
+ * refined (three Newton steps: e0^8 <= 2^-64, within about an ulp) rather
+ * than divided: 2^-8.  Over the theta displacement rho^2 Delta sin^2 moves by
+ * the factor 1 - 2 eps cot(theta) + O(eps), so only points within about
+ * 5e5 eps of the polar axis divide. */
+#define NEWTON_SEED_MAX 0x1p-8
 
 /* Full inverse metric at one point: is = 1/(rho^2 Delta sin^2) divided,
  * inv = is sin^2. */
@@ -475,9 +486,9 @@ static void rhs_core(const oracle_params *P, const double eps_sc[2], double r, d
     /* reciprocals: is = 1/(rho^2 Delta sin^2) divided at (r, theta),
      * inv = is sin^2; at (r + eps, theta), where only rho^2 Delta moves, by a
      * factor 1 + O(eps), is is refined from the base point's; at
-     * (r, theta + eps) likewise where the refinement starts within
-     * NEWTON_SEED_MAX, divided where it does not (within about 1500 eps of
-     * the axis, where sin^2 changes by a large factor over eps) */
+     * (r, theta + eps) by three Newton steps where the refinement starts
+     * within NEWTON_SEED_MAX, divided where it does not (within about 5e5 eps
+     * of the axis, where sin^2 changes by a large factor over eps) */
     if (P->kind == METRIC_MN) {
         /* full evaluations at the three points, then the differences */
         double gr[5], gth[5];
@@ -493,7 +504,7 @@ static void rhs_core(const oracle_params *P, const double eps_sc[2], double r, d
         const double inv = is * s2;
         const double is_r = recip_newton(rho2_delta(P, r + P->eps, s2) * s2, is);
         const double xt = rho2_delta(P, r, se2) * se2;
-        const double is_t = fabs(fma(-xt, is, 1.0)) <= NEWTON_SEED_MAX ? recip_newton(xt, is)
+        const double is_t = fabs(fma(-xt, is, 1.0)) <= NEWTON_SEED_MAX ? recip_newton3(xt, is)
                                                                        : 1.0 / xt;
         metric_from(P, r, s2, inv, is, g);
         metric_diff(P, r + P->eps, s2, is_r * s2, is_r, g, dr);
@@ -924,10 +935,16 @@ long oracle_halved_rotations(int reset)
     return v;
 }
 
-/* Accuracy checks of the Newton-refined reciprocal: out[k] = recip_newton(x[k], y0[k]). */
+/* Accuracy checks of the Newton-refined reciprocals: out[k] = recip_newton(x[k], y0[k])
+ * (two steps) or recip_newton3 (three). */
 void oracle_recip_newton(const double *x, const double *y0, int64_t n, double *out)
 {
     for (int64_t k = 0; k < n; ++k) out[k] = recip_newton(x[k], y0[k]);
+}
+
+void oracle_recip_newton3(const double *x, const double *y0, int64_t n, double *out)
+{
+    for (int64_t k = 0; k < n; ++k) out[k] = recip_newton3(x[k], y0[k]);
 }
 
 static oracle_params make_params(double M, double a, double Q, double dt, double eps,

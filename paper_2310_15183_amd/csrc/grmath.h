@@ -241,6 +241,17 @@ GR_HD double recip_newton(double x, double y0) {
     return fma(y, e, y);
 }
 
+// Three Newton steps: relative error e0^8 plus rounding, within about an
+// ulp for |e0| <= 2^-8.
+GR_HD double recip_newton3(double x, double y0) {
+    double e = fma(-x, y0, 1.0);
+    double y = fma(y0, e, y0);
+    e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
 // -------------------------------------------------------------------- exp
 // x = k ln2 + r, k = rint(x * fl(1/ln2)), r = (x - k LN2_HI) - k LN2_LO via
 // two fma (|r| <= ln2/2); exp r = sum_{n=0}^{13} r^n/n! by Horner in fma

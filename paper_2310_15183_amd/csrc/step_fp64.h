@@ -38,11 +38,11 @@ static __device__ __forceinline__ double div_rn(double a, double x) {
 }
 
 // Largest |1 - x y0| from which the theta-displaced point's reciprocal is
-// refined from the base point's (two Newton steps, correctly rounded there)
-// instead of divided: 2^-15.  rho2 Delta sin^2 moves by the factor
-// 1 - 2 eps cot(theta) + O(eps) over the displacement, so only points within
-// about 1500 eps of the polar axis divide.
-constexpr double NEWTON_SEED_MAX = 0x1p-15;
+// refined from the base point's (three Newton steps: e0^8 <= 2^-64, so within
+// about an ulp) instead of divided: 2^-8.  rho2 Delta sin^2 moves by the
+// factor 1 - 2 eps cot(theta) + O(eps) over the displacement, so only points
+// within about 5e5 eps of the polar axis divide.
+constexpr double NEWTON_SEED_MAX = 0x1p-8;
 
 struct Deriv {
     double qt, qr, qh, qp;   // dq^mu/dtau
@@ -107,7 +107,7 @@ static __device__ __forceinline__ Deriv deriv_from(const InvMetric& g, const Inv
 // Reciprocals: is = 1/(rho2 Delta sin^2) divided at (r, th), inv = is
 // sin^2; at (r+eps, th), where only rho2 Delta moves, by a factor 1 + O(eps),
 // is is refined from the base point's by two Newton steps; at (r, th+eps)
-// likewise where the refinement starts within NEWTON_SEED_MAX and divided
+// by three where the refinement starts within NEWTON_SEED_MAX and divided
 // where it does not (near the axis sin^2 changes by a large factor over eps),
 // inv = is sin^2 there too.
 // s, c: sin and cos of the stage point's theta.
@@ -137,9 +137,9 @@ static __device__ __forceinline__ Deriv rhs_sc(const Hole& H, const Integrator& 
     double is_t;
     if constexpr (SEEDED) {
         *emax = fmax(*emax, fabs(et));
-        is_t = recip_newton(xt, is);
+        is_t = recip_newton3(xt, is);
     } else {
-        is_t = fabs(et) <= NEWTON_SEED_MAX ? recip_newton(xt, is) : rcp_rn(xt);
+        is_t = fabs(et) <= NEWTON_SEED_MAX ? recip_newton3(xt, is) : rcp_rn(xt);
     }
     const InvMetric g = metric_from(H, R0, T0, inv, is);
     const InvMetric dr = metric_diff(H, R1, T0, is_r * T0.s2, is_r, g);

@@ -67,6 +67,28 @@ def test_newton_reciprocal_is_correctly_rounded_for_small_displacements():
     assert abs(far[0] - 1 / 1.1) > 1e-5
 
 
+def test_three_newton_steps_reach_rounding_from_two_to_the_minus_8():
+    """The theta-displaced point's 1/(rho^2 Delta sin^2), three Newton steps
+    from the base point's reciprocal: within 1.5 ulp of 1/x (against 120-bit
+    arithmetic) for starting residuals up to 2^-8, the largest the kernels
+    refine from; two steps from 2^-8 leave ~2^-32, far from rounding."""
+    rng = np.random.default_rng(5)
+    x0 = 10.0 ** rng.uniform(-6, 6, 3000)
+    rel = np.concatenate([rng.uniform(-2.0 ** -8, 2.0 ** -8, 2000),
+                          np.array([2.0 ** -8, -(2.0 ** -8)] * 50),
+                          10.0 ** rng.uniform(-14, -4, 900)])
+    x = x0 * (1.0 + rel)
+    y0 = 1.0 / x0
+    got = oracle.recip_newton(x, y0, steps=3)
+    mp.mp.prec = 120
+    err = np.array([float(abs(mp.mpf(g) - 1 / mp.mpf(xi))) / np.spacing(float(1 / mp.mpf(xi)))
+                    for g, xi in zip(got, x)])
+    assert err.max() <= 1.5
+    assert np.mean(err <= 0.5 + 1e-9) > 0.9
+    two = oracle.recip_newton(np.array([1.0 + 2.0 ** -8]), np.array([1.0]))
+    assert abs(two[0] - 1 / (1.0 + 2.0 ** -8)) > 1e-11
+
+
 # --------------------------------------------------------------------------- metric
 @pytest.mark.parametrize("M,a,Q", [(0.5, 0.24, 0.0), (0.5, 0.24, 0.3), (0.5, 0.49, 0.0),
                                    (0.0, 0.3, 0.0), (0.5, 0.0, 0.0)])
