@@ -30,8 +30,8 @@ FRAMES = {
     "kn40": (0.5, 0.24, 0.3, 20.0, 80 * DEG, 0.0, 75 * DEG, 40, 40),
     "near_extremal40": (0.5, 0.49, 0.0, 20.0, 60 * DEG, 0.0, 75 * DEG, 40, 40),
     "high_latitude": (0.5, 0.1, 0.2, 35.0, 20 * DEG, 0.3, 40 * DEG, 19, 41),
-    # 3e-4 rad from the pole: theta-displaced points divided, not refined
-    "next_to_pole": (0.5, 0.3, 0.1, 20.0, 3e-4, 0.4, 60 * DEG, 16, 16),
+    # 2e-6 rad from the pole: theta-displaced points divided, not refined
+    "next_to_pole": (0.5, 0.3, 0.1, 20.0, 2e-6, 0.4, 60 * DEG, 16, 16),
 }
 MN_FRAMES = {
     "mn_listing_spacetime": (0.5, 0.24, 2.0, 8.0, math.pi / 2, 0.0, 75 * DEG, 24, 24),
