@@ -410,7 +410,8 @@ enum { M_RK4 = 0, M_EULER = 1, M_RK4_TIME = 2 };
 // carried form of rk4_carry: the ray's (sin, cos) pair, rotated by each stage
 // point's increment of theta and, after the update, by the step's; the same
 // Euler and coordinate-time RK4 as euler_generic and rk4t_generic otherwise
-// (p-dot scaled in the right-hand side, IEEE 1/|dt/dtau| per stage).
+// (p-dot scaled in the right-hand side, correctly rounded 1/|dt/dtau| per
+// stage).
 // GENERAL and dmax as for rk4_carry.
 template <int METHOD, bool GENERAL, bool UNIT_COS = false>
 static __device__ __forceinline__ double kn_carry_step(const Hole& H, const Integrator& in,
@@ -449,8 +450,10 @@ static __device__ __forceinline__ double kn_carry_step(const Hole& H, const Inte
         seeded();
         return nu;
     } else {
+        // w = 1/|dt/dtau| correctly rounded (rcp_rn: the same bits as IEEE
+        // division for the finite, normal values a stage produces)
         const auto per_t = [](Deriv& k) {
-            const double w = 1.0 / fabs(k.qt);
+            const double w = rcp_rn(fabs(k.qt));
             k.qt = k.qt * w; k.qr = k.qr * w; k.qh = k.qh * w; k.qp = k.qp * w;
             k.pr = k.pr * w; k.ph = k.ph * w;
         };
